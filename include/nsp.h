@@ -1,0 +1,188 @@
+/*
+ * nsp.h - C ABI of the MI355X (gfx950) projection Navier-Stokes / Parareal
+ * library (libnsp.so).
+ *
+ * The library implements the hot path of the space-time Parareal scheme of
+ * Croce, Ruprecht & Krause for the 3D incompressible Navier-Stokes equations
+ * (Eq. (1)): the fine propagator F and the coarse propagator G, each a
+ * sequence of forward-Euler Chorin-Temam projection steps on a uniform
+ * staggered grid (Sec. 2, discretization paragraph), the pressure Poisson
+ * solve of that projection, and the Parareal update of Eq. (6).
+ *
+ * Conventions shared by every entry point
+ *  - Array arguments are DEVICE pointers owned by the caller, FP64, densely
+ *    packed, x fastest.  For a grid of nx*ny*nz cells one slice holds
+ *        u [nz][ny][nx+1]   (x-faces)      v [nz][ny+1][nx]   (y-faces)
+ *        w [nz+1][ny][nx]   (z-faces)      p [nz][ny][nx]     (cell centres)
+ *    and a batch of B slices is B such arrays back to back (batch-major).
+ *  - y is the vertical direction; the lid (top face y = ly) moves in +x.
+ *  - A face is open when it is interior and both adjacent cells are fluid.
+ *    Values stored at closed faces are never read; every call that writes
+ *    velocities writes 0 there.
+ *  - Every call is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream) and returns after the stream has finished it, so host outputs
+ *    (info, jump) are valid on return.  Calls on one handle must not overlap.
+ *  - No C++ exception crosses this boundary.  Every call returns an
+ *    nsp_status; nsp_last_error() gives a message for the last failure on a
+ *    handle.  On NSP_ERR_NOT_CONVERGED and NSP_ERR_NONFINITE the outputs are
+ *    still written (best iterate).
+ */
+#ifndef NSP_H
+#define NSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NSP_OK = 0,
+    NSP_ERR_ARG = 1,           /* null pointer, bad size, non-integer step count */
+    NSP_ERR_NOT_CONVERGED = 2, /* a Poisson solve hit maxit / max_outer */
+    NSP_ERR_NONFINITE = 3,     /* a residual norm became NaN or Inf */
+    NSP_ERR_HIP = 4,           /* a HIP runtime call failed */
+    NSP_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+} nsp_status;
+
+typedef enum {
+    NSP_FP64 = 0,  /* Jacobi-PCG in FP64 */
+    NSP_MIXED = 1  /* FP32 Jacobi-PCG inner solves, FP64 defect correction */
+} nsp_precision;
+
+typedef struct nsp_handle nsp_handle;
+
+/* Grid of one handle.  The domain is [0,lx]x[0,ly]x[0,lz] with nx*ny*nz
+ * uniform cells (Sec. 2: uniform Cartesian staggered mesh).  `solid_host`
+ * (HOST pointer, nz*ny*nx bytes, nonzero = solid cell, or NULL) is copied at
+ * creation: solid cells approximate obstacles by cell enumeration with
+ * no-slip walls.  The fluid cells must form one face-connected region.
+ * `max_batch` bounds the batch of every later call; workspace for that many
+ * slices is allocated at creation.  periodic_z must be 0 (walls on all six
+ * faces). */
+typedef struct {
+    int nx, ny, nz;
+    double lx, ly, lz;
+    double re;               /* Reynolds number of Eq. (1) */
+    int periodic_z;          /* must be 0 */
+    const uint8_t *solid_host;
+    int max_batch;
+} nsp_grid;
+
+/* Poisson solve options.  The solve of A p = b, A = -D G the compatible
+ * Neumann Laplacian, stops when ||b - A p||_2 <= rtol ||b||_2 (recursive
+ * residual for FP64, recomputed FP64 residual for mixed).  Mixed: each inner
+ * FP32 solve stops at relative residual inner_rtol or maxit iterations; at
+ * most max_outer inner solves. */
+typedef struct {
+    double rtol;
+    int maxit;
+    nsp_precision prec;
+    double inner_rtol;
+    int max_outer;
+} nsp_poisson_opts;
+
+/* Per-slice report of the last call. */
+typedef struct {
+    int iters;          /* CG iterations summed over the steps of the call (inner ones for mixed) */
+    int max_iters;      /* largest per-step CG iteration count */
+    int outer;          /* FP64 restarts, or mixed defect-correction sweeps, summed */
+    int status;         /* worst nsp_status over the steps of this slice */
+    double rel_res_true;/* ||b - A p|| / ||b|| of the last solve, recomputed in FP64 */
+    double div_l2;      /* ||D u||_2 after the last step (= dt * ||b - A p||_2) */
+} nsp_solve_info;
+
+/* A batch of states (u, v, w, p); layout above. */
+typedef struct {
+    double *u, *v, *w, *p;
+} nsp_state;
+
+/* Create a handle: copies the grid and the solid mask to the device, sets
+ * the lid to u = 1 (Sec. 3, both simulations), allocates workspace for
+ * max_batch slices.  Returns NSP_ERR_ARG for non-positive sizes,
+ * NSP_ERR_UNSUPPORTED for periodic_z != 0. */
+nsp_status nsp_create(const nsp_grid *grid, nsp_handle **out);
+nsp_status nsp_destroy(nsp_handle *h);
+const char *nsp_last_error(const nsp_handle *h);
+
+/* Lid: the wall value of u on the top face, one value per top u-face
+ * position, DEVICE array [nz][nx+1] (entries at i = 0 and i = nx are
+ * unused).  Copied. */
+nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev);
+
+/* Pressure Poisson solve of the projection step (Sec. 2): A p = b for a
+ * batch of right-hand sides.  b: [batch] cell arrays, first made mean-free
+ * over the fluid cells (the Neumann problem needs it); not modified.
+ * p: [batch] cell arrays, initial guess on entry, solution on exit with
+ * mean_fluid(p) = 0.  info: HOST array of `batch` entries, or NULL. */
+nsp_status nsp_poisson_solve(nsp_handle *h, const double *b, double *p, int batch,
+                             const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
+
+/* Fine propagator F(y, t1, t0) of Sec. 2.1.2: (t1 - t0)/dt forward-Euler
+ * projection steps, in place on the batch y.  (t1 - t0)/dt must be a
+ * non-negative integer to 1e-9 relative (NSP_ERR_ARG otherwise).  Each step:
+ * predictor with SMART convection and central diffusion, Poisson solve
+ * (warm-started from y.p), velocity correction. */
+nsp_status nsp_fine_step(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double dt,
+                         const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
+
+/* Coarse propagator G(y, t1, t0): the same scheme with the coarse step DT
+ * (Sec. 2.1.2: forward Euler for both, larger step for G). */
+nsp_status nsp_coarse_step(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double DT,
+                           const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
+
+/* Uneven batch: F over several grids in ONE launch.  hs[g] is the handle of
+ * grid g, ys[g] its batch of batches[g] slices.  The launch uses hs[0]'s
+ * synchronisation words; all handles must live on the same device. */
+nsp_status nsp_group_fine_step(nsp_handle *const *hs, const nsp_state *ys, const int *batches, int ngroups,
+                               double t0, double t1, double dt, const nsp_poisson_opts *opts, void *stream,
+                               nsp_solve_info *info);
+
+/* Parareal, Eq. (6), on nslices slices of [t0, T] (slice length
+ * (T - t0)/nslices; fine steps dt and coarse steps DT per slice must be
+ * integers).
+ *   Y  : nslices+1 slice-end states; Y[0] is the initial value.
+ *   Gk : nslices states, Gk[n] = G(Y[n]) of the previous sweep.
+ *   Fk : nslices states of workspace receiving F(Y[n]).
+ * nsp_parareal_start runs the initial coarse sweep Y[n+1] = G(Y[n]) and
+ * fills Gk.  nsp_parareal_iterate performs iteration k (k = 0, 1, ...):
+ * F(Y[n]) for all slices n >= k in one batched launch (slices n < k are
+ * already exact), then the serial sweep n = k .. nslices-1:
+ *   g = G(Ynew[n]);  Ynew[n+1] = F(Y[n]) + (g - Gk[n]);  Gk[n] = g.
+ * jump (HOST, 2 doubles): max over slices and grid points of
+ * |Ynew - Y| for (u,v,w) and for p.  The handle needs max_batch >=
+ * nslices. */
+nsp_status nsp_parareal_start(nsp_handle *h, nsp_state Y, nsp_state Gk, int nslices, double t0, double T,
+                              double DT, const nsp_poisson_opts *coarse, void *stream);
+nsp_status nsp_parareal_iterate(nsp_handle *h, nsp_state Y, nsp_state Fk, nsp_state Gk, int nslices, int k,
+                                double t0, double T, double dt, double DT, const nsp_poisson_opts *fine,
+                                const nsp_poisson_opts *coarse, void *stream, double *jump);
+
+/* Uneven-batch Parareal: iteration k over ngroups grids, F of all grids'
+ * slices in one launch, the coarse sweep batched across grids slice by
+ * slice.  Array arguments are indexed by group; jump receives 2 doubles per
+ * group. */
+nsp_status nsp_group_parareal_start(nsp_handle *const *hs, const nsp_state *Y, const nsp_state *Gk, int ngroups,
+                                    int nslices, double t0, double T, double DT, const nsp_poisson_opts *coarse,
+                                    void *stream);
+nsp_status nsp_group_parareal_iterate(nsp_handle *const *hs, const nsp_state *Y, const nsp_state *Fk,
+                                      const nsp_state *Gk, int ngroups, int nslices, int k, double t0, double T,
+                                      double dt, double DT, const nsp_poisson_opts *fine,
+                                      const nsp_poisson_opts *coarse, void *stream, double *jump);
+
+/* Launch shape used for a batch: workgroups per launch.  0 = automatic.
+ * nsp_autotune times candidate shapes on the handle's own workspace (a
+ * short Poisson solve on a synthetic right-hand side) and keeps the fastest
+ * for (batch, prec); results do not depend on the choice. */
+nsp_status nsp_set_launch(nsp_handle *h, int workgroups);
+nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stream, int *chosen_workgroups);
+
+/* Duration in milliseconds of the last persistent launch made through this
+ * handle, measured with HIP events on the launch stream. */
+nsp_status nsp_last_launch_ms(const nsp_handle *h, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSP_H */

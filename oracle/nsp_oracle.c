@@ -1,0 +1,569 @@
+/*
+ * Plain FP64 CPU oracle for the projection Navier-Stokes step and its
+ * Poisson solve.  TEST INFRASTRUCTURE ONLY: it is linked by the tests,
+ * by the smoke check and by the CPU-baseline leg of the benchmark, never by
+ * the product library.  It shares no code, header or table with the HIP
+ * path.  Everything is written for readability: no blocking, no fast paths.
+ *
+ * What it computes (Croce, Ruprecht, Krause, "Parallel-in-space-and-time
+ * simulation of the 3D unsteady Navier-Stokes equations", Sec. 2):
+ *   - incompressible Navier-Stokes in dimensionless form, Eq. (1);
+ *   - Chorin-Temam projection on a uniform staggered (MAC) grid with forward
+ *     Euler in time, central differences for diffusion and the pressure
+ *     gradient, SMART (bounded QUICK, normalised-variable form of Gaskell &
+ *     Lau) upwinding for convection, first-order cell enumeration for solid
+ *     cells with no-slip walls (Sec. 2, discretization paragraph);
+ *   - the pressure Poisson equation of the projection, solved here with
+ *     Jacobi-preconditioned CG (the paper uses BiCGStab; the operator is
+ *     symmetric positive semi-definite so CG applies), plus an FP32-inner /
+ *     FP64-outer defect-correction variant.
+ *
+ * Readings where the paper is silent (all shared, as written rules, with
+ * the GPU path):
+ *   - a face is open when it is interior and both adjacent cells are fluid;
+ *     closed faces carry velocity 0;
+ *   - stencil values beyond a closed face come from an image rule: along the
+ *     component's own axis the closed face holds 0 and the next position is
+ *     the odd reflection; across it a no-slip wall sits half a cell away and
+ *     the image is 2*wall - mirror value, resolved nearest-first;
+ *   - the lid velocity enters only as the wall value of u on the top face;
+ *   - convection is in conservative flux form, with the transport velocity
+ *     the average of the two straddling normal components;
+ *   - the Poisson right-hand side b = -div(F)/dt is made mean-free over the
+ *     fluid cells, and the pressure gauge is mean_fluid(p) = 0;
+ *   - PCG stops when ||r||_2 <= rtol ||b||_2 on the recursive residual; the
+ *     true residual is then recomputed and, if above 2 rtol ||b||, CG is
+ *     restarted from it.
+ *
+ * OpenMP is used only on loops whose iterations write disjoint outputs, so
+ * results do not depend on the thread count.  Every reduction is a serial
+ * sum in natural (i fastest, then j, then k) order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int nx, ny, nz;
+    double hx, hy, hz;
+    double re;
+    const uint8_t *solid; /* nz*ny*nx, nonzero = solid; NULL = all fluid */
+    const double *lid;    /* nz*(nx+1): wall value of u on the top face (y = Ly) */
+} og_grid;
+
+typedef struct {
+    int iters;    /* CG iterations (inner iterations for the mixed solver) */
+    int outer;    /* defect-correction sweeps (mixed) / restarts (fp64) */
+    int status;   /* 0 ok, 2 not converged, 3 non-finite */
+    double rel_res_true;
+} og_info;
+
+/* ---------------------------------------------------------------- indexing */
+
+static double hdir(const og_grid *g, int d) { return d == 0 ? g->hx : (d == 1 ? g->hy : g->hz); }
+static int ndir(const og_grid *g, int d) { return d == 0 ? g->nx : (d == 1 ? g->ny : g->nz); }
+
+static size_t cidx(const og_grid *g, int i, int j, int k) {
+    return ((size_t)k * g->ny + j) * g->nx + i;
+}
+
+static int fluid(const og_grid *g, int i, int j, int k) {
+    if (i < 0 || i >= g->nx || j < 0 || j >= g->ny || k < 0 || k >= g->nz) return 0;
+    if (g->solid && g->solid[cidx(g, i, j, k)]) return 0;
+    return 1;
+}
+
+/* extent of the face array of component c along direction d */
+static int fext(const og_grid *g, int c, int d) { return ndir(g, d) + (c == d ? 1 : 0); }
+
+static int face_exists(const og_grid *g, int c, const int f[3]) {
+    for (int d = 0; d < 3; ++d)
+        if (f[d] < 0 || f[d] >= fext(g, c, d)) return 0;
+    return 1;
+}
+
+static size_t fidx(const og_grid *g, int c, const int f[3]) {
+    return ((size_t)f[2] * fext(g, c, 1) + f[1]) * fext(g, c, 0) + f[0];
+}
+
+/* the face of component c at f separates cell f - e_c from cell f */
+static int face_open(const og_grid *g, int c, const int f[3]) {
+    if (!face_exists(g, c, f)) return 0;
+    int lo[3] = {f[0], f[1], f[2]};
+    lo[c] -= 1;
+    return fluid(g, lo[0], lo[1], lo[2]) && fluid(g, f[0], f[1], f[2]);
+}
+
+size_t og_face_count(const og_grid *g, int c) {
+    return (size_t)fext(g, c, 0) * fext(g, c, 1) * fext(g, c, 2);
+}
+
+/* real face value: closed faces are walls with zero normal velocity */
+static double real_val(const og_grid *g, int c, const double *phi, const int f[3]) {
+    return face_open(g, c, f) ? phi[fidx(g, c, f)] : 0.0;
+}
+
+/* ----------------------------------------------------------- image values */
+
+/* Value of the no-slip wall seen by component c when the wall lies half a
+ * cell beyond the open face f in direction d, sense s.  Only u sees the lid,
+ * and only across the top boundary of the domain. */
+static double wall_value(const og_grid *g, int c, const int f[3], int d, int s) {
+    if (c == 0 && d == 1 && s > 0 && f[1] == g->ny - 1)
+        return g->lid[(size_t)f[2] * (g->nx + 1) + f[0]];
+    return 0.0;
+}
+
+/* Value used by the stencil of the open face f of component c at offset m
+ * (|m| = 1 or 2) along direction d: the real value where the position is an
+ * open face, the image value otherwise. */
+static double stencil_val(const og_grid *g, int c, const double *phi, const int f[3], int d, int m) {
+    int s = m > 0 ? 1 : -1;
+    int two = (m == 2 || m == -2);
+    int f1[3] = {f[0], f[1], f[2]};
+    int f2[3] = {f[0], f[1], f[2]};
+    f1[d] += s;
+    f2[d] += 2 * s;
+    double phi0 = phi[fidx(g, c, f)];
+    if (d == c) {
+        /* along the component's own axis: a closed face holds 0, the
+         * position beyond it is the odd reflection of phi0 about it */
+        if (!face_open(g, c, f1)) return two ? -phi0 : 0.0;
+        if (!two) return phi[fidx(g, c, f1)];
+        if (!face_open(g, c, f2)) return 0.0;
+        return phi[fidx(g, c, f2)];
+    }
+    /* across the component's axis: a closed neighbour means a wall half a
+     * cell away; images are 2*wall - mirror, mirror resolved nearest-first */
+    if (!face_open(g, c, f1)) {
+        double wv = wall_value(g, c, f, d, s);
+        if (!two) return 2.0 * wv - phi0;
+        return 2.0 * wv - stencil_val(g, c, phi, f, d, -s);
+    }
+    if (!two) return phi[fidx(g, c, f1)];
+    if (!face_open(g, c, f2)) return 2.0 * wall_value(g, c, f1, d, s) - phi[fidx(g, c, f1)];
+    return phi[fidx(g, c, f2)];
+}
+
+/* ------------------------------------------------------------------ SMART */
+
+/* SMART face value in normalised-variable form (Gaskell & Lau 1988): the
+ * upwind, central and downwind values U, C, D give phi_hat = (C-U)/(D-U);
+ * the face value is 3 phi_hat on (0,1/6), 3/4 phi_hat + 3/8 on [1/6,5/6),
+ * 1 on [5/6,1) and phi_hat (first-order upwind) elsewhere. */
+double og_smart(double U, double C, double D) {
+    double delta = D - U;
+    if (delta == 0.0) return C;
+    double ph = (C - U) / delta;
+    double pf;
+    if (ph > 0.0 && ph < 1.0 / 6.0)
+        pf = 3.0 * ph;
+    else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0)
+        pf = 0.75 * ph + 0.375;
+    else if (ph >= 5.0 / 6.0 && ph < 1.0)
+        pf = 1.0;
+    else
+        pf = ph;
+    return U + pf * delta;
+}
+
+/* --------------------------------------------------------- momentum (a1) */
+
+/* Convective flux of component c through the control-volume face at
+ * f + s/2 e_d: transport velocity times the SMART upwind face value. */
+static double conv_flux(const og_grid *g, int c, const double *vel[3], const int f[3], int d, int s) {
+    const double *phi = vel[c];
+    double abar;
+    if (d == c) {
+        int f1[3] = {f[0], f[1], f[2]};
+        f1[d] += s;
+        abar = 0.5 * (real_val(g, c, phi, f) + real_val(g, c, phi, f1));
+    } else {
+        /* the two d-faces straddling position f along c */
+        int q1[3] = {f[0], f[1], f[2]}, q2[3] = {f[0], f[1], f[2]};
+        if (s > 0) { q1[d] += 1; q2[d] += 1; }
+        q1[c] -= 1;
+        abar = 0.5 * (real_val(g, d, vel[d], q1) + real_val(g, d, vel[d], q2));
+    }
+    if (abar == 0.0) return 0.0;
+    double phi0 = phi[fidx(g, c, f)];
+    double U, C, D;
+    if (s > 0) {
+        if (abar > 0.0) { U = stencil_val(g, c, phi, f, d, -1); C = phi0; D = stencil_val(g, c, phi, f, d, 1); }
+        else { U = stencil_val(g, c, phi, f, d, 2); C = stencil_val(g, c, phi, f, d, 1); D = phi0; }
+    } else {
+        if (abar > 0.0) { U = stencil_val(g, c, phi, f, d, -2); C = stencil_val(g, c, phi, f, d, -1); D = phi0; }
+        else { U = stencil_val(g, c, phi, f, d, 1); C = phi0; D = stencil_val(g, c, phi, f, d, -1); }
+    }
+    return abar * og_smart(U, C, D);
+}
+
+/* Predictor F = phi + dt (Lap(phi)/Re - Conv(phi)) for every open face of
+ * every component; closed faces get 0.  out[c] has the layout of vel[c]. */
+void og_momentum(const og_grid *g, const double *u, const double *v, const double *w, double dt,
+                 double *Fu, double *Fv, double *Fw) {
+    const double *vel[3] = {u, v, w};
+    double *out[3] = {Fu, Fv, Fw};
+    for (int c = 0; c < 3; ++c) {
+        int ex = fext(g, c, 0), ey = fext(g, c, 1), ez = fext(g, c, 2);
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < ez; ++k)
+            for (int j = 0; j < ey; ++j)
+                for (int i = 0; i < ex; ++i) {
+                    int f[3] = {i, j, k};
+                    size_t id = fidx(g, c, f);
+                    if (!face_open(g, c, f)) { out[c][id] = 0.0; continue; }
+                    double phi0 = vel[c][id];
+                    double conv = 0.0, lap = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        double h = hdir(g, d);
+                        double fp = conv_flux(g, c, vel, f, d, 1);
+                        double fm = conv_flux(g, c, vel, f, d, -1);
+                        conv += (fp - fm) / h;
+                        double vp = stencil_val(g, c, vel[c], f, d, 1);
+                        double vm = stencil_val(g, c, vel[c], f, d, -1);
+                        lap += (vp - 2.0 * phi0 + vm) / (h * h);
+                    }
+                    out[c][id] = phi0 + dt * (lap / g->re - conv);
+                }
+    }
+}
+
+/* ------------------------------------------------- divergence and gradient */
+
+/* (D.F)_c = sum_d (F(c + e_d/2) - F(c - e_d/2)) / h_d on fluid cells, 0 on
+ * solid cells; closed faces count as 0. */
+void og_divergence(const og_grid *g, const double *Fu, const double *Fv, const double *Fw, double *div) {
+    const double *F[3] = {Fu, Fv, Fw};
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t id = cidx(g, i, j, k);
+                if (!fluid(g, i, j, k)) { div[id] = 0.0; continue; }
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+                    hi[d] += 1;
+                    s += (real_val(g, d, F[d], hi) - real_val(g, d, F[d], lo)) / hdir(g, d);
+                }
+                div[id] = s;
+            }
+}
+
+/* (G p)_f = (p(f) - p(f - e_c)) / h_c on open faces, 0 on closed faces. */
+void og_gradient(const og_grid *g, const double *p, double *Gu, double *Gv, double *Gw) {
+    double *out[3] = {Gu, Gv, Gw};
+    for (int c = 0; c < 3; ++c) {
+        int ex = fext(g, c, 0), ey = fext(g, c, 1), ez = fext(g, c, 2);
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < ez; ++k)
+            for (int j = 0; j < ey; ++j)
+                for (int i = 0; i < ex; ++i) {
+                    int f[3] = {i, j, k};
+                    size_t id = fidx(g, c, f);
+                    if (!face_open(g, c, f)) { out[c][id] = 0.0; continue; }
+                    int lo[3] = {i, j, k};
+                    lo[c] -= 1;
+                    out[c][id] = (p[cidx(g, i, j, k)] - p[cidx(g, lo[0], lo[1], lo[2])]) / hdir(g, c);
+                }
+    }
+}
+
+/* ------------------------------------------------------- Poisson operator */
+
+/* (A p)_c = sum over the open faces of c of (p_c - p_neighbour) / h_d^2;
+ * this is -D G, symmetric positive semi-definite. */
+void og_apply_A(const og_grid *g, const double *p, double *q) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t id = cidx(g, i, j, k);
+                if (!fluid(g, i, j, k)) { q[id] = 0.0; continue; }
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    double h = hdir(g, d);
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        int nb[3] = {i, j, k};
+                        nb[d] += sg;
+                        if (!fluid(g, nb[0], nb[1], nb[2])) continue; /* face closed */
+                        s += (p[id] - p[cidx(g, nb[0], nb[1], nb[2])]) / (h * h);
+                    }
+                }
+                q[id] = s;
+            }
+}
+
+/* Jacobi preconditioner: the diagonal of A. */
+static void diag_A(const og_grid *g, double *dg) {
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t id = cidx(g, i, j, k);
+                double s = 0.0;
+                if (fluid(g, i, j, k))
+                    for (int d = 0; d < 3; ++d) {
+                        double h = hdir(g, d);
+                        for (int sg = -1; sg <= 1; sg += 2) {
+                            int nb[3] = {i, j, k};
+                            nb[d] += sg;
+                            if (fluid(g, nb[0], nb[1], nb[2])) s += 1.0 / (h * h);
+                        }
+                    }
+                dg[id] = s;
+            }
+}
+
+static size_t ncells(const og_grid *g) { return (size_t)g->nx * g->ny * g->nz; }
+
+static int is_fluid_id(const og_grid *g, size_t id) { return !(g->solid && g->solid[id]); }
+
+static double dot(const og_grid *g, const double *a, const double *b) {
+    size_t n = ncells(g);
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* mean over fluid cells */
+static double mean_fluid(const og_grid *g, const double *a) {
+    size_t n = ncells(g), nf = 0;
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i)
+        if (is_fluid_id(g, i)) { s += a[i]; ++nf; }
+    return nf ? s / (double)nf : 0.0;
+}
+
+static void subtract_mean(const og_grid *g, double *a) {
+    double m = mean_fluid(g, a);
+    size_t n = ncells(g);
+    for (size_t i = 0; i < n; ++i)
+        if (is_fluid_id(g, i)) a[i] -= m;
+}
+
+/* ------------------------------------------------------ Jacobi-PCG (a3) */
+
+/* Solves A x = b for a mean-free b, x holding the initial guess on entry.
+ * On exit x is gauge-fixed (mean_fluid(x) = 0). */
+int og_pcg(const og_grid *g, const double *b, double *x, double rtol, int maxit, og_info *info) {
+    size_t n = ncells(g);
+    double *r = malloc(n * sizeof(double)), *z = malloc(n * sizeof(double));
+    double *d = malloc(n * sizeof(double)), *q = malloc(n * sizeof(double));
+    double *dg = malloc(n * sizeof(double));
+    diag_A(g, dg);
+    memset(info, 0, sizeof(*info));
+    double bnorm = sqrt(dot(g, b, b));
+    if (bnorm == 0.0) {
+        for (size_t i = 0; i < n; ++i) x[i] = 0.0;
+        free(r); free(z); free(d); free(q); free(dg);
+        return 0;
+    }
+    int it = 0, status = 0, restarts = 0;
+    double rel_true = 0.0;
+    for (;;) {
+        /* (re)start from the true residual */
+        og_apply_A(g, x, q);
+        for (size_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        for (size_t i = 0; i < n; ++i) z[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0;
+        for (size_t i = 0; i < n; ++i) d[i] = z[i];
+        double rz = dot(g, r, z);
+        double rnorm = sqrt(dot(g, r, r));
+        for (;;) {
+            if (!isfinite(rnorm)) { status = 3; break; }
+            if (rnorm <= rtol * bnorm) break;
+            if (it >= maxit) { status = 2; break; }
+            og_apply_A(g, d, q);
+            double alpha = rz / dot(g, d, q);
+            for (size_t i = 0; i < n; ++i) x[i] += alpha * d[i];
+            for (size_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+            for (size_t i = 0; i < n; ++i) z[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0;
+            double rz_new = dot(g, r, z);
+            double beta = rz_new / rz;
+            rz = rz_new;
+            for (size_t i = 0; i < n; ++i) d[i] = z[i] + beta * d[i];
+            rnorm = sqrt(dot(g, r, r));
+            ++it;
+        }
+        /* true residual */
+        og_apply_A(g, x, q);
+        for (size_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+        rel_true = sqrt(dot(g, r, r)) / bnorm;
+        if (status != 0 || !isfinite(rel_true) || rel_true <= 2.0 * rtol || it >= maxit) break;
+        ++restarts;
+    }
+    if (status == 0 && !isfinite(rel_true)) status = 3;
+    subtract_mean(g, x);
+    info->iters = it;
+    info->outer = restarts;
+    info->status = status;
+    info->rel_res_true = rel_true;
+    free(r); free(z); free(d); free(q); free(dg);
+    return status;
+}
+
+/* ------------------------------------- mixed precision: FP32 inner PCG */
+
+/* (A p)_c in single precision: same open faces, FP32 values and 1/h^2. */
+static void apply_A32(const og_grid *g, const float *p, float *q) {
+    float ih2[3];
+    for (int d = 0; d < 3; ++d) ih2[d] = (float)(1.0 / (hdir(g, d) * hdir(g, d)));
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t id = cidx(g, i, j, k);
+                if (!fluid(g, i, j, k)) { q[id] = 0.0f; continue; }
+                float s = 0.0f;
+                for (int d = 0; d < 3; ++d)
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        int nb[3] = {i, j, k};
+                        nb[d] += sg;
+                        if (!fluid(g, nb[0], nb[1], nb[2])) continue;
+                        s += (p[id] - p[cidx(g, nb[0], nb[1], nb[2])]) * ih2[d];
+                    }
+                q[id] = s;
+            }
+}
+
+/* dot product of FP32 vectors accumulated in FP64 (products are exact) */
+static double dot32(const og_grid *g, const float *a, const float *b) {
+    size_t n = ncells(g);
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i) s += (double)a[i] * (double)b[i];
+    return s;
+}
+
+/* Jacobi-PCG in FP32 for A e = r from e = 0, until ||r_k|| <= eta ||r_0||
+ * or maxit iterations.  Returns the iteration count. */
+static int pcg32(const og_grid *g, const float *dg, const float *rhs, float *e, double eta, int maxit) {
+    size_t n = ncells(g);
+    float *r = malloc(n * sizeof(float)), *z = malloc(n * sizeof(float));
+    float *d = malloc(n * sizeof(float)), *q = malloc(n * sizeof(float));
+    for (size_t i = 0; i < n; ++i) {
+        e[i] = 0.0f;
+        r[i] = rhs[i];
+        z[i] = dg[i] > 0.0f ? r[i] / dg[i] : 0.0f;
+        d[i] = z[i];
+    }
+    double rz = dot32(g, r, z);
+    double r0 = sqrt(dot32(g, r, r));
+    double rnorm = r0;
+    int it = 0;
+    while (rnorm > eta * r0 && it < maxit && isfinite(rnorm)) {
+        apply_A32(g, d, q);
+        float alpha = (float)(rz / dot32(g, d, q));
+        for (size_t i = 0; i < n; ++i) e[i] += alpha * d[i];
+        for (size_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+        for (size_t i = 0; i < n; ++i) z[i] = dg[i] > 0.0f ? r[i] / dg[i] : 0.0f;
+        double rz_new = dot32(g, r, z);
+        float beta = (float)(rz_new / rz);
+        rz = rz_new;
+        for (size_t i = 0; i < n; ++i) d[i] = z[i] + beta * d[i];
+        rnorm = sqrt(dot32(g, r, r));
+        ++it;
+    }
+    free(r); free(z); free(d); free(q);
+    return it;
+}
+
+/* Defect correction: the FP64 residual r = b - A x is recomputed each
+ * sweep; its mean-free FP32 copy is solved to eta by FP32 Jacobi-PCG and the
+ * correction is added in FP64, until ||r||_2 <= rtol ||b||_2. */
+int og_pcg_mixed(const og_grid *g, const double *b, double *x, double rtol, double eta, int maxit,
+                 int max_outer, og_info *info) {
+    size_t n = ncells(g);
+    double *r = malloc(n * sizeof(double)), *dg = malloc(n * sizeof(double));
+    float *dg32 = malloc(n * sizeof(float)), *r32 = malloc(n * sizeof(float)), *e = malloc(n * sizeof(float));
+    diag_A(g, dg);
+    for (size_t i = 0; i < n; ++i) dg32[i] = (float)dg[i];
+    memset(info, 0, sizeof(*info));
+    double bnorm = sqrt(dot(g, b, b));
+    int status = 0, inner = 0, outer = 0;
+    double rel = 0.0;
+    if (bnorm == 0.0) {
+        for (size_t i = 0; i < n; ++i) x[i] = 0.0;
+    } else {
+        for (;;) {
+            og_apply_A(g, x, r);
+            for (size_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+            double rnorm = sqrt(dot(g, r, r));
+            rel = rnorm / bnorm;
+            if (!isfinite(rnorm)) { status = 3; break; }
+            if (rnorm <= rtol * bnorm) break;
+            if (outer >= max_outer) { status = 2; break; }
+            double m = mean_fluid(g, r);
+            for (size_t i = 0; i < n; ++i) r32[i] = is_fluid_id(g, i) ? (float)(r[i] - m) : 0.0f;
+            inner += pcg32(g, dg32, r32, e, eta, maxit);
+            for (size_t i = 0; i < n; ++i) x[i] += (double)e[i];
+            ++outer;
+        }
+        subtract_mean(g, x);
+    }
+    info->iters = inner;
+    info->outer = outer;
+    info->status = status;
+    info->rel_res_true = rel;
+    free(r); free(dg); free(dg32); free(r32); free(e);
+    return status;
+}
+
+/* ------------------------------------------------- correction and step */
+
+/* u = F - dt G p on open faces, 0 on closed faces. */
+void og_correct(const og_grid *g, const double *Fu, const double *Fv, const double *Fw, const double *p,
+                double dt, double *u, double *v, double *w) {
+    const double *F[3] = {Fu, Fv, Fw};
+    double *out[3] = {u, v, w};
+    for (int c = 0; c < 3; ++c) {
+        int ex = fext(g, c, 0), ey = fext(g, c, 1), ez = fext(g, c, 2);
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < ez; ++k)
+            for (int j = 0; j < ey; ++j)
+                for (int i = 0; i < ex; ++i) {
+                    int f[3] = {i, j, k};
+                    size_t id = fidx(g, c, f);
+                    if (!face_open(g, c, f)) { out[c][id] = 0.0; continue; }
+                    int lo[3] = {i, j, k};
+                    lo[c] -= 1;
+                    double gp = (p[cidx(g, i, j, k)] - p[cidx(g, lo[0], lo[1], lo[2])]) / hdir(g, c);
+                    out[c][id] = F[c][id] - dt * gp;
+                }
+    }
+}
+
+/* Poisson right-hand side of the projection: b = -div(F)/dt, made mean-free
+ * over the fluid cells. */
+void og_rhs(const og_grid *g, const double *Fu, const double *Fv, const double *Fw, double dt, double *b) {
+    og_divergence(g, Fu, Fv, Fw, b);
+    size_t n = ncells(g);
+    for (size_t i = 0; i < n; ++i) b[i] = -b[i] / dt;
+    subtract_mean(g, b);
+}
+
+/* nsteps forward-Euler projection steps of size dt, in place on (u,v,w,p).
+ * prec 0: FP64 PCG; prec 1: FP32 inner PCG with FP64 defect correction.
+ * iters (optional, nsteps entries) receives the CG iterations per step.
+ * Returns the worst status over the steps. */
+int og_fine_steps(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
+                  int prec, double rtol, int maxit, double eta, int max_outer, int *iters, double *rel_true) {
+    size_t nu = og_face_count(g, 0), nv = og_face_count(g, 1), nw = og_face_count(g, 2);
+    size_t n = ncells(g);
+    double *Fu = malloc(nu * sizeof(double)), *Fv = malloc(nv * sizeof(double));
+    double *Fw = malloc(nw * sizeof(double)), *b = malloc(n * sizeof(double));
+    int worst = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        og_momentum(g, u, v, w, dt, Fu, Fv, Fw);
+        og_rhs(g, Fu, Fv, Fw, dt, b);
+        og_info info;
+        int st = prec == 0 ? og_pcg(g, b, p, rtol, maxit, &info)
+                           : og_pcg_mixed(g, b, p, rtol, eta, maxit, max_outer, &info);
+        if (st > worst) worst = st;
+        if (iters) iters[s] = info.iters;
+        if (rel_true) rel_true[s] = info.rel_res_true;
+        og_correct(g, Fu, Fv, Fw, p, dt, u, v, w);
+    }
+    free(Fu); free(Fv); free(Fw); free(b);
+    return worst;
+}

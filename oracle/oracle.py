@@ -1,0 +1,289 @@
+"""Plain FP64 CPU oracle: Python side.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg import this module; the product path
+(``paper_1705_06149_amd``) never does, and this module imports nothing from
+it.  The arithmetic of the projection step lives in ``nsp_oracle.c`` (plain
+C, built here with gcc, ``-ffp-contract=off``); this file marshals NumPy
+arrays into it and writes out the Parareal iteration of Eq. (6) of
+Croce, Ruprecht & Krause (Sec. 2.1.2) in NumPy.
+
+Array layout (x fastest, NumPy C order):
+    u: (nz, ny, nx+1)   v: (nz, ny+1, nx)   w: (nz+1, ny, nx)   p: (nz, ny, nx)
+    solid: (nz, ny, nx) uint8, nonzero = solid      lid: (nz, nx+1)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nsp_oracle.c")
+_LIB = os.path.join(_HERE, "libnsp_oracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+                ("re", ctypes.c_double), ("solid", ctypes.c_void_p), ("lid", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_res_true", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        D = ctypes.c_double
+        I = ctypes.c_int
+        G = ctypes.POINTER(_Grid)
+        _lib.og_smart.argtypes = [D, D, D]
+        _lib.og_smart.restype = D
+        _lib.og_momentum.argtypes = [G, P, P, P, D, P, P, P]
+        _lib.og_divergence.argtypes = [G, P, P, P, P]
+        _lib.og_gradient.argtypes = [G, P, P, P, P]
+        _lib.og_apply_A.argtypes = [G, P, P]
+        _lib.og_pcg.argtypes = [G, P, P, D, I, ctypes.POINTER(_Info)]
+        _lib.og_pcg.restype = I
+        _lib.og_pcg_mixed.argtypes = [G, P, P, D, D, I, I, ctypes.POINTER(_Info)]
+        _lib.og_pcg_mixed.restype = I
+        _lib.og_correct.argtypes = [G, P, P, P, P, D, P, P, P]
+        _lib.og_rhs.argtypes = [G, P, P, P, D, P]
+        _lib.og_fine_steps.argtypes = [G, P, P, P, P, I, D, I, D, I, D, I, P, P]
+        _lib.og_fine_steps.restype = I
+    return _lib
+
+
+@dataclass
+class Grid:
+    """Uniform staggered grid on [0,lx]x[0,ly]x[0,lz], y vertical."""
+    nx: int
+    ny: int
+    nz: int
+    lx: float = 1.0
+    ly: float = 1.0
+    lz: float = 1.0
+    re: float = 100.0
+    solid: np.ndarray | None = None
+    lid: np.ndarray | None = None
+    _keep: list = field(default_factory=list, repr=False)
+
+    def __post_init__(self):
+        if self.solid is not None:
+            self.solid = np.ascontiguousarray(self.solid, dtype=np.uint8)
+            assert self.solid.shape == (self.nz, self.ny, self.nx)
+        if self.lid is None:
+            self.lid = np.ones((self.nz, self.nx + 1))
+        self.lid = np.ascontiguousarray(self.lid, dtype=np.float64)
+        assert self.lid.shape == (self.nz, self.nx + 1)
+
+    @property
+    def h(self):
+        return (self.lx / self.nx, self.ly / self.ny, self.lz / self.nz)
+
+    def c(self) -> _Grid:
+        hx, hy, hz = self.h
+        g = _Grid(self.nx, self.ny, self.nz, hx, hy, hz, float(self.re),
+                  self.solid.ctypes.data if self.solid is not None else None, self.lid.ctypes.data)
+        return g
+
+    def shapes(self):
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return (nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx), (nz, ny, nx)
+
+    def zeros_state(self):
+        return tuple(np.zeros(s) for s in self.shapes())
+
+    def fluid(self):
+        if self.solid is None:
+            return np.ones((self.nz, self.ny, self.nx), dtype=bool)
+        return self.solid == 0
+
+
+def _p(a):
+    assert a.flags.c_contiguous
+    return a.ctypes.data
+
+
+def _chk(a, shape, dtype=np.float64):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    assert a.shape == tuple(shape), (a.shape, shape)
+    return a
+
+
+def smart(U, C, D):
+    return lib().og_smart(float(U), float(C), float(D))
+
+
+def momentum(g: Grid, u, v, w, dt):
+    su, sv, sw, _ = g.shapes()
+    u, v, w = _chk(u, su), _chk(v, sv), _chk(w, sw)
+    Fu, Fv, Fw = np.empty(su), np.empty(sv), np.empty(sw)
+    gc = g.c()
+    lib().og_momentum(ctypes.byref(gc), _p(u), _p(v), _p(w), float(dt), _p(Fu), _p(Fv), _p(Fw))
+    return Fu, Fv, Fw
+
+
+def divergence(g: Grid, u, v, w):
+    su, sv, sw, sp = g.shapes()
+    u, v, w = _chk(u, su), _chk(v, sv), _chk(w, sw)
+    out = np.empty(sp)
+    gc = g.c()
+    lib().og_divergence(ctypes.byref(gc), _p(u), _p(v), _p(w), _p(out))
+    return out
+
+
+def gradient(g: Grid, p):
+    su, sv, sw, sp = g.shapes()
+    p = _chk(p, sp)
+    Gu, Gv, Gw = np.empty(su), np.empty(sv), np.empty(sw)
+    gc = g.c()
+    lib().og_gradient(ctypes.byref(gc), _p(p), _p(Gu), _p(Gv), _p(Gw))
+    return Gu, Gv, Gw
+
+
+def apply_A(g: Grid, p):
+    sp = g.shapes()[3]
+    p = _chk(p, sp)
+    q = np.empty(sp)
+    gc = g.c()
+    lib().og_apply_A(ctypes.byref(gc), _p(p), _p(q))
+    return q
+
+
+def rhs(g: Grid, Fu, Fv, Fw, dt):
+    su, sv, sw, sp = g.shapes()
+    b = np.empty(sp)
+    gc = g.c()
+    lib().og_rhs(ctypes.byref(gc), _p(_chk(Fu, su)), _p(_chk(Fv, sv)), _p(_chk(Fw, sw)), float(dt), _p(b))
+    return b
+
+
+def pcg(g: Grid, b, x0=None, rtol=1e-10, maxit=100000):
+    sp = g.shapes()[3]
+    b = _chk(b, sp)
+    x = np.zeros(sp) if x0 is None else _chk(x0, sp).copy()
+    info = _Info()
+    gc = g.c()
+    lib().og_pcg(ctypes.byref(gc), _p(b), _p(x), float(rtol), int(maxit), ctypes.byref(info))
+    return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
+
+
+def pcg_mixed(g: Grid, b, x0=None, rtol=1e-10, eta=1e-5, maxit=100000, max_outer=8):
+    sp = g.shapes()[3]
+    b = _chk(b, sp)
+    x = np.zeros(sp) if x0 is None else _chk(x0, sp).copy()
+    info = _Info()
+    gc = g.c()
+    lib().og_pcg_mixed(ctypes.byref(gc), _p(b), _p(x), float(rtol), float(eta), int(maxit), int(max_outer),
+                       ctypes.byref(info))
+    return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
+
+
+def correct(g: Grid, Fu, Fv, Fw, p, dt):
+    su, sv, sw, sp = g.shapes()
+    u, v, w = np.empty(su), np.empty(sv), np.empty(sw)
+    gc = g.c()
+    lib().og_correct(ctypes.byref(gc), _p(_chk(Fu, su)), _p(_chk(Fv, sv)), _p(_chk(Fw, sw)), _p(_chk(p, sp)),
+                     float(dt), _p(u), _p(v), _p(w))
+    return u, v, w
+
+
+def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta=1e-5, max_outer=8):
+    """nsteps projection steps of size dt; returns (new state, iters, rel_true, status).
+
+    The input state tuple (u, v, w, p) is not modified."""
+    su, sv, sw, sp = g.shapes()
+    u, v, w, p = (_chk(a, s).copy() for a, s in zip(state, (su, sv, sw, sp)))
+    iters = np.zeros(max(nsteps, 1), dtype=np.int32)
+    rel = np.zeros(max(nsteps, 1))
+    gc = g.c()
+    st = lib().og_fine_steps(ctypes.byref(gc), _p(u), _p(v), _p(w), _p(p), int(nsteps), float(dt), int(prec),
+                             float(rtol), int(maxit), float(eta), int(max_outer), _p(iters), _p(rel))
+    return (u, v, w, p), iters[:nsteps], rel[:nsteps], st
+
+
+def propagate(g: Grid, state, t0, t1, step, **opts):
+    """F or G of the paper: integrate from t0 to t1 with steps of size `step`.
+
+    The number of steps (t1 - t0)/step must be an integer (Eq. (5) asks the
+    same of the coarse/fine ratio)."""
+    n = (t1 - t0) / step
+    ns = int(round(n))
+    if ns < 0 or abs(n - ns) > 1e-9 * max(1.0, abs(n)):
+        raise ValueError("(t1-t0)/step = %r is not an integer" % n)
+    out, iters, rel, st = fine_steps(g, state, ns, step, **opts)
+    if st != 0:
+        raise RuntimeError("oracle solve failed with status %d" % st)
+    return out
+
+
+# ------------------------------------------------------------------ Parareal
+
+def parareal(y0, nslices, F, G, n_it=None, tol=None, jump_norm=None, combine=None):
+    """Parareal, Eq. (6): y^{k+1}_{n+1} = G(y^{k+1}_n) + F(y^k_n) - G(y^k_n).
+
+    y0: initial value (any object; states are tuples of arrays or scalars).
+    F(y, n), G(y, n): fine / coarse propagator over slice n.
+    The correction is evaluated as F + (G_new - G_old), so an unchanged coarse
+    input gives a correction of exactly zero.
+    Iterates until k+1 == n_it, until the jump max_n |y^{k+1}_{n+1} - y^k_{n+1}|
+    is below tol, or until k+1 == nslices (then every slice is exact).
+    Returns (Y, history) with Y[n] the slice-end values (Y[0] = y0) and
+    history a list of dicts with the jump of each iteration.
+    """
+    if combine is None:
+        def combine(f, gn, go):
+            if isinstance(f, tuple):
+                return tuple(a + (b - c) for a, b, c in zip(f, gn, go))
+            return f + (gn - go)
+    if jump_norm is None:
+        def jump_norm(a, b):
+            if isinstance(a, tuple):
+                return max(float(np.max(np.abs(x - y))) if np.size(x) else 0.0 for x, y in zip(a, b))
+            return float(abs(a - b))
+    N = nslices
+    Y = [y0]
+    Gold = []
+    for n in range(N):  # initial coarse sweep
+        g = G(Y[n], n)
+        Gold.append(g)
+        Y.append(g)
+    history = [dict(k=-1, jump=None, Y=list(Y))]
+    k = 0
+    while True:
+        Fk = [F(Y[n], n) for n in range(N)]
+        Ynew = [y0]
+        Gnew = []
+        for n in range(N):
+            g = G(Ynew[n], n)
+            Gnew.append(g)
+            Ynew.append(combine(Fk[n], g, Gold[n]))
+        jump = max(jump_norm(Ynew[n + 1], Y[n + 1]) for n in range(N))
+        Y, Gold = Ynew, Gnew
+        history.append(dict(k=k, jump=jump, Y=list(Y)))
+        if (n_it is not None and k + 1 >= n_it) or (tol is not None and jump < tol) or k + 1 >= N:
+            break
+        k += 1
+    return Y, history

@@ -1,0 +1,691 @@
+// Host side of libnsp: the C ABI declared in include/nsp.h.
+//
+// A handle owns one grid (flags, lid, Jacobi table), the workspace of
+// max_batch slices, and the launch resources (per-slice control blocks,
+// tile partials, barrier words, a device copy of the launch parameters).
+// Every entry point validates its arguments, fills a KParams block, copies
+// it to the device on the caller's stream, launches the persistent kernel
+// cooperatively (all workgroups co-resident, which the grid barrier needs),
+// and reads the per-slice control blocks back.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nsp.h"
+#include "nsp_internal.h"
+
+using namespace nsp;
+
+struct LaunchRes {
+    int cap_slices = 0, cap_tiles = 0;
+    SliceCtl *ctl = nullptr;
+    SliceCtl *ctl_host = nullptr;  // pinned
+    double *part = nullptr;
+    SyncWords *sync = nullptr;
+    KParams *params = nullptr;       // device
+    KParams *params_host = nullptr;  // pinned
+    unsigned long long *jump = nullptr;       // device [2*kMaxGroups]
+    unsigned long long *jump_host = nullptr;  // pinned
+};
+
+struct TuneEntry {
+    int batch, prec, workgroups;
+};
+
+struct nsp_handle {
+    int device = 0;
+    int nx = 0, ny = 0, nz = 0;
+    double lx = 1, ly = 1, lz = 1, re = 1;
+    int max_batch = 0;
+    int tile = 0, ntiles = 0;
+    long long ncells = 0, nu = 0, nv = 0, nw = 0;
+    double nfluid = 0;
+    uint8_t *flags = nullptr;
+    double *lid = nullptr;
+    double *idiag = nullptr;
+    float *idiag32 = nullptr;
+    // workspace
+    double *Fu = nullptr, *Fv = nullptr, *Fw = nullptr, *b = nullptr;
+    double *r = nullptr, *d0 = nullptr, *d1 = nullptr, *q = nullptr;
+    float *e = nullptr;
+    nsp_state gs{nullptr, nullptr, nullptr, nullptr};  // scratch state for the coarse sweep
+    LaunchRes L;
+    int max_wg = 0;
+    int fixed_wg = 0;
+    std::vector<TuneEntry> tuned;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0.0;
+    std::string err;
+};
+
+namespace {
+
+nsp_status fail(nsp_handle *h, nsp_status st, const std::string &msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+#define HIPCHK(h, call)                                                                                    \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            return fail((h), NSP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t n) {
+    if (n == 0) n = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
+}
+
+// Tile size: a power of two between 256 and 2048 cells, about ncells/128,
+// fixed by the grid alone so that reductions never depend on the batch.
+int tile_for(long long ncells) {
+    long long t = 256;
+    while (t * 2 <= ncells / 128 && t < 2048) t *= 2;
+    return (int)t;
+}
+
+// Cell flags: open faces, fluid, and whether any cell within Chebyshev
+// distance 3 is solid or outside the domain (then the momentum stencil of
+// the cell's low faces may meet a wall).
+void build_flags(int nx, int ny, int nz, const uint8_t *solid, std::vector<uint8_t> &fl, double &nfluid) {
+    const long long n = (long long)nx * ny * nz;
+    auto id = [&](int i, int j, int k) { return ((long long)k * ny + j) * nx + i; };
+    auto fluid = [&](int i, int j, int k) {
+        if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz) return false;
+        return !(solid && solid[id(i, j, k)]);
+    };
+    fl.assign(n, 0);
+    nfluid = 0;
+    // blocked[c] = 1 if cell is solid; dilate by 3 in each direction (box)
+    std::vector<uint8_t> bad(n), tmp(n);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) bad[id(i, j, k)] = !fluid(i, j, k);
+    const int R = 3;
+    auto dilate = [&](int dir) {
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    uint8_t v = 0;
+                    for (int m = -R; m <= R && !v; ++m) {
+                        int a = i + (dir == 0) * m, b = j + (dir == 1) * m, c = k + (dir == 2) * m;
+                        if (a < 0 || b < 0 || c < 0 || a >= nx || b >= ny || c >= nz) v = 1;
+                        else v = bad[id(a, b, c)];
+                    }
+                    tmp[id(i, j, k)] = v;
+                }
+        bad.swap(tmp);
+    };
+    dilate(0);
+    dilate(1);
+    dilate(2);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                uint8_t f = 0;
+                if (fluid(i, j, k)) {
+                    f |= FL_FLUID;
+                    nfluid += 1;
+                    if (fluid(i - 1, j, k)) f |= FL_XM;
+                    if (fluid(i + 1, j, k)) f |= FL_XP;
+                    if (fluid(i, j - 1, k)) f |= FL_YM;
+                    if (fluid(i, j + 1, k)) f |= FL_YP;
+                    if (fluid(i, j, k - 1)) f |= FL_ZM;
+                    if (fluid(i, j, k + 1)) f |= FL_ZP;
+                }
+                if (bad[id(i, j, k)]) f |= FL_SLOW;
+                fl[id(i, j, k)] = f;
+            }
+}
+
+// true when the fluid cells form one face-connected region
+bool fluid_connected(int nx, int ny, int nz, const std::vector<uint8_t> &fl, double nfluid) {
+    const long long n = (long long)nx * ny * nz;
+    long long start = -1;
+    for (long long c = 0; c < n; ++c)
+        if (fl[c] & FL_FLUID) { start = c; break; }
+    if (start < 0) return false;
+    std::vector<uint8_t> seen(n, 0);
+    std::vector<long long> stack{start};
+    seen[start] = 1;
+    long long count = 0;
+    const long long sy = nx, sz = (long long)nx * ny;
+    while (!stack.empty()) {
+        long long c = stack.back();
+        stack.pop_back();
+        ++count;
+        const uint8_t f = fl[c];
+        const long long nb[6] = {c - 1, c + 1, c - sy, c + sy, c - sz, c + sz};
+        for (int d = 0; d < 6; ++d)
+            if ((f >> d) & 1)
+                if (!seen[nb[d]]) { seen[nb[d]] = 1; stack.push_back(nb[d]); }
+    }
+    return (double)count == nfluid;
+}
+
+nsp_status ensure_launch_res(nsp_handle *h, int nslices, int ntiles) {
+    LaunchRes &L = h->L;
+    if (!L.sync) {
+        HIPCHK(h, dalloc(&L.sync, 1));
+        HIPCHK(h, hipMemset(L.sync, 0, sizeof(SyncWords)));
+        HIPCHK(h, dalloc(&L.params, 1));
+        HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&L.params_host), sizeof(KParams)));
+        HIPCHK(h, dalloc(&L.jump, 2 * kMaxGroups));
+        HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&L.jump_host), 2 * kMaxGroups * sizeof(unsigned long long)));
+    }
+    if (nslices > L.cap_slices) {
+        if (L.ctl) (void)hipFree(L.ctl);
+        if (L.ctl_host) (void)hipHostFree(L.ctl_host);
+        L.ctl = nullptr;
+        L.ctl_host = nullptr;
+        HIPCHK(h, dalloc(&L.ctl, nslices));
+        HIPCHK(h, hipHostMalloc(reinterpret_cast<void **>(&L.ctl_host), nslices * sizeof(SliceCtl)));
+        L.cap_slices = nslices;
+    }
+    if (ntiles > L.cap_tiles) {
+        if (L.part) (void)hipFree(L.part);
+        L.part = nullptr;
+        HIPCHK(h, dalloc(&L.part, (size_t)kNQ * ntiles));
+        L.cap_tiles = ntiles;
+    }
+    return NSP_OK;
+}
+
+bool valid_opts(const nsp_poisson_opts *o) {
+    return o && o->rtol >= 0 && o->maxit >= 0 && (o->prec == NSP_FP64 || o->prec == NSP_MIXED) &&
+           (o->prec == NSP_FP64 || (o->inner_rtol > 0 && o->inner_rtol < 1 && o->max_outer >= 0));
+}
+
+// number of steps (t1 - t0)/dt, which must be a non-negative integer
+bool step_count(double t0, double t1, double dt, int *n) {
+    if (!(dt > 0) || !std::isfinite(t0) || !std::isfinite(t1)) return false;
+    const double x = (t1 - t0) / dt;
+    const double rx = std::nearbyint(x);
+    if (rx < 0 || std::fabs(x - rx) > 1e-9 * std::max(1.0, std::fabs(x)) || rx > 1e9) return false;
+    *n = (int)rx;
+    return true;
+}
+
+void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nslices, int slice0, int tile0,
+                const double *bin) {
+    G.nx = h->nx;
+    G.ny = h->ny;
+    G.nz = h->nz;
+    G.ncells = (int)h->ncells;
+    G.nu = (int)h->nu;
+    G.nv = (int)h->nv;
+    G.nw = (int)h->nw;
+    G.tile = h->tile;
+    G.ntiles = h->ntiles;
+    G.nslices = nslices;
+    G.slice0 = slice0;
+    G.tile0 = tile0;
+    G.nfluid = h->nfluid;
+    const double hh[3] = {h->lx / h->nx, h->ly / h->ny, h->lz / h->nz};
+    for (int d = 0; d < 3; ++d) {
+        G.ih[d] = 1.0 / hh[d];
+        G.ih2[d] = 1.0 / (hh[d] * hh[d]);
+        G.ih2f[d] = (float)G.ih2[d];
+    }
+    G.inv_re = 1.0 / h->re;
+    G.flags = h->flags;
+    G.lid = h->lid;
+    G.idiag = h->idiag;
+    G.idiag32 = h->idiag32;
+    G.u = y.u ? y.u + (long long)slice_off * h->nu : nullptr;
+    G.v = y.v ? y.v + (long long)slice_off * h->nv : nullptr;
+    G.w = y.w ? y.w + (long long)slice_off * h->nw : nullptr;
+    G.p = y.p ? y.p + (long long)slice_off * h->ncells : nullptr;
+    G.Fu = h->Fu;
+    G.Fv = h->Fv;
+    G.Fw = h->Fw;
+    G.b = h->b;
+    G.r = h->r;
+    G.d0 = h->d0;
+    G.d1 = h->d1;
+    G.q = h->q;
+    G.e = h->e;
+    G.bin = bin;
+}
+
+int auto_workgroups(nsp_handle *h, int batch, int prec, int total_tiles) {
+    if (h->fixed_wg > 0) return std::min(h->fixed_wg, std::min(h->max_wg, total_tiles));
+    for (const TuneEntry &t : h->tuned)
+        if (t.batch == batch && t.prec == prec) return std::min(t.workgroups, std::min(h->max_wg, total_tiles));
+    return std::min(h->max_wg, total_tiles);
+}
+
+// Launch the persistent kernel over ngroups groups and read back the
+// per-slice control blocks into info (may be NULL).
+nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
+               const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override) {
+    nsp_handle *h = hs[0];
+    int nslices = 0, ntiles = 0;
+    for (int g = 0; g < ngroups; ++g) {
+        nslices += groups[g].nslices;
+        ntiles += groups[g].nslices * groups[g].ntiles;
+    }
+    if (nslices <= 0) return NSP_OK;
+    if (nslices > kMaxSlices) return fail(h, NSP_ERR_ARG, "more than 64 slices in one launch");
+    nsp_status st = ensure_launch_res(h, nslices, ntiles);
+    if (st != NSP_OK) return st;
+    KParams &P = *h->L.params_host;
+    // the pinned block may still be read by an earlier copy on this stream
+    HIPCHK(h, hipStreamSynchronize(stream));
+    std::memset(&P, 0, sizeof(P));
+    for (int g = 0; g < ngroups; ++g) P.g[g] = groups[g];
+    P.ngroups = ngroups;
+    P.nslices = nslices;
+    P.ntiles = ntiles;
+    P.mode = mode;
+    P.nsteps = nsteps;
+    P.prec = o->prec == NSP_MIXED ? 1 : 0;
+    P.maxit = o->maxit;
+    P.max_outer = o->max_outer;
+    P.xcd_remap = 1;
+    P.dt = dt;
+    P.rtol = o->rtol;
+    P.eta = o->inner_rtol;
+    P.ctl = h->L.ctl;
+    P.part = h->L.part;
+    P.sync = h->L.sync;
+    int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, ntiles))
+                                     : auto_workgroups(h, nslices, P.prec, ntiles);
+    if (wg < 1) wg = 1;
+    HIPCHK(h, hipMemsetAsync(h->L.ctl, 0, nslices * sizeof(SliceCtl), stream));
+    HIPCHK(h, hipMemcpyAsync(h->L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
+    HIPCHK(h, launch_reset_sync(h->L.sync, stream));
+    HIPCHK(h, hipEventRecord(h->ev0, stream));
+    HIPCHK(h, launch_persistent(h->L.params, wg, stream));
+    HIPCHK(h, hipEventRecord(h->ev1, stream));
+    HIPCHK(h, hipMemcpyAsync(h->L.ctl_host, h->L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost, stream));
+    SyncWords sw;
+    HIPCHK(h, hipMemcpyAsync(&sw.any, &h->L.sync->any, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
+    if (sw.abort) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
+    int worst = 0;
+    for (int s = 0; s < nslices; ++s) {
+        const SliceCtl &c = h->L.ctl_host[s];
+        worst = std::max(worst, c.status);
+        if (info) {
+            info[s].iters = c.tot_it;
+            info[s].max_iters = c.max_it;
+            info[s].outer = c.tot_outer;
+            info[s].status = c.status;
+            info[s].rel_res_true = c.rel_true;
+            info[s].div_l2 = mode == MODE_FINE ? dt * c.res_true : 0.0;
+        }
+    }
+    if (worst == 2) return fail(h, NSP_ERR_NOT_CONVERGED, "Poisson solve reached its iteration limit");
+    if (worst == 3) return fail(h, NSP_ERR_NONFINITE, "non-finite residual in the Poisson solve");
+    return NSP_OK;
+}
+
+bool state_ok(const nsp_state &y) { return y.u && y.v && y.w && y.p; }
+
+nsp_state offset_state(nsp_handle *h, nsp_state y, long long slice) {
+    nsp_state o;
+    o.u = y.u + slice * h->nu;
+    o.v = y.v + slice * h->nv;
+    o.w = y.w + slice * h->nw;
+    o.p = y.p + slice * h->ncells;
+    return o;
+}
+
+hipError_t copy_slices(nsp_handle *h, nsp_state dst, nsp_state src, long long n, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_copy_state(dst.u, src.u, n * h->nu, s)) != hipSuccess) return e;
+    if ((e = launch_copy_state(dst.v, src.v, n * h->nv, s)) != hipSuccess) return e;
+    if ((e = launch_copy_state(dst.w, src.w, n * h->nw, s)) != hipSuccess) return e;
+    return launch_copy_state(dst.p, src.p, n * h->ncells, s);
+}
+
+nsp_status propagate(nsp_handle *const *hs, const nsp_state *ys, const int *batches, int ngroups, double t0,
+                     double t1, double step, const nsp_poisson_opts *o, void *stream, nsp_solve_info *info) {
+    if (!hs || !ys || !batches || ngroups < 1 || ngroups > kMaxGroups || !hs[0])
+        return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad group arguments");
+    nsp_handle *h = hs[0];
+    if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
+    int nsteps = 0;
+    if (!step_count(t0, t1, step, &nsteps)) return fail(h, NSP_ERR_ARG, "(t1 - t0)/dt is not a non-negative integer");
+    GroupDesc G[kMaxGroups];
+    int slice0 = 0, tile0 = 0;
+    for (int g = 0; g < ngroups; ++g) {
+        if (!hs[g] || !state_ok(ys[g]) || batches[g] < 0 || batches[g] > hs[g]->max_batch)
+            return fail(h, NSP_ERR_ARG, "null state pointer or batch outside [0, max_batch]");
+        fill_group(G[g], hs[g], ys[g], 0, batches[g], slice0, tile0, nullptr);
+        slice0 += batches[g];
+        tile0 += batches[g] * hs[g]->ntiles;
+    }
+    if (nsteps == 0 || slice0 == 0) return NSP_OK;
+    return run(hs, ngroups, G, MODE_FINE, nsteps, step, o, static_cast<hipStream_t>(stream), info, 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nsp_last_error(const nsp_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
+    if (!g || !out) return NSP_ERR_ARG;
+    *out = nullptr;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->lx > 0) || !(g->ly > 0) || !(g->lz > 0) || !(g->re > 0) ||
+        g->max_batch < 1 || g->max_batch > kMaxSlices)
+        return NSP_ERR_ARG;
+    if ((long long)g->nx * g->ny * g->nz > (1LL << 30)) return NSP_ERR_ARG;
+    if (g->periodic_z) return NSP_ERR_UNSUPPORTED;
+    nsp_handle *h = new (std::nothrow) nsp_handle();
+    if (!h) return NSP_ERR_ARG;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return NSP_ERR_HIP; }
+    h->nx = g->nx; h->ny = g->ny; h->nz = g->nz;
+    h->lx = g->lx; h->ly = g->ly; h->lz = g->lz;
+    h->re = g->re;
+    h->max_batch = g->max_batch;
+    h->ncells = (long long)g->nx * g->ny * g->nz;
+    h->nu = (long long)(g->nx + 1) * g->ny * g->nz;
+    h->nv = (long long)g->nx * (g->ny + 1) * g->nz;
+    h->nw = (long long)g->nx * g->ny * (g->nz + 1);
+    h->tile = tile_for(h->ncells);
+    h->ntiles = (int)((h->ncells + h->tile - 1) / h->tile);
+    std::vector<uint8_t> fl;
+    build_flags(g->nx, g->ny, g->nz, g->solid_host, fl, h->nfluid);
+    if (!fluid_connected(g->nx, g->ny, g->nz, fl, h->nfluid)) {
+        delete h;
+        return NSP_ERR_ARG;
+    }
+    // Jacobi table: 1/diag(A) for each of the 64 open-face patterns
+    const double hh[3] = {g->lx / g->nx, g->ly / g->ny, g->lz / g->nz};
+    double tab[64];
+    float tab32[64];
+    for (int m = 0; m < 64; ++m) {
+        double dg = 0.0;
+        for (int d = 0; d < 3; ++d)
+            for (int s = 0; s < 2; ++s)
+                if (m & (1 << (2 * d + s))) dg += 1.0 / (hh[d] * hh[d]);
+        tab[m] = dg > 0 ? 1.0 / dg : 0.0;
+        tab32[m] = dg > 0 ? (float)(1.0 / dg) : 0.0f;
+    }
+    const long long B = g->max_batch;
+    auto fail_create = [&](hipError_t) {
+        nsp_destroy(h);
+        return NSP_ERR_HIP;
+    };
+    hipError_t e;
+    if ((e = dalloc(&h->flags, h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = hipMemcpy(h->flags, fl.data(), h->ncells, hipMemcpyHostToDevice)) != hipSuccess) return fail_create(e);
+    std::vector<double> lid((size_t)g->nz * (g->nx + 1), 1.0);
+    if ((e = dalloc(&h->lid, lid.size())) != hipSuccess) return fail_create(e);
+    if ((e = hipMemcpy(h->lid, lid.data(), lid.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail_create(e);
+    if ((e = dalloc(&h->idiag, 64)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->idiag32, 64)) != hipSuccess) return fail_create(e);
+    if ((e = hipMemcpy(h->idiag, tab, sizeof(tab), hipMemcpyHostToDevice)) != hipSuccess) return fail_create(e);
+    if ((e = hipMemcpy(h->idiag32, tab32, sizeof(tab32), hipMemcpyHostToDevice)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->Fu, B * h->nu)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->Fv, B * h->nv)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->Fw, B * h->nw)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->b, B * h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->r, B * h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->d0, B * h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->d1, B * h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->q, B * h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->e, B * h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->gs.u, h->nu)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->gs.v, h->nv)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->gs.w, h->nw)) != hipSuccess) return fail_create(e);
+    if ((e = dalloc(&h->gs.p, h->ncells)) != hipSuccess) return fail_create(e);
+    if ((e = hipEventCreate(&h->ev0)) != hipSuccess) return fail_create(e);
+    if ((e = hipEventCreate(&h->ev1)) != hipSuccess) return fail_create(e);
+    if ((e = max_coresident_workgroups(h->device, &h->max_wg)) != hipSuccess) return fail_create(e);
+    if (h->max_wg < 1) return fail_create(hipErrorInvalidValue);
+    if (ensure_launch_res(h, g->max_batch, g->max_batch * h->ntiles) != NSP_OK) return fail_create(hipErrorOutOfMemory);
+    *out = h;
+    return NSP_OK;
+}
+
+nsp_status nsp_destroy(nsp_handle *h) {
+    if (!h) return NSP_ERR_ARG;
+    (void)hipDeviceSynchronize();
+    void *ptrs[] = {h->flags, h->lid, h->idiag, h->idiag32, h->Fu, h->Fv, h->Fw, h->b, h->r, h->d0, h->d1, h->q,
+                    h->e, h->gs.u, h->gs.v, h->gs.w, h->gs.p, h->L.ctl, h->L.part, h->L.sync, h->L.params,
+                    h->L.jump};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->L.ctl_host) (void)hipHostFree(h->L.ctl_host);
+    if (h->L.params_host) (void)hipHostFree(h->L.params_host);
+    if (h->L.jump_host) (void)hipHostFree(h->L.jump_host);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    delete h;
+    return NSP_OK;
+}
+
+nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev) {
+    if (!h || !lid_dev) return fail(h, NSP_ERR_ARG, "null lid pointer");
+    HIPCHK(h, hipMemcpy(h->lid, lid_dev, (size_t)h->nz * (h->nx + 1) * sizeof(double), hipMemcpyDeviceToDevice));
+    return NSP_OK;
+}
+
+nsp_status nsp_poisson_solve(nsp_handle *h, const double *b, double *p, int batch, const nsp_poisson_opts *o,
+                             void *stream, nsp_solve_info *info) {
+    if (!h) return NSP_ERR_ARG;
+    if (!b || !p || batch < 0 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "null pointer or bad batch");
+    if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
+    if (batch == 0) return NSP_OK;
+    GroupDesc G;
+    nsp_state y{nullptr, nullptr, nullptr, p};
+    fill_group(G, h, y, 0, batch, 0, 0, b);
+    nsp_handle *hs[1] = {h};
+    return run(hs, 1, &G, MODE_POISSON, 0, 1.0, o, static_cast<hipStream_t>(stream), info, 0);
+}
+
+nsp_status nsp_fine_step(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double dt,
+                         const nsp_poisson_opts *o, void *stream, nsp_solve_info *info) {
+    if (!h) return NSP_ERR_ARG;
+    nsp_handle *hs[1] = {h};
+    return propagate(hs, &y, &batch, 1, t0, t1, dt, o, stream, info);
+}
+
+nsp_status nsp_coarse_step(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double DT,
+                           const nsp_poisson_opts *o, void *stream, nsp_solve_info *info) {
+    if (!h) return NSP_ERR_ARG;
+    nsp_handle *hs[1] = {h};
+    return propagate(hs, &y, &batch, 1, t0, t1, DT, o, stream, info);
+}
+
+nsp_status nsp_group_fine_step(nsp_handle *const *hs, const nsp_state *ys, const int *batches, int ngroups, double t0,
+                               double t1, double dt, const nsp_poisson_opts *o, void *stream, nsp_solve_info *info) {
+    return propagate(hs, ys, batches, ngroups, t0, t1, dt, o, stream, info);
+}
+
+nsp_status nsp_group_parareal_start(nsp_handle *const *hs, const nsp_state *Y, const nsp_state *Gk, int ngroups,
+                                    int nslices, double t0, double T, double DT, const nsp_poisson_opts *coarse,
+                                    void *stream) {
+    if (!hs || !Y || !Gk || ngroups < 1 || ngroups > kMaxGroups || !hs[0] || nslices < 1)
+        return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad Parareal arguments");
+    nsp_handle *h = hs[0];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double len = (T - t0) / nslices;
+    int nc = 0;
+    if (!step_count(0.0, len, DT, &nc)) return fail(h, NSP_ERR_ARG, "slice length / DT is not an integer");
+    for (int g = 0; g < ngroups; ++g)
+        if (!hs[g] || !state_ok(Y[g]) || !state_ok(Gk[g])) return fail(h, NSP_ERR_ARG, "null state");
+    nsp_state gsv[kMaxGroups];
+    int ones[kMaxGroups];
+    for (int g = 0; g < ngroups; ++g) { gsv[g] = hs[g]->gs; ones[g] = 1; }
+    for (int n = 0; n < nslices; ++n) {
+        for (int g = 0; g < ngroups; ++g)
+            HIPCHK(h, copy_slices(hs[g], hs[g]->gs, offset_state(hs[g], Y[g], n), 1, s));
+        nsp_status st = propagate(hs, gsv, ones, ngroups, t0 + n * len, t0 + (n + 1) * len, DT, coarse, stream, nullptr);
+        if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
+        for (int g = 0; g < ngroups; ++g) {
+            HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Y[g], n + 1), hs[g]->gs, 1, s));
+            HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Gk[g], n), hs[g]->gs, 1, s));
+        }
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    return NSP_OK;
+}
+
+nsp_status nsp_parareal_start(nsp_handle *h, nsp_state Y, nsp_state Gk, int nslices, double t0, double T, double DT,
+                              const nsp_poisson_opts *coarse, void *stream) {
+    nsp_handle *hs[1] = {h};
+    return nsp_group_parareal_start(hs, &Y, &Gk, 1, nslices, t0, T, DT, coarse, stream);
+}
+
+nsp_status nsp_group_parareal_iterate(nsp_handle *const *hs, const nsp_state *Y, const nsp_state *Fk,
+                                      const nsp_state *Gk, int ngroups, int nslices, int k, double t0, double T,
+                                      double dt, double DT, const nsp_poisson_opts *fine,
+                                      const nsp_poisson_opts *coarse, void *stream, double *jump) {
+    if (!hs || !Y || !Fk || !Gk || ngroups < 1 || ngroups > kMaxGroups || !hs[0] || nslices < 1 || k < 0 || !jump)
+        return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad Parareal arguments");
+    nsp_handle *h = hs[0];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double len = (T - t0) / nslices;
+    int nf = 0, nc = 0;
+    if (!step_count(0.0, len, dt, &nf) || !step_count(0.0, len, DT, &nc))
+        return fail(h, NSP_ERR_ARG, "slice length / dt or / DT is not an integer");
+    for (int g = 0; g < ngroups; ++g) {
+        if (!hs[g] || !state_ok(Y[g]) || !state_ok(Fk[g]) || !state_ok(Gk[g]))
+            return fail(h, NSP_ERR_ARG, "null state");
+        if (hs[g]->max_batch < nslices) return fail(h, NSP_ERR_ARG, "max_batch is smaller than nslices");
+    }
+    for (int g = 0; g < 2 * ngroups; ++g) jump[g] = 0.0;
+    if (k >= nslices) return NSP_OK;  // every slice is already exact
+    const int active = nslices - k;
+    // F(Y[n]) for n >= k, all grids' slices in one launch
+    nsp_state fsub[kMaxGroups];
+    int nb[kMaxGroups];
+    for (int g = 0; g < ngroups; ++g) {
+        HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Fk[g], k), offset_state(hs[g], Y[g], k), active, s));
+        fsub[g] = offset_state(hs[g], Fk[g], k);
+        nb[g] = active;
+    }
+    nsp_status st = propagate(hs, fsub, nb, ngroups, t0 + k * len, t0 + (k + 1) * len, dt, fine, stream, nullptr);
+    if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
+    HIPCHK(h, hipMemsetAsync(h->L.jump, 0, 2 * kMaxGroups * sizeof(unsigned long long), s));
+    nsp_state gsv[kMaxGroups];
+    int ones[kMaxGroups];
+    for (int g = 0; g < ngroups; ++g) { gsv[g] = hs[g]->gs; ones[g] = 1; }
+    for (int n = k; n < nslices; ++n) {
+        for (int g = 0; g < ngroups; ++g)
+            HIPCHK(h, copy_slices(hs[g], hs[g]->gs, offset_state(hs[g], Y[g], n), 1, s));
+        st = propagate(hs, gsv, ones, ngroups, t0 + n * len, t0 + (n + 1) * len, DT, coarse, stream, nullptr);
+        if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
+        UpdateParams U;
+        std::memset(&U, 0, sizeof(U));
+        U.jump = h->L.jump;
+        for (int g = 0; g < ngroups; ++g) {
+            nsp_handle *hg = hs[g];
+            const nsp_state y1 = offset_state(hg, Y[g], n + 1), f = offset_state(hg, Fk[g], n),
+                            go = offset_state(hg, Gk[g], n);
+            double *ys[4] = {y1.u, y1.v, y1.w, y1.p};
+            const double *fs[4] = {f.u, f.v, f.w, f.p};
+            const double *gn[4] = {hg->gs.u, hg->gs.v, hg->gs.w, hg->gs.p};
+            double *gos[4] = {go.u, go.v, go.w, go.p};
+            const long long ns[4] = {hg->nu, hg->nv, hg->nw, hg->ncells};
+            for (int c = 0; c < 4; ++c) {
+                UpdateSeg &S = U.seg[U.nseg];
+                S.y = ys[c];
+                S.f = fs[c];
+                S.g = gn[c];
+                S.gold = gos[c];
+                S.n = ns[c];
+                S.jslot = c == 3 ? 1 : 0;
+                U.group_of_seg[U.nseg] = g;
+                ++U.nseg;
+            }
+        }
+        HIPCHK(h, launch_parareal_update(U, s));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->L.jump_host, h->L.jump, 2 * kMaxGroups * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (int g = 0; g < 2 * ngroups; ++g) {
+        double v;
+        std::memcpy(&v, &h->L.jump_host[g], sizeof(v));
+        jump[g] = v;
+    }
+    return NSP_OK;
+}
+
+nsp_status nsp_parareal_iterate(nsp_handle *h, nsp_state Y, nsp_state Fk, nsp_state Gk, int nslices, int k,
+                                double t0, double T, double dt, double DT, const nsp_poisson_opts *fine,
+                                const nsp_poisson_opts *coarse, void *stream, double *jump) {
+    nsp_handle *hs[1] = {h};
+    return nsp_group_parareal_iterate(hs, &Y, &Fk, &Gk, 1, nslices, k, t0, T, dt, DT, fine, coarse, stream, jump);
+}
+
+nsp_status nsp_set_launch(nsp_handle *h, int workgroups) {
+    if (!h || workgroups < 0) return fail(h, NSP_ERR_ARG, "bad workgroup count");
+    h->fixed_wg = workgroups;
+    return NSP_OK;
+}
+
+nsp_status nsp_last_launch_ms(const nsp_handle *h, double *ms) {
+    if (!h || !ms) return NSP_ERR_ARG;
+    *ms = h->last_ms;
+    return NSP_OK;
+}
+
+nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stream, int *chosen) {
+    if (!h || batch < 1 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "bad autotune batch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // synthetic right-hand side (made mean-free inside the solve); every
+    // candidate shape runs the same 40 CG iterations from p = 0
+    std::vector<double> hb((size_t)h->ncells);
+    for (long long c = 0; c < h->ncells; ++c) hb[c] = std::sin(0.37 * (double)c) + std::cos(0.011 * (double)c);
+    double *b = nullptr, *p = nullptr;
+    HIPCHK(h, dalloc(&b, (size_t)batch * h->ncells));
+    HIPCHK(h, dalloc(&p, (size_t)batch * h->ncells));
+    for (int i = 0; i < batch; ++i)
+        HIPCHK(h, hipMemcpy(b + (long long)i * h->ncells, hb.data(), h->ncells * sizeof(double), hipMemcpyHostToDevice));
+    nsp_poisson_opts o{0.0, 40, prec, 1e-30, 1};
+    const int ntiles = batch * h->ntiles;
+    std::vector<int> cands;
+    for (int c : {h->max_wg, h->max_wg * 3 / 4, h->max_wg / 2, h->max_wg / 4, 512, 256, 128})
+        if (c >= 1 && c <= std::min(h->max_wg, ntiles) &&
+            std::find(cands.begin(), cands.end(), c) == cands.end())
+            cands.push_back(c);
+    if (cands.empty()) cands.push_back(std::min(h->max_wg, ntiles));
+    GroupDesc G;
+    nsp_state y{nullptr, nullptr, nullptr, p};
+    fill_group(G, h, y, 0, batch, 0, 0, b);
+    nsp_handle *hs[1] = {h};
+    int best = cands[0];
+    double best_ms = 1e30;
+    for (int c : cands) {
+        double tot = 0;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(h, hipMemsetAsync(p, 0, (size_t)batch * h->ncells * sizeof(double), s));
+            nsp_status st = run(hs, 1, &G, MODE_POISSON, 0, 1.0, &o, s, nullptr, c);
+            if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
+                (void)hipFree(b);
+                (void)hipFree(p);
+                return st;
+            }
+            if (rep > 0) tot += h->last_ms;
+        }
+        if (tot < best_ms) { best_ms = tot; best = c; }
+    }
+    (void)hipFree(b);
+    (void)hipFree(p);
+    const int pr = prec == NSP_MIXED ? 1 : 0;
+    bool found = false;
+    for (TuneEntry &t : h->tuned)
+        if (t.batch == batch && t.prec == pr) { t.workgroups = best; found = true; }
+    if (!found) h->tuned.push_back(TuneEntry{batch, pr, best});
+    if (chosen) *chosen = best;
+    return NSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal data structures shared by the host side and the gfx950 kernels
+// of libnsp.  Not part of the public C ABI (include/nsp.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nsp {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kMaxGroups = 4;    // grids per launch (uneven batch)
+constexpr int kMaxSlices = 64;   // slices per launch
+constexpr int kNQ = 4;           // partial sums per tile
+
+// Per-cell flag byte: which of the six faces of the pressure cell are open,
+// whether the cell is fluid, and whether the momentum stencil of the cell's
+// low faces may touch a wall, an obstacle or the domain boundary (then the
+// image-rule path is taken; otherwise every stencil point is an open face).
+enum : uint8_t {
+    FL_XM = 1, FL_XP = 2, FL_YM = 4, FL_YP = 8, FL_ZM = 16, FL_ZP = 32,
+    FL_OPEN = 63, FL_FLUID = 64, FL_SLOW = 128
+};
+
+// One grid and the batch of slices it carries in a launch.
+struct GroupDesc {
+    int nx, ny, nz;
+    int ncells;            // nx*ny*nz
+    int nu, nv, nw;        // faces per slice of u, v, w
+    int tile;              // cells per tile (multiple of kBlock)
+    int ntiles;            // tiles per slice
+    int nslices;           // slices of this grid in the launch
+    int slice0;            // first slice index of this grid in the launch
+    int tile0;             // first tile index of this grid in the launch
+    double nfluid;         // number of fluid cells
+    double ih[3], ih2[3];  // 1/h, 1/h^2 per direction
+    float ih2f[3];
+    double inv_re;
+    const uint8_t *flags;  // [ncells]
+    const double *lid;     // [nz][nx+1]
+    const double *idiag;   // [64]: 1/diag(A) per open-face pattern
+    const float *idiag32;  // [64]
+    double *u, *v, *w, *p;         // state, slice 0 (slice stride nu/nv/nw/ncells)
+    double *Fu, *Fv, *Fw, *b;      // predictor and right-hand side workspace
+    double *r, *d0, *d1, *q;       // CG vectors (FP32 view in mixed mode)
+    float *e;                      // FP32 defect correction
+    const double *bin;             // Poisson mode: caller's right-hand side
+};
+
+// Per-slice solver state, written by the reducing workgroup at barriers and
+// read by every workgroup after them.
+struct SliceCtl {
+    double bnorm, rz, alpha, beta, r0, mean_b, mean_r, mean_p, rel_true, res_true;
+    int active;   // CG iterating
+    int first;    // next search direction is the preconditioned residual
+    int it;       // CG iterations of the current step
+    int it_in;    // iterations of the current inner (FP32) solve
+    int need;     // mixed: another defect-correction sweep is needed
+    int zero;     // right-hand side is zero: solution is p = 0
+    int restart;  // FP64: restart from the true residual
+    int outer;    // restarts / sweeps of the current step
+    int done;     // current solve finished for this slice
+    int status;   // worst status over the call
+    int step_status; // status of the current solve
+    int tot_it, max_it, tot_outer;
+};
+
+struct SyncWords {
+    unsigned count;    // arrivals at the current barrier
+    unsigned pad0[63];
+    unsigned gen;      // barrier generation
+    unsigned pad1[63];
+    int any;           // control word published by the reducing workgroup
+    int abort;         // set when a barrier wait exceeds its spin limit
+    int pad2[62];
+};
+
+enum Mode : int { MODE_FINE = 0, MODE_POISSON = 1 };
+
+struct KParams {
+    GroupDesc g[kMaxGroups];
+    int ngroups;
+    int nslices;           // total slices in the launch
+    int ntiles;            // total tiles in the launch
+    int mode;
+    int nsteps;
+    int prec;              // 0 fp64, 1 mixed
+    int maxit, max_outer;
+    int xcd_remap;         // contiguous tile ranges per XCD
+    double dt;
+    double rtol, eta;
+    SliceCtl *ctl;         // [nslices]
+    double *part;          // [kNQ][ntiles]
+    SyncWords *sync;
+};
+
+// Launchers implemented in nsp_kernels.hip.
+// P_dev: device copy of the parameters, valid until the launch completes
+hipError_t launch_persistent(const KParams *P_dev, int workgroups, hipStream_t stream);
+hipError_t max_coresident_workgroups(int device, int *out);
+hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream);
+
+struct UpdateSeg {
+    double *y;          // slice-end state to overwrite (y^{k+1}_{n+1})
+    const double *f;    // F(y^k_n)
+    const double *g;    // G(y^{k+1}_n)
+    double *gold;       // G(y^k_n), replaced by g
+    long long n;        // elements
+    int jslot;          // 0: velocity jump, 1: pressure jump
+};
+constexpr int kMaxSegs = 4 * kMaxGroups;
+struct UpdateParams {
+    UpdateSeg seg[kMaxSegs];
+    int nseg;
+    unsigned long long *jump;  // [2 * kMaxGroups] bit patterns of the max |y_new - y_old|
+    int group_of_seg[kMaxSegs];
+};
+hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream);
+hipError_t launch_copy_state(double *dst, const double *src, long long n, hipStream_t stream);
+
+}  // namespace nsp

@@ -1,0 +1,1000 @@
+// gfx950 kernels of libnsp: one persistent, cooperatively launched kernel
+// that runs whole projection steps (or a Poisson solve) for a batch of
+// slices of up to kMaxGroups grids, with the CG loop resident on the device.
+//
+// Method (Croce, Ruprecht & Krause, Sec. 2): forward-Euler Chorin-Temam
+// projection on a uniform staggered grid.  One step:
+//   MOM   predictor F = u + dt (Lap(u)/Re - Conv_SMART(u)) on open faces
+//   RHS   b = -div(F)/dt on fluid cells, then b -= mean_fluid(b)
+//   CG    Jacobi-preconditioned CG on A p = b, A = -D G (7-point, open faces)
+//         [or: FP64 residual + FP32 inner CG + FP64 update, repeated]
+//   CORR  u = F - dt G p on open faces, 0 on closed faces; p gauge-fixed
+//
+// Work is split into tiles of `tile` consecutive cells of one slice; each
+// tile writes its own partial sums (fixed-order wave64 butterflies, then a
+// fixed combination of the four waves), so every reduction result depends
+// only on the grid, never on the launch shape or on the batch it shares.
+// Between phases all workgroups meet at a grid barrier; the last one to
+// arrive sums the tile partials per slice in a fixed order, runs the CG
+// scalar logic (alpha, beta, convergence) for every slice and publishes a
+// control word, then releases the barrier.
+#include "nsp_internal.h"
+
+namespace nsp {
+
+namespace {
+
+constexpr unsigned kSpinLimit = 1u << 23;  // ~seconds: a wait this long means something is broken
+
+enum Red : int {
+    R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- geometry
+
+struct IJK { int i, j, k; };
+
+__device__ __forceinline__ IJK decomp(const GroupDesc &G, int c) {
+    IJK r;
+    int t = c / G.nx;
+    r.i = c - t * G.nx;
+    r.k = t / G.ny;
+    r.j = t - r.k * G.ny;
+    return r;
+}
+
+// extent of component C's face array along direction D
+template <int C, int D>
+__device__ __forceinline__ int fext(const GroupDesc &G) {
+    int n = D == 0 ? G.nx : (D == 1 ? G.ny : G.nz);
+    return n + (C == D ? 1 : 0);
+}
+
+template <int C>
+__device__ __forceinline__ long fidx(const GroupDesc &G, int i, int j, int k) {
+    return ((long)k * fext<C, 1>(G) + j) * fext<C, 0>(G) + i;
+}
+
+template <int C, int D>
+__device__ __forceinline__ long fstride(const GroupDesc &G) {
+    return D == 0 ? 1L : (D == 1 ? (long)fext<C, 0>(G) : (long)fext<C, 0>(G) * fext<C, 1>(G));
+}
+
+__device__ __forceinline__ long cidx(const GroupDesc &G, int i, int j, int k) {
+    return ((long)k * G.ny + j) * G.nx + i;
+}
+
+// Face of component C at (i,j,k) separates cells (i,j,k) - e_C and (i,j,k);
+// it is open when both are fluid cells, which the cell's own "minus" bit
+// records.  Positions outside the face array are not open.
+template <int C>
+__device__ __forceinline__ bool face_open(const GroupDesc &G, int i, int j, int k) {
+    if (i < 0 || j < 0 || k < 0) return false;
+    if (i >= G.nx || j >= G.ny || k >= G.nz) return false;  // includes the high boundary face
+    const uint8_t bit = C == 0 ? FL_XM : (C == 1 ? FL_YM : FL_ZM);
+    return (G.flags[cidx(G, i, j, k)] & bit) != 0;
+}
+
+// Wall value beyond the open face (i,j,k) of component C in direction D,
+// sense S: only u sees the lid, across the top boundary.
+template <int C, int D>
+__device__ __forceinline__ double wall_value(const GroupDesc &G, int i, int j, int k, int S) {
+    if (C == 0 && D == 1 && S > 0 && j == G.ny - 1) return G.lid[(long)k * (G.nx + 1) + i];
+    return 0.0;
+}
+
+// ------------------------------------------------------------------ SMART
+
+// Normalised-variable SMART (Gaskell & Lau): phi_hat = (C-U)/(D-U); face
+// value 3 phi_hat on (0,1/6), 3/4 phi_hat + 3/8 on [1/6,5/6), 1 on [5/6,1),
+// first-order upwind elsewhere.
+__device__ __forceinline__ double smart_face(double U, double C, double D) {
+    double delta = D - U;
+    if (delta == 0.0) return C;
+    double ph = (C - U) / delta;
+    double pf;
+    if (ph > 0.0 && ph < 1.0 / 6.0) pf = 3.0 * ph;
+    else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0) pf = 0.75 * ph + 0.375;
+    else if (ph >= 5.0 / 6.0 && ph < 1.0) pf = 1.0;
+    else pf = ph;
+    return U + pf * delta;
+}
+
+// ------------------------------------------------------- momentum stencil
+
+// Values at offsets -2,-1,+1,+2 along D of the stencil of the open face
+// (i,j,k) of component C.  FAST: every position is an open face.  Otherwise
+// the image rule: along C's own axis a closed face holds 0 and the next
+// position is the odd reflection -phi0; across it a closed neighbour is a
+// no-slip wall half a cell away, image 2*wall - mirror, with the mirror
+// itself resolved first (one-cell gaps).
+template <bool FAST, int C, int D>
+__device__ __forceinline__ void line_values(const GroupDesc &G, const double *__restrict__ phi, int i, int j,
+                                            int k, long id, double phi0, double &vm2, double &vm1, double &vp1,
+                                            double &vp2) {
+    const long s = fstride<C, D>(G);
+    if (FAST) {
+        vm2 = phi[id - 2 * s];
+        vm1 = phi[id - s];
+        vp1 = phi[id + s];
+        vp2 = phi[id + 2 * s];
+        return;
+    }
+    const int di = D == 0, dj = D == 1, dk = D == 2;
+    const bool om1 = face_open<C>(G, i - di, j - dj, k - dk);
+    const bool op1 = face_open<C>(G, i + di, j + dj, k + dk);
+    if (C == D) {
+        vm1 = om1 ? phi[id - s] : 0.0;
+        vp1 = op1 ? phi[id + s] : 0.0;
+        vm2 = !om1 ? -phi0 : (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk) ? phi[id - 2 * s] : 0.0);
+        vp2 = !op1 ? -phi0 : (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk) ? phi[id + 2 * s] : 0.0);
+    } else {
+        const double wm = wall_value<C, D>(G, i, j, k, -1);
+        const double wp = wall_value<C, D>(G, i, j, k, +1);
+        vm1 = om1 ? phi[id - s] : 2.0 * wm - phi0;
+        vp1 = op1 ? phi[id + s] : 2.0 * wp - phi0;
+        if (!op1) vp2 = 2.0 * wp - vm1;
+        else if (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk)) vp2 = phi[id + 2 * s];
+        else vp2 = 2.0 * wall_value<C, D>(G, i + di, j + dj, k + dk, +1) - phi[id + s];
+        if (!om1) vm2 = 2.0 * wm - vp1;
+        else if (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk)) vm2 = phi[id - 2 * s];
+        else vm2 = 2.0 * wall_value<C, D>(G, i - di, j - dj, k - dk, -1) - phi[id - s];
+    }
+}
+
+// real value of component D at face (i,j,k): closed faces hold 0
+template <bool FAST, int D>
+__device__ __forceinline__ double real_face(const GroupDesc &G, const double *__restrict__ a, int i, int j, int k) {
+    if (FAST) return a[fidx<D>(G, i, j, k)];
+    return face_open<D>(G, i, j, k) ? a[fidx<D>(G, i, j, k)] : 0.0;
+}
+
+// Contribution of direction D to the convective and diffusive terms at the
+// open face (i,j,k) of component C.
+template <bool FAST, int C, int D>
+__device__ __forceinline__ void dir_terms(const GroupDesc &G, const double *__restrict__ const *vel, int i, int j,
+                                          int k, long id, double phi0, double &conv, double &lap) {
+    const double *__restrict__ phi = vel[C];
+    double vm2, vm1, vp1, vp2;
+    line_values<FAST, C, D>(G, phi, i, j, k, id, phi0, vm2, vm1, vp1, vp2);
+    double ap, am;
+    if (C == D) {
+        ap = 0.5 * (phi0 + vp1);  // along the own axis the +-1 values are the real ones
+        am = 0.5 * (vm1 + phi0);
+    } else {
+        // the two D-faces straddling the position of the face along C
+        const int ci = C == 0, cj = C == 1, ck = C == 2;
+        const int di = D == 0, dj = D == 1, dk = D == 2;
+        ap = 0.5 * (real_face<FAST, D>(G, vel[D], i - ci + di, j - cj + dj, k - ck + dk) +
+                    real_face<FAST, D>(G, vel[D], i + di, j + dj, k + dk));
+        am = 0.5 * (real_face<FAST, D>(G, vel[D], i - ci, j - cj, k - ck) + real_face<FAST, D>(G, vel[D], i, j, k));
+    }
+    double fp = 0.0, fm = 0.0;
+    if (ap != 0.0) fp = ap * (ap > 0.0 ? smart_face(vm1, phi0, vp1) : smart_face(vp2, vp1, phi0));
+    if (am != 0.0) fm = am * (am > 0.0 ? smart_face(vm2, vm1, phi0) : smart_face(vp1, phi0, vm1));
+    conv += (fp - fm) * G.ih[D];
+    lap += ((vp1 - 2.0 * phi0) + vm1) * G.ih2[D];
+}
+
+template <bool FAST, int C>
+__device__ __forceinline__ double predictor(const GroupDesc &G, const double *__restrict__ const *vel, int i, int j,
+                                            int k, double dt) {
+    const long id = fidx<C>(G, i, j, k);
+    const double phi0 = vel[C][id];
+    double conv = 0.0, lap = 0.0;
+    dir_terms<FAST, C, 0>(G, vel, i, j, k, id, phi0, conv, lap);
+    dir_terms<FAST, C, 1>(G, vel, i, j, k, id, phi0, conv, lap);
+    dir_terms<FAST, C, 2>(G, vel, i, j, k, id, phi0, conv, lap);
+    return phi0 + dt * (lap * G.inv_re - conv);
+}
+
+// ------------------------------------------------------------ the runner
+
+struct Runner {
+    const KParams &P;
+    int tb, te;            // my tile range
+    double *s_red;         // [4 * kNQ] wave partials
+    double *s_sums;        // [kMaxSlices * kNQ]
+    int *s_int;            // [kBlock] scratch ints
+    const double *s_idg;   // [kMaxGroups * 64]
+    const float *s_idg32;  // [kMaxGroups * 64]
+
+    __device__ void locate(int t, int &gi, int &sl) const {
+        gi = 0;
+        while (gi + 1 < P.ngroups && t >= P.g[gi + 1].tile0) ++gi;
+        sl = (t - P.g[gi].tile0) / P.g[gi].ntiles;
+    }
+
+    // Sum the NQ per-thread values over the workgroup in a fixed order and
+    // store them as tile t's partials.
+    template <int NQ>
+    __device__ void store_partials(double (&acc)[NQ], int t) {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double v = wave_sum(acc[q]);
+            if (lane == 0) s_red[wv * kNQ + q] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NQ) {
+            const int q = threadIdx.x;
+            double v = (s_red[0 * kNQ + q] + s_red[1 * kNQ + q]) + (s_red[2 * kNQ + q] + s_red[3 * kNQ + q]);
+            P.part[(long)q * P.ntiles + t] = v;
+        }
+        __syncthreads();
+    }
+
+    // Loop over my tiles; `skip(G, gs)` is uniform per tile; `body(G, sl,
+    // gs, c, acc)` handles cell c of local slice sl (global slice gs).
+    template <int NQ, class Skip, class Body>
+    __device__ void tiles(Skip skip, Body body) {
+        for (int t = tb; t < te; ++t) {
+            int gi, sl;
+            locate(t, gi, sl);
+            const GroupDesc &G = P.g[gi];
+            const int gs = G.slice0 + sl;
+            if (skip(G, gs)) continue;
+            constexpr int NA = NQ > 0 ? NQ : 1;
+            double acc[NA];
+#pragma unroll
+            for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+            const int lt = t - G.tile0 - sl * G.ntiles;
+            const int base = lt * G.tile;
+            const int end = min(base + G.tile, G.ncells);
+            for (int c = base + (int)threadIdx.x; c < end; c += kBlock) body(G, sl, gs, c, acc);
+            if constexpr (NQ > 0) store_partials<NA>(acc, t);
+        }
+    }
+
+    // ------------------------------------------------------- grid barrier
+
+    __device__ __forceinline__ int load_any() const {
+        return __hip_atomic_load(&P.sync->any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // Barrier over the whole grid.  The last workgroup to arrive runs the
+    // reduction `rid`, publishes the control word, and releases the others.
+    // Returns the control word (uniform across the grid), or -1 on abort.
+    __device__ int sync(int rid) {
+        __shared__ int s_last;
+        __shared__ int s_abort;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            SyncWords *S = P.sync;
+            __threadfence();
+            const unsigned g = __hip_atomic_load(&S->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned a = __hip_atomic_fetch_add(&S->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            const int last = (a == gridDim.x - 1);
+            int ab = 0;
+            if (!last) {
+                unsigned spins = 0;
+                while (__hip_atomic_load(&S->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if ((++spins & 255u) == 0) {
+                        if (__hip_atomic_load(&S->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
+                        if (spins > kSpinLimit) {
+                            __hip_atomic_store(&S->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ab = 1;
+                            break;
+                        }
+                    }
+                }
+            }
+            __threadfence();
+            s_last = last;
+            s_abort = ab;
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (s_last) {
+            reduce(rid);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                SyncWords *S = P.sync;
+                __threadfence();
+                __hip_atomic_store(&S->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&S->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (s_abort) return -1;
+        __syncthreads();
+        if (__hip_atomic_load(&P.sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
+        return load_any();
+    }
+
+    // Per-slice sums of nq partial quantities into s_sums, in a fixed order:
+    // eight lanes per slice, lane l summing tiles l, l+8, ..., then an xor
+    // butterfly over the eight lanes.
+    __device__ void slice_sums(int nq) {
+        for (int sb = 0; sb < P.nslices; sb += kBlock / 8) {
+            const int s = sb + (int)threadIdx.x / 8, l = threadIdx.x & 7;
+            double a[kNQ] = {0.0, 0.0, 0.0, 0.0};
+            if (s < P.nslices) {
+                int gi = 0;
+                while (gi + 1 < P.ngroups && s >= P.g[gi + 1].slice0) ++gi;
+                const GroupDesc &G = P.g[gi];
+                const int t0 = G.tile0 + (s - G.slice0) * G.ntiles;
+                for (int q = 0; q < nq; ++q) {
+                    const double *pp = P.part + (long)q * P.ntiles + t0;
+                    double v = 0.0;
+#pragma unroll 4
+                    for (int t = l; t < G.ntiles; t += 8) v += pp[t];
+                    a[q] = v;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kNQ; ++q) {
+                a[q] += __shfl_xor(a[q], 4, 64);
+                a[q] += __shfl_xor(a[q], 2, 64);
+                a[q] += __shfl_xor(a[q], 1, 64);
+            }
+            if (l == 0 && s < P.nslices)
+                for (int q = 0; q < kNQ; ++q) s_sums[s * kNQ + q] = a[q];
+        }
+        __syncthreads();
+    }
+
+    __device__ double nfluid_of(int s) const {
+        int gi = 0;
+        while (gi + 1 < P.ngroups && s >= P.g[gi + 1].slice0) ++gi;
+        return P.g[gi].nfluid;
+    }
+
+    __device__ void finish_solve(SliceCtl &c) {
+        c.done = 1;
+        c.status = max(c.status, c.step_status);
+        c.tot_it += c.it;
+        c.max_it = max(c.max_it, c.it);
+        c.tot_outer += c.outer;
+    }
+
+    // CG scalar logic for one slice after reduction rid; returns this
+    // slice's contribution to the control word.
+    __device__ int control(int rid, int s) {
+        SliceCtl &c = P.ctl[s];
+        const double *S = s_sums + s * kNQ;
+        const double nf = nfluid_of(s);
+        switch (rid) {
+        case R_MEANB:
+            c.mean_b = S[0] / nf;
+            return 0;
+        case R_INIT: {
+            // S0 = ||b||^2, S1 = ||r||^2, S2 = <r,z>
+            c.bnorm = sqrt(S[0]);
+            c.it = 0;
+            c.outer = 0;
+            c.done = 0;
+            c.step_status = 0;
+            c.first = 1;
+            c.zero = (c.bnorm == 0.0);
+            c.active = 0;
+            if (c.zero) return 0;
+            c.rz = S[2];
+            const double rn = sqrt(S[1]);
+            if (!isfinite(rn)) c.step_status = 3;
+            else if (rn > P.rtol * c.bnorm) c.active = (c.it < P.maxit) ? 1 : (c.step_status = 2, 0);
+            return c.active;
+        }
+        case R_A:
+            if (c.active) c.alpha = c.rz / S[0];
+            return 0;
+        case R_B: {
+            // S0 = <r,z>, S1 = ||r||^2
+            if (!c.active) return 0;
+            c.beta = S[0] / c.rz;
+            c.rz = S[0];
+            c.it += 1;
+            c.first = 0;
+            const double rn = sqrt(S[1]);
+            if (!isfinite(rn)) { c.step_status = 3; c.active = 0; }
+            else if (rn <= P.rtol * c.bnorm) c.active = 0;
+            else if (c.it >= P.maxit) { c.step_status = 2; c.active = 0; }
+            return c.active;
+        }
+        case R_TRUE: {
+            // S0 = ||b - A p||^2, S1 = sum p, S2 = <r,z> of the true residual
+            if (c.zero) {
+                c.rel_true = 0.0;
+                c.res_true = 0.0;
+                if (!c.done) finish_solve(c);
+                return 0;
+            }
+            if (c.done) return 0;
+            c.res_true = sqrt(S[0]);
+            c.rel_true = c.res_true / c.bnorm;
+            c.mean_p = S[1] / nf;
+            const bool ok = c.step_status == 0;
+            if (ok && isfinite(c.rel_true) && c.rel_true > 2.0 * P.rtol && c.it < P.maxit) {
+                c.outer += 1;
+                c.rz = S[2];
+                c.first = 1;
+                c.active = 1;
+                return 1;
+            }
+            if (!isfinite(c.rel_true)) c.step_status = 3;
+            finish_solve(c);
+            return 0;
+        }
+        case R_OUT0:
+        case R_OUT: {
+            // S0 = ||r||^2, S1 = sum r, S2 = sum p, S3 = ||b||^2 (first sweep)
+            if (rid == R_OUT0) {
+                c.bnorm = sqrt(S[3]);
+                c.it = 0;
+                c.outer = 0;
+                c.done = 0;
+                c.step_status = 0;
+                c.zero = (c.bnorm == 0.0);
+                c.need = 0;
+            }
+            if (c.done) return 0;
+            if (c.zero) {
+                c.rel_true = 0.0;
+                c.res_true = 0.0;
+                finish_solve(c);
+                return 0;
+            }
+            c.res_true = sqrt(S[0]);
+            c.rel_true = c.res_true / c.bnorm;
+            c.mean_p = S[2] / nf;
+            c.need = 0;
+            if (!isfinite(c.res_true)) c.step_status = 3;
+            else if (c.res_true <= P.rtol * c.bnorm) { /* converged */ }
+            else if (c.outer >= P.max_outer) c.step_status = 2;
+            else { c.need = 1; c.mean_r = S[1] / nf; }
+            if (!c.need) finish_solve(c);
+            return c.need;
+        }
+        case R_CAST: {
+            // S0 = ||r32||^2, S1 = <r32, z32>
+            if (!c.need) return 0;
+            c.outer += 1;
+            c.r0 = sqrt(S[0]);
+            c.rz = S[1];
+            c.it_in = 0;
+            c.first = 1;
+            c.active = (isfinite(c.r0) && c.r0 > P.eta * c.r0 && P.maxit > 0) ? 1 : 0;
+            return c.active;
+        }
+        case R_A32:
+            if (c.active) c.alpha = c.rz / S[0];
+            return 0;
+        case R_B32: {
+            if (!c.active) return 0;
+            c.beta = S[0] / c.rz;
+            c.rz = S[0];
+            c.it_in += 1;
+            c.it += 1;
+            c.first = 0;
+            const double rn = sqrt(S[1]);
+            c.active = (rn > P.eta * c.r0 && c.it_in < P.maxit && isfinite(rn)) ? 1 : 0;
+            return c.active;
+        }
+        default:
+            return 0;
+        }
+    }
+
+    __device__ void reduce(int rid) {
+        if (rid == R_NONE) {
+            if (threadIdx.x == 0) __hip_atomic_store(&P.sync->any, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        int nq = 0;
+        switch (rid) {
+        case R_MEANB: nq = 1; break;
+        case R_A: case R_A32: nq = 1; break;
+        case R_B: case R_B32: case R_CAST: nq = 2; break;
+        case R_INIT: case R_TRUE: nq = 3; break;
+        case R_OUT: nq = 3; break;
+        case R_OUT0: nq = 4; break;
+        }
+        slice_sums(nq);
+        int f = 0;
+        if ((int)threadIdx.x < P.nslices) f = control(rid, threadIdx.x);
+        s_int[threadIdx.x] = f;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int any = 0;
+            for (int s = 0; s < P.nslices; ++s) any |= s_int[s];
+            __hip_atomic_store(&P.sync->any, any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    // ------------------------------------------------------------- phases
+
+    __device__ const SliceCtl &ctl(int gs) const { return P.ctl[gs]; }
+
+    // pressure after the gauge fix of the last solve
+    __device__ __forceinline__ double p_eff(const SliceCtl &c, double p, bool fluid) const {
+        if (c.zero) return 0.0;
+        return fluid ? p - c.mean_p : p;
+    }
+
+    __device__ void phase_mom(bool gauge) {
+        tiles<0>([](const GroupDesc &, int) { return false; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *) {
+                     const IJK x = decomp(G, c);
+                     const uint8_t fl = G.flags[c];
+                     const double *vel[3] = {G.u + (long)sl * G.nu, G.v + (long)sl * G.nv, G.w + (long)sl * G.nw};
+                     double *Fu = G.Fu + (long)sl * G.nu, *Fv = G.Fv + (long)sl * G.nv, *Fw = G.Fw + (long)sl * G.nw;
+                     double fu = 0.0, fv = 0.0, fw = 0.0;
+                     if (!(fl & FL_SLOW)) {
+                         fu = predictor<true, 0>(G, vel, x.i, x.j, x.k, P.dt);
+                         fv = predictor<true, 1>(G, vel, x.i, x.j, x.k, P.dt);
+                         fw = predictor<true, 2>(G, vel, x.i, x.j, x.k, P.dt);
+                     } else {
+                         if (fl & FL_XM) fu = predictor<false, 0>(G, vel, x.i, x.j, x.k, P.dt);
+                         if (fl & FL_YM) fv = predictor<false, 1>(G, vel, x.i, x.j, x.k, P.dt);
+                         if (fl & FL_ZM) fw = predictor<false, 2>(G, vel, x.i, x.j, x.k, P.dt);
+                     }
+                     Fu[fidx<0>(G, x.i, x.j, x.k)] = fu;
+                     Fv[fidx<1>(G, x.i, x.j, x.k)] = fv;
+                     Fw[fidx<2>(G, x.i, x.j, x.k)] = fw;
+                     if (x.i == G.nx - 1) Fu[fidx<0>(G, G.nx, x.j, x.k)] = 0.0;
+                     if (x.j == G.ny - 1) Fv[fidx<1>(G, x.i, G.ny, x.k)] = 0.0;
+                     if (x.k == G.nz - 1) Fw[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
+                     if (gauge) {
+                         double *p = G.p + (long)sl * G.ncells;
+                         p[c] = p_eff(ctl(gs), p[c], fl & FL_FLUID);
+                     }
+                 });
+    }
+
+    __device__ void phase_gauge() {
+        tiles<0>([](const GroupDesc &, int) { return false; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *) {
+                     double *p = G.p + (long)sl * G.ncells;
+                     p[c] = p_eff(ctl(gs), p[c], G.flags[c] & FL_FLUID);
+                 });
+    }
+
+    __device__ void phase_rhs() {
+        tiles<1>([](const GroupDesc &, int) { return false; },
+                 [&](const GroupDesc &G, int sl, int, int c, double *acc) {
+                     double *b = G.b + (long)sl * G.ncells;
+                     if (!(G.flags[c] & FL_FLUID)) { b[c] = 0.0; return; }
+                     const IJK x = decomp(G, c);
+                     const double *Fu = G.Fu + (long)sl * G.nu, *Fv = G.Fv + (long)sl * G.nv,
+                                  *Fw = G.Fw + (long)sl * G.nw;
+                     const long iu = fidx<0>(G, x.i, x.j, x.k), iv = fidx<1>(G, x.i, x.j, x.k),
+                                iw = fidx<2>(G, x.i, x.j, x.k);
+                     double div = (Fu[iu + 1] - Fu[iu]) * G.ih[0];
+                     div += (Fv[iv + G.nx] - Fv[iv]) * G.ih[1];
+                     div += (Fw[iw + (long)G.nx * G.ny] - Fw[iw]) * G.ih[2];
+                     const double bv = -div / P.dt;
+                     b[c] = bv;
+                     acc[0] += bv;
+                 });
+    }
+
+    // Poisson mode: mean of the caller's right-hand side
+    __device__ void phase_meanb_user() {
+        tiles<1>([](const GroupDesc &, int) { return false; },
+                 [&](const GroupDesc &G, int sl, int, int c, double *acc) {
+                     if (G.flags[c] & FL_FLUID) acc[0] += G.bin[(long)sl * G.ncells + c];
+                 });
+    }
+
+    // (A x)_c over the open faces of cell c, in the order x-,x+,y-,y+,z-,z+
+    template <class T, class Get>
+    __device__ __forceinline__ T apply_A(const GroupDesc &G, int c, uint8_t fl, T xc, Get get, const T *ih2) const {
+        T s = T(0);
+        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        if (fl & FL_XM) s += (xc - get(c - 1)) * ih2[0];
+        if (fl & FL_XP) s += (xc - get(c + 1)) * ih2[0];
+        if (fl & FL_YM) s += (xc - get(c - sy)) * ih2[1];
+        if (fl & FL_YP) s += (xc - get(c + sy)) * ih2[1];
+        if (fl & FL_ZM) s += (xc - get(c - sz)) * ih2[2];
+        if (fl & FL_ZP) s += (xc - get(c + sz)) * ih2[2];
+        return s;
+    }
+
+    __device__ __forceinline__ const double *idg(int gi_base) const { return s_idg + gi_base; }
+
+    __device__ int group_index(const GroupDesc &G) const { return (int)(&G - P.g); }
+
+    // FP64 CG, initial residual: b -= mean_b (stored), r = b - A p.
+    // partials: ||b||^2, ||r||^2, <r,z>
+    __device__ void phase_init64(bool from_user) {
+        tiles<3>([](const GroupDesc &, int) { return false; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const long off = (long)sl * G.ncells;
+                     double *b = G.b + off, *r = G.r + off;
+                     const double *p = G.p + off;
+                     const uint8_t fl = G.flags[c];
+                     if (!(fl & FL_FLUID)) { b[c] = 0.0; r[c] = 0.0; return; }
+                     const double bsrc = from_user ? G.bin[off + c] : b[c];
+                     const double bv = bsrc - ctl(gs).mean_b;
+                     b[c] = bv;
+                     const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
+                     const double rv = bv - ap;
+                     r[c] = rv;
+                     const double z = rv * s_idg[group_index(G) * 64 + (fl & FL_OPEN)];
+                     acc[0] += bv * bv;
+                     acc[1] += rv * rv;
+                     acc[2] += rv * z;
+                 });
+    }
+
+    // q = A d_new with d_new = z + beta d_old (z = r/diag), recomputed for
+    // the neighbours from r and d_old; partial <d_new, q>.
+    template <class T>
+    __device__ void phase_A(int par) {
+        tiles<1>([&](const GroupDesc &, int gs) { return !ctl(gs).active; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const long off = (long)sl * G.ncells;
+                     const T *r = reinterpret_cast<const T *>(G.r) + off;
+                     const T *dold = reinterpret_cast<const T *>(par ? G.d1 : G.d0) + off;
+                     T *dnew = reinterpret_cast<T *>(par ? G.d0 : G.d1) + off;
+                     T *q = reinterpret_cast<T *>(G.q) + off;
+                     const uint8_t fl = G.flags[c];
+                     if (!(fl & FL_FLUID)) { dnew[c] = T(0); q[c] = T(0); return; }
+                     const SliceCtl &cs = ctl(gs);
+                     const bool first = cs.first;
+                     const T beta = (T)cs.beta;
+                     const int gb = group_index(G) * 64;
+                     auto dn = [&](long n) -> T {
+                         const uint8_t f = G.flags[n];
+                         T z;
+                         if (sizeof(T) == 8) z = r[n] * (T)s_idg[gb + (f & FL_OPEN)];
+                         else z = r[n] * (T)s_idg32[gb + (f & FL_OPEN)];
+                         return first ? z : z + beta * dold[n];
+                     };
+                     const T dc = dn(c);
+                     T ih2[3];
+                     if (sizeof(T) == 8) { ih2[0] = (T)G.ih2[0]; ih2[1] = (T)G.ih2[1]; ih2[2] = (T)G.ih2[2]; }
+                     else { ih2[0] = (T)G.ih2f[0]; ih2[1] = (T)G.ih2f[1]; ih2[2] = (T)G.ih2f[2]; }
+                     const T qc = apply_A<T>(G, c, fl, dc, dn, ih2);
+                     dnew[c] = dc;
+                     q[c] = qc;
+                     acc[0] += (double)dc * (double)qc;
+                 });
+    }
+
+    // FP64: p += alpha d; r -= alpha q.  partials <r,z>, ||r||^2
+    __device__ void phase_B64(int par) {
+        tiles<2>([&](const GroupDesc &, int gs) { return !ctl(gs).active; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const uint8_t fl = G.flags[c];
+                     if (!(fl & FL_FLUID)) return;
+                     const long off = (long)sl * G.ncells;
+                     const double *d = (par ? G.d0 : G.d1) + off;
+                     const double alpha = ctl(gs).alpha;
+                     double *p = G.p + off, *r = G.r + off;
+                     const double *q = G.q + off;
+                     p[c] = p[c] + alpha * d[c];
+                     const double rv = r[c] - alpha * q[c];
+                     r[c] = rv;
+                     const double z = rv * s_idg[group_index(G) * 64 + (fl & FL_OPEN)];
+                     acc[0] += rv * z;
+                     acc[1] += rv * rv;
+                 });
+    }
+
+    // FP64 true residual r = b - A p (stored for a restart).
+    // partials ||r||^2, sum p, <r,z>
+    __device__ void phase_true64() {
+        tiles<3>([&](const GroupDesc &, int gs) { return ctl(gs).zero || ctl(gs).done; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const uint8_t fl = G.flags[c];
+                     if (!(fl & FL_FLUID)) return;
+                     const long off = (long)sl * G.ncells;
+                     const double *p = G.p + off, *b = G.b + off;
+                     double *r = G.r + off;
+                     const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
+                     const double rv = b[c] - ap;
+                     r[c] = rv;
+                     const double z = rv * s_idg[group_index(G) * 64 + (fl & FL_OPEN)];
+                     acc[0] += rv * rv;
+                     acc[1] += p[c];
+                     acc[2] += rv * z;
+                 });
+    }
+
+    // Mixed: FP64 residual r = b - A p.  First sweep also makes b mean-free.
+    // partials ||r||^2, sum r, sum p, ||b||^2
+    __device__ void phase_out(bool first, bool from_user) {
+        tiles<4>([&](const GroupDesc &, int gs) { return !first && (ctl(gs).done || ctl(gs).zero); },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const long off = (long)sl * G.ncells;
+                     double *b = G.b + off;
+                     const double *p = G.p + off;
+                     const uint8_t fl = G.flags[c];
+                     if (!(fl & FL_FLUID)) { if (first) b[c] = 0.0; return; }
+                     double bv;
+                     if (first) {
+                         const double bsrc = from_user ? G.bin[off + c] : b[c];
+                         bv = bsrc - ctl(gs).mean_b;
+                         b[c] = bv;
+                     } else {
+                         bv = b[c];
+                     }
+                     const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
+                     const double rv = bv - ap;
+                     acc[0] += rv * rv;
+                     acc[1] += rv;
+                     acc[2] += p[c];
+                     acc[3] += bv * bv;
+                 });
+    }
+
+    // Mixed: r32 = fp32(r - mean r), e = 0.  partials ||r32||^2, <r32,z32>
+    __device__ void phase_cast() {
+        tiles<2>([&](const GroupDesc &, int gs) { return !ctl(gs).need; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const long off = (long)sl * G.ncells;
+                     float *r32 = reinterpret_cast<float *>(G.r) + off;
+                     float *e = G.e + off;
+                     const uint8_t fl = G.flags[c];
+                     e[c] = 0.0f;
+                     if (!(fl & FL_FLUID)) { r32[c] = 0.0f; return; }
+                     const double *p = G.p + off, *b = G.b + off;
+                     const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
+                     const double rv = b[c] - ap;
+                     const float rf = (float)(rv - ctl(gs).mean_r);
+                     r32[c] = rf;
+                     const float z = rf * s_idg32[group_index(G) * 64 + (fl & FL_OPEN)];
+                     acc[0] += (double)rf * (double)rf;
+                     acc[1] += (double)rf * (double)z;
+                 });
+    }
+
+    // Mixed inner: e += alpha d; r -= alpha q (FP32).  partials <r,z>, ||r||^2
+    __device__ void phase_B32(int par) {
+        tiles<2>([&](const GroupDesc &, int gs) { return !ctl(gs).active; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const uint8_t fl = G.flags[c];
+                     if (!(fl & FL_FLUID)) return;
+                     const long off = (long)sl * G.ncells;
+                     const float *d = reinterpret_cast<const float *>(par ? G.d0 : G.d1) + off;
+                     const float *q = reinterpret_cast<const float *>(G.q) + off;
+                     float *r = reinterpret_cast<float *>(G.r) + off;
+                     float *e = G.e + off;
+                     const float alpha = (float)ctl(gs).alpha;
+                     e[c] = e[c] + alpha * d[c];
+                     const float rv = r[c] - alpha * q[c];
+                     r[c] = rv;
+                     const float z = rv * s_idg32[group_index(G) * 64 + (fl & FL_OPEN)];
+                     acc[0] += (double)rv * (double)z;
+                     acc[1] += (double)rv * (double)rv;
+                 });
+    }
+
+    // Mixed: p += fp64(e)
+    __device__ void phase_update() {
+        tiles<0>([&](const GroupDesc &, int gs) { return !ctl(gs).need; },
+                 [&](const GroupDesc &G, int sl, int, int c, double *) {
+                     if (!(G.flags[c] & FL_FLUID)) return;
+                     const long off = (long)sl * G.ncells;
+                     G.p[off + c] += (double)G.e[off + c];
+                 });
+    }
+
+    // u = F - dt G p_eff on open faces, 0 on closed faces
+    __device__ void phase_corr() {
+        tiles<0>([](const GroupDesc &, int) { return false; },
+                 [&](const GroupDesc &G, int sl, int gs, int c, double *) {
+                     const IJK x = decomp(G, c);
+                     const uint8_t fl = G.flags[c];
+                     const SliceCtl &cs = ctl(gs);
+                     const long off = (long)sl * G.ncells;
+                     const double *p = G.p + off;
+                     double *u = G.u + (long)sl * G.nu, *v = G.v + (long)sl * G.nv, *w = G.w + (long)sl * G.nw;
+                     const double *Fu = G.Fu + (long)sl * G.nu, *Fv = G.Fv + (long)sl * G.nv,
+                                  *Fw = G.Fw + (long)sl * G.nw;
+                     const long iu = fidx<0>(G, x.i, x.j, x.k), iv = fidx<1>(G, x.i, x.j, x.k),
+                                iw = fidx<2>(G, x.i, x.j, x.k);
+                     const double pc = p_eff(cs, p[c], true);
+                     u[iu] = (fl & FL_XM) ? Fu[iu] - P.dt * ((pc - p_eff(cs, p[c - 1], true)) * G.ih[0]) : 0.0;
+                     v[iv] = (fl & FL_YM) ? Fv[iv] - P.dt * ((pc - p_eff(cs, p[c - G.nx], true)) * G.ih[1]) : 0.0;
+                     w[iw] = (fl & FL_ZM) ? Fw[iw] - P.dt * ((pc - p_eff(cs, p[c - (long)G.nx * G.ny], true)) * G.ih[2])
+                                          : 0.0;
+                     if (x.i == G.nx - 1) u[fidx<0>(G, G.nx, x.j, x.k)] = 0.0;
+                     if (x.j == G.ny - 1) v[fidx<1>(G, x.i, G.ny, x.k)] = 0.0;
+                     if (x.k == G.nz - 1) w[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
+                 });
+    }
+
+    // ---------------------------------------------------------- programs
+
+    // returns false on abort
+    __device__ bool solve64(bool from_user) {
+        phase_init64(from_user);
+        int any = sync(R_INIT);
+        if (any < 0) return false;
+        int iter = 0;
+        for (;;) {
+            while (any > 0) {
+                const int par = iter & 1;
+                phase_A<double>(par);
+                if (sync(R_A) < 0) return false;
+                phase_B64(par);
+                any = sync(R_B);
+                if (any < 0) return false;
+                ++iter;
+            }
+            phase_true64();
+            any = sync(R_TRUE);
+            if (any < 0) return false;
+            if (!any) break;
+        }
+        return true;
+    }
+
+    __device__ bool solve_mixed(bool from_user) {
+        phase_out(true, from_user);
+        int any = sync(R_OUT0);
+        if (any < 0) return false;
+        int iter = 0;
+        while (any > 0) {
+            phase_cast();
+            int act = sync(R_CAST);
+            if (act < 0) return false;
+            while (act > 0) {
+                const int par = iter & 1;
+                phase_A<float>(par);
+                if (sync(R_A32) < 0) return false;
+                phase_B32(par);
+                act = sync(R_B32);
+                if (act < 0) return false;
+                ++iter;
+            }
+            phase_update();
+            if (sync(R_NONE) < 0) return false;
+            phase_out(false, false);
+            any = sync(R_OUT);
+            if (any < 0) return false;
+        }
+        return true;
+    }
+
+    __device__ void run() {
+        if (P.mode == MODE_POISSON) {
+            phase_meanb_user();
+            if (sync(R_MEANB) < 0) return;
+            const bool ok = P.prec == 0 ? solve64(true) : solve_mixed(true);
+            if (!ok) return;
+            phase_gauge();
+            return;
+        }
+        for (int step = 0; step < P.nsteps; ++step) {
+            phase_mom(step > 0);
+            if (sync(R_NONE) < 0) return;
+            phase_rhs();
+            if (sync(R_MEANB) < 0) return;
+            const bool ok = P.prec == 0 ? solve64(false) : solve_mixed(false);
+            if (!ok) return;
+            phase_corr();
+            // the correction reads neighbouring pressures: no cell may be
+            // gauge-shifted before every workgroup has finished it
+            if (sync(R_NONE) < 0) return;
+        }
+        if (P.nsteps > 0) phase_gauge();
+    }
+};
+
+// The launch parameters live in device memory (one block per handle): a
+// by-value parameter block of this size would be copied to scratch.
+// At most 128 VGPRs (4 waves per SIMD): the CG phases need the occupancy;
+// the image-rule momentum path may spill instead.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_persistent(const KParams *__restrict__ Pp) {
+    const KParams &P = *Pp;
+    __shared__ double s_red[4 * kNQ];
+    __shared__ double s_sums[kMaxSlices * kNQ];
+    __shared__ int s_int[kBlock];
+    __shared__ double s_idg[kMaxGroups * 64];
+    __shared__ float s_idg32[kMaxGroups * 64];
+    for (int x = threadIdx.x; x < P.ngroups * 64; x += kBlock) {
+        s_idg[x] = P.g[x / 64].idiag[x % 64];
+        s_idg32[x] = P.g[x / 64].idiag32[x % 64];
+    }
+    __syncthreads();
+    // Logical workgroup index: with xcd_remap, workgroups dispatched to the
+    // same XCD (hardware index modulo 8) receive one contiguous tile range,
+    // so stencil neighbours in the next plane sit in the same L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    int lb = b;
+    if (P.xcd_remap && nb >= 8) {
+        const int x = b & 7, q = nb >> 3, rm = nb & 7;
+        lb = x * q + min(x, rm) + (b >> 3);
+    }
+    Runner R{P, (int)((long)lb * P.ntiles / nb), (int)((long)(lb + 1) * P.ntiles / nb), s_red, s_sums, s_int,
+             s_idg, s_idg32};
+    R.run();
+}
+
+__global__ void k_reset_sync(SyncWords *s) {
+    if (threadIdx.x == 0) {
+        s->count = 0;
+        s->any = 0;
+        s->abort = 0;
+    }
+}
+
+__global__ void k_parareal_update(UpdateParams U) {
+    // grid-stride over all segments, one segment at a time
+    double mx[2] = {0.0, 0.0};
+    for (int si = 0; si < U.nseg; ++si) {
+        const UpdateSeg &S = U.seg[si];
+        double m = 0.0;
+        for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < S.n;
+             x += (long long)gridDim.x * blockDim.x) {
+            const double g = S.g[x];
+            const double y = S.f[x] + (g - S.gold[x]);
+            const double d = fabs(y - S.y[x]);
+            m = (d > m || d != d) ? d : m;
+            S.y[x] = y;
+            S.gold[x] = g;
+        }
+        // reduce max over the wave, then one atomic per wave
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double t = __shfl_xor(m, o, 64);
+            m = (t > m || t != t) ? t : m;
+        }
+        if ((threadIdx.x & 63) == 0 && m != 0.0) {
+            unsigned long long bits = __double_as_longlong(m);
+            const int slot = 2 * U.group_of_seg[si] + S.jslot;
+            __hip_atomic_fetch_max(&U.jump[slot], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        (void)mx;
+    }
+}
+
+__global__ void k_copy(double *__restrict__ dst, const double *__restrict__ src, long long n) {
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x)
+        dst[x] = src[x];
+}
+
+}  // namespace
+
+hipError_t launch_persistent(const KParams *P_dev, int workgroups, hipStream_t stream) {
+    const KParams *arg = P_dev;
+    void *args[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_persistent), dim3(workgroups), dim3(kBlock),
+                                      args, 0, stream);
+}
+
+hipError_t max_coresident_workgroups(int device, int *out) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_persistent),
+                                                               kBlock, 0);
+    if (e != hipSuccess) return e;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return e;
+    *out = per_cu * prop.multiProcessorCount;
+    return hipSuccess;
+}
+
+hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, stream, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream) {
+    long long nmax = 0;
+    for (int i = 0; i < U.nseg; ++i) nmax = U.seg[i].n > nmax ? U.seg[i].n : nmax;
+    long long blocks = (nmax + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_parareal_update, dim3((unsigned)blocks), dim3(256), 0, stream, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_state(double *dst, const double *src, long long n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, stream, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace nsp

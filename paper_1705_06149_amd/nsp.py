@@ -1,0 +1,332 @@
+"""Python binding of libnsp (include/nsp.h): argument marshalling only.
+
+Every array is a contiguous float64 torch tensor on the current HIP device;
+this module checks dtype, device, contiguity and shapes, then passes raw
+pointers and the current stream to the C ABI.  All arithmetic happens in the
+library's gfx950 kernels.  If libnsp.so is missing or a tensor is not on the
+GPU, calls raise: there is no CPU path.
+
+Layout of one slice of a grid with nx*ny*nz cells (y vertical, lid in +x):
+    u (nz, ny, nx+1)   v (nz, ny+1, nx)   w (nz+1, ny, nx)   p (nz, ny, nx)
+A batch adds a leading dimension B.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnsp.so")
+
+NSP_OK, NSP_ERR_ARG, NSP_ERR_NOT_CONVERGED, NSP_ERR_NONFINITE, NSP_ERR_HIP, NSP_ERR_UNSUPPORTED = range(6)
+_STATUS = {0: "NSP_OK", 1: "NSP_ERR_ARG", 2: "NSP_ERR_NOT_CONVERGED", 3: "NSP_ERR_NONFINITE",
+           4: "NSP_ERR_HIP", 5: "NSP_ERR_UNSUPPORTED"}
+FP64, MIXED = 0, 1
+
+
+class NSPError(RuntimeError):
+    def __init__(self, status, msg, info=None):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+        self.info = info
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("re", ctypes.c_double), ("periodic_z", ctypes.c_int),
+                ("solid_host", ctypes.c_void_p), ("max_batch", ctypes.c_int)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("prec", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("max_iters", ctypes.c_int), ("outer", ctypes.c_int),
+                ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double), ("div_l2", ctypes.c_double)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p), ("p", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnsp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("libnsp.so is not built: run paper_1705_06149_amd/build.py")
+        L = ctypes.CDLL(_LIB_PATH)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        S = ctypes.c_int
+        L.nsp_create.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(P)]
+        L.nsp_destroy.argtypes = [P]
+        L.nsp_last_error.argtypes = [P]
+        L.nsp_last_error.restype = ctypes.c_char_p
+        L.nsp_set_lid.argtypes = [P, P]
+        L.nsp_poisson_solve.argtypes = [P, P, P, I, ctypes.POINTER(_Opts), P, P]
+        L.nsp_fine_step.argtypes = [P, _State, I, D, D, D, ctypes.POINTER(_Opts), P, P]
+        L.nsp_coarse_step.argtypes = [P, _State, I, D, D, D, ctypes.POINTER(_Opts), P, P]
+        L.nsp_group_fine_step.argtypes = [P, P, P, I, D, D, D, ctypes.POINTER(_Opts), P, P]
+        L.nsp_parareal_start.argtypes = [P, _State, _State, I, D, D, D, ctypes.POINTER(_Opts), P]
+        L.nsp_parareal_iterate.argtypes = [P, _State, _State, _State, I, I, D, D, D, D,
+                                           ctypes.POINTER(_Opts), ctypes.POINTER(_Opts), P, P]
+        L.nsp_group_parareal_start.argtypes = [P, P, P, I, I, D, D, D, ctypes.POINTER(_Opts), P]
+        L.nsp_group_parareal_iterate.argtypes = [P, P, P, P, I, I, I, D, D, D, D, ctypes.POINTER(_Opts),
+                                                 ctypes.POINTER(_Opts), P, P]
+        L.nsp_set_launch.argtypes = [P, I]
+        L.nsp_autotune.argtypes = [P, I, I, P, ctypes.POINTER(I)]
+        L.nsp_last_launch_ms.argtypes = [P, ctypes.POINTER(D)]
+        for name in ("nsp_create", "nsp_destroy", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
+                     "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
+                     "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
+                     "nsp_last_launch_ms"):
+            getattr(L, name).restype = S
+        _lib = L
+    return _lib
+
+
+@dataclass
+class PoissonOpts:
+    """Options of the Poisson solve (nsp_poisson_opts)."""
+    rtol: float = 1e-10
+    maxit: int = 20000
+    prec: int = FP64
+    inner_rtol: float = 1e-5
+    max_outer: int = 8
+
+    def c(self):
+        return _Opts(float(self.rtol), int(self.maxit), int(self.prec), float(self.inner_rtol), int(self.max_outer))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(t, shape, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64, got %s" % (name, t.dtype))
+    if not t.is_cuda:
+        raise ValueError("%s must be on the GPU (libnsp has no CPU path)" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return t.data_ptr()
+
+
+class Handle:
+    """One grid (nsp_create / nsp_destroy)."""
+
+    def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, re=100.0, solid=None, max_batch=1):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.lx, self.ly, self.lz, self.re = float(lx), float(ly), float(lz), float(re)
+        self.max_batch = int(max_batch)
+        self._solid = None
+        if solid is not None:
+            s = np.ascontiguousarray(np.asarray(solid), dtype=np.uint8)
+            if s.shape != (self.nz, self.ny, self.nx):
+                raise ValueError("solid mask must have shape (nz, ny, nx)")
+            self._solid = s
+        g = _Grid(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.re, 0,
+                  self._solid.ctypes.data if self._solid is not None else None, self.max_batch)
+        h = ctypes.c_void_p()
+        st = lib().nsp_create(ctypes.byref(g), ctypes.byref(h))
+        if st != NSP_OK:
+            raise NSPError(st, "nsp_create failed (sizes, max_batch <= 64, connected fluid region)")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nsp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def shapes(self, batch=None):
+        nx, ny, nz = self.nx, self.ny, self.nz
+        s = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx), (nz, ny, nx)]
+        if batch is not None:
+            s = [(batch,) + x for x in s]
+        return s
+
+    def zeros_state(self, batch=1, device="cuda"):
+        torch = _torch()
+        return tuple(torch.zeros(s, dtype=torch.float64, device=device) for s in self.shapes(batch))
+
+    def _err(self, st, what, info=None):
+        if st != NSP_OK:
+            msg = lib().nsp_last_error(self._h)
+            raise NSPError(st, "%s: %s" % (what, msg.decode() if msg else ""), info)
+
+    def _state(self, y, batch, name="y"):
+        shp = self.shapes(batch)
+        ptrs = [_check(t, s, "%s[%d]" % (name, i)) for i, (t, s) in enumerate(zip(y, shp))]
+        return _State(*ptrs)
+
+    @staticmethod
+    def _batch_of(y):
+        return int(y[0].shape[0])
+
+    def set_lid(self, lid):
+        _check(lid, (self.nz, self.nx + 1), "lid")
+        self._err(lib().nsp_set_lid(self._h, ctypes.c_void_p(lid.data_ptr())), "nsp_set_lid")
+
+    def poisson_solve(self, b, p, opts=None, check=True):
+        """Solve A p = b in place on p (batch = leading dimension)."""
+        opts = opts or PoissonOpts()
+        B = int(b.shape[0])
+        sp = (B, self.nz, self.ny, self.nx)
+        pb, pp = _check(b, sp, "b"), _check(p, sp, "p")
+        info = (_Info * B)()
+        o = opts.c()
+        st = lib().nsp_poisson_solve(self._h, ctypes.c_void_p(pb), ctypes.c_void_p(pp), B, ctypes.byref(o),
+                                     _stream_ptr(), info)
+        res = [_info_dict(x) for x in info]
+        if check:
+            self._err(st, "nsp_poisson_solve", res)
+        return res
+
+    def _prop(self, fn, y, t0, t1, step, opts, check):
+        opts = opts or PoissonOpts()
+        B = self._batch_of(y)
+        s = self._state(y, B)
+        info = (_Info * B)()
+        o = opts.c()
+        st = fn(self._h, s, B, float(t0), float(t1), float(step), ctypes.byref(o), _stream_ptr(), info)
+        res = [_info_dict(x) for x in info]
+        if check:
+            self._err(st, fn.__name__, res)
+        return res
+
+    def fine_step(self, y, t0, t1, dt, opts=None, check=True):
+        """F(y, t1, t0): (t1-t0)/dt projection steps in place on the batch y."""
+        return self._prop(lib().nsp_fine_step, y, t0, t1, dt, opts, check)
+
+    def coarse_step(self, y, t0, t1, DT, opts=None, check=True):
+        """G(y, t1, t0): (t1-t0)/DT projection steps in place on the batch y."""
+        return self._prop(lib().nsp_coarse_step, y, t0, t1, DT, opts, check)
+
+    def parareal_start(self, Y, Gk, nslices, t0, T, DT, coarse=None):
+        coarse = coarse or PoissonOpts()
+        o = coarse.c()
+        st = lib().nsp_parareal_start(self._h, self._state(Y, nslices + 1, "Y"), self._state(Gk, nslices, "Gk"),
+                                      int(nslices), float(t0), float(T), float(DT), ctypes.byref(o), _stream_ptr())
+        self._err(st, "nsp_parareal_start")
+
+    def parareal_iterate(self, Y, Fk, Gk, nslices, k, t0, T, dt, DT, fine=None, coarse=None):
+        """Iteration k of Eq. (6); returns (velocity jump, pressure jump)."""
+        fine = fine or PoissonOpts()
+        coarse = coarse or PoissonOpts()
+        of, oc = fine.c(), coarse.c()
+        jump = (ctypes.c_double * 2)()
+        st = lib().nsp_parareal_iterate(self._h, self._state(Y, nslices + 1, "Y"), self._state(Fk, nslices, "Fk"),
+                                        self._state(Gk, nslices, "Gk"), int(nslices), int(k), float(t0), float(T),
+                                        float(dt), float(DT), ctypes.byref(of), ctypes.byref(oc), _stream_ptr(),
+                                        jump)
+        self._err(st, "nsp_parareal_iterate")
+        return float(jump[0]), float(jump[1])
+
+    def set_launch(self, workgroups):
+        self._err(lib().nsp_set_launch(self._h, int(workgroups)), "nsp_set_launch")
+
+    def autotune(self, batch, prec=FP64):
+        ch = ctypes.c_int()
+        self._err(lib().nsp_autotune(self._h, int(batch), int(prec), _stream_ptr(), ctypes.byref(ch)),
+                  "nsp_autotune")
+        return ch.value
+
+    def last_launch_ms(self):
+        ms = ctypes.c_double()
+        self._err(lib().nsp_last_launch_ms(self._h, ctypes.byref(ms)), "nsp_last_launch_ms")
+        return ms.value
+
+
+def _info_dict(x):
+    return dict(iters=x.iters, max_iters=x.max_iters, outer=x.outer, status=x.status,
+                rel_res_true=x.rel_res_true, div_l2=x.div_l2)
+
+
+def _group_arrays(handles, states, nslices_each, names=("y",)):
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[h.ptr for h in handles])
+    arrs = []
+    for name, st_list in zip(names, states):
+        arr = (_State * n)()
+        for g, (h, y) in enumerate(zip(handles, st_list)):
+            arr[g] = h._state(y, nslices_each[g] if isinstance(nslices_each, (list, tuple)) else nslices_each, name)
+        arrs.append(arr)
+    return hs, arrs
+
+
+def group_fine_step(handles, ys, t0, t1, dt, opts=None, check=True):
+    """F over several grids (an uneven batch) in one launch."""
+    opts = opts or PoissonOpts()
+    batches = [int(y[0].shape[0]) for y in ys]
+    hs, (arr,) = _group_arrays(handles, [ys], batches)
+    bat = (ctypes.c_int * len(handles))(*batches)
+    info = (_Info * sum(batches))()
+    o = opts.c()
+    st = lib().nsp_group_fine_step(hs, arr, bat, len(handles), float(t0), float(t1), float(dt), ctypes.byref(o),
+                                   _stream_ptr(), info)
+    res = [_info_dict(x) for x in info]
+    if check:
+        handles[0]._err(st, "nsp_group_fine_step", res)
+    return res
+
+
+def group_parareal_start(handles, Ys, Gks, nslices, t0, T, DT, coarse=None):
+    coarse = coarse or PoissonOpts()
+    o = coarse.c()
+    n = len(handles)
+    hs, (ya,) = _group_arrays(handles, [Ys], [nslices + 1] * n, ("Y",))
+    _, (ga,) = _group_arrays(handles, [Gks], [nslices] * n, ("Gk",))
+    st = lib().nsp_group_parareal_start(hs, ya, ga, n, int(nslices), float(t0), float(T), float(DT),
+                                        ctypes.byref(o), _stream_ptr())
+    handles[0]._err(st, "nsp_group_parareal_start")
+
+
+def group_parareal_iterate(handles, Ys, Fks, Gks, nslices, k, t0, T, dt, DT, fine=None, coarse=None):
+    """Iteration k over several grids; returns [(velocity jump, pressure jump)] per grid."""
+    fine = fine or PoissonOpts()
+    coarse = coarse or PoissonOpts()
+    of, oc = fine.c(), coarse.c()
+    n = len(handles)
+    hs, (ya,) = _group_arrays(handles, [Ys], [nslices + 1] * n, ("Y",))
+    _, (fa,) = _group_arrays(handles, [Fks], [nslices] * n, ("Fk",))
+    _, (ga,) = _group_arrays(handles, [Gks], [nslices] * n, ("Gk",))
+    jump = (ctypes.c_double * (2 * n))()
+    st = lib().nsp_group_parareal_iterate(hs, ya, fa, ga, n, int(nslices), int(k), float(t0), float(T), float(dt),
+                                          float(DT), ctypes.byref(of), ctypes.byref(oc), _stream_ptr(), jump)
+    handles[0]._err(st, "nsp_group_parareal_iterate")
+    return [(float(jump[2 * g]), float(jump[2 * g + 1])) for g in range(n)]
+
+
+EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
+            "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
+            "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
+            "nsp_last_launch_ms")
