@@ -82,11 +82,12 @@ hipError_t dalloc(T **p, size_t n) {
     return hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
 }
 
-// Tile size: a power of two between 256 and 2048 cells, about ncells/128,
-// fixed by the grid alone so that reductions never depend on the batch.
+// Tile size: a power of two between kBlock and 8 kBlock cells, about
+// ncells/128, fixed by the grid alone so that reductions never depend on
+// the batch.
 int tile_for(long long ncells) {
-    long long t = 256;
-    while (t * 2 <= ncells / 128 && t < 2048) t *= 2;
+    long long t = kBlock;
+    while (t * 2 <= ncells / 128 && t < 8 * kBlock) t *= 2;
     return (int)t;
 }
 
@@ -305,12 +306,12 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     HIPCHK(h, launch_persistent(h->L.params, wg, stream));
     HIPCHK(h, hipEventRecord(h->ev1, stream));
     HIPCHK(h, hipMemcpyAsync(h->L.ctl_host, h->L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost, stream));
-    SyncWords sw;
-    HIPCHK(h, hipMemcpyAsync(&sw.any, &h->L.sync->any, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    int aborted = 0;
+    HIPCHK(h, hipMemcpyAsync(&aborted, &h->L.sync->abort, sizeof(int), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
     float ms = 0;
     if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
-    if (sw.abort) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
+    if (aborted) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
     int worst = 0;
     for (int s = 0; s < nslices; ++s) {
         const SliceCtl &c = h->L.ctl_host[s];

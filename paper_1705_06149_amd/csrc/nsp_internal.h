@@ -7,7 +7,8 @@
 
 namespace nsp {
 
-constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kBlock = 1024;     // threads per workgroup (16 wave64)
+constexpr int kWaves = kBlock / 64;
 constexpr int kMaxGroups = 4;    // grids per launch (uneven batch)
 constexpr int kMaxSlices = 64;   // slices per launch
 constexpr int kNQ = 4;           // partial sums per tile
@@ -61,17 +62,26 @@ struct SliceCtl {
     int done;     // current solve finished for this slice
     int status;   // worst status over the call
     int step_status; // status of the current solve
+    int flag;     // this slice's contribution to the control word
     int tot_it, max_it, tot_outer;
 };
 
+// Grid-barrier words.  Every workgroup announces its arrival by storing the
+// barrier's epoch into its own 128-byte line (plain stores: contended
+// device-scope atomics on one address serialize at ~0.4 us each on this
+// part); per-slice reducer workgroups wait for all arrivals, reduce, and
+// store the epoch into their own "done" line; workgroup 0 waits for the
+// reducers, ORs their control flags and publishes one go-word, replicated
+// over 64 lines so that the pollers do not all hit one address.
+constexpr int kMaxWG = 2048;  // workgroups per launch
+constexpr int kLine = 32;     // 32 words = 128 bytes
+constexpr int kGoCopies = 64;
 struct SyncWords {
-    unsigned count;    // arrivals at the current barrier
-    unsigned pad0[63];
-    unsigned gen;      // barrier generation
-    unsigned pad1[63];
-    int any;           // control word published by the reducing workgroup
+    unsigned arrive[kMaxWG * kLine];
+    unsigned done[(kMaxSlices + 1) * kLine];
+    unsigned go[kGoCopies * kLine];  // (epoch << 1) | control bit, replicated
     int abort;         // set when a barrier wait exceeds its spin limit
-    int pad2[62];
+    int pad[kLine - 1];
 };
 
 enum Mode : int { MODE_FINE = 0, MODE_POISSON = 1 };

@@ -14,17 +14,28 @@
 // tile writes its own partial sums (fixed-order wave64 butterflies, then a
 // fixed combination of the four waves), so every reduction result depends
 // only on the grid, never on the launch shape or on the batch it shares.
-// Between phases all workgroups meet at a grid barrier; the last one to
-// arrive sums the tile partials per slice in a fixed order, runs the CG
-// scalar logic (alpha, beta, convergence) for every slice and publishes a
-// control word, then releases the barrier.
+// Between phases all workgroups meet at a grid barrier built from plain
+// flag stores: one reducer workgroup per slice waits for every arrival, sums
+// that slice's tile partials in a fixed order, runs the CG scalar logic
+// (alpha, beta, convergence) and flags itself done; every workgroup waits
+// for the reducers and ORs the slices' control flags.
 #include "nsp_internal.h"
 
 namespace nsp {
 
 namespace {
 
-constexpr unsigned kSpinLimit = 1u << 23;  // ~seconds: a wait this long means something is broken
+constexpr unsigned kSpinLimit = 1u << 23;
+
+// Pointers taken from the parameter block are generic; accesses through them
+// would be flat instructions (which also wait on LDS traffic).  Everything
+// the kernels touch lives in device global memory, so cast first.
+#define GAS __attribute__((address_space(1)))
+#define LAS __attribute__((address_space(3)))
+template <class T>
+__device__ __forceinline__ GAS T *gp(T *p) { return (GAS T *)p; }
+template <class T>
+__device__ __forceinline__ const GAS T *gp(const T *p) { return (const GAS T *)p; }  // ~seconds: a wait this long means something is broken
 
 enum Red : int {
     R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32
@@ -40,7 +51,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 struct IJK { int i, j, k; };
 
-__device__ __forceinline__ IJK decomp(const GroupDesc &G, int c) {
+__device__ __forceinline__ IJK decomp(const GAS GroupDesc &G, int c) {
     IJK r;
     int t = c / G.nx;
     r.i = c - t * G.nx;
@@ -51,22 +62,22 @@ __device__ __forceinline__ IJK decomp(const GroupDesc &G, int c) {
 
 // extent of component C's face array along direction D
 template <int C, int D>
-__device__ __forceinline__ int fext(const GroupDesc &G) {
+__device__ __forceinline__ int fext(const GAS GroupDesc &G) {
     int n = D == 0 ? G.nx : (D == 1 ? G.ny : G.nz);
     return n + (C == D ? 1 : 0);
 }
 
 template <int C>
-__device__ __forceinline__ long fidx(const GroupDesc &G, int i, int j, int k) {
+__device__ __forceinline__ long fidx(const GAS GroupDesc &G, int i, int j, int k) {
     return ((long)k * fext<C, 1>(G) + j) * fext<C, 0>(G) + i;
 }
 
 template <int C, int D>
-__device__ __forceinline__ long fstride(const GroupDesc &G) {
+__device__ __forceinline__ long fstride(const GAS GroupDesc &G) {
     return D == 0 ? 1L : (D == 1 ? (long)fext<C, 0>(G) : (long)fext<C, 0>(G) * fext<C, 1>(G));
 }
 
-__device__ __forceinline__ long cidx(const GroupDesc &G, int i, int j, int k) {
+__device__ __forceinline__ long cidx(const GAS GroupDesc &G, int i, int j, int k) {
     return ((long)k * G.ny + j) * G.nx + i;
 }
 
@@ -74,18 +85,18 @@ __device__ __forceinline__ long cidx(const GroupDesc &G, int i, int j, int k) {
 // it is open when both are fluid cells, which the cell's own "minus" bit
 // records.  Positions outside the face array are not open.
 template <int C>
-__device__ __forceinline__ bool face_open(const GroupDesc &G, int i, int j, int k) {
+__device__ __forceinline__ bool face_open(const GAS GroupDesc &G, int i, int j, int k) {
     if (i < 0 || j < 0 || k < 0) return false;
     if (i >= G.nx || j >= G.ny || k >= G.nz) return false;  // includes the high boundary face
     const uint8_t bit = C == 0 ? FL_XM : (C == 1 ? FL_YM : FL_ZM);
-    return (G.flags[cidx(G, i, j, k)] & bit) != 0;
+    return (gp(G.flags)[cidx(G, i, j, k)] & bit) != 0;
 }
 
 // Wall value beyond the open face (i,j,k) of component C in direction D,
 // sense S: only u sees the lid, across the top boundary.
 template <int C, int D>
-__device__ __forceinline__ double wall_value(const GroupDesc &G, int i, int j, int k, int S) {
-    if (C == 0 && D == 1 && S > 0 && j == G.ny - 1) return G.lid[(long)k * (G.nx + 1) + i];
+__device__ __forceinline__ double wall_value(const GAS GroupDesc &G, int i, int j, int k, int S) {
+    if (C == 0 && D == 1 && S > 0 && j == G.ny - 1) return gp(G.lid)[(long)k * (G.nx + 1) + i];
     return 0.0;
 }
 
@@ -115,7 +126,7 @@ __device__ __forceinline__ double smart_face(double U, double C, double D) {
 // no-slip wall half a cell away, image 2*wall - mirror, with the mirror
 // itself resolved first (one-cell gaps).
 template <bool FAST, int C, int D>
-__device__ __forceinline__ void line_values(const GroupDesc &G, const double *__restrict__ phi, int i, int j,
+__device__ __forceinline__ void line_values(const GAS GroupDesc &G, const GAS double *__restrict__ phi, int i, int j,
                                             int k, long id, double phi0, double &vm2, double &vm1, double &vp1,
                                             double &vp2) {
     const long s = fstride<C, D>(G);
@@ -150,7 +161,7 @@ __device__ __forceinline__ void line_values(const GroupDesc &G, const double *__
 
 // real value of component D at face (i,j,k): closed faces hold 0
 template <bool FAST, int D>
-__device__ __forceinline__ double real_face(const GroupDesc &G, const double *__restrict__ a, int i, int j, int k) {
+__device__ __forceinline__ double real_face(const GAS GroupDesc &G, const GAS double *__restrict__ a, int i, int j, int k) {
     if (FAST) return a[fidx<D>(G, i, j, k)];
     return face_open<D>(G, i, j, k) ? a[fidx<D>(G, i, j, k)] : 0.0;
 }
@@ -158,9 +169,9 @@ __device__ __forceinline__ double real_face(const GroupDesc &G, const double *__
 // Contribution of direction D to the convective and diffusive terms at the
 // open face (i,j,k) of component C.
 template <bool FAST, int C, int D>
-__device__ __forceinline__ void dir_terms(const GroupDesc &G, const double *__restrict__ const *vel, int i, int j,
+__device__ __forceinline__ void dir_terms(const GAS GroupDesc &G, const GAS double *const *vel, int i, int j,
                                           int k, long id, double phi0, double &conv, double &lap) {
-    const double *__restrict__ phi = vel[C];
+    const GAS double *phi = vel[C];
     double vm2, vm1, vp1, vp2;
     line_values<FAST, C, D>(G, phi, i, j, k, id, phi0, vm2, vm1, vp1, vp2);
     double ap, am;
@@ -183,7 +194,7 @@ __device__ __forceinline__ void dir_terms(const GroupDesc &G, const double *__re
 }
 
 template <bool FAST, int C>
-__device__ __forceinline__ double predictor(const GroupDesc &G, const double *__restrict__ const *vel, int i, int j,
+__device__ __forceinline__ double predictor(const GAS GroupDesc &G, const GAS double *const *vel, int i, int j,
                                             int k, double dt) {
     const long id = fidx<C>(G, i, j, k);
     const double phi0 = vel[C][id];
@@ -197,24 +208,34 @@ __device__ __forceinline__ double predictor(const GroupDesc &G, const double *__
 // ------------------------------------------------------------ the runner
 
 struct Runner {
-    const KParams &P;
+    const GAS KParams &P;
     int tb, te;            // my tile range
-    double *s_red;         // [4 * kNQ] wave partials
-    double *s_sums;        // [kMaxSlices * kNQ]
-    int *s_int;            // [kBlock] scratch ints
-    const double *s_idg;   // [kMaxGroups * 64]
-    const float *s_idg32;  // [kMaxGroups * 64]
+    LAS double *s_red;     // [kWaves * kNQ] wave partials
+    const LAS double *s_idg;   // [kMaxGroups * 64]
+    const LAS float *s_idg32;  // [kMaxGroups * 64]
 
-    __device__ void locate(int t, int &gi, int &sl) const {
+    __device__ __forceinline__ void locate(int t, int &gi, int &sl) const {
         gi = 0;
         while (gi + 1 < P.ngroups && t >= P.g[gi + 1].tile0) ++gi;
         sl = (t - P.g[gi].tile0) / P.g[gi].ntiles;
     }
 
+    // fixed pairwise tree over the per-wave sums of quantity q
+    __device__ __forceinline__ double combine_waves(int q) const {
+        double w[kWaves];
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i) w[i] = s_red[i * kNQ + q];
+#pragma unroll
+        for (int span = 1; span < kWaves; span *= 2)
+#pragma unroll
+            for (int i = 0; i + span < kWaves; i += 2 * span) w[i] = w[i] + w[i + span];
+        return w[0];
+    }
+
     // Sum the NQ per-thread values over the workgroup in a fixed order and
     // store them as tile t's partials.
     template <int NQ>
-    __device__ void store_partials(double (&acc)[NQ], int t) {
+    __device__ __forceinline__ void store_partials(double (&acc)[NQ], int t) {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -224,8 +245,8 @@ struct Runner {
         __syncthreads();
         if (threadIdx.x < NQ) {
             const int q = threadIdx.x;
-            double v = (s_red[0 * kNQ + q] + s_red[1 * kNQ + q]) + (s_red[2 * kNQ + q] + s_red[3 * kNQ + q]);
-            P.part[(long)q * P.ntiles + t] = v;
+            double v = combine_waves(q);
+            gp(P.part)[(long)q * P.ntiles + t] = v;
         }
         __syncthreads();
     }
@@ -233,11 +254,11 @@ struct Runner {
     // Loop over my tiles; `skip(G, gs)` is uniform per tile; `body(G, sl,
     // gs, c, acc)` handles cell c of local slice sl (global slice gs).
     template <int NQ, class Skip, class Body>
-    __device__ void tiles(Skip skip, Body body) {
+    __device__ __forceinline__ void tiles(Skip skip, Body body) {
         for (int t = tb; t < te; ++t) {
             int gi, sl;
             locate(t, gi, sl);
-            const GroupDesc &G = P.g[gi];
+            const GAS GroupDesc &G = P.g[gi];
             const int gs = G.slice0 + sl;
             if (skip(G, gs)) continue;
             constexpr int NA = NQ > 0 ? NQ : 1;
@@ -254,99 +275,154 @@ struct Runner {
 
     // ------------------------------------------------------- grid barrier
 
-    __device__ __forceinline__ int load_any() const {
-        return __hip_atomic_load(&P.sync->any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned epoch = 0;
+
+    __device__ __forceinline__ bool aborted() const {
+        return __hip_atomic_load(&gp(P.sync)->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
 
-    // Barrier over the whole grid.  The last workgroup to arrive runs the
-    // reduction `rid`, publishes the control word, and releases the others.
-    // Returns the control word (uniform across the grid), or -1 on abort.
-    __device__ int sync(int rid) {
-        __shared__ int s_last;
-        __shared__ int s_abort;
+    // Wave 0 only: spin until w[i * kLine] >= e for every i < n (all lanes
+    // load their share each round, then vote); then one acquire fence for the
+    // workgroup.  False if the launch was abandoned.
+    __device__ __forceinline__ bool wave0_wait_all(const GAS unsigned *w, int n, unsigned e) const {
+        const int lane = threadIdx.x & 63;
+        unsigned spins = 0;
+        bool ok = true;
+        for (;;) {
+            int mine = 1;
+            for (int i = lane; i < n; i += 64)
+                mine &= __hip_atomic_load(&w[i * kLine], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= e;
+            if (__all(mine)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if ((++spins & 63u) == 0) {
+                if (aborted()) { ok = false; break; }
+                if (spins > kSpinLimit) {
+                    __hip_atomic_store(&gp(P.sync)->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        return ok;
+    }
+
+    __device__ __forceinline__ static int nq_of(int rid) {
+        switch (rid) {
+        case R_MEANB: case R_A: case R_A32: return 1;
+        case R_B: case R_B32: case R_CAST: return 2;
+        case R_INIT: case R_TRUE: case R_OUT: return 3;
+        case R_OUT0: return 4;
+        default: return 0;
+        }
+    }
+
+    // Fixed-order sum of slice s's tile partials (lane l takes tiles l,
+    // l+256, ...; then the wave butterfly and a fixed four-wave combine),
+    // then the CG scalar logic for the slice.  Whole workgroup.
+    __device__ __forceinline__ void reduce_slice(int rid, int s) {
+        const int nq = nq_of(rid);
+        int gi = 0;
+        while (gi + 1 < P.ngroups && s >= P.g[gi + 1].slice0) ++gi;
+        const GAS GroupDesc &G = P.g[gi];
+        const long t0 = G.tile0 + (long)(s - G.slice0) * G.ntiles;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int q = 0; q < nq; ++q) {
+            const GAS double GAS *pp = gp(P.part) + (long)q * P.ntiles + t0;
+            double v = 0.0;
+            for (int t = threadIdx.x; t < G.ntiles; t += kBlock) v += pp[t];
+            v = wave_sum(v);
+            if (lane == 0) s_red[wv * kNQ + q] = v;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            SyncWords *S = P.sync;
-            __threadfence();
-            const unsigned g = __hip_atomic_load(&S->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned a = __hip_atomic_fetch_add(&S->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            const int last = (a == gridDim.x - 1);
-            int ab = 0;
-            if (!last) {
-                unsigned spins = 0;
-                while (__hip_atomic_load(&S->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if ((++spins & 255u) == 0) {
-                        if (__hip_atomic_load(&S->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
+            double S[kNQ] = {0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < nq; ++q)
+                S[q] = combine_waves(q);
+            P.ctl[s].flag = control(rid, s, S, G.nfluid);
+        }
+        __syncthreads();
+    }
+
+    // Grid barrier.  Returns the control word (the OR of the reduced slices'
+    // flags; uniform across the grid), or -1 if the launch was abandoned.
+    // Each workgroup releases once on arrival (thread 0) and acquires once
+    // (wave 0, after it has seen the flag it polls).
+    __device__ __forceinline__ int sync(int rid) {
+        __shared__ int s_ok, s_ok2, s_go;
+        const unsigned e = ++epoch;
+        GAS SyncWords *S = gp(P.sync);
+        const int nred = rid == R_NONE ? 1 : P.nslices;
+        const bool wave0 = threadIdx.x < 64;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();  // release this workgroup's results
+            __hip_atomic_store(&S->arrive[blockIdx.x * kLine], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if ((int)blockIdx.x < nred) {
+            // reducer: every arrival, then this workgroup's slices
+            if (wave0) {
+                const bool ok = wave0_wait_all(S->arrive, gridDim.x, e);
+                if (threadIdx.x == 0) s_ok = ok;
+            }
+            __syncthreads();
+            if (!s_ok) return -1;
+            if (rid != R_NONE)
+                for (int sl = blockIdx.x; sl < nred; sl += gridDim.x) reduce_slice(rid, sl);
+            if (threadIdx.x == 0 && blockIdx.x != 0) {
+                __threadfence();
+                __hip_atomic_store(&S->done[blockIdx.x * kLine], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (blockIdx.x == 0) {
+                // master: the other reducers, then publish the go-word
+                if (wave0) {
+                    bool ok = true;
+                    const int others = min(nred, (int)gridDim.x);
+                    if (others > 1) ok = wave0_wait_all(S->done + kLine, others - 1, e);
+                    int f = 0;
+                    if (rid != R_NONE)
+                        for (int s2 = threadIdx.x; s2 < P.nslices; s2 += 64)
+                            f |= __hip_atomic_load(&gp(P.ctl)[s2].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int any = __any(f) ? 1 : 0;
+                    if (!ok) { if (threadIdx.x == 0) s_ok2 = 0; }
+                    else {
+                        __threadfence();
+                        __hip_atomic_store(&S->go[threadIdx.x * kLine], (e << 1) | (unsigned)any, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+        }
+        if (wave0) {
+            // everyone: the go-word copy of this workgroup
+            bool ok = true;
+            unsigned v = 0, spins = 0;
+            const GAS unsigned *gw = &S->go[(blockIdx.x % kGoCopies) * kLine];
+            if (threadIdx.x == 0) {
+                for (;;) {
+                    v = __hip_atomic_load(gw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((v >> 1) >= e) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((++spins & 63u) == 0) {
+                        if (aborted()) { ok = false; break; }
                         if (spins > kSpinLimit) {
                             __hip_atomic_store(&S->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ab = 1;
+                            ok = false;
                             break;
                         }
                     }
                 }
+                s_ok2 = ok;
+                s_go = (int)(v & 1u);
             }
-            __threadfence();
-            s_last = last;
-            s_abort = ab;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (s_last) {
-            reduce(rid);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                SyncWords *S = P.sync;
-                __threadfence();
-                __hip_atomic_store(&S->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&S->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        if (s_abort) return -1;
-        __syncthreads();
-        if (__hip_atomic_load(&P.sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
-        return load_any();
+        if (!s_ok2) return -1;
+        return rid == R_NONE ? 0 : s_go;
     }
 
-    // Per-slice sums of nq partial quantities into s_sums, in a fixed order:
-    // eight lanes per slice, lane l summing tiles l, l+8, ..., then an xor
-    // butterfly over the eight lanes.
-    __device__ void slice_sums(int nq) {
-        for (int sb = 0; sb < P.nslices; sb += kBlock / 8) {
-            const int s = sb + (int)threadIdx.x / 8, l = threadIdx.x & 7;
-            double a[kNQ] = {0.0, 0.0, 0.0, 0.0};
-            if (s < P.nslices) {
-                int gi = 0;
-                while (gi + 1 < P.ngroups && s >= P.g[gi + 1].slice0) ++gi;
-                const GroupDesc &G = P.g[gi];
-                const int t0 = G.tile0 + (s - G.slice0) * G.ntiles;
-                for (int q = 0; q < nq; ++q) {
-                    const double *pp = P.part + (long)q * P.ntiles + t0;
-                    double v = 0.0;
-#pragma unroll 4
-                    for (int t = l; t < G.ntiles; t += 8) v += pp[t];
-                    a[q] = v;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kNQ; ++q) {
-                a[q] += __shfl_xor(a[q], 4, 64);
-                a[q] += __shfl_xor(a[q], 2, 64);
-                a[q] += __shfl_xor(a[q], 1, 64);
-            }
-            if (l == 0 && s < P.nslices)
-                for (int q = 0; q < kNQ; ++q) s_sums[s * kNQ + q] = a[q];
-        }
-        __syncthreads();
-    }
-
-    __device__ double nfluid_of(int s) const {
-        int gi = 0;
-        while (gi + 1 < P.ngroups && s >= P.g[gi + 1].slice0) ++gi;
-        return P.g[gi].nfluid;
-    }
-
-    __device__ void finish_solve(SliceCtl &c) {
+    __device__ __forceinline__ void finish_solve(GAS SliceCtl &c) {
         c.done = 1;
         c.status = max(c.status, c.step_status);
         c.tot_it += c.it;
@@ -356,10 +432,8 @@ struct Runner {
 
     // CG scalar logic for one slice after reduction rid; returns this
     // slice's contribution to the control word.
-    __device__ int control(int rid, int s) {
-        SliceCtl &c = P.ctl[s];
-        const double *S = s_sums + s * kNQ;
-        const double nf = nfluid_of(s);
+    __device__ __forceinline__ int control(int rid, int s, const double *S, double nf) {
+        GAS SliceCtl &c = gp(P.ctl)[s];
         switch (rid) {
         case R_MEANB:
             c.mean_b = S[0] / nf;
@@ -481,49 +555,23 @@ struct Runner {
         }
     }
 
-    __device__ void reduce(int rid) {
-        if (rid == R_NONE) {
-            if (threadIdx.x == 0) __hip_atomic_store(&P.sync->any, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
-        int nq = 0;
-        switch (rid) {
-        case R_MEANB: nq = 1; break;
-        case R_A: case R_A32: nq = 1; break;
-        case R_B: case R_B32: case R_CAST: nq = 2; break;
-        case R_INIT: case R_TRUE: nq = 3; break;
-        case R_OUT: nq = 3; break;
-        case R_OUT0: nq = 4; break;
-        }
-        slice_sums(nq);
-        int f = 0;
-        if ((int)threadIdx.x < P.nslices) f = control(rid, threadIdx.x);
-        s_int[threadIdx.x] = f;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int any = 0;
-            for (int s = 0; s < P.nslices; ++s) any |= s_int[s];
-            __hip_atomic_store(&P.sync->any, any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-
     // ------------------------------------------------------------- phases
 
-    __device__ const SliceCtl &ctl(int gs) const { return P.ctl[gs]; }
+    __device__ __forceinline__ const GAS SliceCtl &ctl(int gs) const { return gp(P.ctl)[gs]; }
 
     // pressure after the gauge fix of the last solve
-    __device__ __forceinline__ double p_eff(const SliceCtl &c, double p, bool fluid) const {
+    __device__ __forceinline__ double p_eff(const GAS SliceCtl &c, double p, bool fluid) const {
         if (c.zero) return 0.0;
         return fluid ? p - c.mean_p : p;
     }
 
-    __device__ void phase_mom(bool gauge) {
-        tiles<0>([](const GroupDesc &, int) { return false; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *) {
+    __device__ __forceinline__ void phase_mom(bool gauge) {
+        tiles<0>([](const GAS GroupDesc &, int) { return false; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *) {
                      const IJK x = decomp(G, c);
-                     const uint8_t fl = G.flags[c];
-                     const double *vel[3] = {G.u + (long)sl * G.nu, G.v + (long)sl * G.nv, G.w + (long)sl * G.nw};
-                     double *Fu = G.Fu + (long)sl * G.nu, *Fv = G.Fv + (long)sl * G.nv, *Fw = G.Fw + (long)sl * G.nw;
+                     const uint8_t fl = gp(G.flags)[c];
+                     const GAS double *vel[3] = {gp(G.u) + (long)sl * G.nu, gp(G.v) + (long)sl * G.nv, gp(G.w) + (long)sl * G.nw};
+                     double GAS *Fu = gp(G.Fu) + (long)sl * G.nu, *Fv = gp(G.Fv) + (long)sl * G.nv, *Fw = gp(G.Fw) + (long)sl * G.nw;
                      double fu = 0.0, fv = 0.0, fw = 0.0;
                      if (!(fl & FL_SLOW)) {
                          fu = predictor<true, 0>(G, vel, x.i, x.j, x.k, P.dt);
@@ -541,28 +589,28 @@ struct Runner {
                      if (x.j == G.ny - 1) Fv[fidx<1>(G, x.i, G.ny, x.k)] = 0.0;
                      if (x.k == G.nz - 1) Fw[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
                      if (gauge) {
-                         double *p = G.p + (long)sl * G.ncells;
+                         double GAS *p = gp(G.p) + (long)sl * G.ncells;
                          p[c] = p_eff(ctl(gs), p[c], fl & FL_FLUID);
                      }
                  });
     }
 
-    __device__ void phase_gauge() {
-        tiles<0>([](const GroupDesc &, int) { return false; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *) {
-                     double *p = G.p + (long)sl * G.ncells;
-                     p[c] = p_eff(ctl(gs), p[c], G.flags[c] & FL_FLUID);
+    __device__ __forceinline__ void phase_gauge() {
+        tiles<0>([](const GAS GroupDesc &, int) { return false; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *) {
+                     double GAS *p = gp(G.p) + (long)sl * G.ncells;
+                     p[c] = p_eff(ctl(gs), p[c], gp(G.flags)[c] & FL_FLUID);
                  });
     }
 
-    __device__ void phase_rhs() {
-        tiles<1>([](const GroupDesc &, int) { return false; },
-                 [&](const GroupDesc &G, int sl, int, int c, double *acc) {
-                     double *b = G.b + (long)sl * G.ncells;
-                     if (!(G.flags[c] & FL_FLUID)) { b[c] = 0.0; return; }
+    __device__ __forceinline__ void phase_rhs() {
+        tiles<1>([](const GAS GroupDesc &, int) { return false; },
+                 [&](const GAS GroupDesc &G, int sl, int, int c, double *acc) {
+                     double GAS *b = gp(G.b) + (long)sl * G.ncells;
+                     if (!(gp(G.flags)[c] & FL_FLUID)) { b[c] = 0.0; return; }
                      const IJK x = decomp(G, c);
-                     const double *Fu = G.Fu + (long)sl * G.nu, *Fv = G.Fv + (long)sl * G.nv,
-                                  *Fw = G.Fw + (long)sl * G.nw;
+                     const double GAS *Fu = gp(G.Fu) + (long)sl * G.nu, *Fv = gp(G.Fv) + (long)sl * G.nv,
+                                  *Fw = gp(G.Fw) + (long)sl * G.nw;
                      const long iu = fidx<0>(G, x.i, x.j, x.k), iv = fidx<1>(G, x.i, x.j, x.k),
                                 iw = fidx<2>(G, x.i, x.j, x.k);
                      double div = (Fu[iu + 1] - Fu[iu]) * G.ih[0];
@@ -575,16 +623,16 @@ struct Runner {
     }
 
     // Poisson mode: mean of the caller's right-hand side
-    __device__ void phase_meanb_user() {
-        tiles<1>([](const GroupDesc &, int) { return false; },
-                 [&](const GroupDesc &G, int sl, int, int c, double *acc) {
-                     if (G.flags[c] & FL_FLUID) acc[0] += G.bin[(long)sl * G.ncells + c];
+    __device__ __forceinline__ void phase_meanb_user() {
+        tiles<1>([](const GAS GroupDesc &, int) { return false; },
+                 [&](const GAS GroupDesc &G, int sl, int, int c, double *acc) {
+                     if (gp(G.flags)[c] & FL_FLUID) acc[0] += gp(G.bin)[(long)sl * G.ncells + c];
                  });
     }
 
     // (A x)_c over the open faces of cell c, in the order x-,x+,y-,y+,z-,z+
-    template <class T, class Get>
-    __device__ __forceinline__ T apply_A(const GroupDesc &G, int c, uint8_t fl, T xc, Get get, const T *ih2) const {
+    template <class T, class Get, class H>
+    __device__ __forceinline__ T apply_A(const GAS GroupDesc &G, int c, uint8_t fl, T xc, Get get, const H &ih2) const {
         T s = T(0);
         const long sy = G.nx, sz = (long)G.nx * G.ny;
         if (fl & FL_XM) s += (xc - get(c - 1)) * ih2[0];
@@ -596,21 +644,20 @@ struct Runner {
         return s;
     }
 
-    __device__ __forceinline__ const double *idg(int gi_base) const { return s_idg + gi_base; }
 
-    __device__ int group_index(const GroupDesc &G) const { return (int)(&G - P.g); }
+    __device__ __forceinline__ int group_index(const GAS GroupDesc &G) const { return (int)(&G - P.g); }
 
     // FP64 CG, initial residual: b -= mean_b (stored), r = b - A p.
     // partials: ||b||^2, ||r||^2, <r,z>
-    __device__ void phase_init64(bool from_user) {
-        tiles<3>([](const GroupDesc &, int) { return false; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+    __device__ __forceinline__ void phase_init64(bool from_user) {
+        tiles<3>([](const GAS GroupDesc &, int) { return false; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
                      const long off = (long)sl * G.ncells;
-                     double *b = G.b + off, *r = G.r + off;
-                     const double *p = G.p + off;
-                     const uint8_t fl = G.flags[c];
+                     double GAS *b = gp(G.b) + off, *r = gp(G.r) + off;
+                     const double GAS *p = gp(G.p) + off;
+                     const uint8_t fl = gp(G.flags)[c];
                      if (!(fl & FL_FLUID)) { b[c] = 0.0; r[c] = 0.0; return; }
-                     const double bsrc = from_user ? G.bin[off + c] : b[c];
+                     const double bsrc = from_user ? gp(G.bin)[off + c] : b[c];
                      const double bv = bsrc - ctl(gs).mean_b;
                      b[c] = bv;
                      const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
@@ -623,71 +670,177 @@ struct Runner {
                  });
     }
 
-    // q = A d_new with d_new = z + beta d_old (z = r/diag), recomputed for
-    // the neighbours from r and d_old; partial <d_new, q>.
+    // ------------------------------------------------------------ CG loop
+    //
+    // Per iteration two phases touch every cell once (bytes per cell, FP64 /
+    // FP32 vectors, flags 1 byte):
+    //   A: d_new = z + beta d_old, z = r/diag       read r, d_old  write d_new
+    //      partial <d_new, A d_new>                 (A d_new from neighbours'
+    //      d_new, recomputed from their r and d_old)
+    //   B: q = A d_new; p += alpha d_new; r -= alpha q; partials <r,z>, <r,r>
+    //                                                read p, d_new, r  write p, r
+    // = 66 B (FP64) / 34 B (FP32) per cell per iteration; q is never stored.
+    // Loads are unconditional (neighbour indices clamped into the slice) so
+    // the two cells a thread handles per round have all their loads in
+    // flight together; closed faces are masked afterwards.
+
     template <class T>
-    __device__ void phase_A(int par) {
-        tiles<1>([&](const GroupDesc &, int gs) { return !ctl(gs).active; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
-                     const long off = (long)sl * G.ncells;
-                     const T *r = reinterpret_cast<const T *>(G.r) + off;
-                     const T *dold = reinterpret_cast<const T *>(par ? G.d1 : G.d0) + off;
-                     T *dnew = reinterpret_cast<T *>(par ? G.d0 : G.d1) + off;
-                     T *q = reinterpret_cast<T *>(G.q) + off;
-                     const uint8_t fl = G.flags[c];
-                     if (!(fl & FL_FLUID)) { dnew[c] = T(0); q[c] = T(0); return; }
-                     const SliceCtl &cs = ctl(gs);
-                     const bool first = cs.first;
-                     const T beta = (T)cs.beta;
-                     const int gb = group_index(G) * 64;
-                     auto dn = [&](long n) -> T {
-                         const uint8_t f = G.flags[n];
-                         T z;
-                         if (sizeof(T) == 8) z = r[n] * (T)s_idg[gb + (f & FL_OPEN)];
-                         else z = r[n] * (T)s_idg32[gb + (f & FL_OPEN)];
-                         return first ? z : z + beta * dold[n];
-                     };
-                     const T dc = dn(c);
-                     T ih2[3];
-                     if (sizeof(T) == 8) { ih2[0] = (T)G.ih2[0]; ih2[1] = (T)G.ih2[1]; ih2[2] = (T)G.ih2[2]; }
-                     else { ih2[0] = (T)G.ih2f[0]; ih2[1] = (T)G.ih2f[1]; ih2[2] = (T)G.ih2f[2]; }
-                     const T qc = apply_A<T>(G, c, fl, dc, dn, ih2);
-                     dnew[c] = dc;
-                     q[c] = qc;
-                     acc[0] += (double)dc * (double)qc;
-                 });
+    __device__ __forceinline__ T ih2_of(const GAS GroupDesc &G, int d) const {
+        return sizeof(T) == 8 ? (T)G.ih2[d] : (T)G.ih2f[d];
     }
 
-    // FP64: p += alpha d; r -= alpha q.  partials <r,z>, ||r||^2
-    __device__ void phase_B64(int par) {
-        tiles<2>([&](const GroupDesc &, int gs) { return !ctl(gs).active; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
-                     const uint8_t fl = G.flags[c];
-                     if (!(fl & FL_FLUID)) return;
-                     const long off = (long)sl * G.ncells;
-                     const double *d = (par ? G.d0 : G.d1) + off;
-                     const double alpha = ctl(gs).alpha;
-                     double *p = G.p + off, *r = G.r + off;
-                     const double *q = G.q + off;
-                     p[c] = p[c] + alpha * d[c];
-                     const double rv = r[c] - alpha * q[c];
-                     r[c] = rv;
-                     const double z = rv * s_idg[group_index(G) * 64 + (fl & FL_OPEN)];
-                     acc[0] += rv * z;
-                     acc[1] += rv * rv;
-                 });
+    template <class T>
+    __device__ __forceinline__ T idg_of(int gb, uint8_t f) const {
+        return sizeof(T) == 8 ? (T)s_idg[gb + (f & FL_OPEN)] : (T)s_idg32[gb + (f & FL_OPEN)];
+    }
+
+    // one tile of phase A; returns this thread's share of <d_new, A d_new>
+    template <class T, bool FIRST>
+    __device__ __forceinline__ double tile_A(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ r,
+                             const GAS T *__restrict__ dold, GAS T *__restrict__ dnew, T beta, int base, int end) {
+        const int gb = group_index(G) * 64;
+        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        const long last = G.ncells - 1;
+        const long off[6] = {-1, 1, -sy, sy, -sz, sz};
+        const T h2[3] = {ih2_of<T>(G, 0), ih2_of<T>(G, 1), ih2_of<T>(G, 2)};
+        double acc = 0.0;
+        for (int c0 = base + (int)threadIdx.x; c0 < end; c0 += 2 * kBlock) {
+            const bool has1 = c0 + kBlock < end;
+            const long cc[2] = {c0, has1 ? c0 + kBlock : c0};
+            uint8_t f[2], fn[2][6];
+            T rc[2], dc[2], rn[2][6], dn[2][6];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                f[u] = fl[cc[u]];
+                rc[u] = r[cc[u]];
+                dc[u] = FIRST ? T(0) : dold[cc[u]];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    long n = cc[u] + off[k];
+                    n = n < 0 ? 0 : (n > last ? last : n);
+                    fn[u][k] = fl[n];
+                    rn[u][k] = r[n];
+                    dn[u][k] = FIRST ? T(0) : dold[n];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const T d0 = FIRST ? rc[u] * idg_of<T>(gb, f[u]) : rc[u] * idg_of<T>(gb, f[u]) + beta * dc[u];
+                T q = T(0);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const T dk = FIRST ? rn[u][k] * idg_of<T>(gb, fn[u][k])
+                                       : rn[u][k] * idg_of<T>(gb, fn[u][k]) + beta * dn[u][k];
+                    if (f[u] & (1 << k)) q += (d0 - dk) * h2[k >> 1];
+                }
+                if (u == 0 || has1) {
+                    dnew[cc[u]] = d0;
+                    acc += (double)d0 * (double)q;
+                }
+            }
+        }
+        return acc;
+    }
+
+    template <class T>
+    __device__ __forceinline__ void phase_A(int par) {
+        for (int t = tb; t < te; ++t) {
+            int gi, sl;
+            locate(t, gi, sl);
+            const GAS GroupDesc &G = P.g[gi];
+            const GAS SliceCtl &cs = ctl(G.slice0 + sl);
+            if (!cs.active) continue;
+            const long off = (long)sl * G.ncells;
+            const GAS T *r = gp(reinterpret_cast<const T *>(G.r)) + off;
+            const GAS T *dold = gp(reinterpret_cast<const T *>(par ? G.d1 : G.d0)) + off;
+            GAS T *dnew = gp(reinterpret_cast<T *>(par ? G.d0 : G.d1)) + off;
+            const int lt = t - G.tile0 - sl * G.ntiles;
+            const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+            double acc[1];
+            if (cs.first) acc[0] = tile_A<T, true>(G, gp(G.flags), r, dold, dnew, T(0), base, end);
+            else acc[0] = tile_A<T, false>(G, gp(G.flags), r, dold, dnew, (T)cs.beta, base, end);
+            store_partials<1>(acc, t);
+        }
+    }
+
+    // one tile of phase B: x is p (FP64) or e (FP32)
+    template <class T>
+    __device__ __forceinline__ void tile_B(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ d,
+                           GAS T *__restrict__ x, GAS T *__restrict__ r, T alpha, int base, int end, double (&acc)[2]) {
+        const int gb = group_index(G) * 64;
+        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        const long last = G.ncells - 1;
+        const long off[6] = {-1, 1, -sy, sy, -sz, sz};
+        const T h2[3] = {ih2_of<T>(G, 0), ih2_of<T>(G, 1), ih2_of<T>(G, 2)};
+        for (int c0 = base + (int)threadIdx.x; c0 < end; c0 += 2 * kBlock) {
+            const bool has1 = c0 + kBlock < end;
+            const long cc[2] = {c0, has1 ? c0 + kBlock : c0};
+            uint8_t f[2];
+            T dc[2], xc[2], rc[2], dn[2][6];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                f[u] = fl[cc[u]];
+                dc[u] = d[cc[u]];
+                xc[u] = x[cc[u]];
+                rc[u] = r[cc[u]];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    long n = cc[u] + off[k];
+                    n = n < 0 ? 0 : (n > last ? last : n);
+                    dn[u][k] = d[n];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                T q = T(0);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    if (f[u] & (1 << k)) q += (dc[u] - dn[u][k]) * h2[k >> 1];
+                const T xv = xc[u] + alpha * dc[u];
+                const T rv = rc[u] - alpha * q;
+                const T z = rv * idg_of<T>(gb, f[u]);
+                if (u == 0 || has1) {
+                    x[cc[u]] = xv;
+                    r[cc[u]] = rv;
+                    acc[0] += (double)rv * (double)z;
+                    acc[1] += (double)rv * (double)rv;
+                }
+            }
+        }
+    }
+
+    // FP64: p += alpha d; r -= alpha A d.  partials <r,z>, ||r||^2
+    // FP32 (inner solve of the mixed path): e += alpha d; r -= alpha A d.
+    template <class T>
+    __device__ __forceinline__ void phase_B(int par) {
+        for (int t = tb; t < te; ++t) {
+            int gi, sl;
+            locate(t, gi, sl);
+            const GAS GroupDesc &G = P.g[gi];
+            const GAS SliceCtl &cs = ctl(G.slice0 + sl);
+            if (!cs.active) continue;
+            const long off = (long)sl * G.ncells;
+            const GAS T *d = gp(reinterpret_cast<const T *>(par ? G.d0 : G.d1)) + off;
+            GAS T *x = gp(sizeof(T) == 8 ? reinterpret_cast<T *>(G.p) : reinterpret_cast<T *>(G.e)) + off;
+            GAS T *r = gp(reinterpret_cast<T *>(G.r)) + off;
+            const int lt = t - G.tile0 - sl * G.ntiles;
+            const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+            double acc[2] = {0.0, 0.0};
+            tile_B<T>(G, gp(G.flags), d, x, r, (T)cs.alpha, base, end, acc);
+            store_partials<2>(acc, t);
+        }
     }
 
     // FP64 true residual r = b - A p (stored for a restart).
     // partials ||r||^2, sum p, <r,z>
-    __device__ void phase_true64() {
-        tiles<3>([&](const GroupDesc &, int gs) { return ctl(gs).zero || ctl(gs).done; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
-                     const uint8_t fl = G.flags[c];
+    __device__ __forceinline__ void phase_true64() {
+        tiles<3>([&](const GAS GroupDesc &, int gs) { return ctl(gs).zero || ctl(gs).done; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const uint8_t fl = gp(G.flags)[c];
                      if (!(fl & FL_FLUID)) return;
                      const long off = (long)sl * G.ncells;
-                     const double *p = G.p + off, *b = G.b + off;
-                     double *r = G.r + off;
+                     const double GAS *p = gp(G.p) + off, *b = gp(G.b) + off;
+                     double GAS *r = gp(G.r) + off;
                      const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
                      const double rv = b[c] - ap;
                      r[c] = rv;
@@ -700,17 +853,17 @@ struct Runner {
 
     // Mixed: FP64 residual r = b - A p.  First sweep also makes b mean-free.
     // partials ||r||^2, sum r, sum p, ||b||^2
-    __device__ void phase_out(bool first, bool from_user) {
-        tiles<4>([&](const GroupDesc &, int gs) { return !first && (ctl(gs).done || ctl(gs).zero); },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+    __device__ __forceinline__ void phase_out(bool first, bool from_user) {
+        tiles<4>([&](const GAS GroupDesc &, int gs) { return !first && (ctl(gs).done || ctl(gs).zero); },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
                      const long off = (long)sl * G.ncells;
-                     double *b = G.b + off;
-                     const double *p = G.p + off;
-                     const uint8_t fl = G.flags[c];
+                     double GAS *b = gp(G.b) + off;
+                     const double GAS *p = gp(G.p) + off;
+                     const uint8_t fl = gp(G.flags)[c];
                      if (!(fl & FL_FLUID)) { if (first) b[c] = 0.0; return; }
                      double bv;
                      if (first) {
-                         const double bsrc = from_user ? G.bin[off + c] : b[c];
+                         const double bsrc = from_user ? gp(G.bin)[off + c] : b[c];
                          bv = bsrc - ctl(gs).mean_b;
                          b[c] = bv;
                      } else {
@@ -726,16 +879,16 @@ struct Runner {
     }
 
     // Mixed: r32 = fp32(r - mean r), e = 0.  partials ||r32||^2, <r32,z32>
-    __device__ void phase_cast() {
-        tiles<2>([&](const GroupDesc &, int gs) { return !ctl(gs).need; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
+    __device__ __forceinline__ void phase_cast() {
+        tiles<2>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).need; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
                      const long off = (long)sl * G.ncells;
-                     float *r32 = reinterpret_cast<float *>(G.r) + off;
-                     float *e = G.e + off;
-                     const uint8_t fl = G.flags[c];
+                     float GAS *r32 = gp(reinterpret_cast<float *>(G.r)) + off;
+                     float GAS *e = gp(G.e) + off;
+                     const uint8_t fl = gp(G.flags)[c];
                      e[c] = 0.0f;
                      if (!(fl & FL_FLUID)) { r32[c] = 0.0f; return; }
-                     const double *p = G.p + off, *b = G.b + off;
+                     const double GAS *p = gp(G.p) + off, *b = gp(G.b) + off;
                      const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
                      const double rv = b[c] - ap;
                      const float rf = (float)(rv - ctl(gs).mean_r);
@@ -746,49 +899,28 @@ struct Runner {
                  });
     }
 
-    // Mixed inner: e += alpha d; r -= alpha q (FP32).  partials <r,z>, ||r||^2
-    __device__ void phase_B32(int par) {
-        tiles<2>([&](const GroupDesc &, int gs) { return !ctl(gs).active; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *acc) {
-                     const uint8_t fl = G.flags[c];
-                     if (!(fl & FL_FLUID)) return;
-                     const long off = (long)sl * G.ncells;
-                     const float *d = reinterpret_cast<const float *>(par ? G.d0 : G.d1) + off;
-                     const float *q = reinterpret_cast<const float *>(G.q) + off;
-                     float *r = reinterpret_cast<float *>(G.r) + off;
-                     float *e = G.e + off;
-                     const float alpha = (float)ctl(gs).alpha;
-                     e[c] = e[c] + alpha * d[c];
-                     const float rv = r[c] - alpha * q[c];
-                     r[c] = rv;
-                     const float z = rv * s_idg32[group_index(G) * 64 + (fl & FL_OPEN)];
-                     acc[0] += (double)rv * (double)z;
-                     acc[1] += (double)rv * (double)rv;
-                 });
-    }
-
     // Mixed: p += fp64(e)
-    __device__ void phase_update() {
-        tiles<0>([&](const GroupDesc &, int gs) { return !ctl(gs).need; },
-                 [&](const GroupDesc &G, int sl, int, int c, double *) {
-                     if (!(G.flags[c] & FL_FLUID)) return;
+    __device__ __forceinline__ void phase_update() {
+        tiles<0>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).need; },
+                 [&](const GAS GroupDesc &G, int sl, int, int c, double *) {
+                     if (!(gp(G.flags)[c] & FL_FLUID)) return;
                      const long off = (long)sl * G.ncells;
-                     G.p[off + c] += (double)G.e[off + c];
+                     gp(G.p)[off + c] += (double)gp(G.e)[off + c];
                  });
     }
 
     // u = F - dt G p_eff on open faces, 0 on closed faces
-    __device__ void phase_corr() {
-        tiles<0>([](const GroupDesc &, int) { return false; },
-                 [&](const GroupDesc &G, int sl, int gs, int c, double *) {
+    __device__ __forceinline__ void phase_corr() {
+        tiles<0>([](const GAS GroupDesc &, int) { return false; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *) {
                      const IJK x = decomp(G, c);
-                     const uint8_t fl = G.flags[c];
-                     const SliceCtl &cs = ctl(gs);
+                     const uint8_t fl = gp(G.flags)[c];
+                     const GAS SliceCtl &cs = ctl(gs);
                      const long off = (long)sl * G.ncells;
-                     const double *p = G.p + off;
-                     double *u = G.u + (long)sl * G.nu, *v = G.v + (long)sl * G.nv, *w = G.w + (long)sl * G.nw;
-                     const double *Fu = G.Fu + (long)sl * G.nu, *Fv = G.Fv + (long)sl * G.nv,
-                                  *Fw = G.Fw + (long)sl * G.nw;
+                     const double GAS *p = gp(G.p) + off;
+                     double GAS *u = gp(G.u) + (long)sl * G.nu, *v = gp(G.v) + (long)sl * G.nv, *w = gp(G.w) + (long)sl * G.nw;
+                     const double GAS *Fu = gp(G.Fu) + (long)sl * G.nu, *Fv = gp(G.Fv) + (long)sl * G.nv,
+                                  *Fw = gp(G.Fw) + (long)sl * G.nw;
                      const long iu = fidx<0>(G, x.i, x.j, x.k), iv = fidx<1>(G, x.i, x.j, x.k),
                                 iw = fidx<2>(G, x.i, x.j, x.k);
                      const double pc = p_eff(cs, p[c], true);
@@ -805,7 +937,7 @@ struct Runner {
     // ---------------------------------------------------------- programs
 
     // returns false on abort
-    __device__ bool solve64(bool from_user) {
+    __device__ __forceinline__ bool solve64(bool from_user) {
         phase_init64(from_user);
         int any = sync(R_INIT);
         if (any < 0) return false;
@@ -815,7 +947,7 @@ struct Runner {
                 const int par = iter & 1;
                 phase_A<double>(par);
                 if (sync(R_A) < 0) return false;
-                phase_B64(par);
+                phase_B<double>(par);
                 any = sync(R_B);
                 if (any < 0) return false;
                 ++iter;
@@ -828,7 +960,7 @@ struct Runner {
         return true;
     }
 
-    __device__ bool solve_mixed(bool from_user) {
+    __device__ __forceinline__ bool solve_mixed(bool from_user) {
         phase_out(true, from_user);
         int any = sync(R_OUT0);
         if (any < 0) return false;
@@ -841,7 +973,7 @@ struct Runner {
                 const int par = iter & 1;
                 phase_A<float>(par);
                 if (sync(R_A32) < 0) return false;
-                phase_B32(par);
+                phase_B<float>(par);
                 act = sync(R_B32);
                 if (act < 0) return false;
                 ++iter;
@@ -855,7 +987,7 @@ struct Runner {
         return true;
     }
 
-    __device__ void run() {
+    __device__ __forceinline__ void run() {
         if (P.mode == MODE_POISSON) {
             phase_meanb_user();
             if (sync(R_MEANB) < 0) return;
@@ -886,10 +1018,8 @@ struct Runner {
 // the image-rule momentum path may spill instead.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_persistent(const KParams *__restrict__ Pp) {
-    const KParams &P = *Pp;
-    __shared__ double s_red[4 * kNQ];
-    __shared__ double s_sums[kMaxSlices * kNQ];
-    __shared__ int s_int[kBlock];
+    const GAS KParams &P = *gp(Pp);
+    __shared__ double s_red[kWaves * kNQ];
     __shared__ double s_idg[kMaxGroups * 64];
     __shared__ float s_idg32[kMaxGroups * 64];
     for (int x = threadIdx.x; x < P.ngroups * 64; x += kBlock) {
@@ -906,22 +1036,19 @@ k_persistent(const KParams *__restrict__ Pp) {
         const int x = b & 7, q = nb >> 3, rm = nb & 7;
         lb = x * q + min(x, rm) + (b >> 3);
     }
-    Runner R{P, (int)((long)lb * P.ntiles / nb), (int)((long)(lb + 1) * P.ntiles / nb), s_red, s_sums, s_int,
-             s_idg, s_idg32};
+    Runner R{P, (int)((long)lb * P.ntiles / nb), (int)((long)(lb + 1) * P.ntiles / nb), (LAS double *)s_red,
+             (const LAS double *)s_idg, (const LAS float *)s_idg32};
     R.run();
 }
 
 __global__ void k_reset_sync(SyncWords *s) {
-    if (threadIdx.x == 0) {
-        s->count = 0;
-        s->any = 0;
-        s->abort = 0;
-    }
+    unsigned *w = reinterpret_cast<unsigned *>(s);
+    const long n = sizeof(SyncWords) / sizeof(unsigned);
+    for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) w[x] = 0u;
 }
 
 __global__ void k_parareal_update(UpdateParams U) {
     // grid-stride over all segments, one segment at a time
-    double mx[2] = {0.0, 0.0};
     for (int si = 0; si < U.nseg; ++si) {
         const UpdateSeg &S = U.seg[si];
         double m = 0.0;
@@ -944,7 +1071,6 @@ __global__ void k_parareal_update(UpdateParams U) {
             const int slot = 2 * U.group_of_seg[si] + S.jslot;
             __hip_atomic_fetch_max(&U.jump[slot], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        (void)mx;
     }
 }
 
@@ -975,7 +1101,7 @@ hipError_t max_coresident_workgroups(int device, int *out) {
 }
 
 hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream) {
-    hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, stream, s);
+    hipLaunchKernelGGL(k_reset_sync, dim3(64), dim3(256), 0, stream, s);
     return hipGetLastError();
 }
 
