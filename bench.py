@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Benchmark of the projection-step hot path on one MI355X.
+
+Default workload (the one the fine-step metric is quoted on): the 128^3
+lid-driven cavity, Re = 1000, dt = 5e-4, started from rest; a "step" is one
+full fine projection step (predictor, Poisson right-hand side, Jacobi-PCG to
+1e-10 relative residual, velocity correction) launched as one persistent
+kernel.  W warm-up steps, then K timed steps; value = cells * K / wall time.
+
+Other modes:
+  --mode poisson   batched Poisson microbenchmark (32 x 128^3 right-hand
+                   sides, a working set far above the 256 MB Infinity Cache)
+  --mode parareal  Parareal on the 96^3 cavity (32 slices of 0.02, fine dt
+                   5e-4, coarse dt 1e-2, mixed precision, jump < 1e-6) against
+                   the serial FP64 fine solve on the GPU
+
+Prints ONE JSON line.  The CPU baseline (the plain FP64 oracle, N = 1 only)
+times one fine step of the same workload from the same state on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic bytes per cell of the kernels' phases (FP64 state, 1-byte
+# cell flags; face arrays counted as one entry per cell and component).
+BYTES_CG_ITER = {"fp64": 66.0, "mixed": 34.0}   # one CG iteration
+BYTES_STEP_FIXED = {"fp64": 212.0, "mixed": 212.0}  # momentum, rhs, init/true, correction, gauge
+BYTES_MIXED_SWEEP = 65.0  # mixed: one FP64 residual + cast + update sweep
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_1705_06149_amd/csrc/nsp_kernels.hip", "paper_1705_06149_amd/csrc/nsp_internal.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile(name):
+    """HBM bytes per launch measured with rocprofv3 counters, if the committed
+    summary was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_sha256_16") != _kernel_source_hash():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def bench_fine(args):
+    import torch
+    from paper_1705_06149_amd import nsp
+
+    n, re_, dt = 128, 1000.0, 5e-4
+    prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
+    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=1e-5, max_outer=8)
+    h = nsp.Handle(n, n, n, re=re_, max_batch=1)
+    y = h.zeros_state(1)
+    t = 0.0
+    for _ in range(args.warmup):
+        h.fine_step(y, t, t + dt, dt, opts)
+        t += dt
+    host_state = tuple(a[0].cpu().numpy().copy() for a in y)
+    _sync()
+    iters = 0
+    launch_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = h.fine_step(y, t, t + dt, dt, opts)
+        t += dt
+        iters += info[0]["iters"]
+        launch_ms.append(h.last_launch_ms())
+    _sync()
+    wall = time.perf_counter() - t0
+    cells = n ** 3
+    K = args.steps
+    value = cells * K / wall
+    per_launch_bytes = cells * (BYTES_STEP_FIXED[args.precision] + BYTES_CG_ITER[args.precision] * iters / K)
+    if args.precision == "mixed":
+        per_launch_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
+    avg_launch_s = float(np.mean(launch_ms)) * 1e-3
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    traffic = _traffic_from_profile("k_persistent_cavity128_%s_pmc.txt" % args.precision)
+    out = {
+        "metric": "fine-step cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "cavity128_re1000", "grid": [n, n, n], "re": re_, "dt": dt,
+                   "start": "rest, after %d warm-up steps" % args.warmup, "poisson": "Jacobi-PCG rtol 1e-10",
+                   "precision": args.precision},
+        "cg_iters_per_step": iters / K,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_persistent (one fused fine step per launch)",
+                     "avg_launch_ms": 1e3 * avg_launch_s,
+                     "algorithmic_bytes_per_launch": per_launch_bytes},
+    }
+    h.close()
+    return out, host_state, t
+
+
+def cpu_baseline_fine(args, host_state, t):
+    """The oracle as it stands, one fine step of the same workload from the
+    same state, timed on the host cores."""
+    from oracle import oracle as O
+
+    O.build()
+    n = 128
+    g = O.Grid(n, n, n, re=1000.0)
+    prec = 1 if args.precision == "mixed" else 0
+    t0 = time.perf_counter()
+    _, iters, _, st = O.fine_steps(g, host_state, 1, 5e-4, prec=prec, rtol=1e-10)
+    wall = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n ** 3 / wall, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "1 fine step of the 128^3 cavity from the benchmark's warmed state "
+                      "(%d CG iterations, %.1f s)" % (int(iters[0]), wall)}
+
+
+def bench_poisson(args):
+    import torch
+    from paper_1705_06149_amd import nsp
+
+    n, B = 128, 32
+    prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
+    its = 100
+    h = nsp.Handle(n, n, n, re=1000.0, max_batch=B)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    b = torch.randn((B, n, n, n), dtype=torch.float64, device="cuda", generator=g)
+    p = torch.zeros_like(b)
+    opts = nsp.PoissonOpts(rtol=0.0, maxit=its, prec=prec, inner_rtol=1e-30, max_outer=1)
+    for _ in range(args.warmup):
+        p.zero_()
+        h.poisson_solve(b, p, opts, check=False)
+    _sync()
+    ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p.zero_()
+        h.poisson_solve(b, p, opts, check=False)
+        ms.append(h.last_launch_ms())
+    _sync()
+    wall = time.perf_counter() - t0
+    cells = B * n ** 3
+    per_launch = cells * BYTES_CG_ITER[args.precision] * its
+    achieved = per_launch / (np.mean(ms) * 1e-3) / 1e9
+    out = {
+        "metric": "Poisson HBM GB/s", "value": achieved, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "poisson_32x128cube", "batch": B, "grid": [n, n, n], "cg_iters": its,
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": _traffic_from_profile("k_persistent_poisson32x128_%s_pmc.txt" % args.precision)},
+    }
+    h.close()
+    return out
+
+
+def bench_parareal(args):
+    import torch
+    from paper_1705_06149_amd import nsp
+
+    n, re_, dt, DT, N, T = 96, 1000.0, 5e-4, 1e-2, 32, 0.64
+    tol = 1e-6
+    fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
+    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=1e-5)
+    h = nsp.Handle(n, n, n, re=re_, max_batch=N)
+    # serial FP64 fine solve, batch 1, over [0, T]
+    y = h.zeros_state(1)
+    _sync()
+    t0 = time.perf_counter()
+    for s in range(N):
+        h.fine_step(y, s * T / N, (s + 1) * T / N, dt, fine64)
+    _sync()
+    serial = time.perf_counter() - t0
+    ref = tuple(a[0].clone() for a in y)
+    # batched mixed-precision Parareal
+    shapes = h.shapes()
+    Y = tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in shapes)
+    Fk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
+    Gk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
+    _sync()
+    t0 = time.perf_counter()
+    h.parareal_start(Y, Gk, N, 0.0, T, DT, mixed)
+    jumps = []
+    k = 0
+    while True:
+        jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
+        jumps.append(jv)
+        k += 1
+        if jv < tol or k >= N or k >= args.max_iters:
+            break
+    _sync()
+    par = time.perf_counter() - t0
+    err = float(torch.sqrt(sum(((Y[c][N] - ref[c]) ** 2).sum() for c in range(3)) /
+                           sum((ref[c] ** 2).sum() for c in range(3))))
+    cells = n ** 3
+    nf = int(round(T / dt))
+    out = {
+        "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
+        "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
+                   "jump_tol": tol},
+        "parareal_iterations": k, "jumps": jumps, "serial_fp64_s": serial, "parareal_s": par,
+        "serial_equiv_cell_updates_per_s": cells * nf / par,
+        "end_state_rel_l2_vs_serial_fp64": err,
+        "bound_paper_eq8": N / k,
+    }
+    h.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--mode", choices=["fine", "poisson", "parareal"], default="fine")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--max-iters", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (time slices would shard "
+              "across GPUs with point-to-point sends of slice-end states; not implemented)", file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "fine":
+        out, host_state, t = bench_fine(args)
+        rank = int(os.environ.get("RANK", "0"))
+        if rank == 0 and not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_fine(args, host_state, t)
+    elif args.mode == "poisson":
+        out = bench_poisson(args)
+    else:
+        out = bench_parareal(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
