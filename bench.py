@@ -11,8 +11,10 @@ Other modes:
   --mode poisson   batched Poisson microbenchmark (32 x 128^3 right-hand
                    sides, a working set far above the 256 MB Infinity Cache)
   --mode parareal  Parareal on the 96^3 cavity (32 slices of 0.02, fine dt
-                   5e-4, coarse dt 1e-2, mixed precision, jump < 1e-6) against
-                   the serial FP64 fine solve on the GPU
+                   5e-4, coarse dt --coarse-dt, mixed precision, jump < 1e-6)
+                   against the serial FP64 fine solve on the GPU
+  --mode copy      a plain device-to-device copy of 1 GiB (torch), the
+                   reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE
 
 Prints ONE JSON line.  The CPU baseline (the plain FP64 oracle, N = 1 only)
 times one fine step of the same workload from the same state on the host.
@@ -198,7 +200,7 @@ def bench_parareal(args):
     import torch
     from paper_1705_06149_amd import nsp
 
-    n, re_, dt, DT, N, T = 96, 1000.0, 5e-4, 1e-2, 32, 0.64
+    n, re_, dt, DT, N, T = 96, 1000.0, 5e-4, args.coarse_dt, 32, 0.64
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=1e-5)
@@ -222,8 +224,11 @@ def bench_parareal(args):
     h.parareal_start(Y, Gk, N, 0.0, T, DT, mixed)
     jumps = []
     k = 0
+    iter_s = []
     while True:
+        ti = time.perf_counter()
         jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
+        iter_s.append(time.perf_counter() - ti)
         jumps.append(jv)
         k += 1
         if jv < tol or k >= N or k >= args.max_iters:
@@ -240,7 +245,7 @@ def bench_parareal(args):
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
                    "jump_tol": tol},
-        "parareal_iterations": k, "jumps": jumps, "serial_fp64_s": serial, "parareal_s": par,
+        "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
         "serial_equiv_cell_updates_per_s": cells * nf / par,
         "end_state_rel_l2_vs_serial_fp64": err,
         "bound_paper_eq8": N / k,
@@ -249,14 +254,39 @@ def bench_parareal(args):
     return out
 
 
+def bench_copy(args):
+    import torch
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    _sync()
+    wall = time.perf_counter() - t0
+    gbs = 2 * nbytes * args.steps / wall / 1e9
+    return {"metric": "copy GB/s", "value": gbs, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "copy_1GiB", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["fine", "poisson", "parareal"], default="fine")
+    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "copy"], default="fine")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--max-iters", type=int, default=32)
+    # Forward Euler on the 96^3 grid is stable only while the advective
+    # Courant number plus 2 nu dt sum_d 1/h_d^2 stays below 1: at dt = 1e-2 that
+    # sum is about 0.96 + 0.55 and the coarse propagator blows up; 5e-3 gives
+    # about 0.76.
+    ap.add_argument("--coarse-dt", type=float, default=5e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -270,6 +300,8 @@ def main():
             out["cpu_baseline"] = cpu_baseline_fine(args, host_state, t)
     elif args.mode == "poisson":
         out = bench_poisson(args)
+    elif args.mode == "copy":
+        out = bench_copy(args)
     else:
         out = bench_parareal(args)
     print(json.dumps(out), flush=True)
