@@ -82,12 +82,13 @@ hipError_t dalloc(T **p, size_t n) {
     return hipMalloc(reinterpret_cast<void **>(p), n * sizeof(T));
 }
 
-// Tile size: a power of two between kBlock and 8 kBlock cells, about
-// ncells/128, fixed by the grid alone so that reductions never depend on
-// the batch.
+// Tile size: a power of two between kBlock and 2 kBlock cells, about
+// ncells/256, fixed by the grid alone so that reductions never depend on
+// the batch.  Small tiles keep the window an XCD sweeps at a time (its
+// workgroups times one tile, plus one plane on either side) inside its L2.
 int tile_for(long long ncells) {
     long long t = kBlock;
-    while (t * 2 <= ncells / 128 && t < 8 * kBlock) t *= 2;
+    while (t * 2 <= ncells / 256 && t < 2 * kBlock) t *= 2;
     return (int)t;
 }
 

@@ -209,7 +209,7 @@ __device__ __forceinline__ double predictor(const GAS GroupDesc &G, const GAS do
 
 struct Runner {
     const GAS KParams &P;
-    int tb, te;            // my tile range
+    int tb, te, ts;        // my tiles: tb, tb + ts, ... < te
     LAS double *s_red;     // [kWaves * kNQ] wave partials
     const LAS double *s_idg;   // [kMaxGroups * 64]
     const LAS float *s_idg32;  // [kMaxGroups * 64]
@@ -255,7 +255,7 @@ struct Runner {
     // gs, c, acc)` handles cell c of local slice sl (global slice gs).
     template <int NQ, class Skip, class Body>
     __device__ __forceinline__ void tiles(Skip skip, Body body) {
-        for (int t = tb; t < te; ++t) {
+        for (int t = tb; t < te; t += ts) {
             int gi, sl;
             locate(t, gi, sl);
             const GAS GroupDesc &G = P.g[gi];
@@ -744,7 +744,7 @@ struct Runner {
 
     template <class T>
     __device__ __forceinline__ void phase_A(int par) {
-        for (int t = tb; t < te; ++t) {
+        for (int t = tb; t < te; t += ts) {
             int gi, sl;
             locate(t, gi, sl);
             const GAS GroupDesc &G = P.g[gi];
@@ -813,7 +813,7 @@ struct Runner {
     // FP32 (inner solve of the mixed path): e += alpha d; r -= alpha A d.
     template <class T>
     __device__ __forceinline__ void phase_B(int par) {
-        for (int t = tb; t < te; ++t) {
+        for (int t = tb; t < te; t += ts) {
             int gi, sl;
             locate(t, gi, sl);
             const GAS GroupDesc &G = P.g[gi];
@@ -1027,17 +1027,22 @@ k_persistent(const KParams *__restrict__ Pp) {
         s_idg32[x] = P.g[x / 64].idiag32[x % 64];
     }
     __syncthreads();
-    // Logical workgroup index: with xcd_remap, workgroups dispatched to the
-    // same XCD (hardware index modulo 8) receive one contiguous tile range,
-    // so stencil neighbours in the next plane sit in the same L2.
+    // Tile schedule.  Workgroups are dispatched to the eight XCDs round-robin
+    // (hardware index modulo 8).  Each XCD owns one contiguous range of
+    // tiles, and its workgroups take that range's tiles in turn (stride =
+    // workgroups on the XCD), so at any moment they sweep a narrow window of
+    // consecutive tiles whose neighbouring planes are still in the XCD's L2.
     const int nb = gridDim.x, b = blockIdx.x;
-    int lb = b;
+    int tb = b, te = P.ntiles, ts = nb;
     if (P.xcd_remap && nb >= 8) {
         const int x = b & 7, q = nb >> 3, rm = nb & 7;
-        lb = x * q + min(x, rm) + (b >> 3);
+        const int first = x * q + min(x, rm), count = q + (x < rm ? 1 : 0);
+        const int x0 = (int)((long)first * P.ntiles / nb), x1 = (int)((long)(first + count) * P.ntiles / nb);
+        tb = x0 + (b >> 3);
+        te = x1;
+        ts = count;
     }
-    Runner R{P, (int)((long)lb * P.ntiles / nb), (int)((long)(lb + 1) * P.ntiles / nb), (LAS double *)s_red,
-             (const LAS double *)s_idg, (const LAS float *)s_idg32};
+    Runner R{P, tb, te, ts, (LAS double *)s_red, (const LAS double *)s_idg, (const LAS float *)s_idg32};
     R.run();
 }
 
