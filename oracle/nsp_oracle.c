@@ -567,3 +567,216 @@ int og_fine_steps(const og_grid *g, double *u, double *v, double *w, double *p, 
     free(Fu); free(Fv); free(Fw); free(b);
     return worst;
 }
+
+/* ================================================================ adjoint
+ *
+ * One forward step is u' = P(M(u; lid)), M(u) = u + dt R(u) on open faces
+ * (R = Lap/Re - Conv), P the orthogonal projector onto discretely
+ * divergence-free face fields (P = I - G (G^T G)^+ G^T, since D = -G^T).
+ * The adjoint of a step, given lam' = dJ/du', is
+ *     mu = P lam'                       (P is symmetric: the same projection)
+ *     lam = mu + dt (dR/du)^T mu        (this function)
+ *     g_lid += dt (dR/dlid)^T mu        (this function)
+ * R is piecewise linear in the stencil values: inside each segment of the
+ * SMART diagram the face value is a fixed linear combination of U, C, D
+ * (slopes (0,1,0) upwind, (-2,3,0) steep, (-1/8,3/4,3/8) QUICK, (0,0,1)
+ * capped), and every image value is a linear form in face values and the
+ * lid.  The adjoint differentiates the branch the forward step took; where
+ * the transport velocity is exactly 0 the flux is identically 0 and
+ * contributes nothing.
+ */
+
+typedef struct {
+    int n;
+    size_t idx[4];
+    double coef[4];
+    double lcoef; /* coefficient of the lid value lid[lidx] */
+    size_t lidx;
+} og_form;
+
+static void form_face(og_form *F, size_t idx, double coef) {
+    F->idx[F->n] = idx;
+    F->coef[F->n] = coef;
+    F->n++;
+}
+
+static int wall_is_lid(const og_grid *g, int c, const int f[3], int d, int s) {
+    return c == 0 && d == 1 && s > 0 && f[1] == g->ny - 1;
+}
+
+/* the stencil value of stencil_val() as a linear form */
+static void stencil_form(const og_grid *g, int c, const int f[3], int d, int m, og_form *F) {
+    int s = m > 0 ? 1 : -1;
+    int two = (m == 2 || m == -2);
+    int f1[3] = {f[0], f[1], f[2]};
+    int f2[3] = {f[0], f[1], f[2]};
+    f1[d] += s;
+    f2[d] += 2 * s;
+    size_t i0 = fidx(g, c, f);
+    F->n = 0;
+    F->lcoef = 0.0;
+    F->lidx = (size_t)f[2] * (g->nx + 1) + f[0];
+    if (d == c) {
+        if (!face_open(g, c, f1)) { if (two) form_face(F, i0, -1.0); return; }
+        if (!two) { form_face(F, fidx(g, c, f1), 1.0); return; }
+        if (face_open(g, c, f2)) form_face(F, fidx(g, c, f2), 1.0);
+        return;
+    }
+    if (!face_open(g, c, f1)) {
+        if (wall_is_lid(g, c, f, d, s)) F->lcoef += 2.0;
+        if (!two) { form_face(F, i0, -1.0); return; }
+        og_form inner;
+        stencil_form(g, c, f, d, -s, &inner);
+        for (int k = 0; k < inner.n; ++k) form_face(F, inner.idx[k], -inner.coef[k]);
+        F->lcoef -= inner.lcoef;
+        return;
+    }
+    if (!two) { form_face(F, fidx(g, c, f1), 1.0); return; }
+    if (!face_open(g, c, f2)) {
+        if (wall_is_lid(g, c, f1, d, s)) F->lcoef += 2.0;
+        form_face(F, fidx(g, c, f1), -1.0);
+        return;
+    }
+    form_face(F, fidx(g, c, f2), 1.0);
+}
+
+/* value of a form (used by the tests to check it against stencil_val) */
+double og_stencil_form_value(const og_grid *g, int c, const double *phi, int i, int j, int k, int d, int m) {
+    int f[3] = {i, j, k};
+    og_form F;
+    stencil_form(g, c, f, d, m, &F);
+    double v = 0.0;
+    for (int q = 0; q < F.n; ++q) v += F.coef[q] * phi[F.idx[q]];
+    return v + F.lcoef * g->lid[F.lidx];
+}
+
+double og_stencil_value(const og_grid *g, int c, const double *phi, int i, int j, int k, int d, int m) {
+    int f[3] = {i, j, k};
+    return stencil_val(g, c, phi, f, d, m);
+}
+
+/* slopes of the SMART face value with respect to U, C, D on the branch
+ * og_smart takes */
+static void smart_slopes(double U, double C, double D, double s[3]) {
+    double delta = D - U;
+    s[0] = 0.0; s[1] = 1.0; s[2] = 0.0;
+    if (delta == 0.0) return;
+    double ph = (C - U) / delta;
+    if (ph > 0.0 && ph < 1.0 / 6.0) { s[0] = -2.0; s[1] = 3.0; s[2] = 0.0; }
+    else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0) { s[0] = -0.125; s[1] = 0.75; s[2] = 0.375; }
+    else if (ph >= 5.0 / 6.0 && ph < 1.0) { s[0] = 0.0; s[1] = 0.0; s[2] = 1.0; }
+}
+
+static void scatter_form(const og_form *F, double wgt, double *lam, double *glid) {
+    for (int q = 0; q < F->n; ++q) lam[F->idx[q]] += wgt * F->coef[q];
+    if (F->lcoef != 0.0 && glid) glid[F->lidx] += wgt * F->lcoef;
+}
+
+static double form_value(const og_form *F, const double *phi, const double *lid) {
+    double v = 0.0;
+    for (int q = 0; q < F->n; ++q) v += F->coef[q] * phi[F->idx[q]];
+    return v + F->lcoef * lid[F->lidx];
+}
+
+/* lam = mu + dt (dR/du)^T mu, g_lid += dt (dR/dlid)^T mu, with R evaluated at
+ * (u, v, w).  mu is read on open faces only; lam is written on every face
+ * (0 on closed faces).  Serial loops: the scatter order is fixed. */
+void og_momentum_adjoint(const og_grid *g, const double *u, const double *v, const double *w, double dt,
+                         const double *mu_u, const double *mu_v, const double *mu_w, double *lam_u, double *lam_v,
+                         double *lam_w, double *g_lid) {
+    const double *vel[3] = {u, v, w};
+    const double *mu[3] = {mu_u, mu_v, mu_w};
+    double *lam[3] = {lam_u, lam_v, lam_w};
+    for (int c = 0; c < 3; ++c) {
+        size_t nf = og_face_count(g, c);
+        for (size_t id = 0; id < nf; ++id) lam[c][id] = 0.0;
+    }
+    for (int c = 0; c < 3; ++c) {
+        int ex = fext(g, c, 0), ey = fext(g, c, 1), ez = fext(g, c, 2);
+        for (int k = 0; k < ez; ++k)
+            for (int j = 0; j < ey; ++j)
+                for (int i = 0; i < ex; ++i) {
+                    int f[3] = {i, j, k};
+                    if (!face_open(g, c, f)) continue;
+                    size_t i0 = fidx(g, c, f);
+                    double m0 = mu[c][i0];
+                    lam[c][i0] += m0;
+                    if (m0 == 0.0) continue;
+                    og_form self;
+                    self.n = 0;
+                    self.lcoef = 0.0;
+                    self.lidx = 0;
+                    form_face(&self, i0, 1.0);
+                    for (int d = 0; d < 3; ++d) {
+                        double h = hdir(g, d);
+                        og_form Vm2, Vm1, Vp1, Vp2;
+                        stencil_form(g, c, f, d, -2, &Vm2);
+                        stencil_form(g, c, f, d, -1, &Vm1);
+                        stencil_form(g, c, f, d, 1, &Vp1);
+                        stencil_form(g, c, f, d, 2, &Vp2);
+                        /* diffusion (v+1 - 2 phi0 + v-1)/h^2 / Re */
+                        double wd = dt * m0 / (g->re * h * h);
+                        scatter_form(&Vp1, wd, lam[c], g_lid);
+                        scatter_form(&Vm1, wd, lam[c], g_lid);
+                        lam[c][i0] += -2.0 * wd;
+                        /* convection: -(flux(+) - flux(-))/h */
+                        for (int s = -1; s <= 1; s += 2) {
+                            /* transport velocity: two real face values */
+                            size_t a_idx[2];
+                            int a_comp, a_open[2];
+                            if (d == c) {
+                                int f1[3] = {f[0], f[1], f[2]};
+                                f1[d] += s;
+                                a_comp = c;
+                                a_idx[0] = i0; a_open[0] = 1;
+                                a_open[1] = face_open(g, c, f1);
+                                a_idx[1] = a_open[1] ? fidx(g, c, f1) : 0;
+                            } else {
+                                int q1[3] = {f[0], f[1], f[2]}, q2[3] = {f[0], f[1], f[2]};
+                                if (s > 0) { q1[d] += 1; q2[d] += 1; }
+                                q1[c] -= 1;
+                                a_comp = d;
+                                a_open[0] = face_open(g, d, q1);
+                                a_open[1] = face_open(g, d, q2);
+                                a_idx[0] = a_open[0] ? fidx(g, d, q1) : 0;
+                                a_idx[1] = a_open[1] ? fidx(g, d, q2) : 0;
+                            }
+                            double a1 = a_open[0] ? vel[a_comp][a_idx[0]] : 0.0;
+                            double a2 = a_open[1] ? vel[a_comp][a_idx[1]] : 0.0;
+                            double abar = 0.5 * (a1 + a2);
+                            if (abar == 0.0) continue;
+                            const og_form *U, *C, *D;
+                            if (s > 0) {
+                                if (abar > 0.0) { U = &Vm1; C = &self; D = &Vp1; }
+                                else { U = &Vp2; C = &Vp1; D = &self; }
+                            } else {
+                                if (abar > 0.0) { U = &Vm2; C = &Vm1; D = &self; }
+                                else { U = &Vp1; C = &self; D = &Vm1; }
+                            }
+                            double Uv = form_value(U, vel[c], g->lid), Cv = form_value(C, vel[c], g->lid),
+                                   Dv = form_value(D, vel[c], g->lid);
+                            double phis = og_smart(Uv, Cv, Dv);
+                            double sl[3];
+                            smart_slopes(Uv, Cv, Dv, sl);
+                            /* d(-s flux/h) */
+                            double wc = -(double)s * dt * m0 / h;
+                            if (a_open[0]) lam[a_comp][a_idx[0]] += wc * 0.5 * phis;
+                            if (a_open[1]) lam[a_comp][a_idx[1]] += wc * 0.5 * phis;
+                            scatter_form(U, wc * abar * sl[0], lam[c], g_lid);
+                            scatter_form(C, wc * abar * sl[1], lam[c], g_lid);
+                            scatter_form(D, wc * abar * sl[2], lam[c], g_lid);
+                        }
+                    }
+                }
+    }
+    /* closed faces carry no adjoint */
+    for (int c = 0; c < 3; ++c) {
+        int ex = fext(g, c, 0), ey = fext(g, c, 1), ez = fext(g, c, 2);
+        for (int k = 0; k < ez; ++k)
+            for (int j = 0; j < ey; ++j)
+                for (int i = 0; i < ex; ++i) {
+                    int f[3] = {i, j, k};
+                    if (!face_open(g, c, f)) lam[c][fidx(g, c, f)] = 0.0;
+                }
+    }
+}

@@ -72,6 +72,11 @@ def lib():
         _lib.og_rhs.argtypes = [G, P, P, P, D, P]
         _lib.og_fine_steps.argtypes = [G, P, P, P, P, I, D, I, D, I, D, I, P, P]
         _lib.og_fine_steps.restype = I
+        _lib.og_momentum_adjoint.argtypes = [G, P, P, P, D, P, P, P, P, P, P, P]
+        _lib.og_stencil_form_value.argtypes = [G, I, P, I, I, I, I, I]
+        _lib.og_stencil_form_value.restype = D
+        _lib.og_stencil_value.argtypes = [G, I, P, I, I, I, I, I]
+        _lib.og_stencil_value.restype = D
     return _lib
 
 
@@ -287,3 +292,94 @@ def parareal(y0, nslices, F, G, n_it=None, tol=None, jump_norm=None, combine=Non
             break
         k += 1
     return Y, history
+
+
+# ------------------------------------------------------------------ adjoint
+
+def stencil_value(g: Grid, c, phi, f, d, m, as_form=False):
+    """Stencil value of component c at open face f, offset m along d (the
+    image rule), evaluated directly or through its linear form."""
+    fn = lib().og_stencil_form_value if as_form else lib().og_stencil_value
+    gc = g.c()
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    return fn(ctypes.byref(gc), int(c), _p(phi), int(f[0]), int(f[1]), int(f[2]), int(d), int(m))
+
+
+def momentum_adjoint(g: Grid, u, v, w, dt, mu):
+    """lam = mu + dt (dR/du)^T mu and dt (dR/dlid)^T mu at the state (u, v, w)."""
+    su, sv, sw, _ = g.shapes()
+    u, v, w = _chk(u, su), _chk(v, sv), _chk(w, sw)
+    mu = [_chk(m, s) for m, s in zip(mu, (su, sv, sw))]
+    lam = [np.empty(su), np.empty(sv), np.empty(sw)]
+    glid = np.zeros_like(g.lid)
+    gc = g.c()
+    lib().og_momentum_adjoint(ctypes.byref(gc), _p(u), _p(v), _p(w), float(dt), _p(mu[0]), _p(mu[1]), _p(mu[2]),
+                              _p(lam[0]), _p(lam[1]), _p(lam[2]), _p(glid))
+    return lam, glid
+
+
+def project(g: Grid, F, rtol=1e-12, maxit=100000, p0=None):
+    """P F: the projection of the step applied to a face field (dt = 1)."""
+    b = rhs(g, *F, 1.0)
+    p, info = pcg(g, b, p0, rtol=rtol, maxit=maxit)
+    if info["status"] != 0:
+        raise RuntimeError("oracle projection solve failed: %r" % info)
+    return correct(g, *F, p, 1.0), p
+
+
+def kinetic_energy(g: Grid, state):
+    """J = 1/2 * cell volume * sum of squared face velocities (closed faces are 0)."""
+    hx, hy, hz = g.h
+    vol = hx * hy * hz
+    s = 0.0
+    for a, op in zip(state[:3], _open_masks(g)):
+        s += float(np.sum(a[op] ** 2))
+    return 0.5 * vol * s
+
+
+def _open_masks(g: Grid):
+    """Boolean open-face masks of u, v, w."""
+    fl = g.fluid()
+    nz, ny, nx = fl.shape
+    mu = np.zeros((nz, ny, nx + 1), bool)
+    mu[:, :, 1:nx] = fl[:, :, :-1] & fl[:, :, 1:]
+    mv = np.zeros((nz, ny + 1, nx), bool)
+    mv[:, 1:ny, :] = fl[:, :-1, :] & fl[:, 1:, :]
+    mw = np.zeros((nz + 1, ny, nx), bool)
+    mw[1:nz] = fl[:-1] & fl[1:]
+    return mu, mv, mw
+
+
+def adjoint_gradient(g: Grid, state0, nsteps, dt, rtol=1e-12, ckpt_every=None):
+    """J(u_T) = kinetic energy after nsteps FP64 steps from state0, and its
+    gradient with respect to the initial face velocities and to the lid
+    values (per top u-face position).  Forward states are kept at every
+    `ckpt_every`-th step and recomputed inside each segment (all kept if
+    None)."""
+    ck = ckpt_every or nsteps or 1
+    ckpts = {0: tuple(a.copy() for a in state0)}
+    y = tuple(a.copy() for a in state0)
+    for n in range(nsteps):
+        y, _, _, st = fine_steps(g, y, 1, dt, rtol=rtol)
+        if st != 0:
+            raise RuntimeError("oracle forward step failed")
+        if (n + 1) % ck == 0 and n + 1 < nsteps:
+            ckpts[n + 1] = tuple(a.copy() for a in y)
+    J = kinetic_energy(g, y)
+    hx, hy, hz = g.h
+    masks = _open_masks(g)
+    lam = [hx * hy * hz * np.where(m, a, 0.0) for a, m in zip(y[:3], masks)]
+    glid = np.zeros_like(g.lid)
+    seg_starts = sorted(ckpts)
+    for s0 in reversed(seg_starts):
+        s1 = min(s0 + ck, nsteps)
+        states = [ckpts[s0]]
+        for n in range(s0, s1 - 1):
+            nxt, _, _, _ = fine_steps(g, states[-1], 1, dt, rtol=rtol)
+            states.append(nxt)
+        for n in range(s1 - 1, s0 - 1, -1):
+            mu, _ = project(g, lam, rtol=rtol)
+            u, v, w = states[n - s0][:3]
+            lam, gl = momentum_adjoint(g, u, v, w, dt, mu)
+            glid += gl
+    return J, lam, glid
