@@ -171,6 +171,31 @@ nsp_status nsp_group_parareal_iterate(nsp_handle *const *hs, const nsp_state *Y,
                                       double dt, double DT, const nsp_poisson_opts *fine,
                                       const nsp_poisson_opts *coarse, void *stream, double *jump);
 
+/* Adjoint of the fine propagator F (Sec. 2.1.2) for the objective
+ *     J = 1/2 hx hy hz sum over open faces of (u_T^2 + v_T^2 + w_T^2),
+ * the kinetic energy after nsteps projection steps of size dt from y0
+ * (HOST output *J).  With grad.u/v/w non-NULL also writes dJ/d(u0, v0, w0)
+ * (DEVICE face arrays, 0 on closed faces) and, if g_lid is non-NULL, dJ/dlid
+ * (DEVICE [nz][nx+1], per top u-face lid value).  Each step u' = P(M(u))
+ * (M the predictor, P the orthogonal projection of Sec. 2) is reversed as
+ * mu = P lam' (the same projection, solved in FP64 to opts->rtol), lam =
+ * mu + dt (dR/du)^T mu with the SMART slopes of the branch the forward step
+ * took.  Forward states are stored every ckpt_every steps (0: only the
+ * initial state) and recomputed segment by segment.  y0 is not modified.
+ * The momentum adjoint accumulates with atomic adds, so results may differ
+ * between runs in the last bits.  Workspace (checkpoints, one segment) is
+ * allocated on first use and kept by the handle. */
+nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
+                                  const nsp_poisson_opts *opts, nsp_state grad, double *g_lid, double *J,
+                                  void *stream);
+
+/* Lid profile from sine modes: lid(x, z) = 1 + sum_{m,n=1..M} c[m-1][n-1]
+ * sin(m pi x/lx) sin(n pi z/lz) at the top u-face positions x = i hx,
+ * z = (k+1/2) hz.  coef: DEVICE M*M row-major, lid_dev: DEVICE [nz][nx+1].
+ * nsp_lid_modes_grad is its transpose: g_coef[m][n] = sum g_lid * basis. */
+nsp_status nsp_lid_from_modes(nsp_handle *h, const double *coef, int nmodes, double *lid_dev, void *stream);
+nsp_status nsp_lid_modes_grad(nsp_handle *h, const double *g_lid, int nmodes, double *g_coef, void *stream);
+
 /* Launch shape used for a batch: workgroups per launch.  0 = automatic.
  * nsp_autotune times candidate shapes on the handle's own workspace (a
  * short Poisson solve on a synthetic right-hand side) and keeps the fastest

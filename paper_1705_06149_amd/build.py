@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnsp.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("nsp_kernels.hip", "nsp_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("nsp_kernels.hip", "nsp_adjoint.hip", "nsp_api.hip")]
 HEADERS = [os.path.join(CSRC, "nsp_internal.h"), os.path.join(ROOT, "include", "nsp.h")]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 arithmetic.

@@ -54,6 +54,12 @@ struct nsp_handle {
     float *e = nullptr;
     nsp_state gs{nullptr, nullptr, nullptr, nullptr};  // scratch state for the coarse sweep
     LaunchRes L;
+    // adjoint workspace (allocated on first use)
+    int adj_nck = 0, adj_seg = 0;
+    double *adj_ck = nullptr;    // checkpoints: adj_nck full states
+    double *adj_segu = nullptr;  // velocities of one segment: adj_seg states
+    double *adj_y = nullptr;     // working state
+    double *adj_lam = nullptr, *adj_mu = nullptr, *adj_p = nullptr, *adj_glid = nullptr, *adj_part = nullptr;
     int max_wg = 0;
     int fixed_wg = 0;
     std::vector<TuneEntry> tuned;
@@ -462,6 +468,9 @@ nsp_status nsp_destroy(nsp_handle *h) {
                     h->L.jump};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    void *aptrs[] = {h->adj_ck, h->adj_segu, h->adj_y, h->adj_lam, h->adj_mu, h->adj_p, h->adj_glid, h->adj_part};
+    for (void *p : aptrs)
+        if (p) (void)hipFree(p);
     if (h->L.ctl_host) (void)hipHostFree(h->L.ctl_host);
     if (h->L.params_host) (void)hipHostFree(h->L.params_host);
     if (h->L.jump_host) (void)hipHostFree(h->L.jump_host);
@@ -625,6 +634,167 @@ nsp_status nsp_parareal_iterate(nsp_handle *h, nsp_state Y, nsp_state Fk, nsp_st
                                 const nsp_poisson_opts *coarse, void *stream, double *jump) {
     nsp_handle *hs[1] = {h};
     return nsp_group_parareal_iterate(hs, &Y, &Fk, &Gk, 1, nslices, k, t0, T, dt, DT, fine, coarse, stream, jump);
+}
+
+
+}  // extern "C"
+
+namespace {
+
+long long state_len(const nsp_handle *h) { return h->nu + h->nv + h->nw + h->ncells; }
+
+// a state stored contiguously: u, v, w, p back to back
+nsp_state packed_state(const nsp_handle *h, double *base) {
+    nsp_state s;
+    s.u = base;
+    s.v = base + h->nu;
+    s.w = base + h->nu + h->nv;
+    s.p = base + h->nu + h->nv + h->nw;
+    return s;
+}
+
+AdjParams adj_params(const nsp_handle *h, double dt) {
+    AdjParams A;
+    A.nx = h->nx;
+    A.ny = h->ny;
+    A.nz = h->nz;
+    const double L[3] = {h->lx, h->ly, h->lz};
+    const int n[3] = {h->nx, h->ny, h->nz};
+    for (int d = 0; d < 3; ++d) {
+        A.L[d] = L[d];
+        A.h[d] = L[d] / n[d];
+        A.ih[d] = 1.0 / A.h[d];
+        A.ih2[d] = 1.0 / (A.h[d] * A.h[d]);
+    }
+    A.inv_re = 1.0 / h->re;
+    A.dt = dt;
+    A.flags = h->flags;
+    A.lid = h->lid;
+    return A;
+}
+
+nsp_status ensure_adj(nsp_handle *h, int nck, int seg) {
+    const long long L = state_len(h);
+    if (!h->adj_y) {
+        HIPCHK(h, dalloc(&h->adj_y, L));
+        HIPCHK(h, dalloc(&h->adj_lam, h->nu + h->nv + h->nw));
+        HIPCHK(h, dalloc(&h->adj_mu, h->nu + h->nv + h->nw));
+        HIPCHK(h, dalloc(&h->adj_p, h->ncells));
+        HIPCHK(h, dalloc(&h->adj_glid, (size_t)h->nz * (h->nx + 1)));
+        HIPCHK(h, dalloc(&h->adj_part, 3 * kSumBlocks + 1));
+    }
+    if (nck > h->adj_nck) {
+        if (h->adj_ck) (void)hipFree(h->adj_ck);
+        h->adj_ck = nullptr;
+        HIPCHK(h, dalloc(&h->adj_ck, (size_t)nck * L));
+        h->adj_nck = nck;
+    }
+    if (seg > h->adj_seg) {
+        if (h->adj_segu) (void)hipFree(h->adj_segu);
+        h->adj_segu = nullptr;
+        HIPCHK(h, dalloc(&h->adj_segu, (size_t)seg * (h->nu + h->nv + h->nw)));
+        h->adj_seg = seg;
+    }
+    return NSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
+                                  const nsp_poisson_opts *o, nsp_state grad, double *g_lid, double *J, void *stream) {
+    if (!h) return NSP_ERR_ARG;
+    if (!state_ok(y0) || nsteps < 0 || !(dt > 0) || !J) return fail(h, NSP_ERR_ARG, "bad adjoint arguments");
+    if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
+    const bool want_grad = grad.u && grad.v && grad.w;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int ck = ckpt_every > 0 ? std::min(ckpt_every, std::max(nsteps, 1)) : std::max(nsteps, 1);
+    const int nseg = nsteps > 0 ? (nsteps + ck - 1) / ck : 0;
+    nsp_status st = ensure_adj(h, want_grad ? nseg : 0, want_grad ? ck : 0);
+    if (st != NSP_OK) return st;
+    const long long L = state_len(h);
+    const long long F3 = h->nu + h->nv + h->nw;
+    nsp_state y = packed_state(h, h->adj_y);
+    HIPCHK(h, copy_slices(h, y, y0, 1, s));
+    nsp_handle *hs[1] = {h};
+    int one = 1;
+    // forward sweep, storing the state at the start of every segment
+    for (int sg = 0; sg < nseg; ++sg) {
+        if (want_grad) HIPCHK(h, launch_copy_state(h->adj_ck + (long long)sg * L, h->adj_y, L, s));
+        const int len = std::min(ck, nsteps - sg * ck);
+        st = propagate(hs, &y, &one, 1, 0.0, len * dt, dt, o, stream, nullptr);
+        if (st != NSP_OK) return st;
+    }
+    const AdjParams A = adj_params(h, dt);
+    const double *vel[3] = {y.u, y.v, y.w};
+    HIPCHK(h, launch_sumsq_open(A, vel, h->adj_part, h->adj_part + 3 * kSumBlocks, s));
+    double ss = 0.0;
+    HIPCHK(h, hipMemcpyAsync(&ss, h->adj_part + 3 * kSumBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    const double vol = A.h[0] * A.h[1] * A.h[2];
+    *J = 0.5 * vol * ss;
+    if (!want_grad) return NSP_OK;
+    // lam = dJ/du_T = vol * u_T on open faces
+    double *lam[3] = {h->adj_lam, h->adj_lam + h->nu, h->adj_lam + h->nu + h->nv};
+    double *mu[3] = {h->adj_mu, h->adj_mu + h->nu, h->adj_mu + h->nu + h->nv};
+    HIPCHK(h, launch_scale_open(A, vel, vol, lam, s));
+    HIPCHK(h, hipMemsetAsync(h->adj_glid, 0, (size_t)h->nz * (h->nx + 1) * sizeof(double), s));
+    HIPCHK(h, hipMemsetAsync(h->adj_p, 0, h->ncells * sizeof(double), s));
+    nsp_poisson_opts po = *o;
+    po.prec = NSP_FP64;  // the adjoint differentiates the exact projection
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int len = std::min(ck, nsteps - sg * ck);
+        // recompute the segment, keeping the velocity at the start of each step
+        HIPCHK(h, launch_copy_state(h->adj_y, h->adj_ck + (long long)sg * L, L, s));
+        for (int m = 0; m < len; ++m) {
+            HIPCHK(h, launch_copy_state(h->adj_segu + (long long)m * F3, h->adj_y, F3, s));
+            if (m + 1 < len) {
+                st = propagate(hs, &y, &one, 1, 0.0, dt, dt, o, stream, nullptr);
+                if (st != NSP_OK) return st;
+            }
+        }
+        for (int m = len - 1; m >= 0; --m) {
+            // mu = P lam: the projection of the step applied to lam
+            HIPCHK(h, launch_copy_state(h->Fu, lam[0], h->nu, s));
+            HIPCHK(h, launch_copy_state(h->Fv, lam[1], h->nv, s));
+            HIPCHK(h, launch_copy_state(h->Fw, lam[2], h->nw, s));
+            GroupDesc G;
+            nsp_state muv{mu[0], mu[1], mu[2], h->adj_p};
+            fill_group(G, h, muv, 0, 1, 0, 0, nullptr);
+            st = run(hs, 1, &G, MODE_PROJECT, 0, 1.0, &po, s, nullptr, 0);
+            if (st != NSP_OK) return st;
+            // lam = mu + dt (dR/du)^T mu at the state of step m; lid adjoint
+            const double *um = h->adj_segu + (long long)m * F3;
+            const double *velm[3] = {um, um + h->nu, um + h->nu + h->nv};
+            const double *muc[3] = {mu[0], mu[1], mu[2]};
+            HIPCHK(h, launch_momentum_adjoint(A, velm, muc, lam, h->adj_glid, s));
+        }
+    }
+    HIPCHK(h, launch_copy_state(grad.u, lam[0], h->nu, s));
+    HIPCHK(h, launch_copy_state(grad.v, lam[1], h->nv, s));
+    HIPCHK(h, launch_copy_state(grad.w, lam[2], h->nw, s));
+    if (g_lid) HIPCHK(h, launch_copy_state(g_lid, h->adj_glid, (long long)h->nz * (h->nx + 1), s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return NSP_OK;
+}
+
+nsp_status nsp_lid_from_modes(nsp_handle *h, const double *coef, int nmodes, double *lid_dev, void *stream) {
+    if (!h) return NSP_ERR_ARG;
+    if (!coef || !lid_dev || nmodes < 0 || nmodes > 64) return fail(h, NSP_ERR_ARG, "bad lid-mode arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, launch_lid_synth(adj_params(h, 1.0), coef, nmodes, lid_dev, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return NSP_OK;
+}
+
+nsp_status nsp_lid_modes_grad(nsp_handle *h, const double *g_lid, int nmodes, double *g_coef, void *stream) {
+    if (!h) return NSP_ERR_ARG;
+    if (!g_lid || !g_coef || nmodes < 1 || nmodes > 64) return fail(h, NSP_ERR_ARG, "bad lid-mode arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, launch_lid_project(adj_params(h, 1.0), g_lid, nmodes, g_coef, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return NSP_OK;
 }
 
 nsp_status nsp_set_launch(nsp_handle *h, int workgroups) {

@@ -84,7 +84,10 @@ struct SyncWords {
     int pad[kLine - 1];
 };
 
-enum Mode : int { MODE_FINE = 0, MODE_POISSON = 1 };
+// MODE_FINE: nsteps projection steps on the state; MODE_POISSON: solve
+// A p = bin; MODE_PROJECT: state velocities = P(F workspace), the step's
+// projection applied to a given face field (dt = 1), p the warm start.
+enum Mode : int { MODE_FINE = 0, MODE_POISSON = 1, MODE_PROJECT = 2 };
 
 struct KParams {
     GroupDesc g[kMaxGroups];
@@ -126,5 +129,22 @@ struct UpdateParams {
 };
 hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream);
 hipError_t launch_copy_state(double *dst, const double *src, long long n, hipStream_t stream);
+
+// Adjoint of the fine step (nsp_adjoint.hip).
+struct AdjParams {
+    int nx, ny, nz;
+    double h[3], L[3], ih[3], ih2[3];
+    double inv_re, dt;
+    const uint8_t *flags;
+    const double *lid;
+};
+constexpr int kSumBlocks = 256;
+hipError_t launch_momentum_adjoint(const AdjParams &A, const double *const vel[3], const double *const mu[3],
+                                   double *const lam[3], double *glid, hipStream_t s);
+hipError_t launch_scale_open(const AdjParams &A, const double *const a[3], double scale, double *const out[3],
+                             hipStream_t s);
+hipError_t launch_sumsq_open(const AdjParams &A, const double *const a[3], double *part, double *out, hipStream_t s);
+hipError_t launch_lid_synth(const AdjParams &A, const double *coef, int M, double *lid, hipStream_t s);
+hipError_t launch_lid_project(const AdjParams &A, const double *glid, int M, double *gcoef, hipStream_t s);
 
 }  // namespace nsp

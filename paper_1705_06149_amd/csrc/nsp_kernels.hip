@@ -996,6 +996,15 @@ struct Runner {
             phase_gauge();
             return;
         }
+        if (P.mode == MODE_PROJECT) {
+            phase_rhs();
+            if (sync(R_MEANB) < 0) return;
+            if (!solve64(false)) return;
+            phase_corr();
+            if (sync(R_NONE) < 0) return;
+            phase_gauge();
+            return;
+        }
         for (int step = 0; step < P.nsteps; ++step) {
             phase_mom(step > 0);
             if (sync(R_NONE) < 0) return;

@@ -84,10 +84,14 @@ def lib():
         L.nsp_set_launch.argtypes = [P, I]
         L.nsp_autotune.argtypes = [P, I, I, P, ctypes.POINTER(I)]
         L.nsp_last_launch_ms.argtypes = [P, ctypes.POINTER(D)]
+        L.nsp_fine_solve_adjoint.argtypes = [P, _State, I, D, I, ctypes.POINTER(_Opts), _State, P,
+                                             ctypes.POINTER(D), P]
+        L.nsp_lid_from_modes.argtypes = [P, P, I, P, P]
+        L.nsp_lid_modes_grad.argtypes = [P, P, I, P, P]
         for name in ("nsp_create", "nsp_destroy", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
                      "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
                      "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
-                     "nsp_last_launch_ms"):
+                     "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad"):
             getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -260,6 +264,47 @@ class Handle:
                   "nsp_autotune")
         return ch.value
 
+    def fine_solve_adjoint(self, y0, nsteps, dt, ckpt_every=10, opts=None, grad=True):
+        """J = kinetic energy after nsteps steps from y0 (batch 1), and if grad
+        its gradient with respect to (u0, v0, w0) and to the lid values.
+        Returns (J, (gu, gv, gw) or None, g_lid or None)."""
+        torch = _torch()
+        opts = opts or PoissonOpts(rtol=1e-12)
+        s = self._state(y0, 1, "y0")
+        o = opts.c()
+        J = ctypes.c_double()
+        if grad:
+            g = tuple(torch.zeros(sh, dtype=torch.float64, device=y0[0].device) for sh in self.shapes(1)[:3])
+            gl = torch.zeros((self.nz, self.nx + 1), dtype=torch.float64, device=y0[0].device)
+            gs = _State(g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(), None)
+            glp = ctypes.c_void_p(gl.data_ptr())
+        else:
+            g, gl = None, None
+            gs = _State(None, None, None, None)
+            glp = None
+        st = lib().nsp_fine_solve_adjoint(self._h, s, int(nsteps), float(dt), int(ckpt_every), ctypes.byref(o), gs,
+                                          glp, ctypes.byref(J), _stream_ptr())
+        self._err(st, "nsp_fine_solve_adjoint")
+        return J.value, g, gl
+
+    def lid_from_modes(self, coef):
+        """lid = 1 + sum c[m,n] sin(m pi x) sin(n pi z) at the top u-faces."""
+        torch = _torch()
+        M = int(coef.shape[0])
+        _check(coef, (M, M), "coef")
+        lid = torch.empty((self.nz, self.nx + 1), dtype=torch.float64, device=coef.device)
+        self._err(lib().nsp_lid_from_modes(self._h, ctypes.c_void_p(coef.data_ptr()), M,
+                                           ctypes.c_void_p(lid.data_ptr()), _stream_ptr()), "nsp_lid_from_modes")
+        return lid
+
+    def lid_modes_grad(self, g_lid, nmodes):
+        torch = _torch()
+        _check(g_lid, (self.nz, self.nx + 1), "g_lid")
+        gc = torch.empty((nmodes, nmodes), dtype=torch.float64, device=g_lid.device)
+        self._err(lib().nsp_lid_modes_grad(self._h, ctypes.c_void_p(g_lid.data_ptr()), int(nmodes),
+                                           ctypes.c_void_p(gc.data_ptr()), _stream_ptr()), "nsp_lid_modes_grad")
+        return gc
+
     def last_launch_ms(self):
         ms = ctypes.c_double()
         self._err(lib().nsp_last_launch_ms(self._h, ctypes.byref(ms)), "nsp_last_launch_ms")
@@ -329,4 +374,4 @@ def group_parareal_iterate(handles, Ys, Fks, Gks, nslices, k, t0, T, dt, DT, fin
 EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
             "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
             "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
-            "nsp_last_launch_ms")
+            "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad")
