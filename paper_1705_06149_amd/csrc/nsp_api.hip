@@ -42,6 +42,7 @@ struct nsp_handle {
     double lx = 1, ly = 1, lz = 1, re = 1;
     int max_batch = 0;
     int tile = 0, ntiles = 0;
+    int cby = 0, cbz = 0, cny = 0, cnz = 0, cgtiles = 0;  // CG column tiles (cby = 0: flat tiles)
     long long ncells = 0, nu = 0, nv = 0, nw = 0;
     double nfluid = 0;
     uint8_t *flags = nullptr;
@@ -221,7 +222,7 @@ bool step_count(double t0, double t1, double dt, int *n) {
 }
 
 void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nslices, int slice0, int tile0,
-                const double *bin) {
+                const double *bin, int cgtile0 = -1) {
     G.nx = h->nx;
     G.ny = h->ny;
     G.nz = h->nz;
@@ -234,6 +235,12 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.nslices = nslices;
     G.slice0 = slice0;
     G.tile0 = tile0;
+    G.cby = h->cby;
+    G.cbz = h->cbz;
+    G.cny = h->cny;
+    G.cnz = h->cnz;
+    G.cgtiles = h->cgtiles;
+    G.cgtile0 = cgtile0 >= 0 ? cgtile0 : slice0 * h->cgtiles;
     G.nfluid = h->nfluid;
     const double hh[3] = {h->lx / h->nx, h->ly / h->ny, h->lz / h->nz};
     for (int d = 0; d < 3; ++d) {
@@ -274,14 +281,16 @@ int auto_workgroups(nsp_handle *h, int batch, int prec, int total_tiles) {
 nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
                const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override) {
     nsp_handle *h = hs[0];
-    int nslices = 0, ntiles = 0;
+    int nslices = 0, ntiles = 0, cgtiles = 0;
     for (int g = 0; g < ngroups; ++g) {
         nslices += groups[g].nslices;
         ntiles += groups[g].nslices * groups[g].ntiles;
+        cgtiles += groups[g].nslices * groups[g].cgtiles;
     }
     if (nslices <= 0) return NSP_OK;
     if (nslices > kMaxSlices) return fail(h, NSP_ERR_ARG, "more than 64 slices in one launch");
-    nsp_status st = ensure_launch_res(h, nslices, ntiles);
+    const int pstride = std::max(ntiles, cgtiles);
+    nsp_status st = ensure_launch_res(h, nslices, pstride);
     if (st != NSP_OK) return st;
     KParams &P = *h->L.params_host;
     // the pinned block may still be read by an earlier copy on this stream
@@ -291,6 +300,8 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.ngroups = ngroups;
     P.nslices = nslices;
     P.ntiles = ntiles;
+    P.cgtiles = cgtiles;
+    P.pstride = pstride;
     P.mode = mode;
     P.nsteps = nsteps;
     P.prec = o->prec == NSP_MIXED ? 1 : 0;
@@ -303,8 +314,9 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.ctl = h->L.ctl;
     P.part = h->L.part;
     P.sync = h->L.sync;
-    int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, ntiles))
-                                     : auto_workgroups(h, nslices, P.prec, ntiles);
+    const int units = std::max(ntiles, cgtiles);
+    int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, units))
+                                     : auto_workgroups(h, nslices, P.prec, units);
     if (wg < 1) wg = 1;
     HIPCHK(h, hipMemsetAsync(h->L.ctl, 0, nslices * sizeof(SliceCtl), stream));
     HIPCHK(h, hipMemcpyAsync(h->L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
@@ -365,13 +377,14 @@ nsp_status propagate(nsp_handle *const *hs, const nsp_state *ys, const int *batc
     int nsteps = 0;
     if (!step_count(t0, t1, step, &nsteps)) return fail(h, NSP_ERR_ARG, "(t1 - t0)/dt is not a non-negative integer");
     GroupDesc G[kMaxGroups];
-    int slice0 = 0, tile0 = 0;
+    int slice0 = 0, tile0 = 0, cgtile0 = 0;
     for (int g = 0; g < ngroups; ++g) {
         if (!hs[g] || !state_ok(ys[g]) || batches[g] < 0 || batches[g] > hs[g]->max_batch)
             return fail(h, NSP_ERR_ARG, "null state pointer or batch outside [0, max_batch]");
-        fill_group(G[g], hs[g], ys[g], 0, batches[g], slice0, tile0, nullptr);
+        fill_group(G[g], hs[g], ys[g], 0, batches[g], slice0, tile0, nullptr, cgtile0);
         slice0 += batches[g];
         tile0 += batches[g] * hs[g]->ntiles;
+        cgtile0 += batches[g] * hs[g]->cgtiles;
     }
     if (nsteps == 0 || slice0 == 0) return NSP_OK;
     return run(hs, ngroups, G, MODE_FINE, nsteps, step, o, static_cast<hipStream_t>(stream), info, 0);
@@ -404,6 +417,18 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     h->nw = (long long)g->nx * g->ny * (g->nz + 1);
     h->tile = tile_for(h->ncells);
     h->ntiles = (int)((h->ncells + h->tile - 1) / h->tile);
+    // CG column tiles for grids of at least 64^3 cells whose rows fit in a
+    // workgroup: cby rows (one workgroup-wide plane patch) by 8 planes
+    if (g->nx <= kBlock && h->ncells >= (1LL << 18)) {
+        h->cby = std::min(kBlock / g->nx, g->ny);
+        h->cbz = 8;
+        h->cny = (g->ny + h->cby - 1) / h->cby;
+        h->cnz = (g->nz + h->cbz - 1) / h->cbz;
+        h->cgtiles = h->cny * h->cnz;
+    } else {
+        h->cby = h->cbz = h->cny = h->cnz = 0;
+        h->cgtiles = h->ntiles;
+    }
     std::vector<uint8_t> fl;
     build_flags(g->nx, g->ny, g->nz, g->solid_host, fl, h->nfluid);
     if (!fluid_connected(g->nx, g->ny, g->nz, fl, h->nfluid)) {
@@ -455,7 +480,8 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     if ((e = hipEventCreate(&h->ev1)) != hipSuccess) return fail_create(e);
     if ((e = max_coresident_workgroups(h->device, &h->max_wg)) != hipSuccess) return fail_create(e);
     if (h->max_wg < 1) return fail_create(hipErrorInvalidValue);
-    if (ensure_launch_res(h, g->max_batch, g->max_batch * h->ntiles) != NSP_OK) return fail_create(hipErrorOutOfMemory);
+    if (ensure_launch_res(h, g->max_batch, g->max_batch * std::max(h->ntiles, h->cgtiles)) != NSP_OK)
+        return fail_create(hipErrorOutOfMemory);
     *out = h;
     return NSP_OK;
 }
@@ -822,7 +848,7 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     for (int i = 0; i < batch; ++i)
         HIPCHK(h, hipMemcpy(b + (long long)i * h->ncells, hb.data(), h->ncells * sizeof(double), hipMemcpyHostToDevice));
     nsp_poisson_opts o{0.0, 40, prec, 1e-30, 1};
-    const int ntiles = batch * h->ntiles;
+    const int ntiles = batch * std::max(h->ntiles, h->cgtiles);
     std::vector<int> cands;
     for (int c : {h->max_wg, h->max_wg * 3 / 4, h->max_wg / 2, h->max_wg / 4, 512, 256, 128})
         if (c >= 1 && c <= std::min(h->max_wg, ntiles) &&

@@ -32,6 +32,13 @@ struct GroupDesc {
     int nslices;           // slices of this grid in the launch
     int slice0;            // first slice index of this grid in the launch
     int tile0;             // first tile index of this grid in the launch
+    // CG tiles (phases of the CG loop).  Column tiles: full x rows, cby rows
+    // in y, cbz planes in z; each thread walks z.  cby == 0: the CG loop
+    // uses the flat tiles above.
+    int cby, cbz;          // rows / planes per column tile
+    int cny, cnz;          // column tiles along y / z
+    int cgtiles;           // CG tiles per slice
+    int cgtile0;           // first CG tile index of this grid in the launch
     double nfluid;         // number of fluid cells
     double ih[3], ih2[3];  // 1/h, 1/h^2 per direction
     float ih2f[3];
@@ -94,6 +101,8 @@ struct KParams {
     int ngroups;
     int nslices;           // total slices in the launch
     int ntiles;            // total tiles in the launch
+    int cgtiles;           // total CG tiles in the launch
+    int pstride;           // max(ntiles, cgtiles): stride of the partial-sum rows
     int mode;
     int nsteps;
     int prec;              // 0 fp64, 1 mixed
@@ -102,7 +111,7 @@ struct KParams {
     double dt;
     double rtol, eta;
     SliceCtl *ctl;         // [nslices]
-    double *part;          // [kNQ][ntiles]
+    double *part;          // [kNQ][pstride]
     SyncWords *sync;
 };
 

@@ -210,14 +210,22 @@ __device__ __forceinline__ double predictor(const GAS GroupDesc &G, const GAS do
 struct Runner {
     const GAS KParams &P;
     int tb, te, ts;        // my tiles: tb, tb + ts, ... < te
+    int cb, ce, cs;        // my CG tiles, same scheme over the CG tile list
     LAS double *s_red;     // [kWaves * kNQ] wave partials
     const LAS double *s_idg;   // [kMaxGroups * 64]
     const LAS float *s_idg32;  // [kMaxGroups * 64]
+    LAS double *s_plane;       // [2 * kBlock]: one plane of a column tile, double-buffered
 
     __device__ __forceinline__ void locate(int t, int &gi, int &sl) const {
         gi = 0;
         while (gi + 1 < P.ngroups && t >= P.g[gi + 1].tile0) ++gi;
         sl = (t - P.g[gi].tile0) / P.g[gi].ntiles;
+    }
+
+    __device__ __forceinline__ void locate_cg(int t, int &gi, int &sl) const {
+        gi = 0;
+        while (gi + 1 < P.ngroups && t >= P.g[gi + 1].cgtile0) ++gi;
+        sl = (t - P.g[gi].cgtile0) / P.g[gi].cgtiles;
     }
 
     // fixed pairwise tree over the per-wave sums of quantity q
@@ -246,7 +254,7 @@ struct Runner {
         if (threadIdx.x < NQ) {
             const int q = threadIdx.x;
             double v = combine_waves(q);
-            gp(P.part)[(long)q * P.ntiles + t] = v;
+            gp(P.part)[(long)q * P.pstride + t] = v;
         }
         __syncthreads();
     }
@@ -325,12 +333,14 @@ struct Runner {
         int gi = 0;
         while (gi + 1 < P.ngroups && s >= P.g[gi + 1].slice0) ++gi;
         const GAS GroupDesc &G = P.g[gi];
-        const long t0 = G.tile0 + (long)(s - G.slice0) * G.ntiles;
+        const bool cg = rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32;
+        const int nt = cg ? G.cgtiles : G.ntiles;
+        const long t0 = (cg ? G.cgtile0 : G.tile0) + (long)(s - G.slice0) * nt;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int q = 0; q < nq; ++q) {
-            const GAS double GAS *pp = gp(P.part) + (long)q * P.ntiles + t0;
+            const GAS double *pp = gp(P.part) + (long)q * P.pstride + t0;
             double v = 0.0;
-            for (int t = threadIdx.x; t < G.ntiles; t += kBlock) v += pp[t];
+            for (int t = threadIdx.x; t < nt; t += kBlock) v += pp[t];
             v = wave_sum(v);
             if (lane == 0) s_red[wv * kNQ + q] = v;
         }
@@ -742,23 +752,211 @@ struct Runner {
         return acc;
     }
 
+    // ---------------------------------------------------- column tiles
+    //
+    // A column tile covers full x rows, rows [y0, y1) and planes [z0, z1) of
+    // one slice.  Thread tid owns (x, y) = (tid % nx, y0 + tid / nx) and
+    // walks z keeping d at planes k-1, k, k+1 in registers (loads for the
+    // next plane are issued one step ahead); the plane k values go to LDS
+    // for the x/y neighbours; the rows just outside [y0, y1) are loaded by
+    // the edge-row threads.  Each cell's r, d, flags are read once.
+
+    struct ColPos {
+        int x, yy, y;
+        bool act, lo, hi;
+        long c0;  // index of (x, y, z0)
+    };
+
+    __device__ __forceinline__ ColPos col_pos(const GAS GroupDesc &G, int y0, int y1, int z0) const {
+        ColPos p;
+        const int tid = threadIdx.x;
+        p.x = tid % G.nx;
+        p.yy = tid / G.nx;
+        p.y = y0 + p.yy;
+        p.act = p.yy < G.cby && p.y < y1;
+        p.lo = p.act && p.yy == 0 && p.y > 0;
+        p.hi = p.act && p.y == y1 - 1 && p.y + 1 < G.ny;
+        p.c0 = p.act ? ((long)z0 * G.ny + p.y) * G.nx + p.x : 0;
+        return p;
+    }
+
+    // phase A over one column tile; returns this thread's share of <d_new, A d_new>
+    template <class T, bool FIRST>
+    __device__ double col_A(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ r,
+                            const GAS T *__restrict__ dold, GAS T *__restrict__ dnew, T beta, int y0, int y1, int z0,
+                            int z1) {
+        const int gb = group_index(G) * 64;
+        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
+        const ColPos P0 = col_pos(G, y0, y1, z0);
+        const int tid = threadIdx.x;
+        LAS T *plane = reinterpret_cast<LAS T *>(s_plane);
+        auto dn = [&](uint8_t f, T rv, T dv) -> T {
+            const T z = rv * idg_of<T>(gb, f);
+            return FIRST ? z : z + beta * dv;
+        };
+        T dm = T(0), dc = T(0);
+        uint8_t fc = 0;
+        // next plane (k+1) and halo rows at plane k, prefetched
+        uint8_t fn = 0, fhl = 0, fhh = 0;
+        T rn = T(0), dvn = T(0), rhl = T(0), dhl = T(0), rhh = T(0), dhh = T(0);
+        if (P0.act) {
+            const long c = P0.c0;
+            if (z0 > 0) dm = dn(fl[c - sz], r[c - sz], FIRST ? T(0) : dold[c - sz]);
+            fc = fl[c];
+            dc = dn(fc, r[c], FIRST ? T(0) : dold[c]);
+            if (z0 + 1 < G.nz) {
+                fn = fl[c + sz];
+                rn = r[c + sz];
+                if (!FIRST) dvn = dold[c + sz];
+            }
+            if (P0.lo) { fhl = fl[c - sy]; rhl = r[c - sy]; if (!FIRST) dhl = dold[c - sy]; }
+            if (P0.hi) { fhh = fl[c + sy]; rhh = r[c + sy]; if (!FIRST) dhh = dold[c + sy]; }
+        }
+        double acc = 0.0;
+        int buf = 0;
+        for (int k = z0; k < z1; ++k) {
+            const long c = P0.c0 + (long)(k - z0) * sz;
+            T dp = T(0), hl = T(0), hh = T(0);
+            uint8_t fp = 0;
+            if (P0.act) {
+                if (k + 1 < G.nz) { fp = fn; dp = dn(fn, rn, dvn); }
+                if (P0.lo) hl = dn(fhl, rhl, dhl);
+                if (P0.hi) hh = dn(fhh, rhh, dhh);
+                if (k + 1 < z1) {
+                    // loads for the next step: plane k+2 and the halo rows at k+1
+                    if (k + 2 < G.nz) {
+                        fn = fl[c + 2 * sz];
+                        rn = r[c + 2 * sz];
+                        if (!FIRST) dvn = dold[c + 2 * sz];
+                    }
+                    if (P0.lo) { fhl = fl[c + sz - sy]; rhl = r[c + sz - sy]; if (!FIRST) dhl = dold[c + sz - sy]; }
+                    if (P0.hi) { fhh = fl[c + sz + sy]; rhh = r[c + sz + sy]; if (!FIRST) dhh = dold[c + sz + sy]; }
+                }
+            }
+            LAS T *pl = plane + buf * kBlock;
+            pl[tid] = dc;
+            __syncthreads();
+            if (P0.act) {
+                T q = T(0);
+                if (fc & FL_XM) q += (dc - pl[tid - 1]) * hx;
+                if (fc & FL_XP) q += (dc - pl[tid + 1]) * hx;
+                if (fc & FL_YM) q += (dc - (P0.yy == 0 ? hl : pl[tid - G.nx])) * hy;
+                if (fc & FL_YP) q += (dc - (P0.y == y1 - 1 ? hh : pl[tid + G.nx])) * hy;
+                if (fc & FL_ZM) q += (dc - dm) * hz;
+                if (fc & FL_ZP) q += (dc - dp) * hz;
+                dnew[c] = dc;
+                acc += (double)dc * (double)q;
+            }
+            dm = dc;
+            dc = dp;
+            fc = fp;
+            buf ^= 1;
+        }
+        return acc;
+    }
+
+    // phase B over one column tile: q = A d from d's planes; x += alpha d,
+    // r -= alpha q; partials <r,z>, <r,r>
+    template <class T>
+    __device__ void col_B(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ d,
+                          GAS T *__restrict__ x, GAS T *__restrict__ r, T alpha, int y0, int y1, int z0, int z1,
+                          double (&acc)[2]) {
+        const int gb = group_index(G) * 64;
+        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
+        const ColPos P0 = col_pos(G, y0, y1, z0);
+        const int tid = threadIdx.x;
+        LAS T *plane = reinterpret_cast<LAS T *>(s_plane);
+        T dm = T(0), dc = T(0), dn1 = T(0), hl = T(0), hh = T(0), xc = T(0), rc = T(0);
+        uint8_t fc = 0, fn1 = 0;
+        if (P0.act) {
+            const long c = P0.c0;
+            if (z0 > 0) dm = d[c - sz];
+            dc = d[c];
+            fc = fl[c];
+            xc = x[c];
+            rc = r[c];
+            if (z0 + 1 < G.nz) { dn1 = d[c + sz]; fn1 = fl[c + sz]; }
+            if (P0.lo) hl = d[c - sy];
+            if (P0.hi) hh = d[c + sy];
+        }
+        int buf = 0;
+        for (int k = z0; k < z1; ++k) {
+            const long c = P0.c0 + (long)(k - z0) * sz;
+            const T dp = dn1;
+            const uint8_t fp = fn1;
+            const T hlk = hl, hhk = hh, xk = xc, rk = rc;
+            if (P0.act && k + 1 < z1) {
+                // loads for the next step
+                if (k + 2 < G.nz) { dn1 = d[c + 2 * sz]; fn1 = fl[c + 2 * sz]; }
+                else { dn1 = T(0); fn1 = 0; }
+                xc = x[c + sz];
+                rc = r[c + sz];
+                if (P0.lo) hl = d[c + sz - sy];
+                if (P0.hi) hh = d[c + sz + sy];
+            }
+            LAS T *pl = plane + buf * kBlock;
+            pl[tid] = dc;
+            __syncthreads();
+            if (P0.act && (fc & FL_FLUID)) {
+                T q = T(0);
+                if (fc & FL_XM) q += (dc - pl[tid - 1]) * hx;
+                if (fc & FL_XP) q += (dc - pl[tid + 1]) * hx;
+                if (fc & FL_YM) q += (dc - (P0.yy == 0 ? hlk : pl[tid - G.nx])) * hy;
+                if (fc & FL_YP) q += (dc - (P0.y == y1 - 1 ? hhk : pl[tid + G.nx])) * hy;
+                if (fc & FL_ZM) q += (dc - dm) * hz;
+                if (fc & FL_ZP) q += (dc - dp) * hz;
+                const T xv = xk + alpha * dc;
+                const T rv = rk - alpha * q;
+                const T z = rv * idg_of<T>(gb, fc);
+                x[c] = xv;
+                r[c] = rv;
+                acc[0] += (double)rv * (double)z;
+                acc[1] += (double)rv * (double)rv;
+            }
+            dm = dc;
+            dc = dp;
+            fc = fp;
+            buf ^= 1;
+        }
+    }
+
+    __device__ __forceinline__ void cg_tile_bounds(const GAS GroupDesc &G, int lt, int &y0, int &y1, int &z0,
+                                                   int &z1) const {
+        const int yb = lt % G.cny, zb = lt / G.cny;
+        y0 = yb * G.cby;
+        y1 = min(y0 + G.cby, G.ny);
+        z0 = zb * G.cbz;
+        z1 = min(z0 + G.cbz, G.nz);
+    }
+
     template <class T>
     __device__ __forceinline__ void phase_A(int par) {
-        for (int t = tb; t < te; t += ts) {
+        for (int t = cb; t < ce; t += cs) {
             int gi, sl;
-            locate(t, gi, sl);
+            locate_cg(t, gi, sl);
             const GAS GroupDesc &G = P.g[gi];
-            const GAS SliceCtl &cs = ctl(G.slice0 + sl);
-            if (!cs.active) continue;
+            const GAS SliceCtl &cs_ = ctl(G.slice0 + sl);
+            if (!cs_.active) continue;
             const long off = (long)sl * G.ncells;
             const GAS T *r = gp(reinterpret_cast<const T *>(G.r)) + off;
             const GAS T *dold = gp(reinterpret_cast<const T *>(par ? G.d1 : G.d0)) + off;
             GAS T *dnew = gp(reinterpret_cast<T *>(par ? G.d0 : G.d1)) + off;
-            const int lt = t - G.tile0 - sl * G.ntiles;
-            const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+            const int lt = t - G.cgtile0 - sl * G.cgtiles;
             double acc[1];
-            if (cs.first) acc[0] = tile_A<T, true>(G, gp(G.flags), r, dold, dnew, T(0), base, end);
-            else acc[0] = tile_A<T, false>(G, gp(G.flags), r, dold, dnew, (T)cs.beta, base, end);
+            const bool first = cs_.first;
+            const T beta = first ? T(0) : (T)cs_.beta;
+            if (G.cby > 0) {
+                int y0, y1, z0, z1;
+                cg_tile_bounds(G, lt, y0, y1, z0, z1);
+                acc[0] = first ? col_A<T, true>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1)
+                               : col_A<T, false>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1);
+            } else {
+                const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+                acc[0] = first ? tile_A<T, true>(G, gp(G.flags), r, dold, dnew, beta, base, end)
+                               : tile_A<T, false>(G, gp(G.flags), r, dold, dnew, beta, base, end);
+            }
             store_partials<1>(acc, t);
         }
     }
@@ -813,20 +1011,26 @@ struct Runner {
     // FP32 (inner solve of the mixed path): e += alpha d; r -= alpha A d.
     template <class T>
     __device__ __forceinline__ void phase_B(int par) {
-        for (int t = tb; t < te; t += ts) {
+        for (int t = cb; t < ce; t += cs) {
             int gi, sl;
-            locate(t, gi, sl);
+            locate_cg(t, gi, sl);
             const GAS GroupDesc &G = P.g[gi];
-            const GAS SliceCtl &cs = ctl(G.slice0 + sl);
-            if (!cs.active) continue;
+            const GAS SliceCtl &cs_ = ctl(G.slice0 + sl);
+            if (!cs_.active) continue;
             const long off = (long)sl * G.ncells;
             const GAS T *d = gp(reinterpret_cast<const T *>(par ? G.d0 : G.d1)) + off;
             GAS T *x = gp(sizeof(T) == 8 ? reinterpret_cast<T *>(G.p) : reinterpret_cast<T *>(G.e)) + off;
             GAS T *r = gp(reinterpret_cast<T *>(G.r)) + off;
-            const int lt = t - G.tile0 - sl * G.ntiles;
-            const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+            const int lt = t - G.cgtile0 - sl * G.cgtiles;
             double acc[2] = {0.0, 0.0};
-            tile_B<T>(G, gp(G.flags), d, x, r, (T)cs.alpha, base, end, acc);
+            if (G.cby > 0) {
+                int y0, y1, z0, z1;
+                cg_tile_bounds(G, lt, y0, y1, z0, z1);
+                col_B<T>(G, gp(G.flags), d, x, r, (T)cs_.alpha, y0, y1, z0, z1, acc);
+            } else {
+                const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+                tile_B<T>(G, gp(G.flags), d, x, r, (T)cs_.alpha, base, end, acc);
+            }
             store_partials<2>(acc, t);
         }
     }
@@ -1029,6 +1233,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
 k_persistent(const KParams *__restrict__ Pp) {
     const GAS KParams &P = *gp(Pp);
     __shared__ double s_red[kWaves * kNQ];
+    __shared__ double s_plane[2 * kBlock];
     __shared__ double s_idg[kMaxGroups * 64];
     __shared__ float s_idg32[kMaxGroups * 64];
     for (int x = threadIdx.x; x < P.ngroups * 64; x += kBlock) {
@@ -1041,17 +1246,25 @@ k_persistent(const KParams *__restrict__ Pp) {
     // tiles, and its workgroups take that range's tiles in turn (stride =
     // workgroups on the XCD), so at any moment they sweep a narrow window of
     // consecutive tiles whose neighbouring planes are still in the XCD's L2.
+    // The CG tiles are scheduled the same way over their own list.
     const int nb = gridDim.x, b = blockIdx.x;
-    int tb = b, te = P.ntiles, ts = nb;
-    if (P.xcd_remap && nb >= 8) {
-        const int x = b & 7, q = nb >> 3, rm = nb & 7;
-        const int first = x * q + min(x, rm), count = q + (x < rm ? 1 : 0);
-        const int x0 = (int)((long)first * P.ntiles / nb), x1 = (int)((long)(first + count) * P.ntiles / nb);
-        tb = x0 + (b >> 3);
-        te = x1;
-        ts = count;
+    int sched[2][3];
+    const int totals[2] = {P.ntiles, P.cgtiles};
+    for (int w = 0; w < 2; ++w) {
+        const int T = totals[w];
+        sched[w][0] = b;
+        sched[w][1] = T;
+        sched[w][2] = nb;
+        if (P.xcd_remap && nb >= 8) {
+            const int x = b & 7, q = nb >> 3, rm = nb & 7;
+            const int first = x * q + min(x, rm), count = q + (x < rm ? 1 : 0);
+            sched[w][0] = (int)((long)first * T / nb) + (b >> 3);
+            sched[w][1] = (int)((long)(first + count) * T / nb);
+            sched[w][2] = count;
+        }
     }
-    Runner R{P, tb, te, ts, (LAS double *)s_red, (const LAS double *)s_idg, (const LAS float *)s_idg32};
+    Runner R{P, sched[0][0], sched[0][1], sched[0][2], sched[1][0], sched[1][1], sched[1][2], (LAS double *)s_red,
+             (const LAS double *)s_idg, (const LAS float *)s_idg32, (LAS double *)s_plane};
     R.run();
 }
 
