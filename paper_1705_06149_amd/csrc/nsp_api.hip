@@ -417,9 +417,10 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     h->nw = (long long)g->nx * g->ny * (g->nz + 1);
     h->tile = tile_for(h->ncells);
     h->ntiles = (int)((h->ncells + h->tile - 1) / h->tile);
-    // CG column tiles for grids of at least 64^3 cells whose rows fit in a
-    // workgroup: cby rows (one workgroup-wide plane patch) by 8 planes
-    if (g->nx <= kBlock && h->ncells >= (1LL << 18)) {
+    // CG column tiles for grids of at least 64^3 cells where two x rows fit in
+    // a workgroup (nx a multiple of 32, so halo rows are whole waves): cby rows
+    // (one workgroup-wide plane patch) by 8 planes
+    if (2 * g->nx <= kBlock && g->nx % 32 == 0 && h->ncells >= (1LL << 18)) {
         h->cby = std::min(kBlock / g->nx, g->ny);
         h->cbz = 8;
         h->cny = (g->ny + h->cby - 1) / h->cby;

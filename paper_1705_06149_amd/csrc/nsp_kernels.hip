@@ -214,7 +214,7 @@ struct Runner {
     LAS double *s_red;     // [kWaves * kNQ] wave partials
     const LAS double *s_idg;   // [kMaxGroups * 64]
     const LAS float *s_idg32;  // [kMaxGroups * 64]
-    LAS double *s_plane;       // [2 * kBlock]: one plane of a column tile, double-buffered
+    LAS double *s_plane;       // two buffers of (cby + 2) * nx: a column tile's plane with halo rows
 
     __device__ __forceinline__ void locate(int t, int &gi, int &sl) const {
         gi = 0;
@@ -761,164 +761,196 @@ struct Runner {
     // for the x/y neighbours; the rows just outside [y0, y1) are loaded by
     // the edge-row threads.  Each cell's r, d, flags are read once.
 
+    // The LDS plane holds rows y0-1 .. y1 of plane k (row y0-1 first); the
+    // halo rows y0-1 and y1 are computed by threads 0 .. 2nx-1 as a second
+    // item (whole waves, since column tiles need nx % 32 == 0 and 2nx <= the
+    // workgroup size).  Halo rows outside the domain are never read (their
+    // faces are closed) and are filled from a valid cell.
     struct ColPos {
-        int x, yy, y;
-        bool act, lo, hi;
-        long c0;  // index of (x, y, z0)
+        int yy, y;
+        bool act;
+        bool halo;  // this thread also computes one halo item
+        long c0;    // index of (x, y, z0); clamped to a valid cell for idle threads
+        long h0;    // index of the halo item at z0 (valid cell)
+        int slot;   // LDS slot of the main item
+        int hslot;  // LDS slot of the halo item
     };
 
     __device__ __forceinline__ ColPos col_pos(const GAS GroupDesc &G, int y0, int y1, int z0) const {
         ColPos p;
-        const int tid = threadIdx.x;
-        p.x = tid % G.nx;
-        p.yy = tid / G.nx;
+        const int tid = threadIdx.x, nx = G.nx;
+        const int x = tid % nx;
+        p.yy = tid / nx;
         p.y = y0 + p.yy;
         p.act = p.yy < G.cby && p.y < y1;
-        p.lo = p.act && p.yy == 0 && p.y > 0;
-        p.hi = p.act && p.y == y1 - 1 && p.y + 1 < G.ny;
-        p.c0 = p.act ? ((long)z0 * G.ny + p.y) * G.nx + p.x : 0;
+        const int yc = p.act ? p.y : y0;
+        p.c0 = ((long)z0 * G.ny + yc) * nx + x;
+        p.slot = (p.act ? p.yy + 1 : 1) * nx + x;
+        p.halo = tid < 2 * nx;
+        const bool upper = tid >= nx;
+        int yh = upper ? y1 : y0 - 1;
+        yh = yh < 0 ? 0 : (yh >= G.ny ? G.ny - 1 : yh);
+        p.h0 = ((long)z0 * G.ny + yh) * nx + x;
+        p.hslot = upper ? (y1 - y0 + 1) * nx + x : x;
         return p;
     }
 
-    // phase A over one column tile; returns this thread's share of <d_new, A d_new>
+    template <class T>
+    struct PlaneLoad {
+        uint8_t f, fh;
+        T a, b, ah, bh, c, d;
+    };
+
+    // phase A over one column tile; returns this thread's share of <d_new, A d_new>.
+    // Loads run two planes ahead: two PlaneLoad sets alternate (the loop is
+    // unrolled by two so that no register copy waits for a load in flight).
     template <class T, bool FIRST>
     __device__ double col_A(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ r,
                             const GAS T *__restrict__ dold, GAS T *__restrict__ dnew, T beta, int y0, int y1, int z0,
                             int z1) {
         const int gb = group_index(G) * 64;
-        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        const long sz = (long)G.nx * G.ny;
+        const int nx = G.nx, nz = G.nz;
         const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
         const ColPos P0 = col_pos(G, y0, y1, z0);
-        const int tid = threadIdx.x;
         LAS T *plane = reinterpret_cast<LAS T *>(s_plane);
+        const int pst = (G.cby + 2) * nx;  // one plane buffer
         auto dn = [&](uint8_t f, T rv, T dv) -> T {
             const T z = rv * idg_of<T>(gb, f);
             return FIRST ? z : z + beta * dv;
         };
-        T dm = T(0), dc = T(0);
-        uint8_t fc = 0;
-        // next plane (k+1) and halo rows at plane k, prefetched
-        uint8_t fn = 0, fhl = 0, fhh = 0;
-        T rn = T(0), dvn = T(0), rhl = T(0), dhl = T(0), rhh = T(0), dhh = T(0);
-        if (P0.act) {
-            const long c = P0.c0;
-            if (z0 > 0) dm = dn(fl[c - sz], r[c - sz], FIRST ? T(0) : dold[c - sz]);
-            fc = fl[c];
-            dc = dn(fc, r[c], FIRST ? T(0) : dold[c]);
-            if (z0 + 1 < G.nz) {
-                fn = fl[c + sz];
-                rn = r[c + sz];
-                if (!FIRST) dvn = dold[c + sz];
+        auto load = [&](int k, PlaneLoad<T> &L) {
+            const long o = (long)(min(k, nz - 1) - z0) * sz;
+            L.f = fl[P0.c0 + o];
+            L.a = r[P0.c0 + o];
+            if (!FIRST) L.b = dold[P0.c0 + o];
+            if (P0.halo) {
+                L.fh = fl[P0.h0 + o];
+                L.ah = r[P0.h0 + o];
+                if (!FIRST) L.bh = dold[P0.h0 + o];
             }
-            if (P0.lo) { fhl = fl[c - sy]; rhl = r[c - sy]; if (!FIRST) dhl = dold[c - sy]; }
-            if (P0.hi) { fhh = fl[c + sy]; rhh = r[c + sy]; if (!FIRST) dhh = dold[c + sy]; }
+        };
+        PlaneLoad<T> L0{}, LA{}, LB{};
+        load(z0, L0);
+        T dm;
+        {
+            const long cm = P0.c0 - (z0 > 0 ? sz : 0);
+            const T v = dn(fl[cm], r[cm], FIRST ? T(0) : dold[cm]);
+            dm = z0 > 0 ? v : T(0);
         }
+        T dc = dn(L0.f, L0.a, L0.b), hc = dn(L0.fh, L0.ah, L0.bh);
+        uint8_t fc = L0.f;
+        load(z0 + 1, LA);
+        load(z0 + 2, LB);
         double acc = 0.0;
         int buf = 0;
-        for (int k = z0; k < z1; ++k) {
+        auto step = [&](int k, PlaneLoad<T> &Lk1) {
             const long c = P0.c0 + (long)(k - z0) * sz;
-            T dp = T(0), hl = T(0), hh = T(0);
-            uint8_t fp = 0;
-            if (P0.act) {
-                if (k + 1 < G.nz) { fp = fn; dp = dn(fn, rn, dvn); }
-                if (P0.lo) hl = dn(fhl, rhl, dhl);
-                if (P0.hi) hh = dn(fhh, rhh, dhh);
-                if (k + 1 < z1) {
-                    // loads for the next step: plane k+2 and the halo rows at k+1
-                    if (k + 2 < G.nz) {
-                        fn = fl[c + 2 * sz];
-                        rn = r[c + 2 * sz];
-                        if (!FIRST) dvn = dold[c + 2 * sz];
-                    }
-                    if (P0.lo) { fhl = fl[c + sz - sy]; rhl = r[c + sz - sy]; if (!FIRST) dhl = dold[c + sz - sy]; }
-                    if (P0.hi) { fhh = fl[c + sz + sy]; rhh = r[c + sz + sy]; if (!FIRST) dhh = dold[c + sz + sy]; }
-                }
-            }
-            LAS T *pl = plane + buf * kBlock;
-            pl[tid] = dc;
+            const T dp = k + 1 < nz ? dn(Lk1.f, Lk1.a, Lk1.b) : T(0);
+            const T hn = dn(Lk1.fh, Lk1.ah, Lk1.bh);
+            const uint8_t fp = Lk1.f;
+            load(k + 3, Lk1);
+            LAS T *pl = plane + buf * pst;
+            if (P0.act) pl[P0.slot] = dc;
+            if (P0.halo) pl[P0.hslot] = hc;
             __syncthreads();
-            if (P0.act) {
-                T q = T(0);
-                if (fc & FL_XM) q += (dc - pl[tid - 1]) * hx;
-                if (fc & FL_XP) q += (dc - pl[tid + 1]) * hx;
-                if (fc & FL_YM) q += (dc - (P0.yy == 0 ? hl : pl[tid - G.nx])) * hy;
-                if (fc & FL_YP) q += (dc - (P0.y == y1 - 1 ? hh : pl[tid + G.nx])) * hy;
-                if (fc & FL_ZM) q += (dc - dm) * hz;
-                if (fc & FL_ZP) q += (dc - dp) * hz;
-                dnew[c] = dc;
-                acc += (double)dc * (double)q;
-            }
+            const int sl = P0.slot;
+            T q = T(0);
+            q += (fc & FL_XM) ? (dc - pl[sl - 1]) * hx : T(0);
+            q += (fc & FL_XP) ? (dc - pl[sl + 1]) * hx : T(0);
+            q += (fc & FL_YM) ? (dc - pl[sl - nx]) * hy : T(0);
+            q += (fc & FL_YP) ? (dc - pl[sl + nx]) * hy : T(0);
+            q += (fc & FL_ZM) ? (dc - dm) * hz : T(0);
+            q += (fc & FL_ZP) ? (dc - dp) * hz : T(0);
+            if (P0.act) dnew[c] = dc;
+            acc += P0.act ? (double)dc * (double)q : 0.0;
             dm = dc;
             dc = dp;
             fc = fp;
+            hc = hn;
             buf ^= 1;
+        };
+        for (int k = z0; k < z1; k += 2) {
+            step(k, LA);
+            if (k + 1 < z1) step(k + 1, LB);
         }
         return acc;
     }
 
     // phase B over one column tile: q = A d from d's planes; x += alpha d,
-    // r -= alpha q; partials <r,z>, <r,r>
+    // r -= alpha q; partials <r,z>, <r,r>.  Loads and halos as in col_A.
     template <class T>
     __device__ void col_B(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ d,
                           GAS T *__restrict__ x, GAS T *__restrict__ r, T alpha, int y0, int y1, int z0, int z1,
                           double (&acc)[2]) {
         const int gb = group_index(G) * 64;
-        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        const long sz = (long)G.nx * G.ny;
+        const int nx = G.nx, nz = G.nz;
         const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
         const ColPos P0 = col_pos(G, y0, y1, z0);
-        const int tid = threadIdx.x;
         LAS T *plane = reinterpret_cast<LAS T *>(s_plane);
-        T dm = T(0), dc = T(0), dn1 = T(0), hl = T(0), hh = T(0), xc = T(0), rc = T(0);
-        uint8_t fc = 0, fn1 = 0;
-        if (P0.act) {
-            const long c = P0.c0;
-            if (z0 > 0) dm = d[c - sz];
-            dc = d[c];
-            fc = fl[c];
-            xc = x[c];
-            rc = r[c];
-            if (z0 + 1 < G.nz) { dn1 = d[c + sz]; fn1 = fl[c + sz]; }
-            if (P0.lo) hl = d[c - sy];
-            if (P0.hi) hh = d[c + sy];
+        const int pst = (G.cby + 2) * nx;
+        // plane k: f, a = d, b = x, c = r; ah = halo d
+        auto load = [&](int k, PlaneLoad<T> &L) {
+            const long o = (long)(min(k, nz - 1) - z0) * sz;
+            L.f = fl[P0.c0 + o];
+            L.a = d[P0.c0 + o];
+            L.b = x[P0.c0 + o];
+            L.c = r[P0.c0 + o];
+            if (P0.halo) L.ah = d[P0.h0 + o];
+        };
+        PlaneLoad<T> L0{}, LA{}, LB{};
+        load(z0, L0);
+        T dm;
+        {
+            const long cm = P0.c0 - (z0 > 0 ? sz : 0);
+            const T v = d[cm];
+            dm = z0 > 0 ? v : T(0);
         }
+        T dc = L0.a, hc = L0.ah, xc = L0.b, rc = L0.c;
+        uint8_t fc = L0.f;
+        load(z0 + 1, LA);
+        load(z0 + 2, LB);
         int buf = 0;
-        for (int k = z0; k < z1; ++k) {
+        auto step = [&](int k, PlaneLoad<T> &Lk1) {
             const long c = P0.c0 + (long)(k - z0) * sz;
-            const T dp = dn1;
-            const uint8_t fp = fn1;
-            const T hlk = hl, hhk = hh, xk = xc, rk = rc;
-            if (P0.act && k + 1 < z1) {
-                // loads for the next step
-                if (k + 2 < G.nz) { dn1 = d[c + 2 * sz]; fn1 = fl[c + 2 * sz]; }
-                else { dn1 = T(0); fn1 = 0; }
-                xc = x[c + sz];
-                rc = r[c + sz];
-                if (P0.lo) hl = d[c + sz - sy];
-                if (P0.hi) hh = d[c + sz + sy];
-            }
-            LAS T *pl = plane + buf * kBlock;
-            pl[tid] = dc;
+            const T dp = k + 1 < nz ? Lk1.a : T(0);
+            const T hn = Lk1.ah, xn = Lk1.b, rn = Lk1.c;
+            const uint8_t fp = Lk1.f;
+            load(k + 3, Lk1);
+            LAS T *pl = plane + buf * pst;
+            if (P0.act) pl[P0.slot] = dc;
+            if (P0.halo) pl[P0.hslot] = hc;
             __syncthreads();
-            if (P0.act && (fc & FL_FLUID)) {
-                T q = T(0);
-                if (fc & FL_XM) q += (dc - pl[tid - 1]) * hx;
-                if (fc & FL_XP) q += (dc - pl[tid + 1]) * hx;
-                if (fc & FL_YM) q += (dc - (P0.yy == 0 ? hlk : pl[tid - G.nx])) * hy;
-                if (fc & FL_YP) q += (dc - (P0.y == y1 - 1 ? hhk : pl[tid + G.nx])) * hy;
-                if (fc & FL_ZM) q += (dc - dm) * hz;
-                if (fc & FL_ZP) q += (dc - dp) * hz;
-                const T xv = xk + alpha * dc;
-                const T rv = rk - alpha * q;
-                const T z = rv * idg_of<T>(gb, fc);
+            const int sl = P0.slot;
+            T q = T(0);
+            q += (fc & FL_XM) ? (dc - pl[sl - 1]) * hx : T(0);
+            q += (fc & FL_XP) ? (dc - pl[sl + 1]) * hx : T(0);
+            q += (fc & FL_YM) ? (dc - pl[sl - nx]) * hy : T(0);
+            q += (fc & FL_YP) ? (dc - pl[sl + nx]) * hy : T(0);
+            q += (fc & FL_ZM) ? (dc - dm) * hz : T(0);
+            q += (fc & FL_ZP) ? (dc - dp) * hz : T(0);
+            const T xv = xc + alpha * dc;
+            const T rv = rc - alpha * q;
+            const T z = rv * idg_of<T>(gb, fc);
+            const bool live = P0.act && (fc & FL_FLUID);
+            if (live) {
                 x[c] = xv;
                 r[c] = rv;
-                acc[0] += (double)rv * (double)z;
-                acc[1] += (double)rv * (double)rv;
             }
+            acc[0] += live ? (double)rv * (double)z : 0.0;
+            acc[1] += live ? (double)rv * (double)rv : 0.0;
             dm = dc;
             dc = dp;
             fc = fp;
+            hc = hn;
+            xc = xn;
+            rc = rn;
             buf ^= 1;
+        };
+        for (int k = z0; k < z1; k += 2) {
+            step(k, LA);
+            if (k + 1 < z1) step(k + 1, LB);
         }
     }
 
@@ -1233,7 +1265,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
 k_persistent(const KParams *__restrict__ Pp) {
     const GAS KParams &P = *gp(Pp);
     __shared__ double s_red[kWaves * kNQ];
-    __shared__ double s_plane[2 * kBlock];
+    __shared__ double s_plane[2 * 2 * kBlock];  // (cby + 2) * nx <= kBlock + 2 nx <= 2 kBlock
     __shared__ double s_idg[kMaxGroups * 64];
     __shared__ float s_idg32[kMaxGroups * 64];
     for (int x = threadIdx.x; x < P.ngroups * 64; x += kBlock) {
