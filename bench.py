@@ -190,7 +190,9 @@ def bench_poisson(args):
                    "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": _traffic_from_profile("k_persistent_poisson32x128_%s_pmc.txt" % args.precision)},
+                     "traffic": _traffic_from_profile("k_persistent_poisson32x128_%s_pmc.txt" % args.precision),
+                     "kernel": "k_persistent (%d CG iterations on %d grids per launch)" % (its, B),
+                     "avg_launch_ms": float(np.mean(ms)), "algorithmic_bytes_per_launch": per_launch},
     }
     h.close()
     return out

@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Turn rocprofv3 CSV output of bench.py runs into the short text summaries
+kept under profiles/.
+
+  trace:   python prof_summary.py trace DIR --kernel k_persistent --last K
+               --bench-json FILE --cmd "..." --out profiles/NAME.txt
+           DIR holds `rocprofv3 --kernel-trace --stats --output-format csv
+           -o run` output; the summary lists the per-kernel statistics and the
+           mean duration of the last K dispatches of the kernel (bench.py's
+           timed launches) beside bench.py's own HIP-event figure.
+
+  traffic: python prof_summary.py traffic --fetch DIR --write DIR
+               --copy-fetch DIR --copy-write DIR --kernel k_persistent --last K
+               --bench-json FILE --hash FILE --cmd "..." --out profiles/NAME.txt
+           The four DIRs hold `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
+           output of the benchmark and of bench.py's 1 GiB copy.  Each counter
+           is scaled by what it reads for the copy (bytes moved / counter
+           bytes), and the summary records HBM bytes per launch of the last K
+           dispatches together with the kernel source hash, which bench.py
+           checks before it reports the figure as `traffic`.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+
+
+def _csv(dirpath, suffix):
+    hits = sorted(glob.glob(os.path.join(dirpath, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise SystemExit("no *%s under %s" % (suffix, dirpath))
+    with open(hits[0], newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _bench_line(path):
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"metric"' in line:
+                return json.loads(line)
+    raise SystemExit("no bench.py JSON line in %s" % path)
+
+
+def _short(name):
+    """Bare kernel name: no return type, namespaces, template or argument list."""
+    name = name.replace("(anonymous namespace)", "")
+    for stop in ("(", "<"):
+        name = name.split(stop)[0]
+    return name.split("::")[-1].split(" ")[-1].strip()
+
+
+def _counter(dirpath, counter, kernel):
+    """Per-dispatch values of one counter for one kernel, in dispatch order."""
+    rows = [r for r in _csv(dirpath, "counter_collection.csv") if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [float(r["Counter_Value"]) for r in rows if _short(r["Kernel_Name"]) == kernel]
+
+
+def cmd_trace(a):
+    stats = _csv(a.dir, "kernel_stats.csv")
+    trace = _csv(a.dir, "kernel_trace.csv")
+    bench = _bench_line(a.bench_json)
+    mine = sorted((r for r in trace if _short(r["Kernel_Name"]) == a.kernel), key=lambda r: int(r["Dispatch_Id"]))
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in mine]
+    last = dur[-a.last:]
+    out = ["# rocprofv3 kernel trace of: %s" % a.cmd,
+           "# workload: %s" % json.dumps(bench.get("config", {})),
+           "#",
+           "# per-kernel statistics (all dispatches of the run)",
+           "%-48s %7s %12s %12s %12s %12s" % ("kernel", "calls", "total_ms", "avg_ms", "min_ms", "max_ms")]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        out.append("%-48s %7d %12.3f %12.4f %12.4f %12.4f" % (
+            _short(r["Name"])[:48], int(r["Calls"]), float(r["TotalDurationNs"]) * 1e-6,
+            float(r["AverageNs"]) * 1e-6, float(r["MinNs"]) * 1e-6, float(r["MaxNs"]) * 1e-6))
+    out += ["#",
+            "kernel=%s" % a.kernel,
+            "dispatches=%d" % len(dur),
+            "timed_dispatches=%d" % len(last),
+            "trace_avg_ms_timed=%.4f" % (sum(last) / max(len(last), 1)),
+            "bench_avg_launch_ms=%s" % bench.get("roofline", {}).get("avg_launch_ms", "n/a"),
+            "bench_value=%s %s" % (bench["value"], bench["unit"])]
+    for k in ("cg_iters_per_step",):
+        if k in bench:
+            out.append("%s=%s" % (k, bench[k]))
+    _write(a.out, out)
+
+
+def cmd_traffic(a):
+    bench = _bench_line(a.bench_json)
+    copy = _bench_line(a.copy_json)
+    nread = copy["config"]["bytes_read_per_launch"]
+    nwrite = copy["config"]["bytes_written_per_launch"]
+    cf = _counter(a.copy_fetch, "FETCH_SIZE", "__amd_rocclr_copyBuffer")
+    cw = _counter(a.copy_write, "WRITE_SIZE", "__amd_rocclr_copyBuffer")
+    cf, cw = cf[-1], cw[-1]
+    sf = nread / (cf * 1024.0)
+    sw = nwrite / (cw * 1024.0)
+    f = _counter(a.fetch, "FETCH_SIZE", a.kernel)[-a.last:]
+    w = _counter(a.write, "WRITE_SIZE", a.kernel)[-a.last:]
+    rd = sf * 1024.0 * sum(f) / len(f)
+    wr = sw * 1024.0 * sum(w) / len(w)
+    with open(a.hash) as fh:
+        h = fh.read().strip()
+    alg = bench.get("roofline", {}).get("algorithmic_bytes_per_launch")
+    out = ["# rocprofv3 HBM counters of: %s" % a.cmd,
+           "# workload: %s" % json.dumps(bench.get("config", {})),
+           "# copy calibration: bench.py --mode copy (1 GiB device copy, __amd_rocclr_copyBuffer)",
+           "copy_fetch_kib=%.3f" % cf,
+           "copy_write_kib=%.3f" % cw,
+           "fetch_scale=%.4f" % sf,
+           "write_scale=%.4f" % sw,
+           "kernel=%s" % a.kernel,
+           "dispatches_used=%d" % len(f),
+           "fetch_kib_per_dispatch=%.1f" % (sum(f) / len(f)),
+           "write_kib_per_dispatch=%.1f" % (sum(w) / len(w)),
+           "hbm_read_bytes_per_launch=%.6e" % rd,
+           "hbm_write_bytes_per_launch=%.6e" % wr,
+           "hbm_bytes_per_launch=%.6e" % (rd + wr)]
+    if alg:
+        out += ["algorithmic_bytes_per_launch=%.6e" % alg,
+                "traffic_over_algorithmic=%.4f" % ((rd + wr) / alg)]
+    out.append("kernel_source_sha256_16=%s" % h)
+    _write(a.out, out)
+
+
+def _write(path, lines):
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--kernel", default="k_persistent")
+    t.add_argument("--last", type=int, required=True)
+    t.add_argument("--bench-json", required=True)
+    t.add_argument("--cmd", required=True)
+    t.add_argument("--out", required=True)
+    p = sub.add_parser("traffic")
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--bench-json", "--copy-json", "--hash", "--cmd",
+              "--out"):
+        p.add_argument(k, required=True)
+    p.add_argument("--kernel", default="k_persistent")
+    p.add_argument("--last", type=int, required=True)
+    a = ap.parse_args()
+    if a.cmd_name == "trace":
+        cmd_trace(a)
+    else:
+        cmd_traffic(a)
+
+
+if __name__ == "__main__":
+    main()
