@@ -200,7 +200,7 @@ nsp_status ensure_launch_res(nsp_handle *h, int nslices, int ntiles) {
     if (ntiles > L.cap_tiles) {
         if (L.part) (void)hipFree(L.part);
         L.part = nullptr;
-        HIPCHK(h, dalloc(&L.part, (size_t)kNQ * ntiles));
+        HIPCHK(h, dalloc(&L.part, (size_t)2 * kNQ * ntiles));
         L.cap_tiles = ntiles;
     }
     return NSP_OK;
@@ -318,6 +318,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, units))
                                      : auto_workgroups(h, nslices, P.prec, units);
     if (wg < 1) wg = 1;
+    if (wg > kMaxWG) wg = kMaxWG;
     HIPCHK(h, hipMemsetAsync(h->L.ctl, 0, nslices * sizeof(SliceCtl), stream));
     HIPCHK(h, hipMemcpyAsync(h->L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
     HIPCHK(h, launch_reset_sync(h->L.sync, stream));

@@ -74,21 +74,15 @@ struct SliceCtl {
 };
 
 // Grid-barrier words.  Every workgroup announces its arrival by storing the
-// barrier's epoch into its own 128-byte line (plain stores: contended
-// device-scope atomics on one address serialize at ~0.4 us each on this
-// part); per-slice reducer workgroups wait for all arrivals, reduce, and
-// store the epoch into their own "done" line; workgroup 0 waits for the
-// reducers, ORs their control flags and publishes one go-word, replicated
-// over 64 lines so that the pollers do not all hit one address.
+// barrier's epoch into its own word (plain stores: contended device-scope
+// atomics on one address serialize at ~0.4 us each on this part).  The words
+// are packed so that a poller reads all arrivals in a few cache lines; every
+// workgroup waits for all of them and then reduces the partials itself.
 constexpr int kMaxWG = 2048;  // workgroups per launch
-constexpr int kLine = 32;     // 32 words = 128 bytes
-constexpr int kGoCopies = 64;
 struct SyncWords {
-    unsigned arrive[kMaxWG * kLine];
-    unsigned done[(kMaxSlices + 1) * kLine];
-    unsigned go[kGoCopies * kLine];  // (epoch << 1) | control bit, replicated
+    unsigned arrive[kMaxWG];
     int abort;         // set when a barrier wait exceeds its spin limit
-    int pad[kLine - 1];
+    int pad[63];
 };
 
 // MODE_FINE: nsteps projection steps on the state; MODE_POISSON: solve
@@ -111,7 +105,7 @@ struct KParams {
     double dt;
     double rtol, eta;
     SliceCtl *ctl;         // [nslices]
-    double *part;          // [kNQ][pstride]
+    double *part;          // [2][kNQ][pstride]: double-buffered by barrier parity
     SyncWords *sync;
 };
 

@@ -215,6 +215,12 @@ struct Runner {
     const LAS double *s_idg;   // [kMaxGroups * 64]
     const LAS float *s_idg32;  // [kMaxGroups * 64]
     LAS double *s_plane;       // two buffers of (cby + 2) * nx: a column tile's plane with halo rows
+    LAS SliceCtl *s_ctl;       // [nslices] this workgroup's copy of the slices' CG state
+    const LAS double *s_nf;    // [nslices] fluid cells of the slice's grid
+    const LAS int *s_pb;       // [nslices][2] first partial of the slice (flat, CG tiles)
+    const LAS int *s_pn;       // [nslices][2] partials of the slice (flat, CG tiles)
+    LAS double *s_sum;         // [nslices][kNQ] reduced sums of the last barrier
+    unsigned epoch = 0;        // barriers passed (uniform over the grid)
 
     __device__ __forceinline__ void locate(int t, int &gi, int &sl) const {
         gi = 0;
@@ -254,7 +260,8 @@ struct Runner {
         if (threadIdx.x < NQ) {
             const int q = threadIdx.x;
             double v = combine_waves(q);
-            gp(P.part)[(long)q * P.pstride + t] = v;
+            // partials feed the next barrier (epoch + 1): buffer of its parity
+            gp(P.part)[(long)(((epoch + 1) & 1) * kNQ + q) * P.pstride + t] = v;
         }
         __syncthreads();
     }
@@ -283,14 +290,13 @@ struct Runner {
 
     // ------------------------------------------------------- grid barrier
 
-    unsigned epoch = 0;
 
     __device__ __forceinline__ bool aborted() const {
         return __hip_atomic_load(&gp(P.sync)->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
 
-    // Wave 0 only: spin until w[i * kLine] >= e for every i < n (all lanes
-    // load their share each round, then vote); then one acquire fence for the
+    // Wave 0 only: spin until w[i] >= e for every i < n (all lanes load
+    // their share each round, then vote); then one acquire fence for the
     // workgroup.  False if the launch was abandoned.
     __device__ __forceinline__ bool wave0_wait_all(const GAS unsigned *w, int n, unsigned e) const {
         const int lane = threadIdx.x & 63;
@@ -299,7 +305,7 @@ struct Runner {
         for (;;) {
             int mine = 1;
             for (int i = lane; i < n; i += 64)
-                mine &= __hip_atomic_load(&w[i * kLine], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= e;
+                mine &= __hip_atomic_load(&w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= e;
             if (__all(mine)) break;
             __builtin_amdgcn_s_sleep(1);
             if ((++spins & 63u) == 0) {
@@ -325,114 +331,75 @@ struct Runner {
         }
     }
 
-    // Fixed-order sum of slice s's tile partials (lane l takes tiles l,
-    // l+256, ...; then the wave butterfly and a fixed four-wave combine),
-    // then the CG scalar logic for the slice.  Whole workgroup.
-    __device__ __forceinline__ void reduce_slice(int rid, int s) {
+    // Every workgroup reduces every slice's partials of the barrier just
+    // passed, in one fixed order (wave w takes slices w, w + 16, ...; lane l
+    // sums partials l, l + 64, ...; the wave butterfly combines the lanes), so
+    // all workgroups obtain bit-identical sums.  Lanes of wave 0 then run the
+    // CG scalar logic, one slice each, on this workgroup's copy of the
+    // control blocks.  Returns the OR of the slices' flags.
+    __device__ __forceinline__ int reduce_all(int rid, int buf) {
+        __shared__ int s_any;
         const int nq = nq_of(rid);
-        int gi = 0;
-        while (gi + 1 < P.ngroups && s >= P.g[gi + 1].slice0) ++gi;
-        const GAS GroupDesc &G = P.g[gi];
-        const bool cg = rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32;
-        const int nt = cg ? G.cgtiles : G.ntiles;
-        const long t0 = (cg ? G.cgtile0 : G.tile0) + (long)(s - G.slice0) * nt;
+        const int cg = (rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32) ? 1 : 0;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        for (int q = 0; q < nq; ++q) {
-            const GAS double *pp = gp(P.part) + (long)q * P.pstride + t0;
-            double v = 0.0;
-            for (int t = threadIdx.x; t < nt; t += kBlock) v += pp[t];
-            v = wave_sum(v);
-            if (lane == 0) s_red[wv * kNQ + q] = v;
+        for (int s = wv; s < P.nslices; s += kWaves) {
+            const GAS double *pp = gp(P.part) + (long)(buf * kNQ) * P.pstride + s_pb[2 * s + cg];
+            const int nt = s_pn[2 * s + cg];
+            double v[kNQ] = {0.0, 0.0, 0.0, 0.0};
+            for (int t = lane; t < nt; t += 64)
+#pragma unroll
+                for (int q = 0; q < kNQ; ++q)
+                    if (q < nq) v[q] += pp[(long)q * P.pstride + t];
+#pragma unroll
+            for (int q = 0; q < kNQ; ++q)
+                if (q < nq) {
+                    const double w = wave_sum(v[q]);
+                    if (lane == 0) s_sum[s * kNQ + q] = w;
+                }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double S[kNQ] = {0.0, 0.0, 0.0, 0.0};
-            for (int q = 0; q < nq; ++q)
-                S[q] = combine_waves(q);
-            P.ctl[s].flag = control(rid, s, S, G.nfluid);
+        if (wv == 0) {
+            int f = 0;
+            if (lane < P.nslices) {
+                double S[kNQ] = {0.0, 0.0, 0.0, 0.0};
+                for (int q = 0; q < nq; ++q) S[q] = s_sum[lane * kNQ + q];
+                f = control(rid, lane, S, s_nf[lane]);
+            }
+            const int any = __any(f != 0) ? 1 : 0;
+            if (lane == 0) s_any = any;
         }
         __syncthreads();
+        return s_any;
     }
 
-    // Grid barrier.  Returns the control word (the OR of the reduced slices'
-    // flags; uniform across the grid), or -1 if the launch was abandoned.
-    // Each workgroup releases once on arrival (thread 0) and acquires once
-    // (wave 0, after it has seen the flag it polls).
+    // Grid barrier.  Returns the control word (the OR of the slices' flags
+    // after the reduction rid; identical in every workgroup), or -1 if the
+    // launch was abandoned.  Each workgroup releases once on arrival (thread
+    // 0), waits for every arrival and acquires (wave 0), then reduces the
+    // partials itself: one hop, no master.  The partial buffers alternate
+    // with the barrier's parity: a workgroup can run at most one barrier
+    // ahead of the slowest reader, so the buffer it writes is never the one
+    // being read.
     __device__ __forceinline__ int sync(int rid) {
-        __shared__ int s_ok, s_ok2, s_go;
+        __shared__ int s_ok;
         const unsigned e = ++epoch;
         GAS SyncWords *S = gp(P.sync);
-        const int nred = rid == R_NONE ? 1 : P.nslices;
-        const bool wave0 = threadIdx.x < 64;
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();  // release this workgroup's results
-            __hip_atomic_store(&S->arrive[blockIdx.x * kLine], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&S->arrive[blockIdx.x], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if ((int)blockIdx.x < nred) {
-            // reducer: every arrival, then this workgroup's slices
-            if (wave0) {
-                const bool ok = wave0_wait_all(S->arrive, gridDim.x, e);
-                if (threadIdx.x == 0) s_ok = ok;
-            }
-            __syncthreads();
-            if (!s_ok) return -1;
-            if (rid != R_NONE)
-                for (int sl = blockIdx.x; sl < nred; sl += gridDim.x) reduce_slice(rid, sl);
-            if (threadIdx.x == 0 && blockIdx.x != 0) {
-                __threadfence();
-                __hip_atomic_store(&S->done[blockIdx.x * kLine], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (blockIdx.x == 0) {
-                // master: the other reducers, then publish the go-word
-                if (wave0) {
-                    bool ok = true;
-                    const int others = min(nred, (int)gridDim.x);
-                    if (others > 1) ok = wave0_wait_all(S->done + kLine, others - 1, e);
-                    int f = 0;
-                    if (rid != R_NONE)
-                        for (int s2 = threadIdx.x; s2 < P.nslices; s2 += 64)
-                            f |= __hip_atomic_load(&gp(P.ctl)[s2].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const int any = __any(f) ? 1 : 0;
-                    if (!ok) { if (threadIdx.x == 0) s_ok2 = 0; }
-                    else {
-                        __threadfence();
-                        __hip_atomic_store(&S->go[threadIdx.x * kLine], (e << 1) | (unsigned)any, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-        }
-        if (wave0) {
-            // everyone: the go-word copy of this workgroup
-            bool ok = true;
-            unsigned v = 0, spins = 0;
-            const GAS unsigned *gw = &S->go[(blockIdx.x % kGoCopies) * kLine];
-            if (threadIdx.x == 0) {
-                for (;;) {
-                    v = __hip_atomic_load(gw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((v >> 1) >= e) break;
-                    __builtin_amdgcn_s_sleep(1);
-                    if ((++spins & 63u) == 0) {
-                        if (aborted()) { ok = false; break; }
-                        if (spins > kSpinLimit) {
-                            __hip_atomic_store(&S->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ok = false;
-                            break;
-                        }
-                    }
-                }
-                s_ok2 = ok;
-                s_go = (int)(v & 1u);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (threadIdx.x < 64) {
+            const bool ok = wave0_wait_all(S->arrive, gridDim.x, e);
+            if (threadIdx.x == 0) s_ok = ok;
         }
         __syncthreads();
-        if (!s_ok2) return -1;
-        return rid == R_NONE ? 0 : s_go;
+        if (!s_ok) return -1;
+        if (rid == R_NONE) return 0;
+        return reduce_all(rid, (int)(e & 1u));
     }
 
-    __device__ __forceinline__ void finish_solve(GAS SliceCtl &c) {
+    __device__ __forceinline__ void finish_solve(LAS SliceCtl &c) {
         c.done = 1;
         c.status = max(c.status, c.step_status);
         c.tot_it += c.it;
@@ -443,7 +410,7 @@ struct Runner {
     // CG scalar logic for one slice after reduction rid; returns this
     // slice's contribution to the control word.
     __device__ __forceinline__ int control(int rid, int s, const double *S, double nf) {
-        GAS SliceCtl &c = gp(P.ctl)[s];
+        LAS SliceCtl &c = s_ctl[s];
         switch (rid) {
         case R_MEANB:
             c.mean_b = S[0] / nf;
@@ -567,10 +534,10 @@ struct Runner {
 
     // ------------------------------------------------------------- phases
 
-    __device__ __forceinline__ const GAS SliceCtl &ctl(int gs) const { return gp(P.ctl)[gs]; }
+    __device__ __forceinline__ const LAS SliceCtl &ctl(int gs) const { return s_ctl[gs]; }
 
     // pressure after the gauge fix of the last solve
-    __device__ __forceinline__ double p_eff(const GAS SliceCtl &c, double p, bool fluid) const {
+    __device__ __forceinline__ double p_eff(const LAS SliceCtl &c, double p, bool fluid) const {
         if (c.zero) return 0.0;
         return fluid ? p - c.mean_p : p;
     }
@@ -969,7 +936,7 @@ struct Runner {
             int gi, sl;
             locate_cg(t, gi, sl);
             const GAS GroupDesc &G = P.g[gi];
-            const GAS SliceCtl &cs_ = ctl(G.slice0 + sl);
+            const LAS SliceCtl &cs_ = ctl(G.slice0 + sl);
             if (!cs_.active) continue;
             const long off = (long)sl * G.ncells;
             const GAS T *r = gp(reinterpret_cast<const T *>(G.r)) + off;
@@ -1047,7 +1014,7 @@ struct Runner {
             int gi, sl;
             locate_cg(t, gi, sl);
             const GAS GroupDesc &G = P.g[gi];
-            const GAS SliceCtl &cs_ = ctl(G.slice0 + sl);
+            const LAS SliceCtl &cs_ = ctl(G.slice0 + sl);
             if (!cs_.active) continue;
             const long off = (long)sl * G.ncells;
             const GAS T *d = gp(reinterpret_cast<const T *>(par ? G.d0 : G.d1)) + off;
@@ -1151,7 +1118,7 @@ struct Runner {
                  [&](const GAS GroupDesc &G, int sl, int gs, int c, double *) {
                      const IJK x = decomp(G, c);
                      const uint8_t fl = gp(G.flags)[c];
-                     const GAS SliceCtl &cs = ctl(gs);
+                     const LAS SliceCtl &cs = ctl(gs);
                      const long off = (long)sl * G.ncells;
                      const double GAS *p = gp(G.p) + off;
                      double GAS *u = gp(G.u) + (long)sl * G.nu, *v = gp(G.v) + (long)sl * G.nv, *w = gp(G.w) + (long)sl * G.nw;
@@ -1295,9 +1262,40 @@ k_persistent(const KParams *__restrict__ Pp) {
             sched[w][2] = count;
         }
     }
+    // per-slice tables and this workgroup's copy of the control blocks
+    __shared__ SliceCtl s_ctl[kMaxSlices];
+    __shared__ double s_nf[kMaxSlices];
+    __shared__ int s_pb[2 * kMaxSlices], s_pn[2 * kMaxSlices];
+    __shared__ double s_sum[kMaxSlices * kNQ];
+    constexpr int kCtlWords = sizeof(SliceCtl) / sizeof(int);
+    static_assert(sizeof(SliceCtl) % sizeof(int) == 0, "SliceCtl is copied as words");
+    {
+        const GAS int *src = reinterpret_cast<const GAS int *>(gp(P.ctl));
+        LAS int *dst = reinterpret_cast<LAS int *>((LAS SliceCtl *)s_ctl);
+        for (int x = threadIdx.x; x < P.nslices * kCtlWords; x += kBlock) dst[x] = src[x];
+        for (int sl = threadIdx.x; sl < P.nslices; sl += kBlock) {
+            int gi = 0;
+            while (gi + 1 < P.ngroups && sl >= P.g[gi + 1].slice0) ++gi;
+            const GAS GroupDesc &G = P.g[gi];
+            s_nf[sl] = G.nfluid;
+            s_pb[2 * sl] = G.tile0 + (sl - G.slice0) * G.ntiles;
+            s_pn[2 * sl] = G.ntiles;
+            s_pb[2 * sl + 1] = G.cgtile0 + (sl - G.slice0) * G.cgtiles;
+            s_pn[2 * sl + 1] = G.cgtiles;
+        }
+    }
+    __syncthreads();
     Runner R{P, sched[0][0], sched[0][1], sched[0][2], sched[1][0], sched[1][1], sched[1][2], (LAS double *)s_red,
-             (const LAS double *)s_idg, (const LAS float *)s_idg32, (LAS double *)s_plane};
+             (const LAS double *)s_idg, (const LAS float *)s_idg32, (LAS double *)s_plane, (LAS SliceCtl *)s_ctl,
+             (const LAS double *)s_nf, (const LAS int *)s_pb, (const LAS int *)s_pn, (LAS double *)s_sum};
     R.run();
+    // every workgroup holds the same control blocks: workgroup 0 returns them
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        GAS int *dst = reinterpret_cast<GAS int *>(gp(P.ctl));
+        const LAS int *src = reinterpret_cast<const LAS int *>((LAS SliceCtl *)s_ctl);
+        for (int x = threadIdx.x; x < P.nslices * kCtlWords; x += kBlock) dst[x] = src[x];
+    }
 }
 
 __global__ void k_reset_sync(SyncWords *s) {
