@@ -13,6 +13,8 @@ Other modes:
   --mode parareal  Parareal on the 96^3 cavity (32 slices of 0.02, fine dt
                    5e-4, coarse dt --coarse-dt, mixed precision, jump < 1e-6)
                    against the serial FP64 fine solve on the GPU
+  --mode obstacles uneven batch: 16 slices on each of 64^3, 96^3, 128^3 with
+                   seeded cuboid obstacles, grouped launches, mixed precision
   --mode copy      a plain device-to-device copy of 1 GiB (torch), the
                    reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE
 
@@ -68,6 +70,11 @@ def _traffic_from_profile(name):
         return float(rec["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _log(*a):
+    """Progress line on stderr (long modes print one per stage)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def _sync():
@@ -202,7 +209,8 @@ def bench_parareal(args):
     import torch
     from paper_1705_06149_amd import nsp
 
-    n, re_, dt, DT, N, T = 96, 1000.0, 5e-4, args.coarse_dt, 32, 0.64
+    n, re_, dt, N, T = 96, 1000.0, 5e-4, 32, 0.64
+    DT = args.coarse_dt if args.coarse_dt is not None else 5e-3
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=1e-5)
@@ -213,6 +221,8 @@ def bench_parareal(args):
     t0 = time.perf_counter()
     for s in range(N):
         h.fine_step(y, s * T / N, (s + 1) * T / N, dt, fine64)
+        if s % 8 == 7:
+            _log("serial fp64 slice %d/%d  %.1f s" % (s + 1, N, time.perf_counter() - t0))
     _sync()
     serial = time.perf_counter() - t0
     ref = tuple(a[0].clone() for a in y)
@@ -232,6 +242,7 @@ def bench_parareal(args):
         jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
         iter_s.append(time.perf_counter() - ti)
         jumps.append(jv)
+        _log("parareal iteration %d: %.1f s, jump %.3e" % (k, iter_s[-1], jv))
         k += 1
         if jv < tol or k >= N or k >= args.max_iters:
             break
@@ -253,6 +264,71 @@ def bench_parareal(args):
         "bound_paper_eq8": N / k,
     }
     h.close()
+    return out
+
+
+def bench_obstacles(args):
+    """Uneven batch: 16 Parareal slices on each of 64^3, 96^3 and 128^3 cavities
+    with seeded cuboid obstacles, every fine sweep one grouped launch."""
+    import torch
+    from paper_1705_06149_amd import inputs, nsp
+
+    grids = [(64, 1), (96, 2), (128, 3)]
+    re_, dt, N, T = 1000.0, 5e-4, 16, 0.32
+    DT = args.coarse_dt if args.coarse_dt is not None else 2.5e-3
+    tol = 1e-6
+    fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
+    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=1e-5)
+    hs = [nsp.Handle(n, n, n, re=re_, solid=inputs.obstacle_mask(n, seed), max_batch=N) for n, seed in grids]
+    # serial FP64 fine solve of each grid, batch 1
+    refs, serial = [], 0.0
+    for (n, _), h in zip(grids, hs):
+        y = h.zeros_state(1)
+        _sync()
+        t0 = time.perf_counter()
+        for s in range(N):
+            h.fine_step(y, s * T / N, (s + 1) * T / N, dt, fine64)
+            _log("serial fp64 %d^3 slice %d/%d  %.1f s" % (n, s + 1, N, time.perf_counter() - t0))
+        _sync()
+        serial += time.perf_counter() - t0
+        refs.append(tuple(a[0].clone() for a in y))
+    Ys = [tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in h.shapes()) for h in hs]
+    Fks = [tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in h.shapes()) for h in hs]
+    Gks = [tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in h.shapes()) for h in hs]
+    _sync()
+    t0 = time.perf_counter()
+    nsp.group_parareal_start(hs, Ys, Gks, N, 0.0, T, DT, mixed)
+    k, jumps, iter_s = 0, [], []
+    while True:
+        ti = time.perf_counter()
+        j = nsp.group_parareal_iterate(hs, Ys, Fks, Gks, N, k, 0.0, T, dt, DT, mixed, mixed)
+        iter_s.append(time.perf_counter() - ti)
+        jumps.append([jv for jv, _ in j])
+        _log("parareal iteration %d: %.1f s, jumps %s" % (k, iter_s[-1], jumps[-1]))
+        k += 1
+        if max(jv for jv, _ in j) < tol or k >= N or k >= args.max_iters:
+            break
+    _sync()
+    par = time.perf_counter() - t0
+    errs = []
+    for Y, ref in zip(Ys, refs):
+        errs.append(float(torch.sqrt(sum(((Y[c][N] - ref[c]) ** 2).sum() for c in range(3)) /
+                                     sum((ref[c] ** 2).sum() for c in range(3)))))
+    cells = sum(n ** 3 for n, _ in grids)
+    nf = int(round(T / dt))
+    out = {
+        "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
+        "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "obstacles_64_96_128", "grids": [n for n, _ in grids], "mask_seeds": [s for _, s in grids],
+                   "slices_per_grid": N, "T": T, "dt": dt, "DT": DT, "jump_tol": tol,
+                   "batch_cells": N * cells},
+        "parareal_iterations": k, "jumps_per_grid": jumps, "iteration_s": iter_s, "serial_fp64_s": serial,
+        "parareal_s": par, "serial_equiv_cell_updates_per_s": cells * nf / par,
+        "end_state_rel_l2_vs_serial_fp64": errs,
+    }
+    for h in hs:
+        h.close()
     return out
 
 
@@ -281,14 +357,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "copy"], default="fine")
+    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "copy"], default="fine")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--max-iters", type=int, default=32)
-    # Forward Euler on the 96^3 grid is stable only while the advective
-    # Courant number plus 2 nu dt sum_d 1/h_d^2 stays below 1: at dt = 1e-2 that
-    # sum is about 0.96 + 0.55 and the coarse propagator blows up; 5e-3 gives
-    # about 0.76.
-    ap.add_argument("--coarse-dt", type=float, default=5e-3)
+    # Forward Euler is stable only while the advective Courant number plus
+    # 2 nu dt sum_d 1/h_d^2 stays below 1.  At dt = 1e-2 that sum is about
+    # 0.96 + 0.55 on the 96^3 grid and the coarse propagator blows up; the
+    # defaults are 5e-3 for the 96^3 Parareal run (about 0.76) and 2.5e-3 for
+    # the obstacle batch, whose 128^3 grid needs dt < ~4.4e-3.
+    ap.add_argument("--coarse-dt", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -304,6 +381,8 @@ def main():
         out = bench_poisson(args)
     elif args.mode == "copy":
         out = bench_copy(args)
+    elif args.mode == "obstacles":
+        out = bench_obstacles(args)
     else:
         out = bench_parareal(args)
     print(json.dumps(out), flush=True)
