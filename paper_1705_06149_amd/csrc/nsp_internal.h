@@ -73,15 +73,24 @@ struct SliceCtl {
     int tot_it, max_it, tot_outer;
 };
 
-// Grid-barrier words.  Every workgroup announces its arrival by storing the
-// barrier's epoch into its own word (plain stores: contended device-scope
-// atomics on one address serialize at ~0.4 us each on this part).  The words
-// are packed so that a poller reads all arrivals in a few cache lines; every
-// workgroup waits for all of them and then reduces the partials itself.
+// Grid-barrier words.  A barrier combines arrivals per XCD: every workgroup
+// waits until its stores are acknowledged by its XCD's L2, then increments
+// that XCD's counter with an L2 atomic; the XCD's last arriver writes the
+// whole L2 back once (one release for all its workgroups, instead of one L2
+// write-back per workgroup, which serialise per XCD) and stores the barrier
+// epoch into the XCD's arrival word; every workgroup polls the eight arrival
+// words.  Start-up uses a plain barrier over per-workgroup words, which also
+// records each workgroup's XCD.
 constexpr int kMaxWG = 2048;  // workgroups per launch
+constexpr int kMaxXcd = 16;   // XCC_ID values
 struct SyncWords {
-    unsigned arrive[kMaxWG];
-    int abort;         // set when a barrier wait exceeds its spin limit
+    unsigned arrive[kMaxWG];        // start-up barrier, one word per workgroup
+    unsigned xof[kMaxWG];           // XCD of each workgroup
+    unsigned xarr[kMaxXcd];         // per-XCD arrival epochs (device scope)
+    unsigned pad0[64 - kMaxXcd];
+    unsigned xcnt[kMaxXcd * 64];    // per-XCD counters, 256 bytes apart; each is
+                                    // only ever touched through its XCD's L2
+    int abort;                      // set when a barrier wait exceeds its spin limit
     int pad[63];
 };
 

@@ -41,6 +41,16 @@ enum Red : int {
     R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32
 };
 
+// s_waitcnt operand (gfx9 encoding) for vmcnt(0) with expcnt/lgkmcnt untouched
+constexpr unsigned kWaitVm0 = 0x0F70;
+
+// Hardware XCD (accelerator complex die) index of the executing workgroup.
+__device__ __forceinline__ unsigned hw_xcc_id() {
+    unsigned x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    return x & (kMaxXcd - 1);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -220,6 +230,8 @@ struct Runner {
     const LAS int *s_pb;       // [nslices][2] first partial of the slice (flat, CG tiles)
     const LAS int *s_pn;       // [nslices][2] partials of the slice (flat, CG tiles)
     LAS double *s_sum;         // [nslices][kNQ] reduced sums of the last barrier
+    const LAS unsigned *s_nx;  // [kMaxXcd] workgroups of this launch on each XCD
+    unsigned xcc;              // this workgroup's XCD
     unsigned epoch = 0;        // barriers passed (uniform over the grid)
 
     __device__ __forceinline__ void locate(int t, int &gi, int &sl) const {
@@ -372,26 +384,86 @@ struct Runner {
         return s_any;
     }
 
+    // Start-up barrier: every workgroup records its XCD, releases, stores
+    // epoch 1 into its own word and waits for all; then wave 0 counts the
+    // workgroups per XCD.  Returns false if the launch was abandoned.
+    __device__ __forceinline__ bool startup(LAS unsigned *nx) {
+        __shared__ int s_ok0;
+        GAS SyncWords *S = gp(P.sync);
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(&S->xof[blockIdx.x], xcc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            __hip_atomic_store(&S->arrive[blockIdx.x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (threadIdx.x < 64) {
+            const bool ok = wave0_wait_all(S->arrive, gridDim.x, 1u);
+            unsigned cnt[kMaxXcd];
+#pragma unroll
+            for (int x = 0; x < kMaxXcd; ++x) cnt[x] = 0;
+            for (int i = threadIdx.x; i < (int)gridDim.x; i += 64) {
+                const unsigned x = __hip_atomic_load(&S->xof[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int y = 0; y < kMaxXcd; ++y) cnt[y] += (x == (unsigned)y) ? 1u : 0u;
+            }
+#pragma unroll
+            for (int y = 0; y < kMaxXcd; ++y) {
+                unsigned v = cnt[y];
+                for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                if (threadIdx.x == 0) nx[y] = v;
+            }
+            if (threadIdx.x == 0) s_ok0 = ok;
+        }
+        __syncthreads();
+        epoch = 1;
+        return s_ok0;
+    }
+
     // Grid barrier.  Returns the control word (the OR of the slices' flags
     // after the reduction rid; identical in every workgroup), or -1 if the
-    // launch was abandoned.  Each workgroup releases once on arrival (thread
-    // 0), waits for every arrival and acquires (wave 0), then reduces the
-    // partials itself: one hop, no master.  The partial buffers alternate
-    // with the barrier's parity: a workgroup can run at most one barrier
-    // ahead of the slowest reader, so the buffer it writes is never the one
-    // being read.
+    // launch was abandoned.  Arrival: each wave waits for its own stores to
+    // be acknowledged by the L2, the workgroup increments its XCD's counter
+    // (an L2 atomic: every workgroup of the XCD shares that L2), and the
+    // XCD's last arriver releases once for the XCD (write-back of the L2)
+    // and publishes the epoch.  Departure: wave 0 polls the XCDs' words and
+    // acquires.  Then every workgroup reduces the partials itself: one hop,
+    // no master.  The partial buffers alternate with the barrier's parity: a
+    // workgroup can run at most one barrier ahead of the slowest reader, so
+    // the buffer it writes is never the one being read.
     __device__ __forceinline__ int sync(int rid) {
         __shared__ int s_ok;
         const unsigned e = ++epoch;
         GAS SyncWords *S = gp(P.sync);
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);  // this wave's stores are in the L2
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();  // release this workgroup's results
-            __hip_atomic_store(&S->arrive[blockIdx.x], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned old = __hip_atomic_fetch_add(&S->xcnt[xcc * 64], 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old + 1u == (e - 1u) * s_nx[xcc]) {
+                __threadfence();  // release the whole XCD's results
+                __hip_atomic_store(&S->xarr[xcc], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         if (threadIdx.x < 64) {
-            const bool ok = wave0_wait_all(S->arrive, gridDim.x, e);
-            if (threadIdx.x == 0) s_ok = ok;
+            const int lane = threadIdx.x;
+            unsigned spins = 0;
+            bool ok = true;
+            for (;;) {
+                int mine = 1;
+                if (lane < kMaxXcd && s_nx[lane] > 0)
+                    mine = __hip_atomic_load(&S->xarr[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= e;
+                if (__all(mine)) break;
+                __builtin_amdgcn_s_sleep(1);
+                if ((++spins & 63u) == 0) {
+                    if (aborted()) { ok = false; break; }
+                    if (spins > kSpinLimit) {
+                        __hip_atomic_store(&S->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = false;
+                        break;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (lane == 0) s_ok = ok;
         }
         __syncthreads();
         if (!s_ok) return -1;
@@ -1285,10 +1357,12 @@ k_persistent(const KParams *__restrict__ Pp) {
         }
     }
     __syncthreads();
+    __shared__ unsigned s_nx[kMaxXcd];
     Runner R{P, sched[0][0], sched[0][1], sched[0][2], sched[1][0], sched[1][1], sched[1][2], (LAS double *)s_red,
              (const LAS double *)s_idg, (const LAS float *)s_idg32, (LAS double *)s_plane, (LAS SliceCtl *)s_ctl,
-             (const LAS double *)s_nf, (const LAS int *)s_pb, (const LAS int *)s_pn, (LAS double *)s_sum};
-    R.run();
+             (const LAS double *)s_nf, (const LAS int *)s_pb, (const LAS int *)s_pn, (LAS double *)s_sum,
+             (const LAS unsigned *)s_nx, hw_xcc_id()};
+    if (R.startup((LAS unsigned *)s_nx)) R.run();
     // every workgroup holds the same control blocks: workgroup 0 returns them
     __syncthreads();
     if (blockIdx.x == 0) {
