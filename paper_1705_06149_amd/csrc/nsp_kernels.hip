@@ -51,10 +51,33 @@ __device__ __forceinline__ unsigned hw_xcc_id() {
     return x & (kMaxXcd - 1);
 }
 
+// v of the lane selected by the DPP control CTRL (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a full wave, in one fixed order (so every wave,
+// workgroup and launch gets the same bits from the same values): pairs,
+// quads, half rows and rows by DPP moves (a + b and b + a are the same
+// double, so each group holds one value), then the four row sums as
+// (r0 + r1) + (r2 + r3).  Returns the same value in every lane.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v = v + dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = v + dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = v + dpp_move<0x141>(v);  // row_half_mirror
+    v = v + dpp_move<0x140>(v);  // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // ---------------------------------------------------------------- geometry
