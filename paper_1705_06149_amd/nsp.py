@@ -61,6 +61,9 @@ def lib():
     """Load libnsp.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch first: its HIP runtime is then the one libnsp binds to (loading
+        # libnsp first and torch afterwards leaves two runtimes in the process)
+        _torch()
         if not os.path.exists(_LIB_PATH):
             raise RuntimeError("libnsp.so is not built: run paper_1705_06149_amd/build.py")
         L = ctypes.CDLL(_LIB_PATH)
