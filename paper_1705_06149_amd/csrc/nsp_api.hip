@@ -42,7 +42,8 @@ struct nsp_handle {
     double lx = 1, ly = 1, lz = 1, re = 1;
     int max_batch = 0;
     int tile = 0, ntiles = 0;
-    int cby = 0, cbz = 0, cny = 0, cnz = 0, cgtiles = 0;  // CG column tiles (cby = 0: flat tiles)
+    int cby = 0, cbz = 0, cny = 0, cnz = 0, cgtiles = 0;  // CG column tiles (cby = 0: flat tiles), depth kZSub
+    int cgparts = 0;                                      // CG partials per slice
     long long ncells = 0, nu = 0, nv = 0, nw = 0;
     double nfluid = 0;
     uint8_t *flags = nullptr;
@@ -241,6 +242,8 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.cnz = h->cnz;
     G.cgtiles = h->cgtiles;
     G.cgtile0 = cgtile0 >= 0 ? cgtile0 : slice0 * h->cgtiles;
+    G.cgparts = h->cgparts;
+    G.cgpart0 = slice0 * h->cgparts;  // launch prefixes are recomputed by run()
     G.nfluid = h->nfluid;
     const double hh[3] = {h->lx / h->nx, h->ly / h->ny, h->lz / h->nz};
     for (int d = 0; d < 3; ++d) {
@@ -278,6 +281,39 @@ int auto_workgroups(nsp_handle *h, int batch, int prec, int total_tiles) {
 
 // Launch the persistent kernel over ngroups groups and read back the
 // per-slice control blocks into info (may be NULL).
+// Launch prefixes of the groups' tiles and partials, and the CG tile depth:
+// the deepest of 1, 2, 4 x kZSub planes that leaves at least two CG tiles
+// per workgroup (deeper tiles refill the z pipeline less often).  Partial
+// sums stay per kZSub planes, so the choice does not change any result.
+void layout_groups(GroupDesc *G, int ngroups, int wg, int *ntiles, int *cgtiles, int *cgparts) {
+    int depth = 1;
+    for (int m : {4, 2}) {
+        long long t = 0;
+        for (int g = 0; g < ngroups; ++g)
+            t += (long long)G[g].nslices *
+                 (G[g].cby > 0 ? (long long)G[g].cny * ((G[g].nz + m * kZSub - 1) / (m * kZSub)) : G[g].cgtiles);
+        if (t >= 2LL * wg) { depth = m; break; }
+    }
+    *ntiles = *cgtiles = *cgparts = 0;
+    int slice0 = 0;
+    for (int g = 0; g < ngroups; ++g) {
+        GroupDesc &X = G[g];
+        if (X.cby > 0) {
+            X.cbz = depth * kZSub;
+            X.cnz = (X.nz + X.cbz - 1) / X.cbz;
+            X.cgtiles = X.cny * X.cnz;
+        }
+        X.slice0 = slice0;
+        X.tile0 = *ntiles;
+        X.cgtile0 = *cgtiles;
+        X.cgpart0 = *cgparts;
+        slice0 += X.nslices;
+        *ntiles += X.nslices * X.ntiles;
+        *cgtiles += X.nslices * X.cgtiles;
+        *cgparts += X.nslices * X.cgparts;
+    }
+}
+
 nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
                const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override) {
     nsp_handle *h = hs[0];
@@ -289,14 +325,25 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     }
     if (nslices <= 0) return NSP_OK;
     if (nslices > kMaxSlices) return fail(h, NSP_ERR_ARG, "more than 64 slices in one launch");
-    const int pstride = std::max(ntiles, cgtiles);
+    if (ngroups > kMaxGroups) return fail(h, NSP_ERR_ARG, "too many grids in one launch");
+    // workgroups from the finest tiling, then the tile depth for that count
+    const int units = std::max(ntiles, cgtiles);
+    int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, units))
+                                     : auto_workgroups(h, nslices, o->prec == NSP_MIXED ? 1 : 0, units);
+    if (wg < 1) wg = 1;
+    if (wg > kMaxWG) wg = kMaxWG;
+    GroupDesc lg[kMaxGroups];
+    for (int g = 0; g < ngroups; ++g) lg[g] = groups[g];
+    int cgparts = 0;
+    layout_groups(lg, ngroups, wg, &ntiles, &cgtiles, &cgparts);
+    const int pstride = std::max(ntiles, cgparts);
     nsp_status st = ensure_launch_res(h, nslices, pstride);
     if (st != NSP_OK) return st;
     KParams &P = *h->L.params_host;
     // the pinned block may still be read by an earlier copy on this stream
     HIPCHK(h, hipStreamSynchronize(stream));
     std::memset(&P, 0, sizeof(P));
-    for (int g = 0; g < ngroups; ++g) P.g[g] = groups[g];
+    for (int g = 0; g < ngroups; ++g) P.g[g] = lg[g];
     P.ngroups = ngroups;
     P.nslices = nslices;
     P.ntiles = ntiles;
@@ -314,11 +361,6 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.ctl = h->L.ctl;
     P.part = h->L.part;
     P.sync = h->L.sync;
-    const int units = std::max(ntiles, cgtiles);
-    int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, units))
-                                     : auto_workgroups(h, nslices, P.prec, units);
-    if (wg < 1) wg = 1;
-    if (wg > kMaxWG) wg = kMaxWG;
     HIPCHK(h, hipMemsetAsync(h->L.ctl, 0, nslices * sizeof(SliceCtl), stream));
     HIPCHK(h, hipMemcpyAsync(h->L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
     HIPCHK(h, launch_reset_sync(h->L.sync, stream));
@@ -423,13 +465,15 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     // (one workgroup-wide plane patch) by 8 planes
     if (2 * g->nx <= kBlock && g->nx % 32 == 0 && h->ncells >= (1LL << 18)) {
         h->cby = std::min(kBlock / g->nx, g->ny);
-        h->cbz = 8;
+        h->cbz = kZSub;
         h->cny = (g->ny + h->cby - 1) / h->cby;
         h->cnz = (g->nz + h->cbz - 1) / h->cbz;
         h->cgtiles = h->cny * h->cnz;
+        h->cgparts = h->cgtiles;
     } else {
         h->cby = h->cbz = h->cny = h->cnz = 0;
         h->cgtiles = h->ntiles;
+        h->cgparts = h->ntiles;
     }
     std::vector<uint8_t> fl;
     build_flags(g->nx, g->ny, g->nz, g->solid_host, fl, h->nfluid);

@@ -12,6 +12,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxGroups = 4;    // grids per launch (uneven batch)
 constexpr int kMaxSlices = 64;   // slices per launch
 constexpr int kNQ = 4;           // partial sums per tile
+constexpr int kZSub = 8;         // planes per CG partial sum of a column tile
 
 // Per-cell flag byte: which of the six faces of the pressure cell are open,
 // whether the cell is fluid, and whether the momentum stencil of the cell's
@@ -33,12 +34,16 @@ struct GroupDesc {
     int slice0;            // first slice index of this grid in the launch
     int tile0;             // first tile index of this grid in the launch
     // CG tiles (phases of the CG loop).  Column tiles: full x rows, cby rows
-    // in y, cbz planes in z; each thread walks z.  cby == 0: the CG loop
-    // uses the flat tiles above.
+    // in y, cbz planes in z (a multiple of kZSub, chosen per launch); each
+    // thread walks z.  Partial sums are kept per kZSub planes of a column
+    // whatever cbz is, so results do not depend on the tile depth.  cby ==
+    // 0: the CG loop uses the flat tiles above (one partial per tile).
     int cby, cbz;          // rows / planes per column tile
     int cny, cnz;          // column tiles along y / z
     int cgtiles;           // CG tiles per slice
     int cgtile0;           // first CG tile index of this grid in the launch
+    int cgparts;           // CG partial sums per slice
+    int cgpart0;           // first CG partial index of this grid in the launch
     double nfluid;         // number of fluid cells
     double ih[3], ih2[3];  // 1/h, 1/h^2 per direction
     float ih2f[3];
@@ -105,7 +110,7 @@ struct KParams {
     int nslices;           // total slices in the launch
     int ntiles;            // total tiles in the launch
     int cgtiles;           // total CG tiles in the launch
-    int pstride;           // max(ntiles, cgtiles): stride of the partial-sum rows
+    int pstride;           // max(flat tiles, CG partials): stride of the partial-sum rows
     int mode;
     int nsteps;
     int prec;              // 0 fp64, 1 mixed

@@ -863,13 +863,14 @@ struct Runner {
         T a, b, ah, bh, c, d;
     };
 
-    // phase A over one column tile; returns this thread's share of <d_new, A d_new>.
-    // Loads run two planes ahead: two PlaneLoad sets alternate (the loop is
-    // unrolled by two so that no register copy waits for a load in flight).
+    // phase A over one column tile; stores <d_new, A d_new> per kZSub planes
+    // as partials pbase + (k / kZSub) * cny + yb.  Loads run two planes
+    // ahead: two PlaneLoad sets alternate (the loop is unrolled by two so
+    // that no register copy waits for a load in flight).
     template <class T, bool FIRST>
-    __device__ double col_A(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ r,
-                            const GAS T *__restrict__ dold, GAS T *__restrict__ dnew, T beta, int y0, int y1, int z0,
-                            int z1) {
+    __device__ void col_A(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ r,
+                          const GAS T *__restrict__ dold, GAS T *__restrict__ dnew, T beta, int y0, int y1, int z0,
+                          int z1, int pbase, int yb) {
         const int gb = group_index(G) * 64;
         const long sz = (long)G.nx * G.ny;
         const int nx = G.nx, nz = G.nz;
@@ -931,20 +932,26 @@ struct Runner {
             fc = fp;
             hc = hn;
             buf ^= 1;
+            if ((k + 1) % kZSub == 0 || k + 1 == z1) {
+                double a1[1] = {acc};
+                store_partials<1>(a1, pbase + (k / kZSub) * G.cny + yb);
+                acc = 0.0;
+            }
         };
         for (int k = z0; k < z1; k += 2) {
             step(k, LA);
             if (k + 1 < z1) step(k + 1, LB);
         }
-        return acc;
     }
 
     // phase B over one column tile: q = A d from d's planes; x += alpha d,
-    // r -= alpha q; partials <r,z>, <r,r>.  Loads and halos as in col_A.
+    // r -= alpha q; partials <r,z>, <r,r> per kZSub planes as in col_A.
+    // Loads and halos as in col_A.
     template <class T>
     __device__ void col_B(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ d,
                           GAS T *__restrict__ x, GAS T *__restrict__ r, T alpha, int y0, int y1, int z0, int z1,
-                          double (&acc)[2]) {
+                          int pbase, int yb) {
+        double acc[2] = {0.0, 0.0};
         const int gb = group_index(G) * 64;
         const long sz = (long)G.nx * G.ny;
         const int nx = G.nx, nz = G.nz;
@@ -1009,6 +1016,10 @@ struct Runner {
             xc = xn;
             rc = rn;
             buf ^= 1;
+            if ((k + 1) % kZSub == 0 || k + 1 == z1) {
+                store_partials<2>(acc, pbase + (k / kZSub) * G.cny + yb);
+                acc[0] = acc[1] = 0.0;
+            }
         };
         for (int k = z0; k < z1; k += 2) {
             step(k, LA);
@@ -1017,8 +1028,9 @@ struct Runner {
     }
 
     __device__ __forceinline__ void cg_tile_bounds(const GAS GroupDesc &G, int lt, int &y0, int &y1, int &z0,
-                                                   int &z1) const {
-        const int yb = lt % G.cny, zb = lt / G.cny;
+                                                   int &z1, int &yb) const {
+        yb = lt % G.cny;
+        const int zb = lt / G.cny;
         y0 = yb * G.cby;
         y1 = min(y0 + G.cby, G.ny);
         z0 = zb * G.cbz;
@@ -1038,20 +1050,21 @@ struct Runner {
             const GAS T *dold = gp(reinterpret_cast<const T *>(par ? G.d1 : G.d0)) + off;
             GAS T *dnew = gp(reinterpret_cast<T *>(par ? G.d0 : G.d1)) + off;
             const int lt = t - G.cgtile0 - sl * G.cgtiles;
-            double acc[1];
             const bool first = cs_.first;
             const T beta = first ? T(0) : (T)cs_.beta;
+            const int pbase = G.cgpart0 + sl * G.cgparts;
             if (G.cby > 0) {
-                int y0, y1, z0, z1;
-                cg_tile_bounds(G, lt, y0, y1, z0, z1);
-                acc[0] = first ? col_A<T, true>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1)
-                               : col_A<T, false>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1);
+                int y0, y1, z0, z1, yb;
+                cg_tile_bounds(G, lt, y0, y1, z0, z1, yb);
+                if (first) col_A<T, true>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
+                else col_A<T, false>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
             } else {
                 const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+                double acc[1];
                 acc[0] = first ? tile_A<T, true>(G, gp(G.flags), r, dold, dnew, beta, base, end)
                                : tile_A<T, false>(G, gp(G.flags), r, dold, dnew, beta, base, end);
+                store_partials<1>(acc, pbase + lt);
             }
-            store_partials<1>(acc, t);
         }
     }
 
@@ -1116,16 +1129,17 @@ struct Runner {
             GAS T *x = gp(sizeof(T) == 8 ? reinterpret_cast<T *>(G.p) : reinterpret_cast<T *>(G.e)) + off;
             GAS T *r = gp(reinterpret_cast<T *>(G.r)) + off;
             const int lt = t - G.cgtile0 - sl * G.cgtiles;
-            double acc[2] = {0.0, 0.0};
+            const int pbase = G.cgpart0 + sl * G.cgparts;
             if (G.cby > 0) {
-                int y0, y1, z0, z1;
-                cg_tile_bounds(G, lt, y0, y1, z0, z1);
-                col_B<T>(G, gp(G.flags), d, x, r, (T)cs_.alpha, y0, y1, z0, z1, acc);
+                int y0, y1, z0, z1, yb;
+                cg_tile_bounds(G, lt, y0, y1, z0, z1, yb);
+                col_B<T>(G, gp(G.flags), d, x, r, (T)cs_.alpha, y0, y1, z0, z1, pbase, yb);
             } else {
                 const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+                double acc[2] = {0.0, 0.0};
                 tile_B<T>(G, gp(G.flags), d, x, r, (T)cs_.alpha, base, end, acc);
+                store_partials<2>(acc, pbase + lt);
             }
-            store_partials<2>(acc, t);
         }
     }
 
@@ -1375,8 +1389,8 @@ k_persistent(const KParams *__restrict__ Pp) {
             s_nf[sl] = G.nfluid;
             s_pb[2 * sl] = G.tile0 + (sl - G.slice0) * G.ntiles;
             s_pn[2 * sl] = G.ntiles;
-            s_pb[2 * sl + 1] = G.cgtile0 + (sl - G.slice0) * G.cgtiles;
-            s_pn[2 * sl + 1] = G.cgtiles;
+            s_pb[2 * sl + 1] = G.cgpart0 + (sl - G.slice0) * G.cgparts;
+            s_pn[2 * sl + 1] = G.cgparts;
         }
     }
     __syncthreads();

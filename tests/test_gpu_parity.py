@@ -167,6 +167,36 @@ def test_batched_equals_unbatched(gpu):
     h.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_column_depth_does_not_change_results(gpu, prec):
+    """128^3 Poisson solves: a batch of 8 runs with 32-plane column tiles, a
+    batch of 1 with 8-plane tiles; partial sums are kept per 8 planes, so the
+    slices must agree bitwise (with obstacles, non-cubic grid too)."""
+    for shape, obst in [((128, 128, 128), False), ((128, 96, 112), True)]:
+        nx, ny, nz = shape
+        _say("column depth independence", shape, "obstacles", obst, "prec", prec)
+        solid = inputs.obstacle_mask(nx, 4)[:nz, :ny, :nx] if obst else None
+        if obst:
+            solid = np.ascontiguousarray(solid)
+            from scipy import ndimage
+            lab, _ = ndimage.label(solid == 0)
+            top = np.unique(lab[:, ny - 1, :])
+            solid[~np.isin(lab, top[top > 0])] = 1
+        fluid = np.ones((nz, ny, nx), bool) if solid is None else solid == 0
+        rng = np.random.default_rng(11)
+        B = 8
+        bs = [mean_free(rng.standard_normal((nz, ny, nx)), fluid) for _ in range(B)]
+        h = gpu.Handle(nx, ny, nz, re=100.0, solid=solid, max_batch=B)
+        opts = gpu.PoissonOpts(rtol=1e-10, prec=prec)
+        pb = T(np.zeros((B, nz, ny, nx)))
+        h.poisson_solve(T(np.stack(bs)), pb, opts)
+        for i in (0, 5):
+            p1 = T(np.zeros((1, nz, ny, nx)))
+            h.poisson_solve(T(bs[i][None]), p1, opts)
+            assert np.array_equal(N(pb)[i], N(p1)[0]), (shape, i)
+        h.close()
+
+
 def test_group_launch_equals_single(gpu):
     """Two grids in one launch (uneven batch) equal separate launches bitwise."""
     _say("group launch == single launches")
