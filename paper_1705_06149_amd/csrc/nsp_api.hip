@@ -355,6 +355,12 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.maxit = o->maxit;
     P.max_outer = o->max_outer;
     P.xcd_remap = 1;
+    {
+        // write-through CG stores while the launch is cache-resident (<= 8 M cells)
+        long long cells = 0;
+        for (int g = 0; g < ngroups; ++g) cells += (long long)lg[g].nslices * lg[g].ncells;
+        P.wt = cells <= (8LL << 20) ? 1 : 0;
+    }
     P.dt = dt;
     P.rtol = o->rtol;
     P.eta = o->inner_rtol;

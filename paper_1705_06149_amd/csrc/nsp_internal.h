@@ -116,6 +116,7 @@ struct KParams {
     int prec;              // 0 fp64, 1 mixed
     int maxit, max_outer;
     int xcd_remap;         // contiguous tile ranges per XCD
+    int wt;                // CG outputs by write-through (device-scope) stores
     double dt;
     double rtol, eta;
     SliceCtl *ctl;         // [nslices]
