@@ -227,7 +227,8 @@ def bench_parareal(args):
     _sync()
     serial = time.perf_counter() - t0
     ref = tuple(a[0].clone() for a in y)
-    # batched mixed-precision Parareal
+    # batched mixed-precision Parareal, launch shape autotuned for the full batch
+    tuned_wg, tuned_planes = h.autotune(N, nsp.MIXED)
     shapes = h.shapes()
     Y = tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in shapes)
     Fk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
@@ -263,6 +264,7 @@ def bench_parareal(args):
         "serial_equiv_cell_updates_per_s": cells * nf / par,
         "end_state_rel_l2_vs_serial_fp64": err,
         "bound_paper_eq8": N / k,
+        "autotuned_launch": {"workgroups": tuned_wg, "cg_tile_planes": tuned_planes},
     }
     h.close()
     return out

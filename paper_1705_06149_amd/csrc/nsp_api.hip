@@ -34,6 +34,7 @@ struct LaunchRes {
 
 struct TuneEntry {
     int batch, prec, workgroups;
+    int depth;  // CG column-tile depth in units of kZSub planes (0: by rule)
 };
 
 struct nsp_handle {
@@ -64,6 +65,7 @@ struct nsp_handle {
     double *adj_lam = nullptr, *adj_mu = nullptr, *adj_p = nullptr, *adj_glid = nullptr, *adj_part = nullptr;
     int max_wg = 0;
     int fixed_wg = 0;
+    int force_depth = 0;  // CG column-tile depth (units of kZSub) forced during autotuning
     std::vector<TuneEntry> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
@@ -282,18 +284,20 @@ int auto_workgroups(nsp_handle *h, int batch, int prec, int total_tiles) {
 // Launch the persistent kernel over ngroups groups and read back the
 // per-slice control blocks into info (may be NULL).
 // Launch prefixes of the groups' tiles and partials, and the CG tile depth:
-// the deepest of 1, 2, 4 x kZSub planes that leaves at least two CG tiles
-// per workgroup (deeper tiles refill the z pipeline less often).  Partial
-// sums stay per kZSub planes, so the choice does not change any result.
-void layout_groups(GroupDesc *G, int ngroups, int wg, int *ntiles, int *cgtiles, int *cgparts) {
-    int depth = 1;
+// `depth` x kZSub planes if depth > 0 (autotuned), else the deepest of 1, 2,
+// 4 x kZSub planes that leaves at least two CG tiles per workgroup (deeper
+// tiles refill the z pipeline less often).  Partial sums stay per kZSub
+// planes, so the choice does not change any result.
+void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int *ntiles, int *cgtiles, int *cgparts) {
     for (int m : {4, 2}) {
+        if (depth > 0) break;
         long long t = 0;
         for (int g = 0; g < ngroups; ++g)
             t += (long long)G[g].nslices *
                  (G[g].cby > 0 ? (long long)G[g].cny * ((G[g].nz + m * kZSub - 1) / (m * kZSub)) : G[g].cgtiles);
         if (t >= 2LL * wg) { depth = m; break; }
     }
+    if (depth <= 0) depth = 1;
     *ntiles = *cgtiles = *cgparts = 0;
     int slice0 = 0;
     for (int g = 0; g < ngroups; ++g) {
@@ -334,8 +338,12 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     if (wg > kMaxWG) wg = kMaxWG;
     GroupDesc lg[kMaxGroups];
     for (int g = 0; g < ngroups; ++g) lg[g] = groups[g];
+    int depth = h->force_depth;
+    if (depth <= 0)
+        for (const TuneEntry &t : h->tuned)
+            if (t.batch == nslices && t.prec == (o->prec == NSP_MIXED ? 1 : 0)) depth = t.depth;
     int cgparts = 0;
-    layout_groups(lg, ngroups, wg, &ntiles, &cgtiles, &cgparts);
+    layout_groups(lg, ngroups, wg, depth, &ntiles, &cgtiles, &cgparts);
     const int pstride = std::max(ntiles, cgparts);
     nsp_status st = ensure_launch_res(h, nslices, pstride);
     if (st != NSP_OK) return st;
@@ -887,7 +895,8 @@ nsp_status nsp_last_launch_ms(const nsp_handle *h, double *ms) {
     return NSP_OK;
 }
 
-nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stream, int *chosen) {
+nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stream, int *chosen,
+                        int *chosen_planes) {
     if (!h || batch < 1 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "bad autotune batch");
     hipStream_t s = static_cast<hipStream_t>(stream);
     // synthetic right-hand side (made mean-free inside the solve); every
@@ -911,30 +920,41 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     nsp_state y{nullptr, nullptr, nullptr, p};
     fill_group(G, h, y, 0, batch, 0, 0, b);
     nsp_handle *hs[1] = {h};
-    int best = cands[0];
+    // column-tile depths (units of kZSub planes); flat tiles have none
+    std::vector<int> depths = {1};
+    if (h->cby > 0) depths = {1, 2, 4};
+    int best = cands[0], best_depth = depths[0];
     double best_ms = 1e30;
-    for (int c : cands) {
-        double tot = 0;
-        for (int rep = 0; rep < 3; ++rep) {
-            HIPCHK(h, hipMemsetAsync(p, 0, (size_t)batch * h->ncells * sizeof(double), s));
-            nsp_status st = run(hs, 1, &G, MODE_POISSON, 0, 1.0, &o, s, nullptr, c);
-            if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
-                (void)hipFree(b);
-                (void)hipFree(p);
-                return st;
+    for (int dep : depths)
+        for (int c : cands) {
+            double tot = 0;
+            h->force_depth = dep;
+            for (int rep = 0; rep < 3; ++rep) {
+                nsp_status st = NSP_OK;
+                if (hipMemsetAsync(p, 0, (size_t)batch * h->ncells * sizeof(double), s) != hipSuccess)
+                    st = fail(h, NSP_ERR_HIP, "autotune: memset failed");
+                if (st == NSP_OK) st = run(hs, 1, &G, MODE_POISSON, 0, 1.0, &o, s, nullptr, c);
+                if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
+                    h->force_depth = 0;
+                    (void)hipFree(b);
+                    (void)hipFree(p);
+                    return st;
+                }
+                if (rep > 0) tot += h->last_ms;
             }
-            if (rep > 0) tot += h->last_ms;
+            if (tot < best_ms) { best_ms = tot; best = c; best_depth = dep; }
         }
-        if (tot < best_ms) { best_ms = tot; best = c; }
-    }
+    h->force_depth = 0;
     (void)hipFree(b);
     (void)hipFree(p);
     const int pr = prec == NSP_MIXED ? 1 : 0;
+    const int keep_depth = h->cby > 0 ? best_depth : 0;
     bool found = false;
     for (TuneEntry &t : h->tuned)
-        if (t.batch == batch && t.prec == pr) { t.workgroups = best; found = true; }
-    if (!found) h->tuned.push_back(TuneEntry{batch, pr, best});
+        if (t.batch == batch && t.prec == pr) { t.workgroups = best; t.depth = keep_depth; found = true; }
+    if (!found) h->tuned.push_back(TuneEntry{batch, pr, best, keep_depth});
     if (chosen) *chosen = best;
+    if (chosen_planes) *chosen_planes = keep_depth * kZSub;
     return NSP_OK;
 }
 

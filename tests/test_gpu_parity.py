@@ -197,6 +197,27 @@ def test_column_depth_does_not_change_results(gpu, prec):
         h.close()
 
 
+def test_autotune_keeps_results(gpu):
+    """nsp_autotune picks a workgroup count and a column depth; the solution
+    computed before and after tuning is bitwise the same."""
+    n, B = 128, 4
+    _say("autotune", n, B)
+    rng = np.random.default_rng(3)
+    fluid = np.ones((n, n, n), bool)
+    b = T(np.stack([mean_free(rng.standard_normal((n, n, n)), fluid) for _ in range(B)]))
+    h = gpu.Handle(n, n, n, re=100.0, max_batch=B)
+    opts = gpu.PoissonOpts(rtol=1e-10)
+    p0 = T(np.zeros((B, n, n, n)))
+    h.poisson_solve(b, p0, opts)
+    wg, planes = h.autotune(B, gpu.FP64)
+    _say("  chose", wg, "workgroups,", planes, "planes")
+    assert wg >= 1 and planes in (8, 16, 32)
+    p1 = T(np.zeros((B, n, n, n)))
+    h.poisson_solve(b, p1, opts)
+    assert np.array_equal(N(p0), N(p1))
+    h.close()
+
+
 def test_group_launch_equals_single(gpu):
     """Two grids in one launch (uneven batch) equal separate launches bitwise."""
     _say("group launch == single launches")
