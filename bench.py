@@ -88,7 +88,7 @@ def bench_fine(args):
 
     n, re_, dt = 128, 1000.0, 5e-4
     prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
-    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=1e-5, max_outer=8)
+    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=args.eta, max_outer=8)
     h = nsp.Handle(n, n, n, re=re_, max_batch=1)
     y = h.zeros_state(1)
     t = 0.0
@@ -110,6 +110,15 @@ def bench_fine(args):
     cells = n ** 3
     K = args.steps
     value = cells * K / wall
+    err_vs_fp64 = None
+    if args.precision == "mixed" and args.compare_fp64:
+        # the same K steps in FP64 from the same warmed state
+        import torch
+        y64 = tuple(torch.from_numpy(a[None].copy()).cuda() for a in host_state)
+        o64 = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=nsp.FP64)
+        h.fine_step(y64, t - K * dt, t, dt, o64)
+        err_vs_fp64 = float(torch.sqrt(sum(((y[c] - y64[c]) ** 2).sum() for c in range(3)) /
+                                       sum((y64[c] ** 2).sum() for c in range(3))))
     per_launch_bytes = cells * (BYTES_STEP_FIXED[args.precision] + BYTES_CG_ITER[args.precision] * iters / K)
     if args.precision == "mixed":
         per_launch_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
@@ -133,6 +142,8 @@ def bench_fine(args):
                    "start": "rest, after %d warm-up steps" % args.warmup, "poisson": "Jacobi-PCG rtol 1e-10",
                    "precision": args.precision},
         "cg_iters_per_step": iters / K,
+        "inner_rtol": args.eta if args.precision == "mixed" else None,
+        "velocity_rel_l2_vs_fp64": err_vs_fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_persistent (one fused fine step per launch)",
@@ -214,7 +225,7 @@ def bench_parareal(args):
     DT = args.coarse_dt if args.coarse_dt is not None else 5e-3
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
-    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=1e-5)
+    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=args.eta)
     h = nsp.Handle(n, n, n, re=re_, max_batch=N)
     # serial FP64 fine solve, batch 1, over [0, T]
     y = h.zeros_state(1)
@@ -281,7 +292,7 @@ def bench_obstacles(args):
     DT = args.coarse_dt if args.coarse_dt is not None else 2.5e-3
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
-    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=1e-5)
+    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=args.eta)
     hs = [nsp.Handle(n, n, n, re=re_, solid=inputs.obstacle_mask(n, seed), max_batch=N) for n, seed in grids]
     # serial FP64 fine solve of each grid, batch 1
     refs, serial = [], 0.0
@@ -370,6 +381,9 @@ def main():
     # the obstacle batch, whose 128^3 grid needs dt < ~4.4e-3.
     ap.add_argument("--coarse-dt", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eta", type=float, default=1e-5, help="inner FP32 tolerance of the mixed Poisson solve")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="mixed fine mode: also run the timed steps in FP64 and report the velocity difference")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (time slices would shard "
