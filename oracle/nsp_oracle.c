@@ -50,6 +50,7 @@ typedef struct {
     double re;
     const uint8_t *solid; /* nz*ny*nx, nonzero = solid; NULL = all fluid */
     const double *lid;    /* nz*(nx+1): wall value of u on the top face (y = Ly) */
+    int periodic_z;       /* 1: periodic in z (the paper's runs), 0: walls at z = 0, Lz */
 } og_grid;
 
 typedef struct {
@@ -64,11 +65,21 @@ typedef struct {
 static double hdir(const og_grid *g, int d) { return d == 0 ? g->hx : (d == 1 ? g->hy : g->hz); }
 static int ndir(const og_grid *g, int d) { return d == 0 ? g->nx : (d == 1 ? g->ny : g->nz); }
 
+/* z index of a cell or face position: wrapped into [0, nz) when the domain
+ * is periodic in z (the w face at z = Lz is then the face at z = 0) */
+static int wrapz(const og_grid *g, int k) {
+    if (!g->periodic_z) return k;
+    k %= g->nz;
+    return k < 0 ? k + g->nz : k;
+}
+
 static size_t cidx(const og_grid *g, int i, int j, int k) {
+    k = wrapz(g, k);
     return ((size_t)k * g->ny + j) * g->nx + i;
 }
 
 static int fluid(const og_grid *g, int i, int j, int k) {
+    k = wrapz(g, k);
     if (i < 0 || i >= g->nx || j < 0 || j >= g->ny || k < 0 || k >= g->nz) return 0;
     if (g->solid && g->solid[cidx(g, i, j, k)]) return 0;
     return 1;
@@ -78,12 +89,21 @@ static int fluid(const og_grid *g, int i, int j, int k) {
 static int fext(const og_grid *g, int c, int d) { return ndir(g, d) + (c == d ? 1 : 0); }
 
 static int face_exists(const og_grid *g, int c, const int f[3]) {
-    for (int d = 0; d < 3; ++d)
+    const int k = wrapz(g, f[2]);
+    for (int d = 0; d < 2; ++d)
         if (f[d] < 0 || f[d] >= fext(g, c, d)) return 0;
-    return 1;
+    return k >= 0 && k < fext(g, c, 2);
 }
 
+/* storage index of a face value; with periodic z the position is wrapped,
+ * so reads of the w plane at z = Lz see the plane at z = 0 */
 static size_t fidx(const og_grid *g, int c, const int f[3]) {
+    return ((size_t)wrapz(g, f[2]) * fext(g, c, 1) + f[1]) * fext(g, c, 0) + f[0];
+}
+
+/* storage index without wrapping: where a sweep over every stored face
+ * writes (the duplicate w plane at z = Lz gets the value of z = 0) */
+static size_t fidx_raw(const og_grid *g, int c, const int f[3]) {
     return ((size_t)f[2] * fext(g, c, 1) + f[1]) * fext(g, c, 0) + f[0];
 }
 
@@ -212,8 +232,8 @@ void og_momentum(const og_grid *g, const double *u, const double *v, const doubl
             for (int j = 0; j < ey; ++j)
                 for (int i = 0; i < ex; ++i) {
                     int f[3] = {i, j, k};
-                    size_t id = fidx(g, c, f);
-                    if (!face_open(g, c, f)) { out[c][id] = 0.0; continue; }
+                    size_t id = fidx(g, c, f), od = fidx_raw(g, c, f);
+                    if (!face_open(g, c, f)) { out[c][od] = 0.0; continue; }
                     double phi0 = vel[c][id];
                     double conv = 0.0, lap = 0.0;
                     for (int d = 0; d < 3; ++d) {
@@ -225,7 +245,7 @@ void og_momentum(const og_grid *g, const double *u, const double *v, const doubl
                         double vm = stencil_val(g, c, vel[c], f, d, -1);
                         lap += (vp - 2.0 * phi0 + vm) / (h * h);
                     }
-                    out[c][id] = phi0 + dt * (lap / g->re - conv);
+                    out[c][od] = phi0 + dt * (lap / g->re - conv);
                 }
     }
 }
@@ -262,11 +282,11 @@ void og_gradient(const og_grid *g, const double *p, double *Gu, double *Gv, doub
             for (int j = 0; j < ey; ++j)
                 for (int i = 0; i < ex; ++i) {
                     int f[3] = {i, j, k};
-                    size_t id = fidx(g, c, f);
-                    if (!face_open(g, c, f)) { out[c][id] = 0.0; continue; }
+                    size_t od = fidx_raw(g, c, f);
+                    if (!face_open(g, c, f)) { out[c][od] = 0.0; continue; }
                     int lo[3] = {i, j, k};
                     lo[c] -= 1;
-                    out[c][id] = (p[cidx(g, i, j, k)] - p[cidx(g, lo[0], lo[1], lo[2])]) / hdir(g, c);
+                    out[c][od] = (p[cidx(g, i, j, k)] - p[cidx(g, lo[0], lo[1], lo[2])]) / hdir(g, c);
                 }
     }
 }
@@ -523,12 +543,12 @@ void og_correct(const og_grid *g, const double *Fu, const double *Fv, const doub
             for (int j = 0; j < ey; ++j)
                 for (int i = 0; i < ex; ++i) {
                     int f[3] = {i, j, k};
-                    size_t id = fidx(g, c, f);
-                    if (!face_open(g, c, f)) { out[c][id] = 0.0; continue; }
+                    size_t id = fidx(g, c, f), od = fidx_raw(g, c, f);
+                    if (!face_open(g, c, f)) { out[c][od] = 0.0; continue; }
                     int lo[3] = {i, j, k};
                     lo[c] -= 1;
                     double gp = (p[cidx(g, i, j, k)] - p[cidx(g, lo[0], lo[1], lo[2])]) / hdir(g, c);
-                    out[c][id] = F[c][id] - dt * gp;
+                    out[c][od] = F[c][id] - dt * gp;
                 }
     }
 }

@@ -39,7 +39,8 @@ def build(force: bool = False) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
-                ("re", ctypes.c_double), ("solid", ctypes.c_void_p), ("lid", ctypes.c_void_p)]
+                ("re", ctypes.c_double), ("solid", ctypes.c_void_p), ("lid", ctypes.c_void_p),
+                ("periodic_z", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -92,6 +93,7 @@ class Grid:
     re: float = 100.0
     solid: np.ndarray | None = None
     lid: np.ndarray | None = None
+    periodic_z: bool = False
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -110,7 +112,8 @@ class Grid:
     def c(self) -> _Grid:
         hx, hy, hz = self.h
         g = _Grid(self.nx, self.ny, self.nz, hx, hy, hz, float(self.re),
-                  self.solid.ctypes.data if self.solid is not None else None, self.lid.ctypes.data)
+                  self.solid.ctypes.data if self.solid is not None else None, self.lid.ctypes.data,
+                  1 if self.periodic_z else 0)
         return g
 
     def shapes(self):
@@ -305,8 +308,14 @@ def stencil_value(g: Grid, c, phi, f, d, m, as_form=False):
     return fn(ctypes.byref(gc), int(c), _p(phi), int(f[0]), int(f[1]), int(f[2]), int(d), int(m))
 
 
+def _no_periodic(g: Grid):
+    if g.periodic_z:
+        raise NotImplementedError("the adjoint is implemented for walls in z only")
+
+
 def momentum_adjoint(g: Grid, u, v, w, dt, mu):
     """lam = mu + dt (dR/du)^T mu and dt (dR/dlid)^T mu at the state (u, v, w)."""
+    _no_periodic(g)
     su, sv, sw, _ = g.shapes()
     u, v, w = _chk(u, su), _chk(v, sv), _chk(w, sw)
     mu = [_chk(m, s) for m, s in zip(mu, (su, sv, sw))]
@@ -356,6 +365,7 @@ def adjoint_gradient(g: Grid, state0, nsteps, dt, rtol=1e-12, ckpt_every=None):
     values (per top u-face position).  Forward states are kept at every
     `ckpt_every`-th step and recomputed inside each segment (all kept if
     None)."""
+    _no_periodic(g)
     ck = ckpt_every or nsteps or 1
     ckpts = {0: tuple(a.copy() for a in state0)}
     y = tuple(a.copy() for a in state0)
