@@ -59,13 +59,16 @@ typedef struct nsp_handle nsp_handle;
  * creation: solid cells approximate obstacles by cell enumeration with
  * no-slip walls.  The fluid cells must form one face-connected region.
  * `max_batch` bounds the batch of every later call; workspace for that many
- * slices is allocated at creation.  periodic_z must be 0 (walls on all six
- * faces). */
+ * slices is allocated at creation.  periodic_z = 0: no-slip walls on all
+ * six faces; periodic_z = 1: periodic in z (the boundary condition of the
+ * paper's runs, Sec. 3), walls in x and y.  With periodic z the w array keeps
+ * its nz+1 planes and the plane at z = lz repeats the plane at z = 0: every
+ * call writes both equal, reads use the plane at z = 0. */
 typedef struct {
     int nx, ny, nz;
     double lx, ly, lz;
     double re;               /* Reynolds number of Eq. (1) */
-    int periodic_z;          /* must be 0 */
+    int periodic_z;          /* 0: walls in z, 1: periodic in z */
     const uint8_t *solid_host;
     int max_batch;
 } nsp_grid;
@@ -100,8 +103,9 @@ typedef struct {
 
 /* Create a handle: copies the grid and the solid mask to the device, sets
  * the lid to u = 1 (Sec. 3, both simulations), allocates workspace for
- * max_batch slices.  Returns NSP_ERR_ARG for non-positive sizes,
- * NSP_ERR_UNSUPPORTED for periodic_z != 0. */
+ * max_batch slices.  Returns NSP_ERR_ARG for non-positive sizes, a
+ * max_batch outside 1..64 or fluid cells that are not face-connected
+ * (across the z seam too when periodic). */
 nsp_status nsp_create(const nsp_grid *grid, nsp_handle **out);
 nsp_status nsp_destroy(nsp_handle *h);
 const char *nsp_last_error(const nsp_handle *h);
@@ -184,7 +188,8 @@ nsp_status nsp_group_parareal_iterate(nsp_handle *const *hs, const nsp_state *Y,
  * initial state) and recomputed segment by segment.  y0 is not modified.
  * The momentum adjoint accumulates with atomic adds, so results may differ
  * between runs in the last bits.  Workspace (checkpoints, one segment) is
- * allocated on first use and kept by the handle. */
+ * allocated on first use and kept by the handle.  NSP_ERR_UNSUPPORTED on a
+ * grid periodic in z. */
 nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
                                   const nsp_poisson_opts *opts, nsp_state grad, double *g_lid, double *J,
                                   void *stream);

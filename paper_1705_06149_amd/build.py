@@ -13,7 +13,11 @@ SOURCES = [os.path.join(CSRC, f) for f in ("nsp_kernels.hip", "nsp_adjoint.hip",
 HEADERS = [os.path.join(CSRC, "nsp_internal.h"), os.path.join(ROOT, "include", "nsp.h")]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 arithmetic.
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+# -ffp-contract=off: no multiply-add is fused behind the code's back, so every
+# instantiation of a kernel (store modes, tile depths, batch sizes) computes
+# the same bits from the same values; batched and single runs stay bitwise
+# equal.
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -63,6 +63,7 @@ struct nsp_handle {
     double *adj_segu = nullptr;  // velocities of one segment: adj_seg states
     double *adj_y = nullptr;     // working state
     double *adj_lam = nullptr, *adj_mu = nullptr, *adj_p = nullptr, *adj_glid = nullptr, *adj_part = nullptr;
+    int pz = 0;  // periodic in z
     int max_wg = 0;
     int fixed_wg = 0;
     int force_depth = 0;  // CG column-tile depth (units of kZSub) forced during autotuning
@@ -105,16 +106,20 @@ int tile_for(long long ncells) {
 // Cell flags: open faces, fluid, and whether any cell within Chebyshev
 // distance 3 is solid or outside the domain (then the momentum stencil of
 // the cell's low faces may meet a wall).
-void build_flags(int nx, int ny, int nz, const uint8_t *solid, std::vector<uint8_t> &fl, double &nfluid) {
+void build_flags(int nx, int ny, int nz, const uint8_t *solid, bool pz, std::vector<uint8_t> &fl, double &nfluid) {
     const long long n = (long long)nx * ny * nz;
     auto id = [&](int i, int j, int k) { return ((long long)k * ny + j) * nx + i; };
+    // neighbours across the z ends wrap when the domain is periodic in z
     auto fluid = [&](int i, int j, int k) {
+        if (pz) k = (k % nz + nz) % nz;
         if (i < 0 || j < 0 || k < 0 || i >= nx || j >= ny || k >= nz) return false;
         return !(solid && solid[id(i, j, k)]);
     };
     fl.assign(n, 0);
     nfluid = 0;
-    // blocked[c] = 1 if cell is solid; dilate by 3 in each direction (box)
+    // blocked[c] = 1 if cell is solid; dilate by 3 in each direction (box);
+    // positions beyond any domain face count as blocked, so cells near the
+    // periodic seam also take the general (image-rule, wrapping) path
     std::vector<uint8_t> bad(n), tmp(n);
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
@@ -158,6 +163,8 @@ void build_flags(int nx, int ny, int nz, const uint8_t *solid, std::vector<uint8
 
 // true when the fluid cells form one face-connected region
 bool fluid_connected(int nx, int ny, int nz, const std::vector<uint8_t> &fl, double nfluid) {
+    // (z neighbours are taken modulo the grid, which only matters across a
+    // periodic seam: with walls the z bits at the ends are never set)
     const long long n = (long long)nx * ny * nz;
     long long start = -1;
     for (long long c = 0; c < n; ++c)
@@ -173,7 +180,7 @@ bool fluid_connected(int nx, int ny, int nz, const std::vector<uint8_t> &fl, dou
         stack.pop_back();
         ++count;
         const uint8_t f = fl[c];
-        const long long nb[6] = {c - 1, c + 1, c - sy, c + sy, c - sz, c + sz};
+        const long long nb[6] = {c - 1, c + 1, c - sy, c + sy, (c - sz + n) % n, (c + sz) % n};
         for (int d = 0; d < 6; ++d)
             if ((f >> d) & 1)
                 if (!seen[nb[d]]) { seen[nb[d]] = 1; stack.push_back(nb[d]); }
@@ -247,6 +254,7 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.cgparts = h->cgparts;
     G.cgpart0 = slice0 * h->cgparts;  // launch prefixes are recomputed by run()
     G.nfluid = h->nfluid;
+    G.pz = h->pz;
     const double hh[3] = {h->lx / h->nx, h->ly / h->ny, h->lz / h->nz};
     for (int d = 0; d < 3; ++d) {
         G.ih[d] = 1.0 / hh[d];
@@ -460,7 +468,6 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
         g->max_batch < 1 || g->max_batch > kMaxSlices)
         return NSP_ERR_ARG;
     if ((long long)g->nx * g->ny * g->nz > (1LL << 30)) return NSP_ERR_ARG;
-    if (g->periodic_z) return NSP_ERR_UNSUPPORTED;
     nsp_handle *h = new (std::nothrow) nsp_handle();
     if (!h) return NSP_ERR_ARG;
     if (hipGetDevice(&h->device) != hipSuccess) { delete h; return NSP_ERR_HIP; }
@@ -468,6 +475,7 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     h->lx = g->lx; h->ly = g->ly; h->lz = g->lz;
     h->re = g->re;
     h->max_batch = g->max_batch;
+    h->pz = g->periodic_z ? 1 : 0;
     h->ncells = (long long)g->nx * g->ny * g->nz;
     h->nu = (long long)(g->nx + 1) * g->ny * g->nz;
     h->nv = (long long)g->nx * (g->ny + 1) * g->nz;
@@ -490,7 +498,7 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
         h->cgparts = h->ntiles;
     }
     std::vector<uint8_t> fl;
-    build_flags(g->nx, g->ny, g->nz, g->solid_host, fl, h->nfluid);
+    build_flags(g->nx, g->ny, g->nz, g->solid_host, h->pz != 0, fl, h->nfluid);
     if (!fluid_connected(g->nx, g->ny, g->nz, fl, h->nfluid)) {
         delete h;
         return NSP_ERR_ARG;
@@ -791,6 +799,7 @@ extern "C" {
 nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
                                   const nsp_poisson_opts *o, nsp_state grad, double *g_lid, double *J, void *stream) {
     if (!h) return NSP_ERR_ARG;
+    if (h->pz) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for walls in z only");
     if (!state_ok(y0) || nsteps < 0 || !(dt > 0) || !J) return fail(h, NSP_ERR_ARG, "bad adjoint arguments");
     if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
     const bool want_grad = grad.u && grad.v && grad.w;

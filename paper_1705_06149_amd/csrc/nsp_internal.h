@@ -45,6 +45,8 @@ struct GroupDesc {
     int cgparts;           // CG partial sums per slice
     int cgpart0;           // first CG partial index of this grid in the launch
     double nfluid;         // number of fluid cells
+    int pz;                // periodic in z: cell k = 0 neighbours k = nz - 1; the w plane at
+                           // z = Lz repeats z = 0 (written equal)
     double ih[3], ih2[3];  // 1/h, 1/h^2 per direction
     float ih2f[3];
     double inv_re;
@@ -69,12 +71,10 @@ struct SliceCtl {
     int it_in;    // iterations of the current inner (FP32) solve
     int need;     // mixed: another defect-correction sweep is needed
     int zero;     // right-hand side is zero: solution is p = 0
-    int restart;  // FP64: restart from the true residual
     int outer;    // restarts / sweeps of the current step
     int done;     // current solve finished for this slice
     int status;   // worst status over the call
     int step_status; // status of the current solve
-    int flag;     // this slice's contribution to the control word
     int tot_it, max_it, tot_outer;
 };
 

@@ -41,6 +41,12 @@ enum Red : int {
     R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32
 };
 
+// a * b + c with one rounding.  The build does not contract expressions on
+// its own; the CG kernels fuse explicitly, so every instantiation computes
+// the same bits.
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // s_waitcnt operand (gfx9 encoding) for vmcnt(0) with expcnt/lgkmcnt untouched
 constexpr unsigned kWaitVm0 = 0x0F70;
 
@@ -114,11 +120,19 @@ __device__ __forceinline__ long cidx(const GAS GroupDesc &G, int i, int j, int k
     return ((long)k * G.ny + j) * G.nx + i;
 }
 
+// z position wrapped into [0, nz) on grids periodic in z; unchanged otherwise
+__device__ __forceinline__ int wrapk(const GAS GroupDesc &G, int k) {
+    if (!G.pz) return k;
+    k %= G.nz;
+    return k < 0 ? k + G.nz : k;
+}
+
 // Face of component C at (i,j,k) separates cells (i,j,k) - e_C and (i,j,k);
 // it is open when both are fluid cells, which the cell's own "minus" bit
 // records.  Positions outside the face array are not open.
 template <int C>
 __device__ __forceinline__ bool face_open(const GAS GroupDesc &G, int i, int j, int k) {
+    k = wrapk(G, k);
     if (i < 0 || j < 0 || k < 0) return false;
     if (i >= G.nx || j >= G.ny || k >= G.nz) return false;  // includes the high boundary face
     const uint8_t bit = C == 0 ? FL_XM : (C == 1 ? FL_YM : FL_ZM);
@@ -171,24 +185,29 @@ __device__ __forceinline__ void line_values(const GAS GroupDesc &G, const GAS do
         return;
     }
     const int di = D == 0, dj = D == 1, dk = D == 2;
+    // value at offset m along D (wrapped across the periodic z seam)
+    auto at = [&](int m) -> double {
+        if (D == 2 && G.pz) return phi[fidx<C>(G, i, j, wrapk(G, k + m))];
+        return phi[id + m * s];
+    };
     const bool om1 = face_open<C>(G, i - di, j - dj, k - dk);
     const bool op1 = face_open<C>(G, i + di, j + dj, k + dk);
     if (C == D) {
-        vm1 = om1 ? phi[id - s] : 0.0;
-        vp1 = op1 ? phi[id + s] : 0.0;
-        vm2 = !om1 ? -phi0 : (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk) ? phi[id - 2 * s] : 0.0);
-        vp2 = !op1 ? -phi0 : (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk) ? phi[id + 2 * s] : 0.0);
+        vm1 = om1 ? at(-1) : 0.0;
+        vp1 = op1 ? at(1) : 0.0;
+        vm2 = !om1 ? -phi0 : (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk) ? at(-2) : 0.0);
+        vp2 = !op1 ? -phi0 : (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk) ? at(2) : 0.0);
     } else {
         const double wm = wall_value<C, D>(G, i, j, k, -1);
         const double wp = wall_value<C, D>(G, i, j, k, +1);
-        vm1 = om1 ? phi[id - s] : 2.0 * wm - phi0;
-        vp1 = op1 ? phi[id + s] : 2.0 * wp - phi0;
+        vm1 = om1 ? at(-1) : 2.0 * wm - phi0;
+        vp1 = op1 ? at(1) : 2.0 * wp - phi0;
         if (!op1) vp2 = 2.0 * wp - vm1;
-        else if (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk)) vp2 = phi[id + 2 * s];
-        else vp2 = 2.0 * wall_value<C, D>(G, i + di, j + dj, k + dk, +1) - phi[id + s];
+        else if (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk)) vp2 = at(2);
+        else vp2 = 2.0 * wall_value<C, D>(G, i + di, j + dj, k + dk, +1) - at(1);
         if (!om1) vm2 = 2.0 * wm - vp1;
-        else if (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk)) vm2 = phi[id - 2 * s];
-        else vm2 = 2.0 * wall_value<C, D>(G, i - di, j - dj, k - dk, -1) - phi[id - s];
+        else if (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk)) vm2 = at(-2);
+        else vm2 = 2.0 * wall_value<C, D>(G, i - di, j - dj, k - dk, -1) - at(-1);
     }
 }
 
@@ -196,6 +215,7 @@ __device__ __forceinline__ void line_values(const GAS GroupDesc &G, const GAS do
 template <bool FAST, int D>
 __device__ __forceinline__ double real_face(const GAS GroupDesc &G, const GAS double *__restrict__ a, int i, int j, int k) {
     if (FAST) return a[fidx<D>(G, i, j, k)];
+    k = wrapk(G, k);
     return face_open<D>(G, i, j, k) ? a[fidx<D>(G, i, j, k)] : 0.0;
 }
 
@@ -659,7 +679,9 @@ struct Runner {
                      Fw[fidx<2>(G, x.i, x.j, x.k)] = fw;
                      if (x.i == G.nx - 1) Fu[fidx<0>(G, G.nx, x.j, x.k)] = 0.0;
                      if (x.j == G.ny - 1) Fv[fidx<1>(G, x.i, G.ny, x.k)] = 0.0;
-                     if (x.k == G.nz - 1) Fw[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
+                     // the w plane at z = Lz: a closed wall, or (periodic) the face at z = 0
+                     if (!G.pz && x.k == G.nz - 1) Fw[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
+                     if (G.pz && x.k == 0) Fw[fidx<2>(G, x.i, x.j, G.nz)] = fw;
                      if (gauge) {
                          double GAS *p = gp(G.p) + (long)sl * G.ncells;
                          p[c] = p_eff(ctl(gs), p[c], fl & FL_FLUID);
@@ -711,8 +733,11 @@ struct Runner {
         if (fl & FL_XP) s += (xc - get(c + 1)) * ih2[0];
         if (fl & FL_YM) s += (xc - get(c - sy)) * ih2[1];
         if (fl & FL_YP) s += (xc - get(c + sy)) * ih2[1];
-        if (fl & FL_ZM) s += (xc - get(c - sz)) * ih2[2];
-        if (fl & FL_ZP) s += (xc - get(c + sz)) * ih2[2];
+        // z neighbours wrap around the slice (used only where the bits are set)
+        const long zm = c - sz < 0 ? c - sz + G.ncells : c - sz;
+        const long zp = c + sz >= G.ncells ? c + sz - G.ncells : c + sz;
+        if (fl & FL_ZM) s += (xc - get(zm)) * ih2[2];
+        if (fl & FL_ZP) s += (xc - get(zp)) * ih2[2];
         return s;
     }
 
@@ -802,7 +827,9 @@ struct Runner {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     long n = cc[u] + off[k];
-                    n = n < 0 ? 0 : (n > last ? last : n);
+                    // wrap into the slice: z neighbours across a periodic seam;
+                    // any other out-of-range neighbour is behind a closed face
+                    n = n < 0 ? n + last + 1 : (n > last ? n - last - 1 : n);
                     fn[u][k] = fl[n];
                     rn[u][k] = r[n];
                     dn[u][k] = FIRST ? T(0) : dold[n];
@@ -810,17 +837,18 @@ struct Runner {
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                const T d0 = FIRST ? rc[u] * idg_of<T>(gb, f[u]) : rc[u] * idg_of<T>(gb, f[u]) + beta * dc[u];
+                const T z0 = rc[u] * idg_of<T>(gb, f[u]);
+                const T d0 = FIRST ? z0 : fmaT(beta, dc[u], z0);
                 T q = T(0);
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
-                    const T dk = FIRST ? rn[u][k] * idg_of<T>(gb, fn[u][k])
-                                       : rn[u][k] * idg_of<T>(gb, fn[u][k]) + beta * dn[u][k];
-                    if (f[u] & (1 << k)) q += (d0 - dk) * h2[k >> 1];
+                    const T zk = rn[u][k] * idg_of<T>(gb, fn[u][k]);
+                    const T dk = FIRST ? zk : fmaT(beta, dn[u][k], zk);
+                    if (f[u] & (1 << k)) q = fmaT(d0 - dk, h2[k >> 1], q);
                 }
                 if (u == 0 || has1) {
                     st_out<WT>(&dnew[cc[u]], d0);
-                    acc += (double)d0 * (double)q;
+                    acc = fmaT((double)d0, (double)q, acc);
                 }
             }
         }
@@ -893,10 +921,12 @@ struct Runner {
         const int pst = (G.cby + 2) * nx;  // one plane buffer
         auto dn = [&](uint8_t f, T rv, T dv) -> T {
             const T z = rv * idg_of<T>(gb, f);
-            return FIRST ? z : z + beta * dv;
+            return FIRST ? z : fmaT(beta, dv, z);
         };
+        // planes beyond nz wrap to the bottom (a periodic seam; with walls the
+        // values are masked by the closed faces)
         auto load = [&](int k, PlaneLoad<T> &L) {
-            const long o = (long)(min(k, nz - 1) - z0) * sz;
+            const long o = (long)(k % nz - z0) * sz;
             L.f = fl[P0.c0 + o];
             L.a = r[P0.c0 + o];
             if (!FIRST) L.b = dold[P0.c0 + o];
@@ -911,18 +941,17 @@ struct Runner {
         load(z0, L0);
         load(z0 + 1, LA);
         load(z0 + 2, LB);
-        const long cm = P0.c0 - (z0 > 0 ? sz : 0);
+        const long cm = z0 > 0 ? P0.c0 - sz : P0.c0 + (long)(nz - 1) * sz;
         const uint8_t fm = fl[cm];
         const T rm = r[cm], om = FIRST ? T(0) : dold[cm];
-        const T dmv = dn(fm, rm, om);
-        T dm = z0 > 0 ? dmv : T(0);
+        T dm = dn(fm, rm, om);
         T dc = dn(L0.f, L0.a, L0.b), hc = dn(L0.fh, L0.ah, L0.bh);
         uint8_t fc = L0.f;
         double acc = 0.0;
         int buf = 0;
         auto step = [&](int k, PlaneLoad<T> &Lk1) {
             const long c = P0.c0 + (long)(k - z0) * sz;
-            const T dp = k + 1 < nz ? dn(Lk1.f, Lk1.a, Lk1.b) : T(0);
+            const T dp = dn(Lk1.f, Lk1.a, Lk1.b);
             const T hn = dn(Lk1.fh, Lk1.ah, Lk1.bh);
             const uint8_t fp = Lk1.f;
             load(k + 3, Lk1);
@@ -932,14 +961,14 @@ struct Runner {
             __syncthreads();
             const int sl = P0.slot;
             T q = T(0);
-            q += (fc & FL_XM) ? (dc - pl[sl - 1]) * hx : T(0);
-            q += (fc & FL_XP) ? (dc - pl[sl + 1]) * hx : T(0);
-            q += (fc & FL_YM) ? (dc - pl[sl - nx]) * hy : T(0);
-            q += (fc & FL_YP) ? (dc - pl[sl + nx]) * hy : T(0);
-            q += (fc & FL_ZM) ? (dc - dm) * hz : T(0);
-            q += (fc & FL_ZP) ? (dc - dp) * hz : T(0);
+            q = (fc & FL_XM) ? fmaT(dc - pl[sl - 1], hx, q) : q;
+            q = (fc & FL_XP) ? fmaT(dc - pl[sl + 1], hx, q) : q;
+            q = (fc & FL_YM) ? fmaT(dc - pl[sl - nx], hy, q) : q;
+            q = (fc & FL_YP) ? fmaT(dc - pl[sl + nx], hy, q) : q;
+            q = (fc & FL_ZM) ? fmaT(dc - dm, hz, q) : q;
+            q = (fc & FL_ZP) ? fmaT(dc - dp, hz, q) : q;
             if (P0.act) st_out<WT>(&dnew[c], dc);
-            acc += P0.act ? (double)dc * (double)q : 0.0;
+            acc = P0.act ? fmaT((double)dc, (double)q, acc) : acc;
             dm = dc;
             dc = dp;
             fc = fp;
@@ -974,7 +1003,7 @@ struct Runner {
         const int pst = (G.cby + 2) * nx;
         // plane k: f, a = d, b = x, c = r; ah = halo d
         auto load = [&](int k, PlaneLoad<T> &L) {
-            const long o = (long)(min(k, nz - 1) - z0) * sz;
+            const long o = (long)(k % nz - z0) * sz;
             L.f = fl[P0.c0 + o];
             L.a = d[P0.c0 + o];
             L.b = x[P0.c0 + o];
@@ -986,14 +1015,13 @@ struct Runner {
         load(z0, L0);
         load(z0 + 1, LA);
         load(z0 + 2, LB);
-        const T dmv = d[P0.c0 - (z0 > 0 ? sz : 0)];
-        T dm = z0 > 0 ? dmv : T(0);
+        T dm = d[z0 > 0 ? P0.c0 - sz : P0.c0 + (long)(nz - 1) * sz];
         T dc = L0.a, hc = L0.ah, xc = L0.b, rc = L0.c;
         uint8_t fc = L0.f;
         int buf = 0;
         auto step = [&](int k, PlaneLoad<T> &Lk1) {
             const long c = P0.c0 + (long)(k - z0) * sz;
-            const T dp = k + 1 < nz ? Lk1.a : T(0);
+            const T dp = Lk1.a;
             const T hn = Lk1.ah, xn = Lk1.b, rn = Lk1.c;
             const uint8_t fp = Lk1.f;
             load(k + 3, Lk1);
@@ -1003,22 +1031,22 @@ struct Runner {
             __syncthreads();
             const int sl = P0.slot;
             T q = T(0);
-            q += (fc & FL_XM) ? (dc - pl[sl - 1]) * hx : T(0);
-            q += (fc & FL_XP) ? (dc - pl[sl + 1]) * hx : T(0);
-            q += (fc & FL_YM) ? (dc - pl[sl - nx]) * hy : T(0);
-            q += (fc & FL_YP) ? (dc - pl[sl + nx]) * hy : T(0);
-            q += (fc & FL_ZM) ? (dc - dm) * hz : T(0);
-            q += (fc & FL_ZP) ? (dc - dp) * hz : T(0);
-            const T xv = xc + alpha * dc;
-            const T rv = rc - alpha * q;
+            q = (fc & FL_XM) ? fmaT(dc - pl[sl - 1], hx, q) : q;
+            q = (fc & FL_XP) ? fmaT(dc - pl[sl + 1], hx, q) : q;
+            q = (fc & FL_YM) ? fmaT(dc - pl[sl - nx], hy, q) : q;
+            q = (fc & FL_YP) ? fmaT(dc - pl[sl + nx], hy, q) : q;
+            q = (fc & FL_ZM) ? fmaT(dc - dm, hz, q) : q;
+            q = (fc & FL_ZP) ? fmaT(dc - dp, hz, q) : q;
+            const T xv = fmaT(alpha, dc, xc);
+            const T rv = fmaT(-alpha, q, rc);
             const T z = rv * idg_of<T>(gb, fc);
             const bool live = P0.act && (fc & FL_FLUID);
             if (live) {
                 st_out<WT>(&x[c], xv);
                 st_out<WT>(&r[c], rv);
             }
-            acc[0] += live ? (double)rv * (double)z : 0.0;
-            acc[1] += live ? (double)rv * (double)rv : 0.0;
+            acc[0] = live ? fmaT((double)rv, (double)z, acc[0]) : acc[0];
+            acc[1] = live ? fmaT((double)rv, (double)rv, acc[1]) : acc[1];
             dm = dc;
             dc = dp;
             fc = fp;
@@ -1110,7 +1138,9 @@ struct Runner {
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     long n = cc[u] + off[k];
-                    n = n < 0 ? 0 : (n > last ? last : n);
+                    // wrap into the slice: z neighbours across a periodic seam;
+                    // any other out-of-range neighbour is behind a closed face
+                    n = n < 0 ? n + last + 1 : (n > last ? n - last - 1 : n);
                     dn[u][k] = d[n];
                 }
             }
@@ -1119,15 +1149,15 @@ struct Runner {
                 T q = T(0);
 #pragma unroll
                 for (int k = 0; k < 6; ++k)
-                    if (f[u] & (1 << k)) q += (dc[u] - dn[u][k]) * h2[k >> 1];
-                const T xv = xc[u] + alpha * dc[u];
-                const T rv = rc[u] - alpha * q;
+                    if (f[u] & (1 << k)) q = fmaT(dc[u] - dn[u][k], h2[k >> 1], q);
+                const T xv = fmaT(alpha, dc[u], xc[u]);
+                const T rv = fmaT(-alpha, q, rc[u]);
                 const T z = rv * idg_of<T>(gb, f[u]);
                 if (u == 0 || has1) {
                     st_out<WT>(&x[cc[u]], xv);
                     st_out<WT>(&r[cc[u]], rv);
-                    acc[0] += (double)rv * (double)z;
-                    acc[1] += (double)rv * (double)rv;
+                    acc[0] = fmaT((double)rv, (double)z, acc[0]);
+                    acc[1] = fmaT((double)rv, (double)rv, acc[1]);
                 }
             }
         }
@@ -1259,11 +1289,13 @@ struct Runner {
                      const double pc = p_eff(cs, p[c], true);
                      u[iu] = (fl & FL_XM) ? Fu[iu] - P.dt * ((pc - p_eff(cs, p[c - 1], true)) * G.ih[0]) : 0.0;
                      v[iv] = (fl & FL_YM) ? Fv[iv] - P.dt * ((pc - p_eff(cs, p[c - G.nx], true)) * G.ih[1]) : 0.0;
-                     w[iw] = (fl & FL_ZM) ? Fw[iw] - P.dt * ((pc - p_eff(cs, p[c - (long)G.nx * G.ny], true)) * G.ih[2])
-                                          : 0.0;
+                     const long czm = x.k > 0 ? c - (long)G.nx * G.ny : c - (long)G.nx * G.ny + G.ncells;
+                     const double wv = (fl & FL_ZM) ? Fw[iw] - P.dt * ((pc - p_eff(cs, p[czm], true)) * G.ih[2]) : 0.0;
+                     w[iw] = wv;
                      if (x.i == G.nx - 1) u[fidx<0>(G, G.nx, x.j, x.k)] = 0.0;
                      if (x.j == G.ny - 1) v[fidx<1>(G, x.i, G.ny, x.k)] = 0.0;
-                     if (x.k == G.nz - 1) w[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
+                     if (!G.pz && x.k == G.nz - 1) w[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
+                     if (G.pz && x.k == 0) w[fidx<2>(G, x.i, x.j, G.nz)] = wv;
                  });
     }
 

@@ -141,8 +141,9 @@ def _check(t, shape, name):
 class Handle:
     """One grid (nsp_create / nsp_destroy)."""
 
-    def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, re=100.0, solid=None, max_batch=1):
+    def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, re=100.0, solid=None, max_batch=1, periodic_z=False):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.periodic_z = bool(periodic_z)
         self.lx, self.ly, self.lz, self.re = float(lx), float(ly), float(lz), float(re)
         self.max_batch = int(max_batch)
         self._solid = None
@@ -151,7 +152,7 @@ class Handle:
             if s.shape != (self.nz, self.ny, self.nx):
                 raise ValueError("solid mask must have shape (nz, ny, nx)")
             self._solid = s
-        g = _Grid(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.re, 0,
+        g = _Grid(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.re, 1 if self.periodic_z else 0,
                   self._solid.ctypes.data if self._solid is not None else None, self.max_batch)
         h = ctypes.c_void_p()
         st = lib().nsp_create(ctypes.byref(g), ctypes.byref(h))

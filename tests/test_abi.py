@@ -44,8 +44,8 @@ def test_create_rejects_bad_grid_without_touching_gpu():
     h = ctypes.c_void_p()
     bad = nsp._Grid(0, 4, 4, 1.0, 1.0, 1.0, 100.0, 0, None, 1)
     assert L.nsp_create(ctypes.byref(bad), ctypes.byref(h)) == nsp.NSP_ERR_ARG
-    per = nsp._Grid(4, 4, 4, 1.0, 1.0, 1.0, 100.0, 1, None, 1)
-    assert L.nsp_create(ctypes.byref(per), ctypes.byref(h)) == nsp.NSP_ERR_UNSUPPORTED
+    flat = nsp._Grid(4, 4, 4, 1.0, 0.0, 1.0, 100.0, 1, None, 1)
+    assert L.nsp_create(ctypes.byref(flat), ctypes.byref(h)) == nsp.NSP_ERR_ARG
     big = nsp._Grid(4, 4, 4, 1.0, 1.0, 1.0, 100.0, 0, None, 65)
     assert L.nsp_create(ctypes.byref(big), ctypes.byref(h)) == nsp.NSP_ERR_ARG
     assert L.nsp_destroy(None) == nsp.NSP_ERR_ARG
