@@ -15,6 +15,9 @@ Other modes:
                    against the serial FP64 fine solve on the GPU
   --mode obstacles uneven batch: 16 slices on each of 64^3, 96^3, 128^3 with
                    seeded cuboid obstacles, grouped launches, mixed precision
+  --mode sim1      the paper's first test case: 32 x 32 x 5 quasi-2D cavity,
+                   periodic in z, Re 1000, dt 1e-3 / 1e-2, FP64 Parareal;
+                   defect against the serial fine solution per iteration
   --mode copy      a plain device-to-device copy of 1 GiB (torch), the
                    reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE
 
@@ -346,6 +349,71 @@ def bench_obstacles(args):
     return out
 
 
+def bench_sim1(args):
+    """The paper's first test case (Sec. 3, Table 1): a quasi-2D lid-driven
+    cavity of 32 x 32 x 5 cells on [0,1]^2 x [0,0.1], periodic in z, Re 1000,
+    fine dt 1e-3, coarse dt 1e-2, FP64.  Reports, per Parareal iteration, the
+    defect of every slice end against the serial fine solution (max norm over
+    u, v, w and over p), the quantity the paper plots against N_it."""
+    import torch
+    from paper_1705_06149_amd import nsp
+
+    nx, ny, nz, lz = 32, 32, 5, 0.1
+    re_, dt, DT = 1000.0, 1e-3, 1e-2
+    N, T = args.slices, args.sim_t
+    o64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
+    h = nsp.Handle(nx, ny, nz, lz=lz, re=re_, max_batch=N, periodic_z=True)
+    shapes = h.shapes()
+    ref = tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in shapes)
+    y = h.zeros_state(1)
+    _sync()
+    t0 = time.perf_counter()
+    for n in range(N):
+        h.fine_step(y, n * T / N, (n + 1) * T / N, dt, o64)
+        for c in range(4):
+            ref[c][n + 1].copy_(y[c][0])
+        _log("serial fine slice %d/%d  %.1f s" % (n + 1, N, time.perf_counter() - t0))
+    _sync()
+    serial = time.perf_counter() - t0
+    Y = tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in shapes)
+    Fk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
+    Gk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
+
+    def defect():
+        dv = max(float((Y[c][1:] - ref[c][1:]).abs().max()) for c in range(3))
+        return dv, float((Y[3][1:] - ref[3][1:]).abs().max())
+
+    _sync()
+    t0 = time.perf_counter()
+    h.parareal_start(Y, Gk, N, 0.0, T, DT, o64)
+    defects = [defect()]
+    jumps = []
+    k = 0
+    while k < min(N, args.max_iters):
+        jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, o64, o64)
+        jumps.append((jv, jp))
+        k += 1
+        defects.append(defect())
+        _log("parareal iteration %d: jump %.3e, defect vs serial u,v,w %.3e p %.3e  %.1f s" %
+             (k, jv, defects[-1][0], defects[-1][1], time.perf_counter() - t0))
+    _sync()
+    par = time.perf_counter() - t0
+    nf = int(round(T / dt))
+    out = {
+        "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
+        "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "paper_sim1", "grid": [nx, ny, nz], "domain": [1.0, 1.0, lz], "periodic_z": True,
+                   "re": re_, "slices": N, "T": T, "dt": dt, "DT": DT},
+        "parareal_iterations": k, "serial_fp64_s": serial, "parareal_s": par,
+        "defect_vs_serial_uvw_per_iteration": [d[0] for d in defects],
+        "defect_vs_serial_p_per_iteration": [d[1] for d in defects],
+        "jumps_uvw": [j[0] for j in jumps], "jumps_p": [j[1] for j in jumps],
+    }
+    h.close()
+    return out
+
+
 def bench_copy(args):
     import torch
     nbytes = 1 << 30
@@ -371,9 +439,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "copy"], default="fine")
+    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "copy"], default="fine")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--max-iters", type=int, default=32)
+    ap.add_argument("--slices", type=int, default=16, help="sim1 mode: time slices")
+    ap.add_argument("--sim-t", type=float, default=8.0, help="sim1 mode: end time (the paper runs to 80)")
     # Forward Euler is stable only while the advective Courant number plus
     # 2 nu dt sum_d 1/h_d^2 stays below 1.  At dt = 1e-2 that sum is about
     # 0.96 + 0.55 on the 96^3 grid and the coarse propagator blows up; the
@@ -400,6 +470,8 @@ def main():
         out = bench_copy(args)
     elif args.mode == "obstacles":
         out = bench_obstacles(args)
+    elif args.mode == "sim1":
+        out = bench_sim1(args)
     else:
         out = bench_parareal(args)
     print(json.dumps(out), flush=True)
