@@ -423,6 +423,83 @@ int og_pcg(const og_grid *g, const double *b, double *x, double rtol, int maxit,
     return status;
 }
 
+/* ---------------------------------------------- BiCGStab (Sec. 2) */
+
+/* The paper solves the pressure equation with BiCGStab (van der Vorst 1992).
+ * Right-preconditioned by the Jacobi diagonal M = diag(A), from the warm
+ * start x, shadow residual r^ = r0; per iteration two products with A and
+ * four inner products:
+ *   rho' = <r^, r>;  beta = (rho'/rho)(alpha/omega);  p = r + beta (p - omega v)
+ *   y = M^-1 p;  v = A y;  alpha = rho' / <r^, v>;  s = r - alpha v
+ *   z = M^-1 s;  t = A z;  omega = <t, s> / <t, t>
+ *   x = x + alpha y + omega z;  r = s - omega t
+ * Stops like og_pcg (recursive ||r|| <= rtol ||b||, then the true residual,
+ * restarting from it if above 2 rtol); a breakdown (rho' = 0 or <r^, v> = 0)
+ * also restarts from the true residual, at most 16 restarts. */
+int og_bicgstab(const og_grid *g, const double *b, double *x, double rtol, int maxit, og_info *info) {
+    size_t n = ncells(g);
+    double *r = malloc(n * sizeof(double)), *rh = malloc(n * sizeof(double));
+    double *p = malloc(n * sizeof(double)), *v = malloc(n * sizeof(double));
+    double *y = malloc(n * sizeof(double)), *sv = malloc(n * sizeof(double));
+    double *z = malloc(n * sizeof(double)), *t = malloc(n * sizeof(double));
+    double *dg = malloc(n * sizeof(double));
+    diag_A(g, dg);
+    memset(info, 0, sizeof(*info));
+    double bnorm = sqrt(dot(g, b, b));
+    int it = 0, status = 0, restarts = 0;
+    double rel_true = 0.0;
+    if (bnorm == 0.0) {
+        for (size_t i = 0; i < n; ++i) x[i] = 0.0;
+        goto done;
+    }
+    for (;;) {
+        og_apply_A(g, x, t);
+        for (size_t i = 0; i < n; ++i) { r[i] = b[i] - t[i]; rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
+        double rho = 1.0, alpha = 1.0, omega = 1.0;
+        double rnorm = sqrt(dot(g, r, r));
+        for (;;) {
+            if (!isfinite(rnorm)) { status = 3; break; }
+            if (rnorm <= rtol * bnorm) break;
+            if (it >= maxit) { status = 2; break; }
+            double rho1 = dot(g, rh, r);
+            if (rho1 == 0.0) break;
+            double beta = (rho1 / rho) * (alpha / omega);
+            for (size_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            for (size_t i = 0; i < n; ++i) y[i] = dg[i] > 0.0 ? p[i] / dg[i] : 0.0;
+            og_apply_A(g, y, v);
+            double rv = dot(g, rh, v);
+            if (rv == 0.0) break;
+            alpha = rho1 / rv;
+            for (size_t i = 0; i < n; ++i) sv[i] = r[i] - alpha * v[i];
+            for (size_t i = 0; i < n; ++i) z[i] = dg[i] > 0.0 ? sv[i] / dg[i] : 0.0;
+            og_apply_A(g, z, t);
+            double tt = dot(g, t, t);
+            omega = tt > 0.0 ? dot(g, t, sv) / tt : 0.0;
+            for (size_t i = 0; i < n; ++i) x[i] = x[i] + alpha * y[i] + omega * z[i];
+            for (size_t i = 0; i < n; ++i) r[i] = sv[i] - omega * t[i];
+            rho = rho1;
+            rnorm = sqrt(dot(g, r, r));
+            ++it;
+            if (omega == 0.0) break;
+        }
+        og_apply_A(g, x, t);
+        for (size_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+        rel_true = sqrt(dot(g, r, r)) / bnorm;
+        if (status != 0 || !isfinite(rel_true) || rel_true <= 2.0 * rtol || it >= maxit) break;
+        if (++restarts > 16) { status = 2; break; }
+    }
+    if (status == 0 && !isfinite(rel_true)) status = 3;
+    if (status == 0 && it >= maxit && rel_true > 2.0 * rtol) status = 2;
+    subtract_mean(g, x);
+done:
+    info->iters = it;
+    info->outer = restarts;
+    info->status = status;
+    info->rel_res_true = rel_true;
+    free(r); free(rh); free(p); free(v); free(y); free(sv); free(z); free(t); free(dg);
+    return status;
+}
+
 /* ------------------------------------- mixed precision: FP32 inner PCG */
 
 /* (A p)_c in single precision: same open faces, FP32 values and 1/h^2. */
@@ -566,8 +643,20 @@ void og_rhs(const og_grid *g, const double *Fu, const double *Fv, const double *
  * prec 0: FP64 PCG; prec 1: FP32 inner PCG with FP64 defect correction.
  * iters (optional, nsteps entries) receives the CG iterations per step.
  * Returns the worst status over the steps. */
+int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
+                         int prec, int solver, double rtol, int maxit, double eta, int max_outer, int *iters,
+                         double *rel_true);
+
 int og_fine_steps(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
                   int prec, double rtol, int maxit, double eta, int max_outer, int *iters, double *rel_true) {
+    return og_fine_steps_solver(g, u, v, w, p, nsteps, dt, prec, 0, rtol, maxit, eta, max_outer, iters, rel_true);
+}
+
+/* as og_fine_steps; solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed), 1: FP64
+ * Jacobi-BiCGStab (prec ignored) */
+int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
+                         int prec, int solver, double rtol, int maxit, double eta, int max_outer, int *iters,
+                         double *rel_true) {
     size_t nu = og_face_count(g, 0), nv = og_face_count(g, 1), nw = og_face_count(g, 2);
     size_t n = ncells(g);
     double *Fu = malloc(nu * sizeof(double)), *Fv = malloc(nv * sizeof(double));
@@ -577,8 +666,9 @@ int og_fine_steps(const og_grid *g, double *u, double *v, double *w, double *p, 
         og_momentum(g, u, v, w, dt, Fu, Fv, Fw);
         og_rhs(g, Fu, Fv, Fw, dt, b);
         og_info info;
-        int st = prec == 0 ? og_pcg(g, b, p, rtol, maxit, &info)
-                           : og_pcg_mixed(g, b, p, rtol, eta, maxit, max_outer, &info);
+        int st = solver == 1 ? og_bicgstab(g, b, p, rtol, maxit, &info)
+                 : prec == 0 ? og_pcg(g, b, p, rtol, maxit, &info)
+                             : og_pcg_mixed(g, b, p, rtol, eta, maxit, max_outer, &info);
         if (st > worst) worst = st;
         if (iters) iters[s] = info.iters;
         if (rel_true) rel_true[s] = info.rel_res_true;

@@ -73,6 +73,10 @@ def lib():
         _lib.og_rhs.argtypes = [G, P, P, P, D, P]
         _lib.og_fine_steps.argtypes = [G, P, P, P, P, I, D, I, D, I, D, I, P, P]
         _lib.og_fine_steps.restype = I
+        _lib.og_fine_steps_solver.argtypes = [G, P, P, P, P, I, D, I, I, D, I, D, I, P, P]
+        _lib.og_fine_steps_solver.restype = I
+        _lib.og_bicgstab.argtypes = [G, P, P, D, I, ctypes.POINTER(_Info)]
+        _lib.og_bicgstab.restype = I
         _lib.og_momentum_adjoint.argtypes = [G, P, P, P, D, P, P, P, P, P, P, P]
         _lib.og_stencil_form_value.argtypes = [G, I, P, I, I, I, I, I]
         _lib.og_stencil_form_value.restype = D
@@ -198,6 +202,17 @@ def pcg(g: Grid, b, x0=None, rtol=1e-10, maxit=100000):
     return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
 
 
+def bicgstab(g: Grid, b, x0=None, rtol=1e-10, maxit=100000):
+    """FP64 Jacobi-preconditioned BiCGStab, the paper's pressure solver (Sec. 2)."""
+    sp = g.shapes()[3]
+    b = _chk(b, sp)
+    x = np.zeros(sp) if x0 is None else _chk(x0, sp).copy()
+    info = _Info()
+    gc = g.c()
+    lib().og_bicgstab(ctypes.byref(gc), _p(b), _p(x), float(rtol), int(maxit), ctypes.byref(info))
+    return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
+
+
 def pcg_mixed(g: Grid, b, x0=None, rtol=1e-10, eta=1e-5, maxit=100000, max_outer=8):
     sp = g.shapes()[3]
     b = _chk(b, sp)
@@ -218,8 +233,9 @@ def correct(g: Grid, Fu, Fv, Fw, p, dt):
     return u, v, w
 
 
-def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta=1e-5, max_outer=8):
+def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta=1e-5, max_outer=8, solver=0):
     """nsteps projection steps of size dt; returns (new state, iters, rel_true, status).
+    solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed); 1: FP64 Jacobi-BiCGStab.
 
     The input state tuple (u, v, w, p) is not modified."""
     su, sv, sw, sp = g.shapes()
@@ -227,8 +243,9 @@ def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta
     iters = np.zeros(max(nsteps, 1), dtype=np.int32)
     rel = np.zeros(max(nsteps, 1))
     gc = g.c()
-    st = lib().og_fine_steps(ctypes.byref(gc), _p(u), _p(v), _p(w), _p(p), int(nsteps), float(dt), int(prec),
-                             float(rtol), int(maxit), float(eta), int(max_outer), _p(iters), _p(rel))
+    st = lib().og_fine_steps_solver(ctypes.byref(gc), _p(u), _p(v), _p(w), _p(p), int(nsteps), float(dt),
+                                    int(prec), int(solver), float(rtol), int(maxit), float(eta), int(max_outer),
+                                    _p(iters), _p(rel))
     return (u, v, w, p), iters[:nsteps], rel[:nsteps], st
 
 
