@@ -51,6 +51,11 @@ typedef enum {
     NSP_MIXED = 1  /* FP32 Jacobi-PCG inner solves, FP64 defect correction */
 } nsp_precision;
 
+typedef enum {
+    NSP_PCG = 0,      /* Jacobi-preconditioned CG (A is symmetric positive semi-definite) */
+    NSP_BICGSTAB = 1  /* Jacobi-preconditioned BiCGStab, the paper's solver (Sec. 2); FP64 only */
+} nsp_solver;
+
 typedef struct nsp_handle nsp_handle;
 
 /* Grid of one handle.  The domain is [0,lx]x[0,ly]x[0,lz] with nx*ny*nz
@@ -77,13 +82,18 @@ typedef struct {
  * Neumann Laplacian, stops when ||b - A p||_2 <= rtol ||b||_2 (recursive
  * residual for FP64, recomputed FP64 residual for mixed).  Mixed: each inner
  * FP32 solve stops at relative residual inner_rtol or maxit iterations; at
- * most max_outer inner solves. */
+ * most max_outer inner solves.  solver NSP_BICGSTAB (FP64 only, else
+ * NSP_ERR_UNSUPPORTED): right-preconditioned BiCGStab from the same warm
+ * start, restarted from the true residual after a breakdown (at most 16
+ * times); its workspace (three vectors per slice) is allocated on first use.
+ * `iters` then counts BiCGStab iterations (two products with A each). */
 typedef struct {
     double rtol;
     int maxit;
     nsp_precision prec;
     double inner_rtol;
     int max_outer;
+    nsp_solver solver;
 } nsp_poisson_opts;
 
 /* Per-slice report of the last call. */

@@ -55,6 +55,7 @@ struct nsp_handle {
     double *Fu = nullptr, *Fv = nullptr, *Fw = nullptr, *b = nullptr;
     double *r = nullptr, *d0 = nullptr, *d1 = nullptr, *q = nullptr;
     float *e = nullptr;
+    double *bv0 = nullptr, *bv1 = nullptr, *brh = nullptr;  // BiCGStab (allocated on first use)
     nsp_state gs{nullptr, nullptr, nullptr, nullptr};  // scratch state for the coarse sweep
     LaunchRes L;
     // adjoint workspace (allocated on first use)
@@ -218,7 +219,8 @@ nsp_status ensure_launch_res(nsp_handle *h, int nslices, int ntiles) {
 
 bool valid_opts(const nsp_poisson_opts *o) {
     return o && o->rtol >= 0 && o->maxit >= 0 && (o->prec == NSP_FP64 || o->prec == NSP_MIXED) &&
-           (o->prec == NSP_FP64 || (o->inner_rtol > 0 && o->inner_rtol < 1 && o->max_outer >= 0));
+           (o->prec == NSP_FP64 || (o->inner_rtol > 0 && o->inner_rtol < 1 && o->max_outer >= 0)) &&
+           (o->solver == NSP_PCG || o->solver == NSP_BICGSTAB);
 }
 
 // number of steps (t1 - t0)/dt, which must be a non-negative integer
@@ -279,6 +281,9 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.d1 = h->d1;
     G.q = h->q;
     G.e = h->e;
+    G.bv0 = h->bv0;
+    G.bv1 = h->bv1;
+    G.brh = h->brh;
     G.bin = bin;
 }
 
@@ -338,6 +343,8 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     if (nslices <= 0) return NSP_OK;
     if (nslices > kMaxSlices) return fail(h, NSP_ERR_ARG, "more than 64 slices in one launch");
     if (ngroups > kMaxGroups) return fail(h, NSP_ERR_ARG, "too many grids in one launch");
+    if (o->solver == NSP_BICGSTAB && o->prec != NSP_FP64)
+        return fail(h, NSP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
     // workgroups from the finest tiling, then the tile depth for that count
     const int units = std::max(ntiles, cgtiles);
     int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, units))
@@ -346,6 +353,19 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     if (wg > kMaxWG) wg = kMaxWG;
     GroupDesc lg[kMaxGroups];
     for (int g = 0; g < ngroups; ++g) lg[g] = groups[g];
+    if (o->solver == NSP_BICGSTAB)
+        for (int g = 0; g < ngroups; ++g) {
+            nsp_handle *hg = hs[g];
+            if (!hg->bv0) {
+                const size_t n = (size_t)hg->max_batch * hg->ncells;
+                HIPCHK(h, dalloc(&hg->bv0, n));
+                HIPCHK(h, dalloc(&hg->bv1, n));
+                HIPCHK(h, dalloc(&hg->brh, n));
+            }
+            lg[g].bv0 = hg->bv0;
+            lg[g].bv1 = hg->bv1;
+            lg[g].brh = hg->brh;
+        }
     int depth = h->force_depth;
     if (depth <= 0)
         for (const TuneEntry &t : h->tuned)
@@ -371,6 +391,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.maxit = o->maxit;
     P.max_outer = o->max_outer;
     P.xcd_remap = 1;
+    P.solver = o->solver;
     {
         // write-through CG stores while the launch is cache-resident (<= 8 M cells)
         long long cells = 0;
@@ -562,7 +583,8 @@ nsp_status nsp_destroy(nsp_handle *h) {
                     h->L.jump};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    void *aptrs[] = {h->adj_ck, h->adj_segu, h->adj_y, h->adj_lam, h->adj_mu, h->adj_p, h->adj_glid, h->adj_part};
+    void *aptrs[] = {h->adj_ck, h->adj_segu, h->adj_y, h->adj_lam, h->adj_mu, h->adj_p, h->adj_glid, h->adj_part,
+                     h->bv0, h->bv1, h->brh};
     for (void *p : aptrs)
         if (p) (void)hipFree(p);
     if (h->L.ctl_host) (void)hipHostFree(h->L.ctl_host);

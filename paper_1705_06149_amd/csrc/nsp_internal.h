@@ -56,7 +56,8 @@ struct GroupDesc {
     const float *idiag32;  // [64]
     double *u, *v, *w, *p;         // state, slice 0 (slice stride nu/nv/nw/ncells)
     double *Fu, *Fv, *Fw, *b;      // predictor and right-hand side workspace
-    double *r, *d0, *d1, *q;       // CG vectors (FP32 view in mixed mode)
+    double *r, *d0, *d1, *q;       // CG vectors (FP32 view in mixed mode); BiCGStab: p in d0/d1, t in q
+    double *bv0, *bv1, *brh;       // BiCGStab: v (two buffers) and the shadow residual
     float *e;                      // FP32 defect correction
     const double *bin;             // Poisson mode: caller's right-hand side
 };
@@ -65,6 +66,7 @@ struct GroupDesc {
 // read by every workgroup after them.
 struct SliceCtl {
     double bnorm, rz, alpha, beta, r0, mean_b, mean_r, mean_p, rel_true, res_true;
+    double omega;  // BiCGStab (rz holds rho = <r^, r>)
     int active;   // CG iterating
     int first;    // next search direction is the preconditioned residual
     int it;       // CG iterations of the current step
@@ -116,6 +118,7 @@ struct KParams {
     int prec;              // 0 fp64, 1 mixed
     int maxit, max_outer;
     int xcd_remap;         // contiguous tile ranges per XCD
+    int solver;            // 0: Jacobi-PCG, 1: Jacobi-BiCGStab (FP64)
     int wt;                // CG outputs by write-through (device-scope) stores
     double dt;
     double rtol, eta;

@@ -38,7 +38,7 @@ template <class T>
 __device__ __forceinline__ const GAS T *gp(const T *p) { return (const GAS T *)p; }  // ~seconds: a wait this long means something is broken
 
 enum Red : int {
-    R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32
+    R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32, R_BG1, R_BG2, R_BG3
 };
 
 // a * b + c with one rounding.  The build does not contract expressions on
@@ -378,8 +378,8 @@ struct Runner {
 
     __device__ __forceinline__ static int nq_of(int rid) {
         switch (rid) {
-        case R_MEANB: case R_A: case R_A32: return 1;
-        case R_B: case R_B32: case R_CAST: return 2;
+        case R_MEANB: case R_A: case R_A32: case R_BG1: return 1;
+        case R_B: case R_B32: case R_CAST: case R_BG2: case R_BG3: return 2;
         case R_INIT: case R_TRUE: case R_OUT: return 3;
         case R_OUT0: return 4;
         default: return 0;
@@ -542,6 +542,12 @@ struct Runner {
             c.active = 0;
             if (c.zero) return 0;
             c.rz = S[2];
+            if (P.solver == 1) {
+                // BiCGStab: r^ = r0, so rho = <r^, r0> = ||r0||^2; alpha = omega = 1
+                c.rz = S[1];
+                c.alpha = 1.0;
+                c.omega = 1.0;
+            }
             const double rn = sqrt(S[1]);
             if (!isfinite(rn)) c.step_status = 3;
             else if (rn > P.rtol * c.bnorm) c.active = (c.it < P.maxit) ? 1 : (c.step_status = 2, 0);
@@ -577,8 +583,19 @@ struct Runner {
             c.mean_p = S[1] / nf;
             const bool ok = c.step_status == 0;
             if (ok && isfinite(c.rel_true) && c.rel_true > 2.0 * P.rtol && c.it < P.maxit) {
+                if (P.solver == 1 && c.outer >= 16) {
+                    // BiCGStab broke down repeatedly: give up
+                    c.step_status = 2;
+                    finish_solve(c);
+                    return 0;
+                }
                 c.outer += 1;
                 c.rz = S[2];
+                if (P.solver == 1) {  // restart BiCGStab with r^ = r
+                    c.rz = S[0];
+                    c.alpha = 1.0;
+                    c.omega = 1.0;
+                }
                 c.first = 1;
                 c.active = 1;
                 return 1;
@@ -641,6 +658,33 @@ struct Runner {
             const double rn = sqrt(S[1]);
             c.active = (rn > P.eta * c.r0 && c.it_in < P.maxit && isfinite(rn)) ? 1 : 0;
             return c.active;
+        }
+        case R_BG1: {
+            // S0 = <r^, v>: alpha = rho / <r^, v> (zero: breakdown, restart)
+            if (!c.active) return 0;
+            if (S[0] == 0.0 || !isfinite(S[0])) { c.active = 0; return 0; }
+            c.alpha = c.rz / S[0];
+            return 0;
+        }
+        case R_BG2: {
+            // S0 = <t, s>, S1 = <t, t>
+            if (!c.active) return 0;
+            c.omega = S[1] > 0.0 ? S[0] / S[1] : 0.0;
+            return 0;
+        }
+        case R_BG3: {
+            // S0 = <r^, r_new> (the next rho), S1 = ||r_new||^2
+            if (!c.active) return 0;
+            c.it += 1;
+            c.first = 0;
+            const double rn = sqrt(S[1]);
+            if (!isfinite(rn)) { c.step_status = 3; c.active = 0; return 0; }
+            if (rn <= P.rtol * c.bnorm) { c.active = 0; return 0; }
+            if (c.it >= P.maxit) { c.step_status = 2; c.active = 0; return 0; }
+            if (S[0] == 0.0 || c.omega == 0.0) { c.active = 0; return 0; }  // breakdown: restart
+            c.beta = (S[0] / c.rz) * (c.alpha / c.omega);
+            c.rz = S[0];
+            return 1;
         }
         default:
             return 0;
@@ -1214,6 +1258,90 @@ struct Runner {
                  });
     }
 
+    // ------------------------------------------------------- BiCGStab
+    //
+    // The paper's solver (Sec. 2), Jacobi right-preconditioned, FP64, flat
+    // tiles; three phases per iteration (bytes per cell: 49, 25, 65):
+    //   BG1: p = r + beta (p - omega v), v = A M^-1 p    partial <r^, v>
+    //   BG2: s = r - alpha v, t = A M^-1 s               partials <t,s>, <t,t>
+    //   BG3: x += alpha M^-1 p + omega M^-1 s, r = s - omega t
+    //                                                    partials <r^, r>, ||r||^2
+    // p and v alternate between two buffers (par), since neighbours read the
+    // old values while the new ones are written; s is recomputed, never
+    // stored.  After a (re)start (first) the old p and v are zero and r^ = r.
+
+    __device__ __forceinline__ double bg_idg(const GAS GroupDesc &G, uint8_t f) const {
+        return s_idg[group_index(G) * 64 + (f & FL_OPEN)];
+    }
+
+    __device__ __forceinline__ void phase_bg1(int par) {
+        tiles<1>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).active; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const LAS SliceCtl &cs = ctl(gs);
+                     const long off = (long)sl * G.ncells;
+                     const GAS uint8_t *fl = gp(G.flags);
+                     const double GAS *r = gp(G.r) + off;
+                     const double GAS *pold = gp(par ? G.d1 : G.d0) + off, *vold = gp(par ? G.bv1 : G.bv0) + off;
+                     double GAS *pnew = gp(par ? G.d0 : G.d1) + off, *vnew = gp(par ? G.bv0 : G.bv1) + off;
+                     double GAS *rh = gp(G.brh) + off;
+                     const bool first = cs.first;
+                     const double beta = cs.beta, omega = cs.omega;
+                     auto pval = [&](long n) {
+                         return first ? r[n] : r[n] + beta * (pold[n] - omega * vold[n]);
+                     };
+                     const uint8_t f = fl[c];
+                     const double pc = pval(c);
+                     const double yc = bg_idg(G, f) * pc;
+                     const double vc = apply_A<double>(G, c, f, yc, [&](long n) { return bg_idg(G, fl[n]) * pval(n); },
+                                                       G.ih2);
+                     pnew[c] = pc;
+                     vnew[c] = vc;
+                     double rhc;
+                     if (first) { rhc = r[c]; rh[c] = rhc; }
+                     else rhc = rh[c];
+                     acc[0] += rhc * vc;
+                 });
+    }
+
+    __device__ __forceinline__ void phase_bg2(int par) {
+        tiles<2>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).active; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const LAS SliceCtl &cs = ctl(gs);
+                     const long off = (long)sl * G.ncells;
+                     const GAS uint8_t *fl = gp(G.flags);
+                     const double GAS *r = gp(G.r) + off, *v = gp(par ? G.bv0 : G.bv1) + off;
+                     double GAS *t = gp(G.q) + off;
+                     const double alpha = cs.alpha;
+                     const uint8_t f = fl[c];
+                     const double sc = r[c] - alpha * v[c];
+                     const double zc = bg_idg(G, f) * sc;
+                     const double tc = apply_A<double>(
+                         G, c, f, zc, [&](long n) { return bg_idg(G, fl[n]) * (r[n] - alpha * v[n]); }, G.ih2);
+                     t[c] = tc;
+                     acc[0] += tc * sc;
+                     acc[1] += tc * tc;
+                 });
+    }
+
+    __device__ __forceinline__ void phase_bg3(int par) {
+        tiles<2>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).active; },
+                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
+                     const LAS SliceCtl &cs = ctl(gs);
+                     const long off = (long)sl * G.ncells;
+                     const uint8_t f = gp(G.flags)[c];
+                     const double GAS *p = gp(par ? G.d0 : G.d1) + off, *v = gp(par ? G.bv0 : G.bv1) + off;
+                     const double GAS *t = gp(G.q) + off, *rh = gp(G.brh) + off;
+                     double GAS *x = gp(G.p) + off, *r = gp(G.r) + off;
+                     const double alpha = cs.alpha, omega = cs.omega, idg = bg_idg(G, f);
+                     const double sc = r[c] - alpha * v[c];
+                     x[c] = x[c] + alpha * (idg * p[c]) + omega * (idg * sc);
+                     const double rn = sc - omega * t[c];
+                     r[c] = rn;
+                     acc[0] += rh[c] * rn;
+                     acc[1] += rn * rn;
+                 });
+    }
+
     // Mixed: FP64 residual r = b - A p.  First sweep also makes b mean-free.
     // partials ||r||^2, sum r, sum p, ||b||^2
     __device__ __forceinline__ void phase_out(bool first, bool from_user) {
@@ -1325,6 +1453,30 @@ struct Runner {
         return true;
     }
 
+    __device__ __forceinline__ bool solve_bicg(bool from_user) {
+        phase_init64(from_user);
+        int any = sync(R_INIT);
+        if (any < 0) return false;
+        int par = 0;
+        for (;;) {
+            while (any > 0) {
+                phase_bg1(par);
+                if (sync(R_BG1) < 0) return false;
+                phase_bg2(par);
+                if (sync(R_BG2) < 0) return false;
+                phase_bg3(par);
+                any = sync(R_BG3);
+                if (any < 0) return false;
+                par ^= 1;
+            }
+            phase_true64();
+            any = sync(R_TRUE);
+            if (any < 0) return false;
+            if (!any) break;
+        }
+        return true;
+    }
+
     __device__ __forceinline__ bool solve_mixed(bool from_user) {
         phase_out(true, from_user);
         int any = sync(R_OUT0);
@@ -1356,7 +1508,7 @@ struct Runner {
         if (P.mode == MODE_POISSON) {
             phase_meanb_user();
             if (sync(R_MEANB) < 0) return;
-            const bool ok = P.prec == 0 ? solve64(true) : solve_mixed(true);
+            const bool ok = P.prec == 0 ? (P.solver == 1 ? solve_bicg(true) : solve64(true)) : solve_mixed(true);
             if (!ok) return;
             phase_gauge();
             return;
@@ -1375,7 +1527,7 @@ struct Runner {
             if (sync(R_NONE) < 0) return;
             phase_rhs();
             if (sync(R_MEANB) < 0) return;
-            const bool ok = P.prec == 0 ? solve64(false) : solve_mixed(false);
+            const bool ok = P.prec == 0 ? (P.solver == 1 ? solve_bicg(false) : solve64(false)) : solve_mixed(false);
             if (!ok) return;
             phase_corr();
             // the correction reads neighbouring pressures: no cell may be

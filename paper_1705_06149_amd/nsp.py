@@ -21,6 +21,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnsp.so")
 
 NSP_OK, NSP_ERR_ARG, NSP_ERR_NOT_CONVERGED, NSP_ERR_NONFINITE, NSP_ERR_HIP, NSP_ERR_UNSUPPORTED = range(6)
+PCG, BICGSTAB = 0, 1
 _STATUS = {0: "NSP_OK", 1: "NSP_ERR_ARG", 2: "NSP_ERR_NOT_CONVERGED", 3: "NSP_ERR_NONFINITE",
            4: "NSP_ERR_HIP", 5: "NSP_ERR_UNSUPPORTED"}
 FP64, MIXED = 0, 1
@@ -42,7 +43,7 @@ class _Grid(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("prec", ctypes.c_int),
-                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int)]
+                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("solver", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -108,9 +109,11 @@ class PoissonOpts:
     prec: int = FP64
     inner_rtol: float = 1e-5
     max_outer: int = 8
+    solver: int = 0  # PCG or BICGSTAB
 
     def c(self):
-        return _Opts(float(self.rtol), int(self.maxit), int(self.prec), float(self.inner_rtol), int(self.max_outer))
+        return _Opts(float(self.rtol), int(self.maxit), int(self.prec), float(self.inner_rtol), int(self.max_outer),
+                     int(self.solver))
 
 
 def _torch():
