@@ -43,6 +43,7 @@ PEAK_HBM_GBS = 8000.0
 # Algorithmic bytes per cell of the kernels' phases (FP64 state, 1-byte
 # cell flags; face arrays counted as one entry per cell and component).
 BYTES_CG_ITER = {"fp64": 66.0, "mixed": 34.0}   # one CG iteration
+BYTES_BICG_ITER = 139.0  # one BiCGStab iteration (FP64): phases of 49, 25 and 65 B
 BYTES_STEP_FIXED = {"fp64": 212.0, "mixed": 212.0}  # momentum, rhs, init/true, correction, gauge
 BYTES_MIXED_SWEEP = 65.0  # mixed: one FP64 residual + cast + update sweep
 
@@ -91,7 +92,8 @@ def bench_fine(args):
 
     n, re_, dt = 128, 1000.0, 5e-4
     prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
-    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=args.eta, max_outer=8)
+    solver = nsp.BICGSTAB if args.solver == "bicgstab" else nsp.PCG
+    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=args.eta, max_outer=8, solver=solver)
     h = nsp.Handle(n, n, n, re=re_, max_batch=1)
     y = h.zeros_state(1)
     t = 0.0
@@ -122,12 +124,14 @@ def bench_fine(args):
         h.fine_step(y64, t - K * dt, t, dt, o64)
         err_vs_fp64 = float(torch.sqrt(sum(((y[c] - y64[c]) ** 2).sum() for c in range(3)) /
                                        sum((y64[c] ** 2).sum() for c in range(3))))
-    per_launch_bytes = cells * (BYTES_STEP_FIXED[args.precision] + BYTES_CG_ITER[args.precision] * iters / K)
+    per_iter = BYTES_BICG_ITER if args.solver == "bicgstab" else BYTES_CG_ITER[args.precision]
+    per_launch_bytes = cells * (BYTES_STEP_FIXED[args.precision] + per_iter * iters / K)
     if args.precision == "mixed":
         per_launch_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     achieved = per_launch_bytes / avg_launch_s / 1e9
-    traffic = _traffic_from_profile("k_persistent_cavity128_%s_pmc.txt" % args.precision)
+    sfx = "_bicgstab" if args.solver == "bicgstab" else ""
+    traffic = _traffic_from_profile("k_persistent_cavity128_%s%s_pmc.txt" % (args.precision, sfx))
     out = {
         "metric": "fine-step cell-updates/s",
         "value": value,
@@ -142,7 +146,8 @@ def bench_fine(args):
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "cavity128_re1000", "grid": [n, n, n], "re": re_, "dt": dt,
-                   "start": "rest, after %d warm-up steps" % args.warmup, "poisson": "Jacobi-PCG rtol 1e-10",
+                   "start": "rest, after %d warm-up steps" % args.warmup,
+                   "poisson": ("Jacobi-BiCGStab" if args.solver == "bicgstab" else "Jacobi-PCG") + " rtol 1e-10",
                    "precision": args.precision},
         "cg_iters_per_step": iters / K,
         "inner_rtol": args.eta if args.precision == "mixed" else None,
@@ -187,7 +192,8 @@ def bench_poisson(args):
     g = torch.Generator(device="cuda").manual_seed(0)
     b = torch.randn((B, n, n, n), dtype=torch.float64, device="cuda", generator=g)
     p = torch.zeros_like(b)
-    opts = nsp.PoissonOpts(rtol=0.0, maxit=its, prec=prec, inner_rtol=1e-30, max_outer=1)
+    solver = nsp.BICGSTAB if args.solver == "bicgstab" else nsp.PCG
+    opts = nsp.PoissonOpts(rtol=0.0, maxit=its, prec=prec, inner_rtol=1e-30, max_outer=1, solver=solver)
     for _ in range(args.warmup):
         p.zero_()
         h.poisson_solve(b, p, opts, check=False)
@@ -201,18 +207,19 @@ def bench_poisson(args):
     _sync()
     wall = time.perf_counter() - t0
     cells = B * n ** 3
-    per_launch = cells * BYTES_CG_ITER[args.precision] * its
+    per_launch = cells * (BYTES_BICG_ITER if args.solver == "bicgstab" else BYTES_CG_ITER[args.precision]) * its
     achieved = per_launch / (np.mean(ms) * 1e-3) / 1e9
     out = {
         "metric": "Poisson HBM GB/s", "value": achieved, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "poisson_32x128cube", "batch": B, "grid": [n, n, n], "cg_iters": its,
-                   "precision": args.precision},
+        "config": {"workload": "poisson_32x128cube", "batch": B, "grid": [n, n, n], "iterations": its,
+                   "solver": args.solver, "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": _traffic_from_profile("k_persistent_poisson32x128_%s_pmc.txt" % args.precision),
+                     "traffic": _traffic_from_profile("k_persistent_poisson32x128_%s%s_pmc.txt" % (
+                         args.precision, "_bicgstab" if args.solver == "bicgstab" else "")),
                      "kernel": "k_persistent (%d CG iterations on %d grids per launch)" % (its, B),
                      "avg_launch_ms": float(np.mean(ms)), "algorithmic_bytes_per_launch": per_launch},
     }
@@ -441,6 +448,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "copy"], default="fine")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--solver", choices=["pcg", "bicgstab"], default="pcg",
+                    help="pressure solver: Jacobi-PCG, or the paper's BiCGStab (FP64)")
     ap.add_argument("--max-iters", type=int, default=32)
     ap.add_argument("--slices", type=int, default=16, help="sim1 mode: time slices")
     ap.add_argument("--sim-t", type=float, default=8.0, help="sim1 mode: end time (the paper runs to 80)")
