@@ -202,12 +202,14 @@ def bench_poisson(args):
     t0 = time.perf_counter()
     for _ in range(args.steps):
         p.zero_()
-        h.poisson_solve(b, p, opts, check=False)
+        info = h.poisson_solve(b, p, opts, check=False)
         ms.append(h.last_launch_ms())
     _sync()
     wall = time.perf_counter() - t0
     cells = B * n ** 3
     per_launch = cells * (BYTES_BICG_ITER if args.solver == "bicgstab" else BYTES_CG_ITER[args.precision]) * its
+    if args.precision == "mixed":
+        per_launch += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
     achieved = per_launch / (np.mean(ms) * 1e-3) / 1e9
     out = {
         "metric": "Poisson HBM GB/s", "value": achieved, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -249,7 +251,7 @@ def bench_parareal(args):
     serial = time.perf_counter() - t0
     ref = tuple(a[0].clone() for a in y)
     # batched mixed-precision Parareal, launch shape autotuned for the full batch
-    tuned_wg, tuned_planes = h.autotune(N, nsp.MIXED)
+    tuned_wg, tuned_planes, tuned_items = h.autotune(N, nsp.MIXED)
     shapes = h.shapes()
     Y = tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in shapes)
     Fk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
@@ -285,7 +287,8 @@ def bench_parareal(args):
         "serial_equiv_cell_updates_per_s": cells * nf / par,
         "end_state_rel_l2_vs_serial_fp64": err,
         "bound_paper_eq8": N / k,
-        "autotuned_launch": {"workgroups": tuned_wg, "cg_tile_planes": tuned_planes},
+        "autotuned_launch": {"workgroups": tuned_wg, "cg_tile_planes": tuned_planes,
+                             "cg_rows_per_thread": tuned_items},
     }
     h.close()
     return out

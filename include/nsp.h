@@ -215,14 +215,15 @@ nsp_status nsp_lid_modes_grad(nsp_handle *h, const double *g_lid, int nmodes, do
  * nsp_autotune times candidate shapes on the handle's own workspace (a
  * 40-iteration Poisson solve on a synthetic right-hand side): workgroup
  * counts and, where the CG phases use column tiles, tile depths of 8, 16 or
- * 32 planes; it keeps the fastest for (batch, prec) and reports it in
- * *chosen_workgroups and *chosen_planes (0 for flat tiles; both may be
- * NULL).  Results do not depend on the choice: partial sums are kept per
- * tile and per 8 planes.  It allocates and frees two batch-sized device
- * arrays and synchronises the stream. */
+ * 32 planes and (NSP_MIXED) one or two rows per thread; it keeps the fastest
+ * for (batch, prec) and reports it in *chosen_workgroups, *chosen_planes and
+ * *chosen_items (0 for flat tiles; each may be NULL).  Results do not depend
+ * on the choice: partial sums are kept per tile, or per block of rows and 8
+ * planes.  It allocates and frees two batch-sized device arrays and
+ * synchronises the stream. */
 nsp_status nsp_set_launch(nsp_handle *h, int workgroups);
 nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stream, int *chosen_workgroups,
-                        int *chosen_planes);
+                        int *chosen_planes, int *chosen_items);
 
 /* Duration in milliseconds of the last persistent launch made through this
  * handle, measured with HIP events on the launch stream. */

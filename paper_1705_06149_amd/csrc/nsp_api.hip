@@ -35,6 +35,7 @@ struct LaunchRes {
 struct TuneEntry {
     int batch, prec, workgroups;
     int depth;  // CG column-tile depth in units of kZSub planes (0: by rule)
+    int items;  // CG column items per thread (0: by rule)
 };
 
 struct nsp_handle {
@@ -44,6 +45,7 @@ struct nsp_handle {
     int max_batch = 0;
     int tile = 0, ntiles = 0;
     int cby = 0, cbz = 0, cny = 0, cnz = 0, cgtiles = 0;  // CG column tiles (cby = 0: flat tiles), depth kZSub
+    int crb = 0, cnb = 0;  // rows per partial block (one workgroup-wide plane patch), blocks along y
     int cgparts = 0;                                      // CG partials per slice
     long long ncells = 0, nu = 0, nv = 0, nw = 0;
     double nfluid = 0;
@@ -68,6 +70,7 @@ struct nsp_handle {
     int max_wg = 0;
     int fixed_wg = 0;
     int force_depth = 0;  // CG column-tile depth (units of kZSub) forced during autotuning
+    int force_items = 0;  // CG column items per thread forced during autotuning
     std::vector<TuneEntry> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
@@ -251,6 +254,9 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.cbz = h->cbz;
     G.cny = h->cny;
     G.cnz = h->cnz;
+    G.crb = h->crb;
+    G.cni = 1;
+    G.cnb = h->cnb;
     G.cgtiles = h->cgtiles;
     G.cgtile0 = cgtile0 >= 0 ? cgtile0 : slice0 * h->cgtiles;
     G.cgparts = h->cgparts;
@@ -294,28 +300,59 @@ int auto_workgroups(nsp_handle *h, int batch, int prec, int total_tiles) {
     return std::min(h->max_wg, total_tiles);
 }
 
-// Launch the persistent kernel over ngroups groups and read back the
-// per-slice control blocks into info (may be NULL).
-// Launch prefixes of the groups' tiles and partials, and the CG tile depth:
-// `depth` x kZSub planes if depth > 0 (autotuned), else the deepest of 1, 2,
-// 4 x kZSub planes that leaves at least two CG tiles per workgroup (deeper
-// tiles refill the z pipeline less often).  Partial sums stay per kZSub
-// planes, so the choice does not change any result.
-void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int *ntiles, int *cgtiles, int *cgparts) {
+// Launch prefixes of the groups' tiles and partials, the CG tile depth and
+// the items per thread.  Items: `items` if > 0, else in FP32 launches (fp32
+// != 0) the count with the shorter estimated critical path, the largest
+// number of plane steps one workgroup makes (tiles per workgroup x planes per
+// tile), a two-item plane step costing 1.75 one-item ones (measured on 96^3
+// and 128^3 batches); FP64 launches always use one item (two FP64 items would
+// not fit the LDS plane buffers).  Depth: `depth` x kZSub planes if depth > 0,
+// else the deepest of 1, 2, 4 x kZSub planes that leaves at least two CG
+// tiles per workgroup (deeper tiles refill the z pipeline less often).
+// Partial sums stay per crb rows and kZSub planes, so neither choice changes
+// a result.
+void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int fp32, int *ntiles, int *cgtiles,
+                   int *cgparts) {
+    auto count = [&](int ni, int m) {
+        long long t = 0;
+        for (int g = 0; g < ngroups; ++g) {
+            const GroupDesc &X = G[g];
+            if (X.crb > 0) {
+                const int rows = ni * X.crb;
+                t += (long long)X.nslices * ((X.ny + rows - 1) / rows) * ((X.nz + m * kZSub - 1) / (m * kZSub));
+            } else {
+                t += (long long)X.nslices * X.cgtiles;
+            }
+        }
+        return t;
+    };
+    // estimated plane steps of the busiest workgroup, in quarters of a one-item step
+    auto path = [&](int ni) {
+        long long best = -1;
+        for (int m : {1, 2, 4}) {
+            const long long c = (count(ni, m) + wg - 1) / wg * m * (ni == 2 ? 7 : 4);
+            if (best < 0 || c < best) best = c;
+        }
+        return best;
+    };
+    bool two = fp32 != 0;
+    for (int g = 0; g < ngroups; ++g)
+        if (G[g].crb > 0 && G[g].cnb < 2) two = false;
+    if (!two) items = 1;
+    if (items <= 0) items = path(2) < path(1) ? 2 : 1;
     for (int m : {4, 2}) {
         if (depth > 0) break;
-        long long t = 0;
-        for (int g = 0; g < ngroups; ++g)
-            t += (long long)G[g].nslices *
-                 (G[g].cby > 0 ? (long long)G[g].cny * ((G[g].nz + m * kZSub - 1) / (m * kZSub)) : G[g].cgtiles);
-        if (t >= 2LL * wg) { depth = m; break; }
+        if (count(items, m) >= 2LL * wg) { depth = m; break; }
     }
     if (depth <= 0) depth = 1;
     *ntiles = *cgtiles = *cgparts = 0;
     int slice0 = 0;
     for (int g = 0; g < ngroups; ++g) {
         GroupDesc &X = G[g];
-        if (X.cby > 0) {
+        if (X.crb > 0) {
+            X.cni = items;
+            X.cby = std::min(items * X.crb, X.ny);
+            X.cny = (X.ny + X.cby - 1) / X.cby;
             X.cbz = depth * kZSub;
             X.cnz = (X.nz + X.cbz - 1) / X.cbz;
             X.cgtiles = X.cny * X.cnz;
@@ -331,6 +368,8 @@ void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int *ntiles, in
     }
 }
 
+// Launch the persistent kernel over ngroups groups and read back the
+// per-slice control blocks into info (may be NULL).
 nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
                const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override) {
     nsp_handle *h = hs[0];
@@ -366,12 +405,15 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
             lg[g].bv1 = hg->bv1;
             lg[g].brh = hg->brh;
         }
-    int depth = h->force_depth;
-    if (depth <= 0)
+    int depth = h->force_depth, items = h->force_items;
+    if (depth <= 0 && items <= 0)
         for (const TuneEntry &t : h->tuned)
-            if (t.batch == nslices && t.prec == (o->prec == NSP_MIXED ? 1 : 0)) depth = t.depth;
+            if (t.batch == nslices && t.prec == (o->prec == NSP_MIXED ? 1 : 0)) {
+                depth = t.depth;
+                items = t.items;
+            }
     int cgparts = 0;
-    layout_groups(lg, ngroups, wg, depth, &ntiles, &cgtiles, &cgparts);
+    layout_groups(lg, ngroups, wg, depth, items, o->prec == NSP_MIXED, &ntiles, &cgtiles, &cgparts);
     const int pstride = std::max(ntiles, cgparts);
     nsp_status st = ensure_launch_res(h, nslices, pstride);
     if (st != NSP_OK) return st;
@@ -507,14 +549,15 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     // a workgroup (nx a multiple of 32, so halo rows are whole waves): cby rows
     // (one workgroup-wide plane patch) by 8 planes
     if (2 * g->nx <= kBlock && g->nx % 32 == 0 && h->ncells >= (1LL << 18)) {
-        h->cby = std::min(kBlock / g->nx, g->ny);
+        h->cby = h->crb = std::min(kBlock / g->nx, g->ny);
+        h->cnb = (g->ny + h->crb - 1) / h->crb;
         h->cbz = kZSub;
         h->cny = (g->ny + h->cby - 1) / h->cby;
         h->cnz = (g->nz + h->cbz - 1) / h->cbz;
         h->cgtiles = h->cny * h->cnz;
         h->cgparts = h->cgtiles;
     } else {
-        h->cby = h->cbz = h->cny = h->cnz = 0;
+        h->cby = h->cbz = h->cny = h->cnz = h->crb = h->cnb = 0;
         h->cgtiles = h->ntiles;
         h->cgparts = h->ntiles;
     }
@@ -927,7 +970,7 @@ nsp_status nsp_last_launch_ms(const nsp_handle *h, double *ms) {
 }
 
 nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stream, int *chosen,
-                        int *chosen_planes) {
+                        int *chosen_planes, int *chosen_items) {
     if (!h || batch < 1 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "bad autotune batch");
     hipStream_t s = static_cast<hipStream_t>(stream);
     // synthetic right-hand side (made mean-free inside the solve); every
@@ -952,40 +995,49 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     fill_group(G, h, y, 0, batch, 0, 0, b);
     nsp_handle *hs[1] = {h};
     // column-tile depths (units of kZSub planes); flat tiles have none
-    std::vector<int> depths = {1};
-    if (h->cby > 0) depths = {1, 2, 4};
-    int best = cands[0], best_depth = depths[0];
+    std::vector<int> depths = {1}, itemss = {1};
+    if (h->crb > 0) depths = {1, 2, 4};
+    if (h->crb > 0 && prec == NSP_MIXED && h->cnb >= 2) itemss = {1, 2};
+    int best = cands[0], best_depth = depths[0], best_items = itemss[0];
     double best_ms = 1e30;
+    for (int ni : itemss)
     for (int dep : depths)
         for (int c : cands) {
             double tot = 0;
             h->force_depth = dep;
+            h->force_items = ni;
             for (int rep = 0; rep < 3; ++rep) {
                 nsp_status st = NSP_OK;
                 if (hipMemsetAsync(p, 0, (size_t)batch * h->ncells * sizeof(double), s) != hipSuccess)
                     st = fail(h, NSP_ERR_HIP, "autotune: memset failed");
                 if (st == NSP_OK) st = run(hs, 1, &G, MODE_POISSON, 0, 1.0, &o, s, nullptr, c);
                 if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
-                    h->force_depth = 0;
+                    h->force_depth = h->force_items = 0;
                     (void)hipFree(b);
                     (void)hipFree(p);
                     return st;
                 }
                 if (rep > 0) tot += h->last_ms;
             }
-            if (tot < best_ms) { best_ms = tot; best = c; best_depth = dep; }
+            if (tot < best_ms) { best_ms = tot; best = c; best_depth = dep; best_items = ni; }
         }
-    h->force_depth = 0;
+    h->force_depth = h->force_items = 0;
     (void)hipFree(b);
     (void)hipFree(p);
     const int pr = prec == NSP_MIXED ? 1 : 0;
-    const int keep_depth = h->cby > 0 ? best_depth : 0;
+    const int keep_depth = h->crb > 0 ? best_depth : 0, keep_items = h->crb > 0 ? best_items : 0;
     bool found = false;
     for (TuneEntry &t : h->tuned)
-        if (t.batch == batch && t.prec == pr) { t.workgroups = best; t.depth = keep_depth; found = true; }
-    if (!found) h->tuned.push_back(TuneEntry{batch, pr, best, keep_depth});
+        if (t.batch == batch && t.prec == pr) {
+            t.workgroups = best;
+            t.depth = keep_depth;
+            t.items = keep_items;
+            found = true;
+        }
+    if (!found) h->tuned.push_back(TuneEntry{batch, pr, best, keep_depth, keep_items});
     if (chosen) *chosen = best;
     if (chosen_planes) *chosen_planes = keep_depth * kZSub;
+    if (chosen_items) *chosen_items = keep_items;
     return NSP_OK;
 }
 

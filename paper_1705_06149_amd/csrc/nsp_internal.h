@@ -35,11 +35,14 @@ struct GroupDesc {
     int tile0;             // first tile index of this grid in the launch
     // CG tiles (phases of the CG loop).  Column tiles: full x rows, cby rows
     // in y, cbz planes in z (a multiple of kZSub, chosen per launch); each
-    // thread walks z.  Partial sums are kept per kZSub planes of a column
-    // whatever cbz is, so results do not depend on the tile depth.  cby ==
-    // 0: the CG loop uses the flat tiles above (one partial per tile).
+    // thread walks z carrying cni items (rows yy and yy + crb; cni = 2 only
+    // in FP32 launches), so cby = cni * crb.  Partial sums are kept per crb
+    // rows and kZSub planes whatever cbz and cni are, so results depend on
+    // neither.  cby == 0: the CG loop uses the flat tiles above (one partial
+    // per tile).
     int cby, cbz;          // rows / planes per column tile
     int cny, cnz;          // column tiles along y / z
+    int crb, cni, cnb;     // rows per partial block, items per thread, row blocks along y
     int cgtiles;           // CG tiles per slice
     int cgtile0;           // first CG tile index of this grid in the launch
     int cgparts;           // CG partial sums per slice

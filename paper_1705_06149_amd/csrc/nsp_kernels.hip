@@ -913,26 +913,32 @@ struct Runner {
     // item (whole waves, since column tiles need nx % 32 == 0 and 2nx <= the
     // workgroup size).  Halo rows outside the domain are never read (their
     // faces are closed) and are filled from a valid cell.
+    // A thread carries NI items of a column tile: rows yy and yy + crb (NI =
+    // 2, FP32 launches with enough tiles) of the x position tid % nx.  Partial
+    // sums are kept per block of crb rows and kZSub planes whatever NI and
+    // the tile depth are, so neither changes a result.
+    template <int NI>
     struct ColPos {
-        int yy, y;
-        bool act;
-        bool halo;  // this thread also computes one halo item
-        long c0;    // index of (x, y, z0); clamped to a valid cell for idle threads
-        long h0;    // index of the halo item at z0 (valid cell)
-        int slot;   // LDS slot of the main item
-        int hslot;  // LDS slot of the halo item
+        bool act[NI];   // item inside the tile
+        bool halo;      // this thread also computes one halo item
+        long c0[NI];    // index of the item at z0; clamped to a valid cell when idle
+        long h0;        // index of the halo item at z0 (valid cell)
+        int slot[NI];   // LDS slot of the item
+        int hslot;      // LDS slot of the halo item
     };
 
-    __device__ __forceinline__ ColPos col_pos(const GAS GroupDesc &G, int y0, int y1, int z0) const {
-        ColPos p;
-        const int tid = threadIdx.x, nx = G.nx;
-        const int x = tid % nx;
-        p.yy = tid / nx;
-        p.y = y0 + p.yy;
-        p.act = p.yy < G.cby && p.y < y1;
-        const int yc = p.act ? p.y : y0;
-        p.c0 = ((long)z0 * G.ny + yc) * nx + x;
-        p.slot = (p.act ? p.yy + 1 : 1) * nx + x;
+    template <int NI>
+    __device__ __forceinline__ ColPos<NI> col_pos(const GAS GroupDesc &G, int y0, int y1, int z0) const {
+        ColPos<NI> p;
+        const int tid = threadIdx.x, nx = G.nx, R = G.crb;
+        const int x = tid % nx, yy = tid / nx;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int row = yy + u * R, y = y0 + row;
+            p.act[u] = yy < R && row < G.cby && y < y1;
+            p.c0[u] = ((long)z0 * G.ny + (p.act[u] ? y : y0)) * nx + x;
+            p.slot[u] = (p.act[u] ? row + 1 : 1) * nx + x;
+        }
         p.halo = tid < 2 * nx;
         const bool upper = tid >= nx;
         int yh = upper ? y1 : y0 - 1;
@@ -942,17 +948,40 @@ struct Runner {
         return p;
     }
 
-    template <class T>
+    template <class T, int NI>
     struct PlaneLoad {
-        uint8_t f, fh;
-        T a, b, ah, bh, c, d;
+        uint8_t f[NI], fh;
+        T a[NI], b[NI], c[NI], ah, bh;
     };
 
-    // phase A over one column tile; stores <d_new, A d_new> per kZSub planes
-    // as partials pbase + (k / kZSub) * cny + yb.  Loads run two planes
-    // ahead: two PlaneLoad sets alternate (the loop is unrolled by two so
-    // that no register copy waits for a load in flight).
-    template <class T, bool FIRST, bool WT>
+    // Partials of NI items (NQ quantities each), stored at t[u] where ok[u]
+    // (the last tile of a grid may carry a row block beyond the grid).
+    template <int NQ, int NI>
+    __device__ __forceinline__ void store_item_partials(double (&acc)[NI][NQ], const int (&t)[NI],
+                                                        const bool (&ok)[NI]) {
+        static_assert(NQ * NI <= kNQ, "wave partial slots");
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int u = 0; u < NI; ++u)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const double v = wave_sum(acc[u][q]);
+                if (lane == 0) s_red[wv * kNQ + u * NQ + q] = v;
+            }
+        __syncthreads();
+        if (threadIdx.x < NQ * NI) {
+            const int u = threadIdx.x / NQ, q = threadIdx.x % NQ;
+            const double v = combine_waves(u * NQ + q);
+            if (ok[u]) gp(P.part)[(long)(((epoch + 1) & 1) * kNQ + q) * P.pstride + t[u]] = v;
+        }
+        __syncthreads();
+    }
+
+    // phase A over one column tile; stores <d_new, A d_new> per crb rows and
+    // kZSub planes as partials pbase + (k / kZSub) * cnb + row block.  Loads
+    // run two planes ahead: two PlaneLoad sets alternate (the loop is
+    // unrolled by two so that no register copy waits for a load in flight).
+    template <class T, bool FIRST, bool WT, int NI>
     __device__ void col_A(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ r,
                           const GAS T *__restrict__ dold, GAS T *__restrict__ dnew, T beta, int y0, int y1, int z0,
                           int z1, int pbase, int yb) {
@@ -960,7 +989,7 @@ struct Runner {
         const long sz = (long)G.nx * G.ny;
         const int nx = G.nx, nz = G.nz;
         const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
-        const ColPos P0 = col_pos(G, y0, y1, z0);
+        const ColPos<NI> P0 = col_pos<NI>(G, y0, y1, z0);
         LAS T *plane = reinterpret_cast<LAS T *>(s_plane);
         const int pst = (G.cby + 2) * nx;  // one plane buffer
         auto dn = [&](uint8_t f, T rv, T dv) -> T {
@@ -969,11 +998,14 @@ struct Runner {
         };
         // planes beyond nz wrap to the bottom (a periodic seam; with walls the
         // values are masked by the closed faces)
-        auto load = [&](int k, PlaneLoad<T> &L) {
+        auto load = [&](int k, PlaneLoad<T, NI> &L) {
             const long o = (long)(k % nz - z0) * sz;
-            L.f = fl[P0.c0 + o];
-            L.a = r[P0.c0 + o];
-            if (!FIRST) L.b = dold[P0.c0 + o];
+#pragma unroll
+            for (int u = 0; u < NI; ++u) {
+                L.f[u] = fl[P0.c0[u] + o];
+                L.a[u] = r[P0.c0[u] + o];
+                if (!FIRST) L.b[u] = dold[P0.c0[u] + o];
+            }
             if (P0.halo) {
                 L.fh = fl[P0.h0 + o];
                 L.ah = r[P0.h0 + o];
@@ -981,47 +1013,74 @@ struct Runner {
             }
         };
         // every prologue load is issued before any of them is used
-        PlaneLoad<T> L0{}, LA{}, LB{};
+        PlaneLoad<T, NI> L0{}, LA{}, LB{};
         load(z0, L0);
         load(z0 + 1, LA);
         load(z0 + 2, LB);
-        const long cm = z0 > 0 ? P0.c0 - sz : P0.c0 + (long)(nz - 1) * sz;
-        const uint8_t fm = fl[cm];
-        const T rm = r[cm], om = FIRST ? T(0) : dold[cm];
-        T dm = dn(fm, rm, om);
-        T dc = dn(L0.f, L0.a, L0.b), hc = dn(L0.fh, L0.ah, L0.bh);
-        uint8_t fc = L0.f;
-        double acc = 0.0;
+        T dm[NI], dc[NI];
+        uint8_t fc[NI];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const long cm = z0 > 0 ? P0.c0[u] - sz : P0.c0[u] + (long)(nz - 1) * sz;
+            const uint8_t fm = fl[cm];
+            const T rm = r[cm], om = FIRST ? T(0) : dold[cm];
+            dm[u] = dn(fm, rm, om);
+            dc[u] = dn(L0.f[u], L0.a[u], L0.b[u]);
+            fc[u] = L0.f[u];
+        }
+        T hc = dn(L0.fh, L0.ah, L0.bh);
+        double acc[NI][1];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) acc[u][0] = 0.0;
         int buf = 0;
-        auto step = [&](int k, PlaneLoad<T> &Lk1) {
-            const long c = P0.c0 + (long)(k - z0) * sz;
-            const T dp = dn(Lk1.f, Lk1.a, Lk1.b);
+        auto step = [&](int k, PlaneLoad<T, NI> &Lk1) {
+            T dp[NI];
+            uint8_t fp[NI];
+#pragma unroll
+            for (int u = 0; u < NI; ++u) {
+                dp[u] = dn(Lk1.f[u], Lk1.a[u], Lk1.b[u]);
+                fp[u] = Lk1.f[u];
+            }
             const T hn = dn(Lk1.fh, Lk1.ah, Lk1.bh);
-            const uint8_t fp = Lk1.f;
             load(k + 3, Lk1);
             LAS T *pl = plane + buf * pst;
-            if (P0.act) pl[P0.slot] = dc;
+#pragma unroll
+            for (int u = 0; u < NI; ++u)
+                if (P0.act[u]) pl[P0.slot[u]] = dc[u];
             if (P0.halo) pl[P0.hslot] = hc;
             __syncthreads();
-            const int sl = P0.slot;
-            T q = T(0);
-            q = (fc & FL_XM) ? fmaT(dc - pl[sl - 1], hx, q) : q;
-            q = (fc & FL_XP) ? fmaT(dc - pl[sl + 1], hx, q) : q;
-            q = (fc & FL_YM) ? fmaT(dc - pl[sl - nx], hy, q) : q;
-            q = (fc & FL_YP) ? fmaT(dc - pl[sl + nx], hy, q) : q;
-            q = (fc & FL_ZM) ? fmaT(dc - dm, hz, q) : q;
-            q = (fc & FL_ZP) ? fmaT(dc - dp, hz, q) : q;
-            if (P0.act) st_out<WT>(&dnew[c], dc);
-            acc = P0.act ? fmaT((double)dc, (double)q, acc) : acc;
-            dm = dc;
-            dc = dp;
-            fc = fp;
+#pragma unroll
+            for (int u = 0; u < NI; ++u) {
+                const int sl = P0.slot[u];
+                const uint8_t f = fc[u];
+                const T d0 = dc[u];
+                T q = T(0);
+                q = (f & FL_XM) ? fmaT(d0 - pl[sl - 1], hx, q) : q;
+                q = (f & FL_XP) ? fmaT(d0 - pl[sl + 1], hx, q) : q;
+                q = (f & FL_YM) ? fmaT(d0 - pl[sl - nx], hy, q) : q;
+                q = (f & FL_YP) ? fmaT(d0 - pl[sl + nx], hy, q) : q;
+                q = (f & FL_ZM) ? fmaT(d0 - dm[u], hz, q) : q;
+                q = (f & FL_ZP) ? fmaT(d0 - dp[u], hz, q) : q;
+                if (P0.act[u]) st_out<WT>(&dnew[P0.c0[u] + (long)(k - z0) * sz], d0);
+                acc[u][0] = P0.act[u] ? fmaT((double)d0, (double)q, acc[u][0]) : acc[u][0];
+                dm[u] = d0;
+                dc[u] = dp[u];
+                fc[u] = fp[u];
+            }
             hc = hn;
             buf ^= 1;
             if ((k + 1) % kZSub == 0 || k + 1 == z1) {
-                double a1[1] = {acc};
-                store_partials<1>(a1, pbase + (k / kZSub) * G.cny + yb);
-                acc = 0.0;
+                int t[NI];
+                bool ok[NI];
+#pragma unroll
+                for (int u = 0; u < NI; ++u) {
+                    const int rb = yb * G.cni + u;
+                    t[u] = pbase + (k / kZSub) * G.cnb + rb;
+                    ok[u] = rb < G.cnb;
+                }
+                store_item_partials<1, NI>(acc, t, ok);
+#pragma unroll
+                for (int u = 0; u < NI; ++u) acc[u][0] = 0.0;
             }
         };
         for (int k = z0; k < z1; k += 2) {
@@ -1031,81 +1090,129 @@ struct Runner {
     }
 
     // phase B over one column tile: q = A d from d's planes; x += alpha d,
-    // r -= alpha q; partials <r,z>, <r,r> per kZSub planes as in col_A.
-    // Loads and halos as in col_A.
-    template <class T, bool WT>
+    // r -= alpha q; partials <r,z>, <r,r> per crb rows and kZSub planes as in
+    // col_A.  Loads and halos as in col_A.
+    template <class T, bool WT, int NI>
     __device__ void col_B(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ d,
                           GAS T *__restrict__ x, GAS T *__restrict__ r, T alpha, int y0, int y1, int z0, int z1,
                           int pbase, int yb) {
-        double acc[2] = {0.0, 0.0};
+        double acc[NI][2];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) acc[u][0] = acc[u][1] = 0.0;
         const int gb = group_index(G) * 64;
         const long sz = (long)G.nx * G.ny;
         const int nx = G.nx, nz = G.nz;
         const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
-        const ColPos P0 = col_pos(G, y0, y1, z0);
+        const ColPos<NI> P0 = col_pos<NI>(G, y0, y1, z0);
         LAS T *plane = reinterpret_cast<LAS T *>(s_plane);
         const int pst = (G.cby + 2) * nx;
         // plane k: f, a = d, b = x, c = r; ah = halo d
-        auto load = [&](int k, PlaneLoad<T> &L) {
+        auto load = [&](int k, PlaneLoad<T, NI> &L) {
             const long o = (long)(k % nz - z0) * sz;
-            L.f = fl[P0.c0 + o];
-            L.a = d[P0.c0 + o];
-            L.b = x[P0.c0 + o];
-            L.c = r[P0.c0 + o];
+#pragma unroll
+            for (int u = 0; u < NI; ++u) {
+                L.f[u] = fl[P0.c0[u] + o];
+                L.a[u] = d[P0.c0[u] + o];
+                L.b[u] = x[P0.c0[u] + o];
+                L.c[u] = r[P0.c0[u] + o];
+            }
             if (P0.halo) L.ah = d[P0.h0 + o];
         };
         // every prologue load is issued before any of them is used
-        PlaneLoad<T> L0{}, LA{}, LB{};
+        PlaneLoad<T, NI> L0{}, LA{}, LB{};
         load(z0, L0);
         load(z0 + 1, LA);
         load(z0 + 2, LB);
-        T dm = d[z0 > 0 ? P0.c0 - sz : P0.c0 + (long)(nz - 1) * sz];
-        T dc = L0.a, hc = L0.ah, xc = L0.b, rc = L0.c;
-        uint8_t fc = L0.f;
+        T dm[NI], dc[NI], xc[NI], rc[NI];
+        uint8_t fc[NI];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            dm[u] = d[z0 > 0 ? P0.c0[u] - sz : P0.c0[u] + (long)(nz - 1) * sz];
+            dc[u] = L0.a[u];
+            xc[u] = L0.b[u];
+            rc[u] = L0.c[u];
+            fc[u] = L0.f[u];
+        }
+        T hc = L0.ah;
         int buf = 0;
-        auto step = [&](int k, PlaneLoad<T> &Lk1) {
-            const long c = P0.c0 + (long)(k - z0) * sz;
-            const T dp = Lk1.a;
-            const T hn = Lk1.ah, xn = Lk1.b, rn = Lk1.c;
-            const uint8_t fp = Lk1.f;
+        auto step = [&](int k, PlaneLoad<T, NI> &Lk1) {
+            T dp[NI], xn[NI], rn[NI];
+            uint8_t fp[NI];
+#pragma unroll
+            for (int u = 0; u < NI; ++u) {
+                dp[u] = Lk1.a[u];
+                xn[u] = Lk1.b[u];
+                rn[u] = Lk1.c[u];
+                fp[u] = Lk1.f[u];
+            }
+            const T hn = Lk1.ah;
             load(k + 3, Lk1);
             LAS T *pl = plane + buf * pst;
-            if (P0.act) pl[P0.slot] = dc;
+#pragma unroll
+            for (int u = 0; u < NI; ++u)
+                if (P0.act[u]) pl[P0.slot[u]] = dc[u];
             if (P0.halo) pl[P0.hslot] = hc;
             __syncthreads();
-            const int sl = P0.slot;
-            T q = T(0);
-            q = (fc & FL_XM) ? fmaT(dc - pl[sl - 1], hx, q) : q;
-            q = (fc & FL_XP) ? fmaT(dc - pl[sl + 1], hx, q) : q;
-            q = (fc & FL_YM) ? fmaT(dc - pl[sl - nx], hy, q) : q;
-            q = (fc & FL_YP) ? fmaT(dc - pl[sl + nx], hy, q) : q;
-            q = (fc & FL_ZM) ? fmaT(dc - dm, hz, q) : q;
-            q = (fc & FL_ZP) ? fmaT(dc - dp, hz, q) : q;
-            const T xv = fmaT(alpha, dc, xc);
-            const T rv = fmaT(-alpha, q, rc);
-            const T z = rv * idg_of<T>(gb, fc);
-            const bool live = P0.act && (fc & FL_FLUID);
-            if (live) {
-                st_out<WT>(&x[c], xv);
-                st_out<WT>(&r[c], rv);
+#pragma unroll
+            for (int u = 0; u < NI; ++u) {
+                const int sl = P0.slot[u];
+                const uint8_t f = fc[u];
+                const T d0 = dc[u];
+                T q = T(0);
+                q = (f & FL_XM) ? fmaT(d0 - pl[sl - 1], hx, q) : q;
+                q = (f & FL_XP) ? fmaT(d0 - pl[sl + 1], hx, q) : q;
+                q = (f & FL_YM) ? fmaT(d0 - pl[sl - nx], hy, q) : q;
+                q = (f & FL_YP) ? fmaT(d0 - pl[sl + nx], hy, q) : q;
+                q = (f & FL_ZM) ? fmaT(d0 - dm[u], hz, q) : q;
+                q = (f & FL_ZP) ? fmaT(d0 - dp[u], hz, q) : q;
+                const T xv = fmaT(alpha, d0, xc[u]);
+                const T rv = fmaT(-alpha, q, rc[u]);
+                const T z = rv * idg_of<T>(gb, f);
+                const bool live = P0.act[u] && (f & FL_FLUID);
+                const long c = P0.c0[u] + (long)(k - z0) * sz;
+                if (live) {
+                    st_out<WT>(&x[c], xv);
+                    st_out<WT>(&r[c], rv);
+                }
+                acc[u][0] = live ? fmaT((double)rv, (double)z, acc[u][0]) : acc[u][0];
+                acc[u][1] = live ? fmaT((double)rv, (double)rv, acc[u][1]) : acc[u][1];
+                dm[u] = d0;
+                dc[u] = dp[u];
+                fc[u] = fp[u];
+                xc[u] = xn[u];
+                rc[u] = rn[u];
             }
-            acc[0] = live ? fmaT((double)rv, (double)z, acc[0]) : acc[0];
-            acc[1] = live ? fmaT((double)rv, (double)rv, acc[1]) : acc[1];
-            dm = dc;
-            dc = dp;
-            fc = fp;
             hc = hn;
-            xc = xn;
-            rc = rn;
             buf ^= 1;
             if ((k + 1) % kZSub == 0 || k + 1 == z1) {
-                store_partials<2>(acc, pbase + (k / kZSub) * G.cny + yb);
-                acc[0] = acc[1] = 0.0;
+                int t[NI];
+                bool ok[NI];
+#pragma unroll
+                for (int u = 0; u < NI; ++u) {
+                    const int rb = yb * G.cni + u;
+                    t[u] = pbase + (k / kZSub) * G.cnb + rb;
+                    ok[u] = rb < G.cnb;
+                }
+                store_item_partials<2, NI>(acc, t, ok);
+#pragma unroll
+                for (int u = 0; u < NI; ++u) acc[u][0] = acc[u][1] = 0.0;
             }
         };
         for (int k = z0; k < z1; k += 2) {
             step(k, LA);
             if (k + 1 < z1) step(k + 1, LB);
+        }
+    }
+
+    template <class T, int NI>
+    __device__ __forceinline__ void col_A_ni(const GAS GroupDesc &G, bool first, const GAS T *r, const GAS T *dold,
+                                             GAS T *dnew, T beta, int y0, int y1, int z0, int z1, int pbase, int yb) {
+        if (P.wt) {
+            if (first) col_A<T, true, true, NI>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
+            else col_A<T, false, true, NI>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
+        } else {
+            if (first) col_A<T, true, false, NI>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
+            else col_A<T, false, false, NI>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
         }
     }
 
@@ -1138,13 +1245,13 @@ struct Runner {
             if (G.cby > 0) {
                 int y0, y1, z0, z1, yb;
                 cg_tile_bounds(G, lt, y0, y1, z0, z1, yb);
-                if (P.wt) {
-                    if (first) col_A<T, true, true>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
-                    else col_A<T, false, true>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
-                } else {
-                    if (first) col_A<T, true, false>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
-                    else col_A<T, false, false>(G, gp(G.flags), r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
+                if constexpr (sizeof(T) == 4) {
+                    if (G.cni == 2) {
+                        col_A_ni<T, 2>(G, first, r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
+                        continue;
+                    }
                 }
+                col_A_ni<T, 1>(G, first, r, dold, dnew, beta, y0, y1, z0, z1, pbase, yb);
             } else {
                 const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
                 double acc[1];
@@ -1226,8 +1333,16 @@ struct Runner {
             if (G.cby > 0) {
                 int y0, y1, z0, z1, yb;
                 cg_tile_bounds(G, lt, y0, y1, z0, z1, yb);
-                if (P.wt) col_B<T, true>(G, gp(G.flags), d, x, r, (T)cs_.alpha, y0, y1, z0, z1, pbase, yb);
-                else col_B<T, false>(G, gp(G.flags), d, x, r, (T)cs_.alpha, y0, y1, z0, z1, pbase, yb);
+                const T al = (T)cs_.alpha;
+                if constexpr (sizeof(T) == 4) {
+                    if (G.cni == 2) {
+                        if (P.wt) col_B<T, true, 2>(G, gp(G.flags), d, x, r, al, y0, y1, z0, z1, pbase, yb);
+                        else col_B<T, false, 2>(G, gp(G.flags), d, x, r, al, y0, y1, z0, z1, pbase, yb);
+                        continue;
+                    }
+                }
+                if (P.wt) col_B<T, true, 1>(G, gp(G.flags), d, x, r, al, y0, y1, z0, z1, pbase, yb);
+                else col_B<T, false, 1>(G, gp(G.flags), d, x, r, al, y0, y1, z0, z1, pbase, yb);
             } else {
                 const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
                 double acc[2] = {0.0, 0.0};

@@ -86,7 +86,7 @@ def lib():
         L.nsp_group_parareal_iterate.argtypes = [P, P, P, P, I, I, I, D, D, D, D, ctypes.POINTER(_Opts),
                                                  ctypes.POINTER(_Opts), P, P]
         L.nsp_set_launch.argtypes = [P, I]
-        L.nsp_autotune.argtypes = [P, I, I, P, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.nsp_autotune.argtypes = [P, I, I, P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
         L.nsp_last_launch_ms.argtypes = [P, ctypes.POINTER(D)]
         L.nsp_fine_solve_adjoint.argtypes = [P, _State, I, D, I, ctypes.POINTER(_Opts), _State, P,
                                              ctypes.POINTER(D), P]
@@ -266,11 +266,12 @@ class Handle:
         self._err(lib().nsp_set_launch(self._h, int(workgroups)), "nsp_set_launch")
 
     def autotune(self, batch, prec=FP64):
-        """Time launch shapes for (batch, prec); returns (workgroups, column-tile planes or 0)."""
-        ch, pl = ctypes.c_int(), ctypes.c_int()
+        """Time launch shapes for (batch, prec); returns (workgroups, column-tile
+        planes, rows per thread), the last two 0 for flat tiles."""
+        ch, pl, it = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         self._err(lib().nsp_autotune(self._h, int(batch), int(prec), _stream_ptr(), ctypes.byref(ch),
-                                     ctypes.byref(pl)), "nsp_autotune")
-        return ch.value, pl.value
+                                     ctypes.byref(pl), ctypes.byref(it)), "nsp_autotune")
+        return ch.value, pl.value, it.value
 
     def fine_solve_adjoint(self, y0, nsteps, dt, ckpt_every=10, opts=None, grad=True):
         """J = kinetic energy after nsteps steps from y0 (batch 1), and if grad

@@ -169,10 +169,12 @@ def test_batched_equals_unbatched(gpu):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_column_depth_does_not_change_results(gpu, prec):
-    """128^3 Poisson solves: a batch of 8 runs with 32-plane column tiles, a
-    batch of 1 with 8-plane tiles; partial sums are kept per 8 planes, so the
-    slices must agree bitwise (with obstacles, non-cubic grid too)."""
-    for shape, obst in [((128, 128, 128), False), ((128, 96, 112), True)]:
+    """128 x ny x nz Poisson solves: a batch of 8 runs with deeper column
+    tiles (and, in FP32 inner solves, two rows per thread), a batch of 1 with
+    8-plane tiles and one row per thread; partial sums are kept per row block
+    and 8 planes, so the slices must agree bitwise (with obstacles, a ragged
+    last row block, an odd number of row blocks, nz not a multiple of 16)."""
+    for shape, obst in [((128, 128, 128), False), ((128, 92, 112), True), ((128, 88, 120), False)]:
         nx, ny, nz = shape
         _say("column depth independence", shape, "obstacles", obst, "prec", prec)
         solid = inputs.obstacle_mask(nx, 4)[:nz, :ny, :nx] if obst else None
@@ -197,21 +199,23 @@ def test_column_depth_does_not_change_results(gpu, prec):
         h.close()
 
 
-def test_autotune_keeps_results(gpu):
-    """nsp_autotune picks a workgroup count and a column depth; the solution
-    computed before and after tuning is bitwise the same."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_keeps_results(gpu, prec):
+    """nsp_autotune picks a workgroup count, a column depth and (FP32 inner
+    solves) the rows per thread; the solution computed before and after
+    tuning is bitwise the same."""
     n, B = 128, 4
-    _say("autotune", n, B)
+    _say("autotune", n, B, "prec", prec)
     rng = np.random.default_rng(3)
     fluid = np.ones((n, n, n), bool)
     b = T(np.stack([mean_free(rng.standard_normal((n, n, n)), fluid) for _ in range(B)]))
     h = gpu.Handle(n, n, n, re=100.0, max_batch=B)
-    opts = gpu.PoissonOpts(rtol=1e-10)
+    opts = gpu.PoissonOpts(rtol=1e-10, prec=prec)
     p0 = T(np.zeros((B, n, n, n)))
     h.poisson_solve(b, p0, opts)
-    wg, planes = h.autotune(B, gpu.FP64)
-    _say("  chose", wg, "workgroups,", planes, "planes")
-    assert wg >= 1 and planes in (8, 16, 32)
+    wg, planes, items = h.autotune(B, prec)
+    _say("  chose", wg, "workgroups,", planes, "planes,", items, "rows per thread")
+    assert wg >= 1 and planes in (8, 16, 32) and items in ((1,) if prec == 0 else (1, 2))
     p1 = T(np.zeros((B, n, n, n)))
     h.poisson_solve(b, p1, opts)
     assert np.array_equal(N(p0), N(p1))
