@@ -18,6 +18,9 @@ Other modes:
   --mode sim1      the paper's first test case: 32 x 32 x 5 quasi-2D cavity,
                    periodic in z, Re 1000, dt 1e-3 / 1e-2, FP64 Parareal;
                    defect against the serial fine solution per iteration
+  --mode sim2      the paper's second test case: 32^3 cavity periodic in z
+                   with 49 seeded cubes along the median plane, T = 24;
+                   with --temporal-error also max |F_dt - F_dt/10| at T
   --mode copy      a plain device-to-device copy of 1 GiB (torch), the
                    reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE
 
@@ -359,20 +362,30 @@ def bench_obstacles(args):
     return out
 
 
-def bench_sim1(args):
-    """The paper's first test case (Sec. 3, Table 1): a quasi-2D lid-driven
-    cavity of 32 x 32 x 5 cells on [0,1]^2 x [0,0.1], periodic in z, Re 1000,
-    fine dt 1e-3, coarse dt 1e-2, FP64.  Reports, per Parareal iteration, the
-    defect of every slice end against the serial fine solution (max norm over
-    u, v, w and over p), the quantity the paper plots against N_it."""
+def bench_paper_sim(args, sim):
+    """The paper's test cases (Sec. 3, Table 1), periodic in z, Re 1000, lid
+    u = 1, fine dt 1e-3, coarse dt 1e-2, FP64:
+      Sim 1: a quasi-2D cavity of 32 x 32 x 5 cells on [0,1]^2 x [0,0.1], T = 80;
+      Sim 2: 32^3 cells on [0,1]^3 with 49 cubes along the median plane, T = 24
+             (seeded cubes: the paper does not give their layout).
+    Reports, per Parareal iteration, the defect of every slice end against
+    the serial fine solution (max norm over u, v, w and over p), the quantity
+    the paper plots against N_it; with --temporal-error also the temporal
+    error of the fine propagator at T, max |F_dt - F_dt/10| over u, v, w (and
+    p), the threshold the paper compares the defect with."""
     import torch
-    from paper_1705_06149_amd import nsp
+    from paper_1705_06149_amd import inputs, nsp
 
-    nx, ny, nz, lz = 32, 32, 5, 0.1
+    if sim == 1:
+        nx, ny, nz, lz, solid, T_def = 32, 32, 5, 0.1, None, 80.0
+    else:
+        nx, ny, nz, lz, T_def = 32, 32, 32, 1.0, 24.0
+        solid = inputs.median_plane_cubes(32, seed=49)
     re_, dt, DT = 1000.0, 1e-3, 1e-2
-    N, T = args.slices, args.sim_t
+    N = args.slices
+    T = args.sim_t if args.sim_t is not None else T_def
     o64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
-    h = nsp.Handle(nx, ny, nz, lz=lz, re=re_, max_batch=N, periodic_z=True)
+    h = nsp.Handle(nx, ny, nz, lz=lz, re=re_, solid=solid, max_batch=N, periodic_z=True)
     shapes = h.shapes()
     ref = tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in shapes)
     y = h.zeros_state(1)
@@ -398,14 +411,17 @@ def bench_sim1(args):
     h.parareal_start(Y, Gk, N, 0.0, T, DT, o64)
     defects = [defect()]
     jumps = []
+    iter_wall = []
     k = 0
     while k < min(N, args.max_iters):
         jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, o64, o64)
         jumps.append((jv, jp))
         k += 1
         defects.append(defect())
+        _sync()
+        iter_wall.append(time.perf_counter() - t0)
         _log("parareal iteration %d: jump %.3e, defect vs serial u,v,w %.3e p %.3e  %.1f s" %
-             (k, jv, defects[-1][0], defects[-1][1], time.perf_counter() - t0))
+             (k, jv, defects[-1][0], defects[-1][1], iter_wall[-1]))
     _sync()
     par = time.perf_counter() - t0
     nf = int(round(T / dt))
@@ -413,13 +429,26 @@ def bench_sim1(args):
         "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
         "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "paper_sim1", "grid": [nx, ny, nz], "domain": [1.0, 1.0, lz], "periodic_z": True,
+        "config": {"workload": "paper_sim%d" % sim, "grid": [nx, ny, nz], "domain": [1.0, 1.0, lz],
+                   "periodic_z": True, "obstacles": "49 seeded cubes, median plane" if solid is not None else None,
                    "re": re_, "slices": N, "T": T, "dt": dt, "DT": DT},
         "parareal_iterations": k, "serial_fp64_s": serial, "parareal_s": par,
+        "wall_s_after_iteration": iter_wall,
         "defect_vs_serial_uvw_per_iteration": [d[0] for d in defects],
         "defect_vs_serial_p_per_iteration": [d[1] for d in defects],
         "jumps_uvw": [j[0] for j in jumps], "jumps_p": [j[1] for j in jumps],
     }
+    if args.temporal_error:
+        # serial F with dt/10 over [0, T], slice by slice (progress per slice)
+        yr = h.zeros_state(1)
+        t1 = time.perf_counter()
+        for n in range(N):
+            h.fine_step(yr, n * T / N, (n + 1) * T / N, dt / 10, o64)
+            _log("reference F_dt/10 slice %d/%d  %.1f s" % (n + 1, N, time.perf_counter() - t1))
+        _sync()
+        out["temporal_error_uvw"] = max(float((yr[c][0] - ref[c][N]).abs().max()) for c in range(3))
+        out["temporal_error_p"] = float((yr[3][0] - ref[3][N]).abs().max())
+        out["reference_dt10_s"] = time.perf_counter() - t1
     h.close()
     return out
 
@@ -449,13 +478,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "copy"], default="fine")
+    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "sim2", "copy"],
+                    default="fine")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--solver", choices=["pcg", "bicgstab"], default="pcg",
                     help="pressure solver: Jacobi-PCG, or the paper's BiCGStab (FP64)")
     ap.add_argument("--max-iters", type=int, default=32)
-    ap.add_argument("--slices", type=int, default=16, help="sim1 mode: time slices")
-    ap.add_argument("--sim-t", type=float, default=8.0, help="sim1 mode: end time (the paper runs to 80)")
+    ap.add_argument("--slices", type=int, default=16, help="sim1/sim2 modes: time slices")
+    ap.add_argument("--sim-t", type=float, default=None,
+                    help="sim1/sim2 modes: end time (default the paper's: 80 and 24)")
+    ap.add_argument("--temporal-error", action="store_true",
+                    help="sim1/sim2 modes: also run F with dt/10 and report max |F_dt - F_dt/10| at T")
     # Forward Euler is stable only while the advective Courant number plus
     # 2 nu dt sum_d 1/h_d^2 stays below 1.  At dt = 1e-2 that sum is about
     # 0.96 + 0.55 on the 96^3 grid and the coarse propagator blows up; the
@@ -482,8 +515,8 @@ def main():
         out = bench_copy(args)
     elif args.mode == "obstacles":
         out = bench_obstacles(args)
-    elif args.mode == "sim1":
-        out = bench_sim1(args)
+    elif args.mode in ("sim1", "sim2"):
+        out = bench_paper_sim(args, int(args.mode[3]))
     else:
         out = bench_parareal(args)
     print(json.dumps(out), flush=True)

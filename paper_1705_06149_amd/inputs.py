@@ -73,6 +73,50 @@ def obstacle_mask(n, seed, frac=0.05, smin=4, smax=12, margin=1):
     return solid
 
 
+def median_plane_cubes(n, seed, count=49, smin=2, smax=3):
+    """Seeded cubes along the median plane of an n^3 cavity periodic in z, a
+    stand-in for the 49-cube geometry of the paper's fully 3D test case
+    (Sec. 3), whose layout is not given.
+
+    `count` cubes with edges uniform in [smin, smax] cells; the centre height
+    is the middle of the box (y = n/2) up to one cell, x uniform with one
+    fluid cell to the side walls, z uniform over the period (a cube may wrap
+    across the periodic seam).  Fluid cells that cannot be reached from the
+    row under the lid (face-connected, the seam included) are made solid.
+    Returns uint8 (n, n, n) indexed [k, j, i], 1 = solid.
+    """
+    from scipy import ndimage
+
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((n, n, n), dtype=np.uint8)
+    for _ in range(count):
+        s = int(rng.integers(smin, smax + 1))
+        x0 = int(rng.integers(1, n - s))
+        y0 = n // 2 - s // 2 + int(rng.integers(-1, 2))
+        z0 = int(rng.integers(0, n))
+        for k in range(s):
+            solid[(z0 + k) % n, y0:y0 + s, x0:x0 + s] = 1
+    lab, nlab = ndimage.label(solid == 0, structure=ndimage.generate_binary_structure(3, 1))
+    # regions that touch across the periodic seam are one region
+    root = np.arange(nlab + 1)
+
+    def find(a):
+        while root[a] != a:
+            root[a] = root[root[a]]
+            a = root[a]
+        return a
+
+    for a, b in set(zip(lab[0].ravel().tolist(), lab[-1].ravel().tolist())):
+        if a and b:
+            ra, rb = find(a), find(b)
+            if ra != rb:
+                root[rb] = ra
+    lab = np.array([find(a) for a in range(nlab + 1)])[lab]
+    top = np.unique(lab[:, n - 1, :])
+    solid[~np.isin(lab, top[top > 0])] = 1
+    return solid
+
+
 def div_free_perturbation(nx, ny, nz, seed, sigma=1e-2, lx=1.0, ly=1.0, lz=1.0):
     """Seeded divergence-free velocity field: the staggered-grid curl of a
     random N(0,1) edge potential that vanishes on boundary edges (so every
