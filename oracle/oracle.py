@@ -314,6 +314,79 @@ def parareal(y0, nslices, F, G, n_it=None, tol=None, jump_norm=None, combine=Non
     return Y, history
 
 
+# ------------------------------------------------- coarser-grid coarse propagator
+
+# The paper takes G on the fine grid with a larger time step and leaves other
+# coarse propagators to future work (Sec. 2.1.2).  The variant here runs G on
+# a grid with half the cells in each direction:
+#     G~(y) = P( G_c( R(y) ) ),
+# R the restriction to the coarse grid, P the prolongation back.  Fine cell
+# (k, j, i) lies in coarse cell (k//2, j//2, i//2).  R averages the four fine
+# faces that tile a coarse face (so the flux through it, and with it the
+# discrete divergence, is kept) and the eight fine cells of a coarse cell; P
+# copies a coarse face value to the fine faces inside it, interpolates
+# linearly along the normal for fine faces halfway between two coarse faces,
+# and copies a coarse cell's pressure to its eight fine cells.  So R(P(y)) = y
+# and P keeps a divergence-free field divergence-free.  Parareal, Eq. (6),
+# is unchanged with G~ in place of G.
+
+
+def _coarse_ok(g: Grid, gc: Grid):
+    if (g.nx, g.ny, g.nz) != (2 * gc.nx, 2 * gc.ny, 2 * gc.nz):
+        raise ValueError("the coarse grid must have half the cells of the fine grid in every direction")
+    if (g.lx, g.ly, g.lz, g.periodic_z) != (gc.lx, gc.ly, gc.lz, gc.periodic_z):
+        raise ValueError("fine and coarse grids must cover the same box with the same boundaries")
+    if g.solid is not None or gc.solid is not None:
+        raise NotImplementedError("coarser-grid G is defined here for cavities without obstacles")
+
+
+def restrict(g: Grid, gc: Grid, state):
+    """R: fine state (u, v, w, p) -> coarse state.  Sums are taken pairwise
+    in a fixed order: (a + b) + (c + d), then scaled."""
+    _coarse_ok(g, gc)
+    u, v, w, p = state
+    # u faces at even x positions; the four fine faces (k, j) in {2K, 2K+1} x {2J, 2J+1}
+    U = u[:, :, 0::2]
+    Uc = 0.25 * ((U[0::2, 0::2] + U[0::2, 1::2]) + (U[1::2, 0::2] + U[1::2, 1::2]))
+    V = v[:, 0::2, :]
+    Vc = 0.25 * ((V[0::2, :, 0::2] + V[0::2, :, 1::2]) + (V[1::2, :, 0::2] + V[1::2, :, 1::2]))
+    W = w[0::2]
+    Wc = 0.25 * ((W[:, 0::2, 0::2] + W[:, 0::2, 1::2]) + (W[:, 1::2, 0::2] + W[:, 1::2, 1::2]))
+    pz0 = (p[0::2, 0::2, 0::2] + p[0::2, 0::2, 1::2]) + (p[0::2, 1::2, 0::2] + p[0::2, 1::2, 1::2])
+    pz1 = (p[1::2, 0::2, 0::2] + p[1::2, 0::2, 1::2]) + (p[1::2, 1::2, 0::2] + p[1::2, 1::2, 1::2])
+    Pc = 0.125 * (pz0 + pz1)
+    return tuple(np.ascontiguousarray(a) for a in (Uc, Vc, Wc, Pc))
+
+
+def prolong(g: Grid, gc: Grid, state_c):
+    """P: coarse state -> fine state."""
+    _coarse_ok(g, gc)
+    Uc, Vc, Wc, Pc = state_c
+    nx, ny, nz = g.nx, g.ny, g.nz
+    u = np.empty((nz, ny, nx + 1))
+    v = np.empty((nz, ny + 1, nx))
+    w = np.empty((nz + 1, ny, nx))
+    # copy across the face (each coarse face value to its 2 x 2 fine faces)
+    Ue = np.repeat(np.repeat(Uc, 2, axis=0), 2, axis=1)
+    u[:, :, 0::2] = Ue
+    u[:, :, 1::2] = 0.5 * (Ue[:, :, :-1] + Ue[:, :, 1:])
+    Ve = np.repeat(np.repeat(Vc, 2, axis=0), 2, axis=2)
+    v[:, 0::2, :] = Ve
+    v[:, 1::2, :] = 0.5 * (Ve[:, :-1, :] + Ve[:, 1:, :])
+    We = np.repeat(np.repeat(Wc, 2, axis=1), 2, axis=2)
+    w[0::2] = We
+    w[1::2] = 0.5 * (We[:-1] + We[1:])
+    p = np.repeat(np.repeat(np.repeat(Pc, 2, axis=0), 2, axis=1), 2, axis=2)
+    return u, v, w, np.ascontiguousarray(p)
+
+
+def coarse_grid_propagator(g: Grid, gc: Grid, DT, **opts):
+    """G~(y, t0, t1) = P(G_c(R(y))) with steps DT on the coarse grid."""
+    def G(y, t0, t1):
+        return prolong(g, gc, propagate(gc, restrict(g, gc, y), t0, t1, DT, **opts))
+    return G
+
+
 # ------------------------------------------------------------------ adjoint
 
 def stencil_value(g: Grid, c, phi, f, d, m, as_form=False):
