@@ -12,7 +12,8 @@ Other modes:
                    sides, a working set far above the 256 MB Infinity Cache)
   --mode parareal  Parareal on the 96^3 cavity (32 slices of 0.02, fine dt
                    5e-4, coarse dt --coarse-dt, mixed precision, jump < 1e-6)
-                   against the serial FP64 fine solve on the GPU
+                   against the serial FP64 fine solve on the GPU; with
+                   --coarse-grid the coarse propagator runs on 48^3
   --mode obstacles uneven batch: 16 slices on each of 64^3, 96^3, 128^3 with
                    seeded cuboid obstacles, grouped launches, mixed precision
   --mode sim1      the paper's first test case: 32 x 32 x 5 quasi-2D cavity,
@@ -237,11 +238,15 @@ def bench_parareal(args):
     from paper_1705_06149_amd import nsp
 
     n, re_, dt, N, T = 96, 1000.0, 5e-4, 32, 0.64
-    DT = args.coarse_dt if args.coarse_dt is not None else 5e-3
+    cgrid = args.coarse_grid
+    # on the 48^3 coarse grid the configuration's coarse step 1e-2 is stable
+    # (Courant number 0.48, diffusion term 0.14)
+    DT = args.coarse_dt if args.coarse_dt is not None else (1e-2 if cgrid else 5e-3)
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=args.eta)
     h = nsp.Handle(n, n, n, re=re_, max_batch=N)
+    hc = nsp.Handle(n // 2, n // 2, n // 2, re=re_, max_batch=1) if cgrid else None
     # serial FP64 fine solve, batch 1, over [0, T]
     y = h.zeros_state(1)
     _sync()
@@ -261,13 +266,19 @@ def bench_parareal(args):
     Gk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
     _sync()
     t0 = time.perf_counter()
-    h.parareal_start(Y, Gk, N, 0.0, T, DT, mixed)
+    if cgrid:
+        h.parareal_start_cgrid(hc, Y, Gk, N, 0.0, T, DT, mixed)
+    else:
+        h.parareal_start(Y, Gk, N, 0.0, T, DT, mixed)
     jumps = []
     k = 0
     iter_s = []
     while True:
         ti = time.perf_counter()
-        jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
+        if cgrid:
+            jv, jp = h.parareal_iterate_cgrid(hc, Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
+        else:
+            jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
         iter_s.append(time.perf_counter() - ti)
         jumps.append(jv)
         _log("parareal iteration %d: %.1f s, jump %.3e" % (k, iter_s[-1], jv))
@@ -285,7 +296,7 @@ def bench_parareal(args):
         "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
-                   "jump_tol": tol},
+                   "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n]},
         "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
         "serial_equiv_cell_updates_per_s": cells * nf / par,
         "end_state_rel_l2_vs_serial_fp64": err,
@@ -294,6 +305,8 @@ def bench_parareal(args):
                              "cg_rows_per_thread": tuned_items},
     }
     h.close()
+    if hc is not None:
+        hc.close()
     return out
 
 
@@ -495,6 +508,9 @@ def main():
     # defaults are 5e-3 for the 96^3 Parareal run (about 0.76) and 2.5e-3 for
     # the obstacle batch, whose 128^3 grid needs dt < ~4.4e-3.
     ap.add_argument("--coarse-dt", type=float, default=None)
+    ap.add_argument("--coarse-grid", action="store_true",
+                    help="parareal mode: coarse propagator on a grid with half the cells per direction "
+                         "(restriction, coarse steps, prolongation); coarse dt defaults to 1e-2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eta", type=float, default=1e-5, help="inner FP32 tolerance of the mixed Poisson solve")
     ap.add_argument("--compare-fp64", action="store_true",

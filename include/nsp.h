@@ -185,6 +185,38 @@ nsp_status nsp_group_parareal_iterate(nsp_handle *const *hs, const nsp_state *Y,
                                       double dt, double DT, const nsp_poisson_opts *fine,
                                       const nsp_poisson_opts *coarse, void *stream, double *jump);
 
+/* Coarser-grid coarse propagator.  The paper runs G on the fine grid with a
+ * larger step and leaves other coarse propagators to future work (Sec.
+ * 2.1.2).  Here G~(y) = P(G_c(R(y))): G_c is the projection step of
+ * Sec. 2 on the grid of the coarse handle hc, which must have half the
+ * cells of h in every direction (nx, ny, nz of h even), the same box and the
+ * same z boundary, and neither grid may hold obstacles (else
+ * NSP_ERR_UNSUPPORTED; a size or box mismatch is NSP_ERR_ARG).  Fine cell
+ * (k, j, i) lies in coarse cell (k/2, j/2, i/2).
+ *   R (nsp_restrict): a coarse face value is the mean of the four fine faces
+ *     tiling it (so the flux through it, and the discrete divergence, are
+ *     kept); a coarse pressure is the mean of its eight fine cells.
+ *   P (nsp_prolong): a fine face inside a coarse face takes its value; a
+ *     fine face halfway between two coarse faces takes their mean; a fine
+ *     cell takes its coarse cell's pressure.  R(P(y)) = y, and P keeps a
+ *     divergence-free field (zero normal velocity on the walls)
+ *     divergence-free.
+ * yf / yc: DEVICE states of `batch` slices on the fine / coarse grid
+ * (caller-owned, layout as nsp_state); the output is overwritten, nothing is
+ * allocated.  nsp_parareal_start_cgrid / nsp_parareal_iterate_cgrid are
+ * nsp_parareal_start / nsp_parareal_iterate with G~ in place of G: Y, Fk and
+ * Gk stay fine-grid states (Gk[n] = G~(Y[n]) of the previous sweep), coarse
+ * steps of size DT run on hc (its Reynolds number and lid), and the update
+ * of Eq. (6) and its exactness after nslices iterations are unchanged. */
+nsp_status nsp_restrict(nsp_handle *h, nsp_handle *hc, nsp_state yf, nsp_state yc, int batch, void *stream);
+nsp_status nsp_prolong(nsp_handle *h, nsp_handle *hc, nsp_state yc, nsp_state yf, int batch, void *stream);
+nsp_status nsp_parareal_start_cgrid(nsp_handle *h, nsp_handle *hc, nsp_state Y, nsp_state Gk, int nslices,
+                                    double t0, double T, double DT, const nsp_poisson_opts *coarse, void *stream);
+nsp_status nsp_parareal_iterate_cgrid(nsp_handle *h, nsp_handle *hc, nsp_state Y, nsp_state Fk, nsp_state Gk,
+                                      int nslices, int k, double t0, double T, double dt, double DT,
+                                      const nsp_poisson_opts *fine, const nsp_poisson_opts *coarse, void *stream,
+                                      double *jump);
+
 /* Adjoint of the fine propagator F (Sec. 2.1.2) for the objective
  *     J = 1/2 hx hy hz sum over open faces of (u_T^2 + v_T^2 + w_T^2),
  * the kinetic energy after nsteps projection steps of size dt from y0

@@ -518,6 +518,162 @@ nsp_status propagate(nsp_handle *const *hs, const nsp_state *ys, const int *batc
     return run(hs, ngroups, G, MODE_FINE, nsteps, step, o, static_cast<hipStream_t>(stream), info, 0);
 }
 
+// A coarse handle for the coarser-grid coarse propagator: half the cells of
+// the fine grid in every direction, the same box and boundaries, no obstacles.
+nsp_status check_pair(nsp_handle *h, nsp_handle *hc) {
+    if (!h || !hc) return fail(h ? h : hc, NSP_ERR_ARG, "null handle");
+    if (h->nx != 2 * hc->nx || h->ny != 2 * hc->ny || h->nz != 2 * hc->nz)
+        return fail(h, NSP_ERR_ARG, "the coarse grid must have half the fine grid's cells in every direction");
+    if (h->lx != hc->lx || h->ly != hc->ly || h->lz != hc->lz || h->pz != hc->pz)
+        return fail(h, NSP_ERR_ARG, "fine and coarse grids must cover the same box with the same boundaries");
+    if (h->nfluid != (double)h->ncells || hc->nfluid != (double)hc->ncells)
+        return fail(h, NSP_ERR_UNSUPPORTED, "the coarser-grid coarse propagator takes grids without obstacles");
+    return NSP_OK;
+}
+
+// fine -> coarse (restriction) or coarse -> fine (prolongation) of `batch`
+// slices; h is the fine handle
+hipError_t transfer(nsp_handle *h, nsp_state src, nsp_state dst, int batch, bool prolong, hipStream_t s) {
+    TransferParams T;
+    T.prolong = prolong ? 1 : 0;
+    T.nx = h->nx;
+    T.ny = h->ny;
+    T.nz = h->nz;
+    T.batch = batch;
+    T.src[0] = src.u;
+    T.src[1] = src.v;
+    T.src[2] = src.w;
+    T.src[3] = src.p;
+    T.dst[0] = dst.u;
+    T.dst[1] = dst.v;
+    T.dst[2] = dst.w;
+    T.dst[3] = dst.p;
+    return launch_transfer(T, s);
+}
+
+// Coarse propagator over one slice for every group: hs[g]->gs <- G(Y[g] slice
+// n) with G on the handle's own grid, or, with coarse handles hcs, G~ =
+// P(G_c(R(y))) on hcs[g]'s grid.
+nsp_status coarse_slice(nsp_handle *const *hs, nsp_handle *const *hcs, const nsp_state *Y, int ngroups, int n,
+                        double t0, double t1, double DT, const nsp_poisson_opts *coarse, hipStream_t s) {
+    nsp_handle *h = hs[0];
+    nsp_state gsv[kMaxGroups];
+    int ones[kMaxGroups];
+    for (int g = 0; g < ngroups; ++g) {
+        ones[g] = 1;
+        if (hcs) {
+            HIPCHK(h, transfer(hs[g], offset_state(hs[g], Y[g], n), hcs[g]->gs, 1, false, s));
+            gsv[g] = hcs[g]->gs;
+        } else {
+            HIPCHK(h, copy_slices(hs[g], hs[g]->gs, offset_state(hs[g], Y[g], n), 1, s));
+            gsv[g] = hs[g]->gs;
+        }
+    }
+    nsp_status st = propagate(hcs ? hcs : hs, gsv, ones, ngroups, t0, t1, DT, coarse, s, nullptr);
+    if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
+        if (hcs) h->err = "coarse grid: " + hcs[0]->err;
+        return st;
+    }
+    if (hcs)
+        for (int g = 0; g < ngroups; ++g) HIPCHK(h, transfer(hs[g], hcs[g]->gs, hs[g]->gs, 1, true, s));
+    return NSP_OK;
+}
+
+nsp_status parareal_start_impl(nsp_handle *const *hs, nsp_handle *const *hcs, const nsp_state *Y,
+                               const nsp_state *Gk, int ngroups, int nslices, double t0, double T, double DT,
+                               const nsp_poisson_opts *coarse, void *stream) {
+    if (!hs || !Y || !Gk || ngroups < 1 || ngroups > kMaxGroups || !hs[0] || nslices < 1)
+        return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad Parareal arguments");
+    nsp_handle *h = hs[0];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double len = (T - t0) / nslices;
+    int nc = 0;
+    if (!step_count(0.0, len, DT, &nc)) return fail(h, NSP_ERR_ARG, "slice length / DT is not an integer");
+    for (int g = 0; g < ngroups; ++g)
+        if (!hs[g] || !state_ok(Y[g]) || !state_ok(Gk[g])) return fail(h, NSP_ERR_ARG, "null state");
+    for (int n = 0; n < nslices; ++n) {
+        nsp_status st = coarse_slice(hs, hcs, Y, ngroups, n, t0 + n * len, t0 + (n + 1) * len, DT, coarse, s);
+        if (st != NSP_OK) return st;
+        for (int g = 0; g < ngroups; ++g) {
+            HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Y[g], n + 1), hs[g]->gs, 1, s));
+            HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Gk[g], n), hs[g]->gs, 1, s));
+        }
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
+    return NSP_OK;
+}
+
+nsp_status parareal_iterate_impl(nsp_handle *const *hs, nsp_handle *const *hcs, const nsp_state *Y,
+                                 const nsp_state *Fk, const nsp_state *Gk, int ngroups, int nslices, int k, double t0,
+                                 double T, double dt, double DT, const nsp_poisson_opts *fine,
+                                 const nsp_poisson_opts *coarse, void *stream, double *jump) {
+    if (!hs || !Y || !Fk || !Gk || ngroups < 1 || ngroups > kMaxGroups || !hs[0] || nslices < 1 || k < 0 || !jump)
+        return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad Parareal arguments");
+    nsp_handle *h = hs[0];
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double len = (T - t0) / nslices;
+    int nf = 0, nc = 0;
+    if (!step_count(0.0, len, dt, &nf) || !step_count(0.0, len, DT, &nc))
+        return fail(h, NSP_ERR_ARG, "slice length / dt or / DT is not an integer");
+    for (int g = 0; g < ngroups; ++g) {
+        if (!hs[g] || !state_ok(Y[g]) || !state_ok(Fk[g]) || !state_ok(Gk[g]))
+            return fail(h, NSP_ERR_ARG, "null state");
+        if (hs[g]->max_batch < nslices) return fail(h, NSP_ERR_ARG, "max_batch is smaller than nslices");
+    }
+    for (int g = 0; g < 2 * ngroups; ++g) jump[g] = 0.0;
+    if (k >= nslices) return NSP_OK;  // every slice is already exact
+    const int active = nslices - k;
+    // F(Y[n]) for n >= k, all grids' slices in one launch
+    nsp_state fsub[kMaxGroups];
+    int nb[kMaxGroups];
+    for (int g = 0; g < ngroups; ++g) {
+        HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Fk[g], k), offset_state(hs[g], Y[g], k), active, s));
+        fsub[g] = offset_state(hs[g], Fk[g], k);
+        nb[g] = active;
+    }
+    nsp_status st = propagate(hs, fsub, nb, ngroups, t0 + k * len, t0 + (k + 1) * len, dt, fine, stream, nullptr);
+    if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
+    HIPCHK(h, hipMemsetAsync(h->L.jump, 0, 2 * kMaxGroups * sizeof(unsigned long long), s));
+    for (int n = k; n < nslices; ++n) {
+        st = coarse_slice(hs, hcs, Y, ngroups, n, t0 + n * len, t0 + (n + 1) * len, DT, coarse, s);
+        if (st != NSP_OK) return st;
+        UpdateParams U;
+        std::memset(&U, 0, sizeof(U));
+        U.jump = h->L.jump;
+        for (int g = 0; g < ngroups; ++g) {
+            nsp_handle *hg = hs[g];
+            const nsp_state y1 = offset_state(hg, Y[g], n + 1), f = offset_state(hg, Fk[g], n),
+                            go = offset_state(hg, Gk[g], n);
+            double *ys[4] = {y1.u, y1.v, y1.w, y1.p};
+            const double *fs[4] = {f.u, f.v, f.w, f.p};
+            const double *gn[4] = {hg->gs.u, hg->gs.v, hg->gs.w, hg->gs.p};
+            double *gos[4] = {go.u, go.v, go.w, go.p};
+            const long long ns[4] = {hg->nu, hg->nv, hg->nw, hg->ncells};
+            for (int c = 0; c < 4; ++c) {
+                UpdateSeg &S = U.seg[U.nseg];
+                S.y = ys[c];
+                S.f = fs[c];
+                S.g = gn[c];
+                S.gold = gos[c];
+                S.n = ns[c];
+                S.jslot = c == 3 ? 1 : 0;
+                U.group_of_seg[U.nseg] = g;
+                ++U.nseg;
+            }
+        }
+        HIPCHK(h, launch_parareal_update(U, s));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->L.jump_host, h->L.jump, 2 * kMaxGroups * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (int g = 0; g < 2 * ngroups; ++g) {
+        double v;
+        std::memcpy(&v, &h->L.jump_host[g], sizeof(v));
+        jump[g] = v;
+    }
+    return NSP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -680,121 +836,63 @@ nsp_status nsp_group_fine_step(nsp_handle *const *hs, const nsp_state *ys, const
 nsp_status nsp_group_parareal_start(nsp_handle *const *hs, const nsp_state *Y, const nsp_state *Gk, int ngroups,
                                     int nslices, double t0, double T, double DT, const nsp_poisson_opts *coarse,
                                     void *stream) {
-    if (!hs || !Y || !Gk || ngroups < 1 || ngroups > kMaxGroups || !hs[0] || nslices < 1)
-        return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad Parareal arguments");
-    nsp_handle *h = hs[0];
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const double len = (T - t0) / nslices;
-    int nc = 0;
-    if (!step_count(0.0, len, DT, &nc)) return fail(h, NSP_ERR_ARG, "slice length / DT is not an integer");
-    for (int g = 0; g < ngroups; ++g)
-        if (!hs[g] || !state_ok(Y[g]) || !state_ok(Gk[g])) return fail(h, NSP_ERR_ARG, "null state");
-    nsp_state gsv[kMaxGroups];
-    int ones[kMaxGroups];
-    for (int g = 0; g < ngroups; ++g) { gsv[g] = hs[g]->gs; ones[g] = 1; }
-    for (int n = 0; n < nslices; ++n) {
-        for (int g = 0; g < ngroups; ++g)
-            HIPCHK(h, copy_slices(hs[g], hs[g]->gs, offset_state(hs[g], Y[g], n), 1, s));
-        nsp_status st = propagate(hs, gsv, ones, ngroups, t0 + n * len, t0 + (n + 1) * len, DT, coarse, stream, nullptr);
-        if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
-        for (int g = 0; g < ngroups; ++g) {
-            HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Y[g], n + 1), hs[g]->gs, 1, s));
-            HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Gk[g], n), hs[g]->gs, 1, s));
-        }
-    }
-    HIPCHK(h, hipStreamSynchronize(s));
-    return NSP_OK;
+    return parareal_start_impl(hs, nullptr, Y, Gk, ngroups, nslices, t0, T, DT, coarse, stream);
 }
 
 nsp_status nsp_parareal_start(nsp_handle *h, nsp_state Y, nsp_state Gk, int nslices, double t0, double T, double DT,
                               const nsp_poisson_opts *coarse, void *stream) {
     nsp_handle *hs[1] = {h};
-    return nsp_group_parareal_start(hs, &Y, &Gk, 1, nslices, t0, T, DT, coarse, stream);
+    return parareal_start_impl(hs, nullptr, &Y, &Gk, 1, nslices, t0, T, DT, coarse, stream);
 }
 
 nsp_status nsp_group_parareal_iterate(nsp_handle *const *hs, const nsp_state *Y, const nsp_state *Fk,
                                       const nsp_state *Gk, int ngroups, int nslices, int k, double t0, double T,
                                       double dt, double DT, const nsp_poisson_opts *fine,
                                       const nsp_poisson_opts *coarse, void *stream, double *jump) {
-    if (!hs || !Y || !Fk || !Gk || ngroups < 1 || ngroups > kMaxGroups || !hs[0] || nslices < 1 || k < 0 || !jump)
-        return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad Parareal arguments");
-    nsp_handle *h = hs[0];
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const double len = (T - t0) / nslices;
-    int nf = 0, nc = 0;
-    if (!step_count(0.0, len, dt, &nf) || !step_count(0.0, len, DT, &nc))
-        return fail(h, NSP_ERR_ARG, "slice length / dt or / DT is not an integer");
-    for (int g = 0; g < ngroups; ++g) {
-        if (!hs[g] || !state_ok(Y[g]) || !state_ok(Fk[g]) || !state_ok(Gk[g]))
-            return fail(h, NSP_ERR_ARG, "null state");
-        if (hs[g]->max_batch < nslices) return fail(h, NSP_ERR_ARG, "max_batch is smaller than nslices");
-    }
-    for (int g = 0; g < 2 * ngroups; ++g) jump[g] = 0.0;
-    if (k >= nslices) return NSP_OK;  // every slice is already exact
-    const int active = nslices - k;
-    // F(Y[n]) for n >= k, all grids' slices in one launch
-    nsp_state fsub[kMaxGroups];
-    int nb[kMaxGroups];
-    for (int g = 0; g < ngroups; ++g) {
-        HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Fk[g], k), offset_state(hs[g], Y[g], k), active, s));
-        fsub[g] = offset_state(hs[g], Fk[g], k);
-        nb[g] = active;
-    }
-    nsp_status st = propagate(hs, fsub, nb, ngroups, t0 + k * len, t0 + (k + 1) * len, dt, fine, stream, nullptr);
-    if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
-    HIPCHK(h, hipMemsetAsync(h->L.jump, 0, 2 * kMaxGroups * sizeof(unsigned long long), s));
-    nsp_state gsv[kMaxGroups];
-    int ones[kMaxGroups];
-    for (int g = 0; g < ngroups; ++g) { gsv[g] = hs[g]->gs; ones[g] = 1; }
-    for (int n = k; n < nslices; ++n) {
-        for (int g = 0; g < ngroups; ++g)
-            HIPCHK(h, copy_slices(hs[g], hs[g]->gs, offset_state(hs[g], Y[g], n), 1, s));
-        st = propagate(hs, gsv, ones, ngroups, t0 + n * len, t0 + (n + 1) * len, DT, coarse, stream, nullptr);
-        if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
-        UpdateParams U;
-        std::memset(&U, 0, sizeof(U));
-        U.jump = h->L.jump;
-        for (int g = 0; g < ngroups; ++g) {
-            nsp_handle *hg = hs[g];
-            const nsp_state y1 = offset_state(hg, Y[g], n + 1), f = offset_state(hg, Fk[g], n),
-                            go = offset_state(hg, Gk[g], n);
-            double *ys[4] = {y1.u, y1.v, y1.w, y1.p};
-            const double *fs[4] = {f.u, f.v, f.w, f.p};
-            const double *gn[4] = {hg->gs.u, hg->gs.v, hg->gs.w, hg->gs.p};
-            double *gos[4] = {go.u, go.v, go.w, go.p};
-            const long long ns[4] = {hg->nu, hg->nv, hg->nw, hg->ncells};
-            for (int c = 0; c < 4; ++c) {
-                UpdateSeg &S = U.seg[U.nseg];
-                S.y = ys[c];
-                S.f = fs[c];
-                S.g = gn[c];
-                S.gold = gos[c];
-                S.n = ns[c];
-                S.jslot = c == 3 ? 1 : 0;
-                U.group_of_seg[U.nseg] = g;
-                ++U.nseg;
-            }
-        }
-        HIPCHK(h, launch_parareal_update(U, s));
-    }
-    HIPCHK(h, hipMemcpyAsync(h->L.jump_host, h->L.jump, 2 * kMaxGroups * sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    for (int g = 0; g < 2 * ngroups; ++g) {
-        double v;
-        std::memcpy(&v, &h->L.jump_host[g], sizeof(v));
-        jump[g] = v;
-    }
-    return NSP_OK;
+    return parareal_iterate_impl(hs, nullptr, Y, Fk, Gk, ngroups, nslices, k, t0, T, dt, DT, fine, coarse, stream,
+                                 jump);
 }
 
 nsp_status nsp_parareal_iterate(nsp_handle *h, nsp_state Y, nsp_state Fk, nsp_state Gk, int nslices, int k,
                                 double t0, double T, double dt, double DT, const nsp_poisson_opts *fine,
                                 const nsp_poisson_opts *coarse, void *stream, double *jump) {
     nsp_handle *hs[1] = {h};
-    return nsp_group_parareal_iterate(hs, &Y, &Fk, &Gk, 1, nslices, k, t0, T, dt, DT, fine, coarse, stream, jump);
+    return parareal_iterate_impl(hs, nullptr, &Y, &Fk, &Gk, 1, nslices, k, t0, T, dt, DT, fine, coarse, stream, jump);
 }
 
+nsp_status nsp_restrict(nsp_handle *h, nsp_handle *hc, nsp_state yf, nsp_state yc, int batch, void *stream) {
+    nsp_status st = check_pair(h, hc);
+    if (st != NSP_OK) return st;
+    if (!state_ok(yf) || !state_ok(yc) || batch < 0) return fail(h, NSP_ERR_ARG, "null state or negative batch");
+    HIPCHK(h, transfer(h, yf, yc, batch, false, static_cast<hipStream_t>(stream)));
+    return NSP_OK;
+}
+
+nsp_status nsp_prolong(nsp_handle *h, nsp_handle *hc, nsp_state yc, nsp_state yf, int batch, void *stream) {
+    nsp_status st = check_pair(h, hc);
+    if (st != NSP_OK) return st;
+    if (!state_ok(yf) || !state_ok(yc) || batch < 0) return fail(h, NSP_ERR_ARG, "null state or negative batch");
+    HIPCHK(h, transfer(h, yc, yf, batch, true, static_cast<hipStream_t>(stream)));
+    return NSP_OK;
+}
+
+nsp_status nsp_parareal_start_cgrid(nsp_handle *h, nsp_handle *hc, nsp_state Y, nsp_state Gk, int nslices, double t0,
+                                    double T, double DT, const nsp_poisson_opts *coarse, void *stream) {
+    nsp_status st = check_pair(h, hc);
+    if (st != NSP_OK) return st;
+    nsp_handle *hs[1] = {h}, *hcs[1] = {hc};
+    return parareal_start_impl(hs, hcs, &Y, &Gk, 1, nslices, t0, T, DT, coarse, stream);
+}
+
+nsp_status nsp_parareal_iterate_cgrid(nsp_handle *h, nsp_handle *hc, nsp_state Y, nsp_state Fk, nsp_state Gk,
+                                      int nslices, int k, double t0, double T, double dt, double DT,
+                                      const nsp_poisson_opts *fine, const nsp_poisson_opts *coarse, void *stream,
+                                      double *jump) {
+    nsp_status st = check_pair(h, hc);
+    if (st != NSP_OK) return st;
+    nsp_handle *hs[1] = {h}, *hcs[1] = {hc};
+    return parareal_iterate_impl(hs, hcs, &Y, &Fk, &Gk, 1, nslices, k, t0, T, dt, DT, fine, coarse, stream, jump);
+}
 
 }  // extern "C"
 

@@ -152,6 +152,18 @@ struct UpdateParams {
     int group_of_seg[kMaxSegs];
 };
 hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream);
+
+// Grid transfers between a fine grid and one with half its cells in every
+// direction (nx, ny, nz of the fine grid, all even).  Component c = 0..3 is
+// u, v, w, p; src/dst hold `batch` slices back to back.
+struct TransferParams {
+    int prolong;                    // 0: restrict fine -> coarse; 1: prolong coarse -> fine
+    int nx, ny, nz;                 // fine grid
+    int batch;
+    const double *src[4];
+    double *dst[4];
+};
+hipError_t launch_transfer(const TransferParams &T, hipStream_t stream);
 hipError_t launch_copy_state(double *dst, const double *src, long long n, hipStream_t stream);
 
 // Adjoint of the fine step (nsp_adjoint.hip).

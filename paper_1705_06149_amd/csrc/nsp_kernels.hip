@@ -1735,6 +1735,77 @@ __global__ void k_reset_sync(SyncWords *s) {
     for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) w[x] = 0u;
 }
 
+// Restriction (coarse output element) or prolongation (fine output element)
+// between a fine MAC grid and the grid with half its cells per direction:
+// fine cell (k, j, i) lies in coarse cell (k/2, j/2, i/2).  Restriction
+// averages the four fine faces tiling a coarse face, summed (a + b) + (c + d)
+// with a, b the pair at the lower index of the slower direction, and the
+// eight fine cells of a coarse cell (two such four-sums, lower z first).
+// Prolongation copies a coarse face to the fine faces inside it and averages
+// the two coarse faces around a fine face halfway between them; pressure is
+// copied to the eight fine cells.
+__global__ void k_transfer(TransferParams T) {
+    const long nx = T.nx, ny = T.ny, nz = T.nz, cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    // per-slice element counts of the fine and coarse components
+    const long fn[4] = {(nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1), nx * ny * nz};
+    const long cn[4] = {(cx + 1) * cy * cz, cx * (cy + 1) * cz, cx * cy * (cz + 1), cx * cy * cz};
+    for (int c = 0; c < 4; ++c) {
+        const long on = T.prolong ? fn[c] : cn[c];  // output elements per slice
+        const long total = on * T.batch;
+        const double *src = T.src[c];
+        double *dst = T.dst[c];
+        for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+            const long sl = e / on, r = e - sl * on;
+            if (!T.prolong) {
+                const double *f = src + sl * fn[c];
+                double out;
+                if (c == 0) {  // coarse u (K, J, I) of [cz][cy][cx+1]; fine u of [nz][ny][nx+1]
+                    const long I = r % (cx + 1), J = (r / (cx + 1)) % cy, K = r / ((cx + 1) * cy);
+                    auto at = [&](long k, long j) { return f[(k * ny + j) * (nx + 1) + 2 * I]; };
+                    out = 0.25 * ((at(2 * K, 2 * J) + at(2 * K, 2 * J + 1)) + (at(2 * K + 1, 2 * J) + at(2 * K + 1, 2 * J + 1)));
+                } else if (c == 1) {  // coarse v of [cz][cy+1][cx]; fine v of [nz][ny+1][nx]
+                    const long I = r % cx, J = (r / cx) % (cy + 1), K = r / (cx * (cy + 1));
+                    auto at = [&](long k, long i) { return f[(k * (ny + 1) + 2 * J) * nx + i]; };
+                    out = 0.25 * ((at(2 * K, 2 * I) + at(2 * K, 2 * I + 1)) + (at(2 * K + 1, 2 * I) + at(2 * K + 1, 2 * I + 1)));
+                } else if (c == 2) {  // coarse w of [cz+1][cy][cx]; fine w of [nz+1][ny][nx]
+                    const long I = r % cx, J = (r / cx) % cy, K = r / (cx * cy);
+                    auto at = [&](long j, long i) { return f[(2 * K * ny + j) * nx + i]; };
+                    out = 0.25 * ((at(2 * J, 2 * I) + at(2 * J, 2 * I + 1)) + (at(2 * J + 1, 2 * I) + at(2 * J + 1, 2 * I + 1)));
+                } else {  // coarse p of [cz][cy][cx]
+                    const long I = r % cx, J = (r / cx) % cy, K = r / (cx * cy);
+                    auto at = [&](long k, long j, long i) { return f[(k * ny + j) * nx + i]; };
+                    const double z0 = (at(2 * K, 2 * J, 2 * I) + at(2 * K, 2 * J, 2 * I + 1)) +
+                                      (at(2 * K, 2 * J + 1, 2 * I) + at(2 * K, 2 * J + 1, 2 * I + 1));
+                    const double z1 = (at(2 * K + 1, 2 * J, 2 * I) + at(2 * K + 1, 2 * J, 2 * I + 1)) +
+                                      (at(2 * K + 1, 2 * J + 1, 2 * I) + at(2 * K + 1, 2 * J + 1, 2 * I + 1));
+                    out = 0.125 * (z0 + z1);
+                }
+                dst[e] = out;
+            } else {
+                const double *g = src + sl * cn[c];
+                double out;
+                if (c == 0) {  // fine u (k, j, i) of [nz][ny][nx+1]
+                    const long i = r % (nx + 1), j = (r / (nx + 1)) % ny, k = r / ((nx + 1) * ny);
+                    const long b = ((k / 2) * cy + j / 2) * (cx + 1);
+                    out = (i & 1) ? 0.5 * (g[b + i / 2] + g[b + i / 2 + 1]) : g[b + i / 2];
+                } else if (c == 1) {  // fine v of [nz][ny+1][nx]
+                    const long i = r % nx, j = (r / nx) % (ny + 1), k = r / (nx * (ny + 1));
+                    const long b = (k / 2) * (cy + 1) * cx + i / 2;
+                    out = (j & 1) ? 0.5 * (g[b + (j / 2) * cx] + g[b + (j / 2 + 1) * cx]) : g[b + (j / 2) * cx];
+                } else if (c == 2) {  // fine w of [nz+1][ny][nx]
+                    const long i = r % nx, j = (r / nx) % ny, k = r / (nx * ny);
+                    const long b = (j / 2) * cx + i / 2, pl = cy * cx;
+                    out = (k & 1) ? 0.5 * (g[b + (k / 2) * pl] + g[b + (k / 2 + 1) * pl]) : g[b + (k / 2) * pl];
+                } else {
+                    const long i = r % nx, j = (r / nx) % ny, k = r / (nx * ny);
+                    out = g[((k / 2) * cy + j / 2) * cx + i / 2];
+                }
+                dst[e] = out;
+            }
+        }
+    }
+}
+
 __global__ void k_parareal_update(UpdateParams U) {
     // grid-stride over all segments, one segment at a time
     for (int si = 0; si < U.nseg; ++si) {
@@ -1800,6 +1871,15 @@ hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream) {
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_parareal_update, dim3((unsigned)blocks), dim3(256), 0, stream, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_transfer(const TransferParams &T, hipStream_t stream) {
+    const long long n = (long long)(T.nx + 1) * (T.ny + 1) * (T.nz + 1) * T.batch;
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_transfer, dim3((unsigned)blocks), dim3(256), 0, stream, T);
     return hipGetLastError();
 }
 

@@ -85,6 +85,11 @@ def lib():
         L.nsp_group_parareal_start.argtypes = [P, P, P, I, I, D, D, D, ctypes.POINTER(_Opts), P]
         L.nsp_group_parareal_iterate.argtypes = [P, P, P, P, I, I, I, D, D, D, D, ctypes.POINTER(_Opts),
                                                  ctypes.POINTER(_Opts), P, P]
+        L.nsp_restrict.argtypes = [P, P, _State, _State, I, P]
+        L.nsp_prolong.argtypes = [P, P, _State, _State, I, P]
+        L.nsp_parareal_start_cgrid.argtypes = [P, P, _State, _State, I, D, D, D, ctypes.POINTER(_Opts), P]
+        L.nsp_parareal_iterate_cgrid.argtypes = [P, P, _State, _State, _State, I, I, D, D, D, D,
+                                                 ctypes.POINTER(_Opts), ctypes.POINTER(_Opts), P, P]
         L.nsp_set_launch.argtypes = [P, I]
         L.nsp_autotune.argtypes = [P, I, I, P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
         L.nsp_last_launch_ms.argtypes = [P, ctypes.POINTER(D)]
@@ -95,7 +100,8 @@ def lib():
         for name in ("nsp_create", "nsp_destroy", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
                      "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
                      "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
-                     "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad"):
+                     "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
+                     "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid"):
             getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -262,6 +268,40 @@ class Handle:
         self._err(st, "nsp_parareal_iterate")
         return float(jump[0]), float(jump[1])
 
+    def restrict(self, hc, yf, yc):
+        """yc <- R(yf): fine-grid states (this handle) to states on the grid of
+        the coarse handle hc (half the cells per direction); batch = leading
+        dimension."""
+        B = self._batch_of(yf)
+        self._err(lib().nsp_restrict(self._h, hc._h, self._state(yf, B, "yf"), hc._state(yc, B, "yc"), B,
+                                     _stream_ptr()), "nsp_restrict")
+
+    def prolong(self, hc, yc, yf):
+        """yf <- P(yc): states on hc's grid to fine-grid states."""
+        B = self._batch_of(yc)
+        self._err(lib().nsp_prolong(self._h, hc._h, hc._state(yc, B, "yc"), self._state(yf, B, "yf"), B,
+                                    _stream_ptr()), "nsp_prolong")
+
+    def parareal_start_cgrid(self, hc, Y, Gk, nslices, t0, T, DT, coarse=None):
+        """parareal_start with the coarse propagator P(G_c(R(y))) on hc's grid."""
+        o = (coarse or PoissonOpts()).c()
+        st = lib().nsp_parareal_start_cgrid(self._h, hc._h, self._state(Y, nslices + 1, "Y"),
+                                            self._state(Gk, nslices, "Gk"), int(nslices), float(t0), float(T),
+                                            float(DT), ctypes.byref(o), _stream_ptr())
+        self._err(st, "nsp_parareal_start_cgrid")
+
+    def parareal_iterate_cgrid(self, hc, Y, Fk, Gk, nslices, k, t0, T, dt, DT, fine=None, coarse=None):
+        """parareal_iterate with the coarse propagator P(G_c(R(y))) on hc's grid;
+        returns (velocity jump, pressure jump)."""
+        of, oc = (fine or PoissonOpts()).c(), (coarse or PoissonOpts()).c()
+        jump = (ctypes.c_double * 2)()
+        st = lib().nsp_parareal_iterate_cgrid(self._h, hc._h, self._state(Y, nslices + 1, "Y"),
+                                              self._state(Fk, nslices, "Fk"), self._state(Gk, nslices, "Gk"),
+                                              int(nslices), int(k), float(t0), float(T), float(dt), float(DT),
+                                              ctypes.byref(of), ctypes.byref(oc), _stream_ptr(), jump)
+        self._err(st, "nsp_parareal_iterate_cgrid")
+        return float(jump[0]), float(jump[1])
+
     def set_launch(self, workgroups):
         self._err(lib().nsp_set_launch(self._h, int(workgroups)), "nsp_set_launch")
 
@@ -383,4 +423,5 @@ def group_parareal_iterate(handles, Ys, Fks, Gks, nslices, k, t0, T, dt, DT, fin
 EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
             "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
             "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
-            "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad")
+            "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
+            "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid")
