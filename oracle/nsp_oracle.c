@@ -51,6 +51,7 @@ typedef struct {
     const uint8_t *solid; /* nz*ny*nx, nonzero = solid; NULL = all fluid */
     const double *lid;    /* nz*(nx+1): wall value of u on the top face (y = Ly) */
     int periodic_z;       /* 1: periodic in z (the paper's runs), 0: walls at z = 0, Lz */
+    int slip_obstacles;   /* 1: free-slip on obstacle surfaces, 0: no-slip (the paper's) */
 } og_grid;
 
 typedef struct {
@@ -135,6 +136,17 @@ static double wall_value(const og_grid *g, int c, const int f[3], int d, int s) 
     return 0.0;
 }
 
+/* The closed position f of a component across whose axis d the stencil
+ * looks lies in the grid along d when a solid cell closes it (an obstacle
+ * wall), outside when the domain boundary does.  With free-slip obstacles
+ * the image across an obstacle wall is the mirror value itself (zero
+ * tangential stress) instead of 2*wall - mirror. */
+static int slip_wall(const og_grid *g, const int f[3], int d) {
+    if (!g->slip_obstacles) return 0;
+    if (d == 2 && g->periodic_z) return 1;
+    return f[d] >= 0 && f[d] < ndir(g, d);
+}
+
 /* Value used by the stencil of the open face f of component c at offset m
  * (|m| = 1 or 2) along direction d: the real value where the position is an
  * open face, the image value otherwise. */
@@ -155,14 +167,18 @@ static double stencil_val(const og_grid *g, int c, const double *phi, const int 
         return phi[fidx(g, c, f2)];
     }
     /* across the component's axis: a closed neighbour means a wall half a
-     * cell away; images are 2*wall - mirror, mirror resolved nearest-first */
+     * cell away; images are 2*wall - mirror (no-slip) or the mirror value
+     * (free-slip obstacle), mirror resolved nearest-first */
     if (!face_open(g, c, f1)) {
-        double wv = wall_value(g, c, f, d, s);
-        if (!two) return 2.0 * wv - phi0;
-        return 2.0 * wv - stencil_val(g, c, phi, f, d, -s);
+        double mirror = two ? stencil_val(g, c, phi, f, d, -s) : phi0;
+        if (slip_wall(g, f1, d)) return mirror;
+        return 2.0 * wall_value(g, c, f, d, s) - mirror;
     }
     if (!two) return phi[fidx(g, c, f1)];
-    if (!face_open(g, c, f2)) return 2.0 * wall_value(g, c, f1, d, s) - phi[fidx(g, c, f1)];
+    if (!face_open(g, c, f2)) {
+        if (slip_wall(g, f2, d)) return phi[fidx(g, c, f1)];
+        return 2.0 * wall_value(g, c, f1, d, s) - phi[fidx(g, c, f1)];
+    }
     return phi[fidx(g, c, f2)];
 }
 

@@ -40,7 +40,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
                 ("re", ctypes.c_double), ("solid", ctypes.c_void_p), ("lid", ctypes.c_void_p),
-                ("periodic_z", ctypes.c_int)]
+                ("periodic_z", ctypes.c_int), ("slip_obstacles", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -98,6 +98,7 @@ class Grid:
     solid: np.ndarray | None = None
     lid: np.ndarray | None = None
     periodic_z: bool = False
+    slip_obstacles: bool = False
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -117,7 +118,7 @@ class Grid:
         hx, hy, hz = self.h
         g = _Grid(self.nx, self.ny, self.nz, hx, hy, hz, float(self.re),
                   self.solid.ctypes.data if self.solid is not None else None, self.lid.ctypes.data,
-                  1 if self.periodic_z else 0)
+                  1 if self.periodic_z else 0, 1 if self.slip_obstacles else 0)
         return g
 
     def shapes(self):
@@ -401,6 +402,8 @@ def stencil_value(g: Grid, c, phi, f, d, m, as_form=False):
 def _no_periodic(g: Grid):
     if g.periodic_z:
         raise NotImplementedError("the adjoint is implemented for walls in z only")
+    if g.slip_obstacles:
+        raise NotImplementedError("the adjoint is implemented for no-slip obstacles only")
 
 
 def momentum_adjoint(g: Grid, u, v, w, dt, mu):
