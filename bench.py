@@ -11,7 +11,7 @@ Other modes:
   --mode poisson   batched Poisson microbenchmark (32 x 128^3 right-hand
                    sides, a working set far above the 256 MB Infinity Cache)
   --mode parareal  Parareal on the 96^3 cavity (32 slices of 0.02, fine dt
-                   5e-4, coarse dt --coarse-dt, mixed precision, jump < 1e-6)
+                   5e-4, coarse dt --coarse-dt, mixed-precision F, FP64 G, jump < 1e-6)
                    against the serial FP64 fine solve on the GPU; with
                    --coarse-grid the coarse propagator runs on 48^3
   --mode obstacles uneven batch: 16 slices on each of 64^3, 96^3, 128^3 with
@@ -90,6 +90,21 @@ def _sync():
     torch.cuda.synchronize()
 
 
+def _fine_solid(args):
+    """--obstacles: the 128^3 cavity of the obstacle batch (seed 3, cuboids
+    of 4..12 cells, >= 5 % solid)."""
+    if not args.obstacles:
+        return None
+    from paper_1705_06149_amd import inputs
+    return inputs.obstacle_mask(128, seed=3)
+
+
+def _fine_workload(args):
+    if not args.obstacles:
+        return "cavity128_re1000"
+    return "cavity128_obstacles_%s_re1000" % ("slip" if args.slip else "noslip")
+
+
 def bench_fine(args):
     import torch
     from paper_1705_06149_amd import nsp
@@ -98,7 +113,7 @@ def bench_fine(args):
     prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
     solver = nsp.BICGSTAB if args.solver == "bicgstab" else nsp.PCG
     opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=args.eta, max_outer=8, solver=solver)
-    h = nsp.Handle(n, n, n, re=re_, max_batch=1)
+    h = nsp.Handle(n, n, n, re=re_, max_batch=1, solid=_fine_solid(args), slip_obstacles=args.slip)
     y = h.zeros_state(1)
     t = 0.0
     for _ in range(args.warmup):
@@ -135,7 +150,8 @@ def bench_fine(args):
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     achieved = per_launch_bytes / avg_launch_s / 1e9
     sfx = "_bicgstab" if args.solver == "bicgstab" else ""
-    traffic = _traffic_from_profile("k_persistent_cavity128_%s%s_pmc.txt" % (args.precision, sfx))
+    traffic = (_traffic_from_profile("k_persistent_cavity128_%s%s_pmc.txt" % (args.precision, sfx))
+               if not args.obstacles else None)
     out = {
         "metric": "fine-step cell-updates/s",
         "value": value,
@@ -149,7 +165,7 @@ def bench_fine(args):
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "cavity128_re1000", "grid": [n, n, n], "re": re_, "dt": dt,
+        "config": {"workload": _fine_workload(args), "grid": [n, n, n], "re": re_, "dt": dt,
                    "start": "rest, after %d warm-up steps" % args.warmup,
                    "poisson": ("Jacobi-BiCGStab" if args.solver == "bicgstab" else "Jacobi-PCG") + " rtol 1e-10",
                    "precision": args.precision},
@@ -173,7 +189,7 @@ def cpu_baseline_fine(args, host_state, t):
 
     O.build()
     n = 128
-    g = O.Grid(n, n, n, re=1000.0)
+    g = O.Grid(n, n, n, re=1000.0, solid=_fine_solid(args), slip_obstacles=args.slip)
     prec = 1 if args.precision == "mixed" else 0
     nsteps = 2
     t0 = time.perf_counter()
@@ -245,6 +261,10 @@ def bench_parareal(args):
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=args.eta)
+    # the serial coarse sweep is a batch of one, latency-bound: FP32 saves no
+    # time there and each defect-correction restart adds iterations, so G
+    # solves in FP64 (measured at 96^3: 2.0 s per sweep vs 2.8 s mixed)
+    coarse = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     h = nsp.Handle(n, n, n, re=re_, max_batch=N)
     hc = nsp.Handle(n // 2, n // 2, n // 2, re=re_, max_batch=1) if cgrid else None
     # serial FP64 fine solve, batch 1, over [0, T]
@@ -267,18 +287,18 @@ def bench_parareal(args):
     _sync()
     t0 = time.perf_counter()
     if cgrid:
-        h.parareal_start_cgrid(hc, Y, Gk, N, 0.0, T, DT, mixed)
+        h.parareal_start_cgrid(hc, Y, Gk, N, 0.0, T, DT, coarse)
     else:
-        h.parareal_start(Y, Gk, N, 0.0, T, DT, mixed)
+        h.parareal_start(Y, Gk, N, 0.0, T, DT, coarse)
     jumps = []
     k = 0
     iter_s = []
     while True:
         ti = time.perf_counter()
         if cgrid:
-            jv, jp = h.parareal_iterate_cgrid(hc, Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
+            jv, jp = h.parareal_iterate_cgrid(hc, Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, coarse)
         else:
-            jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, mixed)
+            jv, jp = h.parareal_iterate(Y, Fk, Gk, N, k, 0.0, T, dt, DT, mixed, coarse)
         iter_s.append(time.perf_counter() - ti)
         jumps.append(jv)
         _log("parareal iteration %d: %.1f s, jump %.3e" % (k, iter_s[-1], jv))
@@ -296,7 +316,8 @@ def bench_parareal(args):
         "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
-                   "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n]},
+                   "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n],
+                   "fine_poisson": "mixed, eta %g" % args.eta, "coarse_poisson": "fp64"},
         "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
         "serial_equiv_cell_updates_per_s": cells * nf / par,
         "end_state_rel_l2_vs_serial_fp64": err,
@@ -322,6 +343,10 @@ def bench_obstacles(args):
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=args.eta)
+    # the serial coarse sweep is a batch of one, latency-bound: FP32 saves no
+    # time there and each defect-correction restart adds iterations, so G
+    # solves in FP64 (measured at 96^3: 2.0 s per sweep vs 2.8 s mixed)
+    coarse = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     hs = [nsp.Handle(n, n, n, re=re_, solid=inputs.obstacle_mask(n, seed), max_batch=N) for n, seed in grids]
     # serial FP64 fine solve of each grid, batch 1
     refs, serial = [], 0.0
@@ -340,11 +365,11 @@ def bench_obstacles(args):
     Gks = [tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in h.shapes()) for h in hs]
     _sync()
     t0 = time.perf_counter()
-    nsp.group_parareal_start(hs, Ys, Gks, N, 0.0, T, DT, mixed)
+    nsp.group_parareal_start(hs, Ys, Gks, N, 0.0, T, DT, coarse)
     k, jumps, iter_s = 0, [], []
     while True:
         ti = time.perf_counter()
-        j = nsp.group_parareal_iterate(hs, Ys, Fks, Gks, N, k, 0.0, T, dt, DT, mixed, mixed)
+        j = nsp.group_parareal_iterate(hs, Ys, Fks, Gks, N, k, 0.0, T, dt, DT, mixed, coarse)
         iter_s.append(time.perf_counter() - ti)
         jumps.append([jv for jv, _ in j])
         _log("parareal iteration %d: %.1f s, jumps %s" % (k, iter_s[-1], jumps[-1]))
@@ -512,6 +537,9 @@ def main():
                     help="parareal mode: coarse propagator on a grid with half the cells per direction "
                          "(restriction, coarse steps, prolongation); coarse dt defaults to 1e-2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--obstacles", action="store_true",
+                    help="fine mode: the 128^3 cavity with the seeded cuboid obstacles of the obstacle batch")
+    ap.add_argument("--slip", action="store_true", help="with --obstacles: free-slip obstacle walls")
     ap.add_argument("--eta", type=float, default=1e-5, help="inner FP32 tolerance of the mixed Poisson solve")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="mixed fine mode: also run the timed steps in FP64 and report the velocity difference")

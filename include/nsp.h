@@ -68,7 +68,13 @@ typedef struct nsp_handle nsp_handle;
  * six faces; periodic_z = 1: periodic in z (the boundary condition of the
  * paper's runs, Sec. 3), walls in x and y.  With periodic z the w array keeps
  * its nz+1 planes and the plane at z = lz repeats the plane at z = 0: every
- * call writes both equal, reads use the plane at z = 0. */
+ * call writes both equal, reads use the plane at z = 0.  slip_obstacles = 1
+ * makes obstacle surfaces free-slip (an extension: the paper's obstacles are
+ * no-slip, Sec. 3): zero normal velocity and zero tangential stress, i.e. the
+ * stencil image of a tangential component across an obstacle face is its
+ * mirror value instead of minus it; the domain walls and the lid are not
+ * obstacles and stay no-slip.  The adjoint refuses such grids
+ * (NSP_ERR_UNSUPPORTED); any other value is NSP_ERR_ARG. */
 typedef struct {
     int nx, ny, nz;
     double lx, ly, lz;
@@ -76,6 +82,7 @@ typedef struct {
     int periodic_z;          /* 0: walls in z, 1: periodic in z */
     const uint8_t *solid_host;
     int max_batch;
+    int slip_obstacles;      /* 0: no-slip obstacle walls (the paper's), 1: free-slip */
 } nsp_grid;
 
 /* Poisson solve options.  The solve of A p = b, A = -D G the compatible

@@ -66,7 +66,8 @@ struct nsp_handle {
     double *adj_segu = nullptr;  // velocities of one segment: adj_seg states
     double *adj_y = nullptr;     // working state
     double *adj_lam = nullptr, *adj_mu = nullptr, *adj_p = nullptr, *adj_glid = nullptr, *adj_part = nullptr;
-    int pz = 0;  // periodic in z
+    int pz = 0;    // periodic in z
+    int slip = 0;  // free-slip obstacle walls
     int max_wg = 0;
     int fixed_wg = 0;
     int force_depth = 0;  // CG column-tile depth (units of kZSub) forced during autotuning
@@ -263,6 +264,7 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.cgpart0 = slice0 * h->cgparts;  // launch prefixes are recomputed by run()
     G.nfluid = h->nfluid;
     G.pz = h->pz;
+    G.slip = h->slip;
     const double hh[3] = {h->lx / h->nx, h->ly / h->ny, h->lz / h->nz};
     for (int d = 0; d < 3; ++d) {
         G.ih[d] = 1.0 / hh[d];
@@ -684,7 +686,7 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     if (!g || !out) return NSP_ERR_ARG;
     *out = nullptr;
     if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->lx > 0) || !(g->ly > 0) || !(g->lz > 0) || !(g->re > 0) ||
-        g->max_batch < 1 || g->max_batch > kMaxSlices)
+        g->max_batch < 1 || g->max_batch > kMaxSlices || (g->slip_obstacles != 0 && g->slip_obstacles != 1))
         return NSP_ERR_ARG;
     if ((long long)g->nx * g->ny * g->nz > (1LL << 30)) return NSP_ERR_ARG;
     nsp_handle *h = new (std::nothrow) nsp_handle();
@@ -695,6 +697,7 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     h->re = g->re;
     h->max_batch = g->max_batch;
     h->pz = g->periodic_z ? 1 : 0;
+    h->slip = g->slip_obstacles;
     h->ncells = (long long)g->nx * g->ny * g->nz;
     h->nu = (long long)(g->nx + 1) * g->ny * g->nz;
     h->nv = (long long)g->nx * (g->ny + 1) * g->nz;
@@ -963,6 +966,7 @@ nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, doubl
                                   const nsp_poisson_opts *o, nsp_state grad, double *g_lid, double *J, void *stream) {
     if (!h) return NSP_ERR_ARG;
     if (h->pz) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for walls in z only");
+    if (h->slip) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for no-slip obstacles only");
     if (!state_ok(y0) || nsteps < 0 || !(dt > 0) || !J) return fail(h, NSP_ERR_ARG, "bad adjoint arguments");
     if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
     const bool want_grad = grad.u && grad.v && grad.w;

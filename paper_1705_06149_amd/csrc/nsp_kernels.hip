@@ -170,8 +170,8 @@ __device__ __forceinline__ double smart_face(double U, double C, double D) {
 // (i,j,k) of component C.  FAST: every position is an open face.  Otherwise
 // the image rule: along C's own axis a closed face holds 0 and the next
 // position is the odd reflection -phi0; across it a closed neighbour is a
-// no-slip wall half a cell away, image 2*wall - mirror, with the mirror
-// itself resolved first (one-cell gaps).
+// wall half a cell away, image 2*wall - mirror (no-slip) or the mirror value
+// (free-slip obstacle), with the mirror itself resolved first (one-cell gaps).
 template <bool FAST, int C, int D>
 __device__ __forceinline__ void line_values(const GAS GroupDesc &G, const GAS double *__restrict__ phi, int i, int j,
                                             int k, long id, double phi0, double &vm2, double &vm1, double &vp1,
@@ -198,16 +198,21 @@ __device__ __forceinline__ void line_values(const GAS GroupDesc &G, const GAS do
         vm2 = !om1 ? -phi0 : (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk) ? at(-2) : 0.0);
         vp2 = !op1 ? -phi0 : (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk) ? at(2) : 0.0);
     } else {
+        // a closed position inside the grid along D is closed by a solid
+        // cell (an obstacle wall); with free-slip obstacles its image is the
+        // mirror value itself instead of 2*wall - mirror
+        const int pD = D == 0 ? i : (D == 1 ? j : k), nD = D == 0 ? G.nx : (D == 1 ? G.ny : G.nz);
+        auto slip = [&](int m) { return G.slip && ((D == 2 && G.pz) || (pD + m >= 0 && pD + m < nD)); };
         const double wm = wall_value<C, D>(G, i, j, k, -1);
         const double wp = wall_value<C, D>(G, i, j, k, +1);
-        vm1 = om1 ? at(-1) : 2.0 * wm - phi0;
-        vp1 = op1 ? at(1) : 2.0 * wp - phi0;
-        if (!op1) vp2 = 2.0 * wp - vm1;
+        vm1 = om1 ? at(-1) : (slip(-1) ? phi0 : 2.0 * wm - phi0);
+        vp1 = op1 ? at(1) : (slip(1) ? phi0 : 2.0 * wp - phi0);
+        if (!op1) vp2 = slip(1) ? vm1 : 2.0 * wp - vm1;
         else if (face_open<C>(G, i + 2 * di, j + 2 * dj, k + 2 * dk)) vp2 = at(2);
-        else vp2 = 2.0 * wall_value<C, D>(G, i + di, j + dj, k + dk, +1) - at(1);
-        if (!om1) vm2 = 2.0 * wm - vp1;
+        else vp2 = slip(2) ? at(1) : 2.0 * wall_value<C, D>(G, i + di, j + dj, k + dk, +1) - at(1);
+        if (!om1) vm2 = slip(-1) ? vp1 : 2.0 * wm - vp1;
         else if (face_open<C>(G, i - 2 * di, j - 2 * dj, k - 2 * dk)) vm2 = at(-2);
-        else vm2 = 2.0 * wall_value<C, D>(G, i - di, j - dj, k - dk, -1) - at(-1);
+        else vm2 = slip(-2) ? at(-1) : 2.0 * wall_value<C, D>(G, i - di, j - dj, k - dk, -1) - at(-1);
     }
 }
 

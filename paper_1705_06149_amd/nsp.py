@@ -38,7 +38,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("re", ctypes.c_double), ("periodic_z", ctypes.c_int),
-                ("solid_host", ctypes.c_void_p), ("max_batch", ctypes.c_int)]
+                ("solid_host", ctypes.c_void_p), ("max_batch", ctypes.c_int), ("slip_obstacles", ctypes.c_int)]
 
 
 class _Opts(ctypes.Structure):
@@ -150,7 +150,8 @@ def _check(t, shape, name):
 class Handle:
     """One grid (nsp_create / nsp_destroy)."""
 
-    def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, re=100.0, solid=None, max_batch=1, periodic_z=False):
+    def __init__(self, nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, re=100.0, solid=None, max_batch=1, periodic_z=False,
+                 slip_obstacles=False):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.periodic_z = bool(periodic_z)
         self.lx, self.ly, self.lz, self.re = float(lx), float(ly), float(lz), float(re)
@@ -161,8 +162,10 @@ class Handle:
             if s.shape != (self.nz, self.ny, self.nx):
                 raise ValueError("solid mask must have shape (nz, ny, nx)")
             self._solid = s
+        self.slip_obstacles = bool(slip_obstacles)
         g = _Grid(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.re, 1 if self.periodic_z else 0,
-                  self._solid.ctypes.data if self._solid is not None else None, self.max_batch)
+                  self._solid.ctypes.data if self._solid is not None else None, self.max_batch,
+                  1 if self.slip_obstacles else 0)
         h = ctypes.c_void_p()
         st = lib().nsp_create(ctypes.byref(g), ctypes.byref(h))
         if st != NSP_OK:

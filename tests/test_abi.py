@@ -48,5 +48,7 @@ def test_create_rejects_bad_grid_without_touching_gpu():
     assert L.nsp_create(ctypes.byref(flat), ctypes.byref(h)) == nsp.NSP_ERR_ARG
     big = nsp._Grid(4, 4, 4, 1.0, 1.0, 1.0, 100.0, 0, None, 65)
     assert L.nsp_create(ctypes.byref(big), ctypes.byref(h)) == nsp.NSP_ERR_ARG
+    slip = nsp._Grid(4, 4, 4, 1.0, 1.0, 1.0, 100.0, 0, None, 1, 2)
+    assert L.nsp_create(ctypes.byref(slip), ctypes.byref(h)) == nsp.NSP_ERR_ARG
     assert L.nsp_destroy(None) == nsp.NSP_ERR_ARG
     assert L.nsp_last_error(None) == b"null handle"

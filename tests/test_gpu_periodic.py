@@ -127,6 +127,37 @@ def test_paper_sim1_geometry_fine_steps(gpu, oracle):
     h.close()
 
 
+def test_paper_sim2_geometry_fine_steps(gpu, oracle):
+    """32^3 cells on [0,1]^3, periodic in z, 49 seeded cubes along the median
+    plane (the stand-in for the paper's fully 3D case, Sec. 3), Re 1000, lid
+    u = 1, dt 1e-3: 25 steps from rest and, in a batch of 2, 5 more steps
+    from a random state, against the oracle."""
+    n = 32
+    _say("sim2 geometry", n)
+    solid = inputs.median_plane_cubes(n, seed=49)
+    g = oracle.Grid(n, n, n, re=1000.0, solid=solid, periodic_z=True)
+    ref, iters, _, st = oracle.fine_steps(g, g.zeros_state(), 25, 1e-3, rtol=1e-10)
+    assert st == 0
+    h = gpu.Handle(n, n, n, re=1000.0, solid=solid, max_batch=2, periodic_z=True)
+    y = h.zeros_state(1)
+    info = h.fine_step(y, 0.0, 0.025, 1e-3, gpu.PoissonOpts(rtol=1e-10))
+    out = [N(a)[0] for a in y]
+    e = rel_l2(out[:3], ref[:3])
+    _say("  from rest: velocity rel L2", e, "CG iters gpu", info[0]["iters"], "oracle", int(iters.sum()))
+    assert e <= 1e-10
+    assert np.array_equal(out[2][-1], out[2][0])
+    st0 = periodic_state(n, n, n, 12, 0.3)
+    ref, _, _, s = oracle.fine_steps(g, st0, 5, 1e-3, rtol=1e-11)
+    assert s == 0
+    yb = tuple(T(np.stack([a, a])) for a in st0)
+    h.fine_step(yb, 0.0, 0.005, 1e-3, gpu.PoissonOpts(rtol=1e-11))
+    for b in range(2):
+        e = rel_l2([N(a)[b] for a in yb[:3]], ref[:3])
+        _say("  random state, slice", b, "velocity rel L2", e)
+        assert e <= 1e-10
+    h.close()
+
+
 @pytest.mark.parametrize("shape", [(20, 20, 16), (64, 64, 64)])
 def test_periodic_random_state_with_obstacles(gpu, oracle, shape):
     nx, ny, nz = shape
