@@ -112,6 +112,37 @@ def test_projection_identity(oracle):
     assert np.linalg.norm(div) == pytest.approx(dt * info["rel_res_true"] * np.linalg.norm(b), rel=1e-6)
 
 
+def test_projection_is_an_orthogonal_projector(oracle):
+    """The projection of Sec. 2, P F = F - G phi with A phi = -D F (dt = 1),
+    on open-face fields: P(P a) = P a, <P a, b> = <a, P b> (every face
+    carries the same weight hx hy hz, so the plain sum is the inner
+    product), P G q = 0 for any cell field q, and D P a = 0.  The adjoint's
+    mu = P lam' relies on the symmetry."""
+    rng = np.random.default_rng(12)
+    solid = inputs.obstacle_mask(10, seed=6, frac=0.06, smin=2, smax=4)[:8, :9, :10]
+    solid = np.ascontiguousarray(solid)
+    for sol in (None, solid):
+        g = oracle.Grid(10, 9, 8, lx=1.0, ly=0.9, lz=0.7, solid=sol)
+        masks = oracle._open_masks(g)
+        a = tuple(rng.standard_normal(m.shape) * m for m in masks)
+        b = tuple(rng.standard_normal(m.shape) * m for m in masks)
+        Pa, _ = oracle.project(g, a, rtol=1e-14)
+        Pb, _ = oracle.project(g, b, rtol=1e-14)
+        PPa, _ = oracle.project(g, Pa, rtol=1e-14)
+        na = np.sqrt(sum(np.sum(x * x) for x in a))
+        nb = np.sqrt(sum(np.sum(x * x) for x in b))
+        assert max(np.max(np.abs(x - y)) for x, y in zip(PPa, Pa)) <= 1e-11 * na
+        lhs = sum(np.sum(x * y) for x, y in zip(Pa, b))
+        rhs_ = sum(np.sum(x * y) for x, y in zip(a, Pb))
+        assert abs(lhs - rhs_) <= 1e-11 * na * nb
+        assert np.max(np.abs(oracle.divergence(g, *Pa))) <= 1e-9 * na / min(g.h)
+        q = rng.standard_normal((g.nz, g.ny, g.nx))
+        Gq = tuple(x * m for x, m in zip(oracle.gradient(g, q), masks))
+        PGq, _ = oracle.project(g, Gq, rtol=1e-14)
+        nq = np.sqrt(sum(np.sum(x * x) for x in Gq))
+        assert max(np.max(np.abs(x)) for x in PGq) <= 1e-10 * nq
+
+
 def test_z_mirror_symmetry(oracle):
     """Walls and lid symmetric under z -> Lz - z: u, v, p stay even, w odd."""
     n = 10
