@@ -11,6 +11,11 @@ times, on sampled outputs the oracle computes one by one.
 * Groups of small obstacle grids: grouped Parareal equals each grid's serial
   fine solution after N iterations on N slices (bitwise), iterates match the
   single-grid Parareal bitwise, and the slice ends match the oracle.
+* Parareal at 96^3 with 32 slices, in the benchmark's configuration
+  (autotuned launch, mixed-precision F, FP64 G, dt 5e-4, DT 5e-3): after the
+  first iteration slice 1 is bitwise the batch-1 fine propagation of y0,
+  sampled F outputs are bitwise the batch-1 propagation of their inputs, and
+  each updated slice end is F + (G_new - G_old) of the stored pieces.
 """
 import numpy as np
 import pytest
@@ -150,3 +155,46 @@ def test_group_parareal_obstacles_exact(gpu, oracle):
         assert e <= 1e-10
     for h in hs:
         h.close()
+
+
+def test_parareal96_full_size_first_iteration(gpu):
+    n, Ns, dt, DT, T_end = 96, 32, 5e-4, 5e-3, 0.64
+    sl = T_end / Ns
+    _say("parareal full size", n, Ns)
+    h = gpu.Handle(n, n, n, re=1000.0, max_batch=Ns)
+    wg, planes, items = h.autotune(Ns, gpu.MIXED)
+    _say("  autotuned", wg, planes, items)
+    fine = gpu.PoissonOpts(rtol=1e-10, prec=gpu.MIXED, inner_rtol=1e-5)
+    coarse = gpu.PoissonOpts(rtol=1e-10, prec=gpu.FP64)
+    y0 = inputs.rest_state(n, n, n)
+    Y = tuple(T(np.stack([a] * (Ns + 1))) for a in y0)
+    Fk = tuple(T(np.zeros((Ns,) + a.shape)) for a in y0)
+    Gk = tuple(T(np.zeros((Ns,) + a.shape)) for a in y0)
+    h.parareal_start(Y, Gk, Ns, 0.0, T_end, DT, coarse)
+    Y_old = [N(a) for a in Y]
+    G_old = [N(a) for a in Gk]
+    jv, jp = h.parareal_iterate(Y, Fk, Gk, Ns, 0, 0.0, T_end, dt, DT, fine, coarse)
+    _say("  jump", jv, jp)
+    assert np.isfinite(jv) and 0 < jv < 1
+    Yn = [N(a) for a in Y]
+    Fn = [N(a) for a in Fk]
+    Gn = [N(a) for a in Gk]
+    # slice 1: exact after one iteration, the batch-1 fine solve of y0
+    ys = tuple(T(a[None]) for a in y0)
+    h.fine_step(ys, 0.0, sl, dt, fine)
+    for c in range(4):
+        assert np.array_equal(Yn[c][1], N(ys[c])[0]), c
+    # sampled F outputs equal the batch-1 propagation of their inputs
+    for m in (7, 31):
+        ys = tuple(T(a[m][None]) for a in Y_old)
+        h.fine_step(ys, m * sl, (m + 1) * sl, dt, fine)
+        for c in range(4):
+            assert np.array_equal(Fn[c][m], N(ys[c])[0]), (m, c)
+    # the update of Eq. (6) from the stored pieces
+    for m in (1, 8, 32):
+        for c in range(4):
+            assert np.array_equal(Yn[c][m], Fn[c][m - 1] + (Gn[c][m - 1] - G_old[c][m - 1])), (m, c)
+    # the jump is the max over slices of |Y_new - Y_old| in u, v, w
+    j = max(float(np.max(np.abs(Yn[c][1:] - Y_old[c][1:]))) for c in range(3))
+    assert j == jv
+    h.close()
