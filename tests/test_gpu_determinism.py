@@ -88,3 +88,29 @@ def test_parareal_resume_after_save(gpu):
     for a, b in zip(Y, ref):
         assert np.array_equal(N(a), b)
     h.close()
+
+
+def test_maximum_batch_of_64_slices(gpu):
+    """A launch with the maximum of 64 slices (random states on a ragged
+    20 x 18 x 14 grid with obstacles): every sampled slice equals its
+    single-slice launch bitwise; 65 slices are refused."""
+    nx, ny, nz, B = 20, 18, 14, 64
+    _say("maximum batch", B)
+    from scipy import ndimage
+    solid = np.ascontiguousarray(inputs.obstacle_mask(20, 4, frac=0.05, smin=2, smax=4)[:nz, :ny, :nx])
+    lab, _ = ndimage.label(solid == 0)
+    top = np.unique(lab[:, ny - 1, :])
+    solid[~np.isin(lab, top[top > 0])] = 1
+    h = gpu.Handle(nx, ny, nz, re=300.0, solid=solid, max_batch=B)
+    sts = [inputs.random_state(nx, ny, nz, seed=100 + b, scale=0.2, pscale=0.0) for b in range(B)]
+    y = tuple(T(np.stack([s[c] for s in sts])) for c in range(4))
+    opts = gpu.PoissonOpts(rtol=1e-10)
+    h.fine_step(y, 0.0, 0.002, 1e-3, opts)
+    for b in (0, 37, 63):
+        y1 = tuple(T(a[None]) for a in sts[b])
+        h.fine_step(y1, 0.0, 0.002, 1e-3, opts)
+        for c in range(4):
+            assert np.array_equal(N(y[c])[b], N(y1[c])[0]), (b, c)
+    h.close()
+    with pytest.raises(gpu.NSPError):
+        gpu.Handle(nx, ny, nz, max_batch=B + 1)
