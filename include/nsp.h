@@ -113,7 +113,9 @@ typedef struct {
     double div_l2;      /* ||D u||_2 after the last step (= dt * ||b - A p||_2) */
 } nsp_solve_info;
 
-/* A batch of states (u, v, w, p); layout above. */
+/* A batch of states (u, v, w, p); layout above.  Every call taking a batch
+ * accepts batch 0 as a no-op (NSP_OK, nothing read or written; the pointers
+ * may then be NULL); a batch below 0 or above max_batch is NSP_ERR_ARG. */
 typedef struct {
     double *u, *v, *w, *p;
 } nsp_state;
@@ -154,8 +156,9 @@ nsp_status nsp_coarse_step(nsp_handle *h, nsp_state y, int batch, double t0, dou
                            const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
 
 /* Uneven batch: F over several grids in ONE launch.  hs[g] is the handle of
- * grid g, ys[g] its batch of batches[g] slices.  The launch uses hs[0]'s
- * synchronisation words; all handles must live on the same device. */
+ * grid g, ys[g] its batch of batches[g] slices (groups with batches[g] = 0
+ * take no part).  The launch uses hs[0]'s synchronisation words; all handles
+ * must live on the same device. */
 nsp_status nsp_group_fine_step(nsp_handle *const *hs, const nsp_state *ys, const int *batches, int ngroups,
                                double t0, double t1, double dt, const nsp_poisson_opts *opts, void *stream,
                                nsp_solve_info *info);

@@ -506,18 +506,23 @@ nsp_status propagate(nsp_handle *const *hs, const nsp_state *ys, const int *batc
     if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
     int nsteps = 0;
     if (!step_count(t0, t1, step, &nsteps)) return fail(h, NSP_ERR_ARG, "(t1 - t0)/dt is not a non-negative integer");
+    // groups with an empty batch take no part (their pointers may be null)
     GroupDesc G[kMaxGroups];
-    int slice0 = 0, tile0 = 0, cgtile0 = 0;
+    nsp_handle *used[kMaxGroups];
+    int ng = 0, slice0 = 0, tile0 = 0, cgtile0 = 0;
     for (int g = 0; g < ngroups; ++g) {
-        if (!hs[g] || !state_ok(ys[g]) || batches[g] < 0 || batches[g] > hs[g]->max_batch)
-            return fail(h, NSP_ERR_ARG, "null state pointer or batch outside [0, max_batch]");
-        fill_group(G[g], hs[g], ys[g], 0, batches[g], slice0, tile0, nullptr, cgtile0);
+        if (!hs[g] || batches[g] < 0 || batches[g] > hs[g]->max_batch)
+            return fail(h, NSP_ERR_ARG, "null handle or batch outside [0, max_batch]");
+        if (batches[g] == 0) continue;
+        if (!state_ok(ys[g])) return fail(h, NSP_ERR_ARG, "null state pointer");
+        fill_group(G[ng], hs[g], ys[g], 0, batches[g], slice0, tile0, nullptr, cgtile0);
+        used[ng++] = hs[g];
         slice0 += batches[g];
         tile0 += batches[g] * hs[g]->ntiles;
         cgtile0 += batches[g] * hs[g]->cgtiles;
     }
     if (nsteps == 0 || slice0 == 0) return NSP_OK;
-    return run(hs, ngroups, G, MODE_FINE, nsteps, step, o, static_cast<hipStream_t>(stream), info, 0);
+    return run(used, ng, G, MODE_FINE, nsteps, step, o, static_cast<hipStream_t>(stream), info, 0);
 }
 
 // A coarse handle for the coarser-grid coarse propagator: half the cells of
@@ -807,9 +812,10 @@ nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev) {
 nsp_status nsp_poisson_solve(nsp_handle *h, const double *b, double *p, int batch, const nsp_poisson_opts *o,
                              void *stream, nsp_solve_info *info) {
     if (!h) return NSP_ERR_ARG;
-    if (!b || !p || batch < 0 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "null pointer or bad batch");
+    if (batch < 0 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "batch outside [0, max_batch]");
     if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
-    if (batch == 0) return NSP_OK;
+    if (batch == 0) return NSP_OK;  // nothing to solve; b and p may be null
+    if (!b || !p) return fail(h, NSP_ERR_ARG, "null pointer");
     GroupDesc G;
     nsp_state y{nullptr, nullptr, nullptr, p};
     fill_group(G, h, y, 0, batch, 0, 0, b);

@@ -344,6 +344,19 @@ def test_error_paths(gpu):
     y3 = h.zeros_state(1)
     h.fine_step(y3, 0.5, 0.5, 1e-3)
     assert float(y3[0].abs().max()) == 0.0
+    # an empty batch is a no-op (null pointers from empty tensors)
+    assert h.fine_step(h.zeros_state(0), 0.0, 0.002, 1e-3) == []
+    e0 = torch.zeros((0, n, n, n), dtype=torch.float64, device="cuda")
+    assert h.poisson_solve(e0, e0.clone()) == []
+    # a grouped launch skips a group with an empty batch
+    h2 = gpu.Handle(n + 2, n, n, max_batch=1)
+    ya, yb = h.zeros_state(0), h2.zeros_state(1)
+    gpu.group_fine_step([h, h2], [ya, yb], 0.0, 0.002, 1e-3)
+    ref = h2.zeros_state(1)
+    h2.fine_step(ref, 0.0, 0.002, 1e-3)
+    for a, b in zip(yb, ref):
+        assert torch.equal(a, b)
+    h2.close()
     h.close()
     del torch
 
