@@ -491,6 +491,99 @@ def bench_paper_sim(args, sim):
     return out
 
 
+BYTES_PROJECT_FIXED = 163.0  # adjoint projection launch: a fine step's fixed bytes without the predictor
+
+
+def bench_adjoint(args):
+    """The adjoint workload: 96^3 cavity, Re 400, 100 fine steps of 1e-3,
+    J = kinetic energy at T, gradients with respect to the initial velocity
+    (a seeded divergence-free N(0, 1e-2) perturbation) and the 16 x 16 lid
+    sine coefficients, checkpoints every 10 steps, FP64.  A "step" is one
+    whole gradient evaluation (forward sweep, recomputation from the
+    checkpoints, reverse sweep); value = cells x fine steps / wall time per
+    gradient.  The roofline is that of k_persistent over every launch inside
+    the evaluations (forward segments and the reverse projections), from the
+    library's launch statistics (HIP events on the launch stream)."""
+    import torch
+    from paper_1705_06149_amd import inputs, nsp
+
+    n, re_, dt, nsteps, ck, M = 96, 400.0, 1e-3, 100, 10, 16
+    K = args.steps if args.steps_given else 2
+    W = args.warmup if args.warmup_given else 1
+    h = nsp.Handle(n, n, n, re=re_, max_batch=1)
+    u0 = inputs.div_free_perturbation(n, n, n, seed=5, sigma=1e-2)
+    y0 = tuple(torch.from_numpy(np.ascontiguousarray(a[None])).cuda() for a in u0) + (
+        torch.zeros((1, n, n, n), dtype=torch.float64, device="cuda"),)
+    g = torch.Generator(device="cuda").manual_seed(16)
+    coef = 1e-2 * torch.randn((M, M), dtype=torch.float64, device="cuda", generator=g)
+    h.set_lid(h.lid_from_modes(coef))
+    opts = nsp.PoissonOpts(rtol=1e-12)
+
+    def gradient():
+        J, gu, glid = h.fine_solve_adjoint(y0, nsteps, dt, ckpt_every=ck, opts=opts)
+        return J, gu, h.lid_modes_grad(glid, M)
+
+    for _ in range(W):
+        gradient()
+    _sync()
+    h.launch_stats(reset=True)
+    t0 = time.perf_counter()
+    for i in range(K):
+        J, gu, gc = gradient()
+        _log("adjoint gradient %d/%d  %.1f s" % (i + 1, K, time.perf_counter() - t0))
+    _sync()
+    wall = time.perf_counter() - t0
+    st = h.launch_stats()
+    cells = n ** 3
+    fine, proj = st["fine"], st["project"]
+    byts = (fine["cell_steps"] * BYTES_STEP_FIXED["fp64"] + fine["cg_cell_iters"] * BYTES_CG_ITER["fp64"] +
+            proj["cell_steps"] * BYTES_PROJECT_FIXED + proj["cg_cell_iters"] * BYTES_CG_ITER["fp64"])
+    kms = fine["ms"] + proj["ms"]
+    launches = fine["launches"] + proj["launches"]
+    achieved = byts / (kms * 1e-3) / 1e9
+    out = {
+        "metric": "adjoint cell-updates/s", "value": cells * nsteps * K / wall, "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * wall / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "adjoint96_re400", "grid": [n, n, n], "re": re_, "dt": dt, "fine_steps": nsteps,
+                   "checkpoint_every": ck, "lid_modes": [M, M], "poisson": "Jacobi-PCG rtol 1e-12",
+                   "step": "one gradient of J (forward, recomputation, reverse)"},
+        "J": J, "grad_u0_l2": float(torch.sqrt(sum((a ** 2).sum() for a in gu))),
+        "grad_lid_coef_l2": float(torch.linalg.norm(gc)),
+        "k_persistent_share_of_wall": kms * 1e-3 / wall,
+        "forward_cg_iters_per_step": fine["cg_cell_iters"] / max(fine["cell_steps"], 1.0),
+        "reverse_cg_iters_per_projection": proj["cg_cell_iters"] / max(proj["cell_steps"], 1.0),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_persistent (forward segments and reverse projections)",
+                     "avg_launch_ms": kms / max(launches, 1), "launches": launches,
+                     "algorithmic_bytes_per_launch": byts / max(launches, 1)},
+    }
+    h.close()
+    return out
+
+
+def cpu_baseline_adjoint(args):
+    """The oracle's adjoint gradient on the same 96^3 workload, over a bounded
+    sample of 2 fine steps, timed on the host cores."""
+    from oracle import oracle as O
+    from paper_1705_06149_amd import inputs
+
+    O.build()
+    n, M, nsteps = 96, 16, 2
+    rng = np.random.default_rng(16)
+    basis = inputs.lid_profile_basis(n, n, M)
+    lid = 1.0 + np.tensordot(1e-2 * rng.standard_normal((M, M)), basis, axes=([0, 1], [0, 1]))
+    g = O.Grid(n, n, n, re=400.0, lid=lid)
+    u0 = inputs.div_free_perturbation(n, n, n, seed=5, sigma=1e-2)
+    st0 = (u0[0], u0[1], u0[2], np.zeros((n, n, n)))
+    t0 = time.perf_counter()
+    O.adjoint_gradient(g, st0, nsteps, 1e-3, rtol=1e-12, ckpt_every=1)
+    wall = time.perf_counter() - t0
+    return {"value": n ** 3 * nsteps / wall, "unit": "cell-updates/s", "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "kind": "oracle",
+            "sample": "gradient of J over %d fine steps of the 96^3 adjoint workload (%.1f s)" % (nsteps, wall)}
+
+
 def bench_copy(args):
     import torch
     nbytes = 1 << 30
@@ -514,9 +607,9 @@ def bench_copy(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "sim2", "copy"],
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 30; adjoint mode: 2 gradients)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 5; adjoint mode: 1)")
+    ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "sim2", "adjoint", "copy"],
                     default="fine")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--solver", choices=["pcg", "bicgstab"], default="pcg",
@@ -544,6 +637,11 @@ def main():
     ap.add_argument("--compare-fp64", action="store_true",
                     help="mixed fine mode: also run the timed steps in FP64 and report the velocity difference")
     args = ap.parse_args()
+    args.steps_given, args.warmup_given = args.steps is not None, args.warmup is not None
+    if args.steps is None:
+        args.steps = 30
+    if args.warmup is None:
+        args.warmup = 5
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (time slices would shard "
               "across GPUs with point-to-point sends of slice-end states; not implemented)", file=sys.stderr)
@@ -559,6 +657,10 @@ def main():
         out = bench_copy(args)
     elif args.mode == "obstacles":
         out = bench_obstacles(args)
+    elif args.mode == "adjoint":
+        out = bench_adjoint(args)
+        if int(os.environ.get("RANK", "0")) == 0 and not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_adjoint(args)
     elif args.mode in ("sim1", "sim2"):
         out = bench_paper_sim(args, int(args.mode[3]))
     else:

@@ -253,6 +253,23 @@ nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, doubl
 nsp_status nsp_lid_from_modes(nsp_handle *h, const double *coef, int nmodes, double *lid_dev, void *stream);
 nsp_status nsp_lid_modes_grad(nsp_handle *h, const double *g_lid, int nmodes, double *g_coef, void *stream);
 
+/* Launch statistics of the persistent kernel, per launch kind: [0] fine /
+ * coarse steps (also the Parareal sweeps), [1] Poisson solves, [2] the
+ * projection of the adjoint's reverse step.  Counted since the last reset
+ * over every launch this handle made (grouped launches count on the first
+ * handle); nsp_autotune's trial launches are not counted.  For measurement:
+ * launch durations come from HIP events recorded on the launch stream around
+ * each launch.  out: HOST array of 3 entries, or NULL; reset != 0 clears the
+ * counters after reading them. */
+typedef struct {
+    long long launches;
+    double ms;             /* summed launch durations */
+    double cell_steps;     /* sum over launches and slices of cells x steps (x 1 for solves) */
+    double cg_cell_iters;  /* sum over slices of cells x Krylov iterations (inner ones for mixed) */
+    double cell_sweeps;    /* sum over slices of cells x defect-correction sweeps / restarts */
+} nsp_launch_stats;
+nsp_status nsp_launch_stats_get(nsp_handle *h, nsp_launch_stats out[3], int reset);
+
 /* Launch shape used for a batch: workgroups per launch.  0 = automatic.
  * nsp_autotune times candidate shapes on the handle's own workspace (a
  * 40-iteration Poisson solve on a synthetic right-hand side): workgroup

@@ -75,6 +75,7 @@ struct nsp_handle {
     std::vector<TuneEntry> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0.0;
+    nsp_launch_stats stats[3] = {};  // per launch kind (fine, poisson, project), since the last reset
     std::string err;
 };
 
@@ -461,7 +462,18 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     float ms = 0;
     if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
     if (aborted) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
+    nsp_launch_stats &S = h->stats[mode];
+    S.launches += 1;
+    S.ms += ms;
     int worst = 0;
+    for (int g = 0, s = 0; g < ngroups; ++g)
+        for (int k = 0; k < lg[g].nslices; ++k, ++s) {
+            const SliceCtl &c = h->L.ctl_host[s];
+            const double cells = (double)lg[g].ncells;
+            S.cell_steps += cells * (mode == MODE_FINE ? nsteps : 1);
+            S.cg_cell_iters += cells * c.tot_it;
+            S.cell_sweeps += cells * c.tot_outer;
+        }
     for (int s = 0; s < nslices; ++s) {
         const SliceCtl &c = h->L.ctl_host[s];
         worst = std::max(worst, c.status);
@@ -1065,6 +1077,15 @@ nsp_status nsp_lid_modes_grad(nsp_handle *h, const double *g_lid, int nmodes, do
     return NSP_OK;
 }
 
+nsp_status nsp_launch_stats_get(nsp_handle *h, nsp_launch_stats out[3], int reset) {
+    if (!h) return NSP_ERR_ARG;
+    for (int m = 0; m < 3; ++m) {
+        if (out) out[m] = h->stats[m];
+        if (reset) h->stats[m] = nsp_launch_stats{};
+    }
+    return NSP_OK;
+}
+
 nsp_status nsp_set_launch(nsp_handle *h, int workgroups) {
     if (!h || workgroups < 0) return fail(h, NSP_ERR_ARG, "bad workgroup count");
     h->fixed_wg = workgroups;
@@ -1106,6 +1127,8 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     std::vector<int> depths = {1}, itemss = {1};
     if (h->crb > 0) depths = {1, 2, 4};
     if (h->crb > 0 && prec == NSP_MIXED && h->cnb >= 2) itemss = {1, 2};
+    nsp_launch_stats keep_stats[3];
+    for (int m = 0; m < 3; ++m) keep_stats[m] = h->stats[m];  // the trial launches are not counted
     int best = cands[0], best_depth = depths[0], best_items = itemss[0];
     double best_ms = 1e30;
     for (int ni : itemss)
@@ -1121,6 +1144,7 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
                 if (st == NSP_OK) st = run(hs, 1, &G, MODE_POISSON, 0, 1.0, &o, s, nullptr, c);
                 if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
                     h->force_depth = h->force_items = 0;
+                    for (int m = 0; m < 3; ++m) h->stats[m] = keep_stats[m];
                     (void)hipFree(b);
                     (void)hipFree(p);
                     return st;
@@ -1130,6 +1154,7 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
             if (tot < best_ms) { best_ms = tot; best = c; best_depth = dep; best_items = ni; }
         }
     h->force_depth = h->force_items = 0;
+    for (int m = 0; m < 3; ++m) h->stats[m] = keep_stats[m];
     (void)hipFree(b);
     (void)hipFree(p);
     const int pr = prec == NSP_MIXED ? 1 : 0;

@@ -51,6 +51,11 @@ class _Info(ctypes.Structure):
                 ("status", ctypes.c_int), ("rel_res_true", ctypes.c_double), ("div_l2", ctypes.c_double)]
 
 
+class _LaunchStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_longlong), ("ms", ctypes.c_double), ("cell_steps", ctypes.c_double),
+                ("cg_cell_iters", ctypes.c_double), ("cell_sweeps", ctypes.c_double)]
+
+
 class _State(ctypes.Structure):
     _fields_ = [("u", ctypes.c_void_p), ("v", ctypes.c_void_p), ("w", ctypes.c_void_p), ("p", ctypes.c_void_p)]
 
@@ -90,6 +95,7 @@ def lib():
         L.nsp_parareal_start_cgrid.argtypes = [P, P, _State, _State, I, D, D, D, ctypes.POINTER(_Opts), P]
         L.nsp_parareal_iterate_cgrid.argtypes = [P, P, _State, _State, _State, I, I, D, D, D, D,
                                                  ctypes.POINTER(_Opts), ctypes.POINTER(_Opts), P, P]
+        L.nsp_launch_stats_get.argtypes = [P, P, I]
         L.nsp_set_launch.argtypes = [P, I]
         L.nsp_autotune.argtypes = [P, I, I, P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
         L.nsp_last_launch_ms.argtypes = [P, ctypes.POINTER(D)]
@@ -101,7 +107,8 @@ def lib():
                      "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
                      "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
                      "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
-                     "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid"):
+                     "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
+                     "nsp_launch_stats_get"):
             getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -305,6 +312,14 @@ class Handle:
         self._err(st, "nsp_parareal_iterate_cgrid")
         return float(jump[0]), float(jump[1])
 
+    def launch_stats(self, reset=False):
+        """Persistent-kernel launch statistics since the last reset, as dicts
+        for the launch kinds 'fine', 'poisson' and 'project'."""
+        arr = (_LaunchStats * 3)()
+        self._err(lib().nsp_launch_stats_get(self._h, arr, 1 if reset else 0), "nsp_launch_stats_get")
+        return {k: {f: getattr(x, f) for f, _ in _LaunchStats._fields_}
+                for k, x in zip(("fine", "poisson", "project"), arr)}
+
     def set_launch(self, workgroups):
         self._err(lib().nsp_set_launch(self._h, int(workgroups)), "nsp_set_launch")
 
@@ -427,4 +442,5 @@ EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_p
             "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
             "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
             "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
-            "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid")
+            "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
+            "nsp_launch_stats_get")

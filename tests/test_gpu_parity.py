@@ -373,3 +373,29 @@ def test_zero_lid_stays_zero(gpu):
         assert float(t.abs().max()) == 0.0
     assert info[0]["iters"] == 0
     h.close()
+
+
+def test_launch_stats_count_what_ran(gpu):
+    """nsp_launch_stats_get: launches, cell-steps and CG cell-iterations per
+    launch kind, matching the per-slice solve info; autotune trials are not
+    counted; reset clears."""
+    n, B = 16, 3
+    _say("launch stats")
+    h = gpu.Handle(n, n, n, re=200.0, max_batch=B)
+    h.launch_stats(reset=True)
+    y = tuple(T(np.stack([a] * B)) for a in inputs.random_state(n, n, n, seed=1, scale=0.1, pscale=0.0))
+    info = h.fine_step(y, 0.0, 0.004, 1e-3)
+    b = T(np.random.default_rng(2).standard_normal((B, n, n, n)))
+    pinfo = h.poisson_solve(b, T(np.zeros((B, n, n, n))))
+    h.autotune(B, gpu.FP64)
+    st = h.launch_stats(reset=True)
+    cells = n ** 3
+    assert st["fine"]["launches"] == 1 and st["poisson"]["launches"] == 1 and st["project"]["launches"] == 0
+    assert st["fine"]["cell_steps"] == B * cells * 4
+    assert st["fine"]["cg_cell_iters"] == cells * sum(x["iters"] for x in info)
+    assert st["poisson"]["cell_steps"] == B * cells
+    assert st["poisson"]["cg_cell_iters"] == cells * sum(x["iters"] for x in pinfo)
+    assert st["fine"]["ms"] > 0 and st["poisson"]["ms"] > 0
+    st = h.launch_stats()
+    assert all(v["launches"] == 0 for v in st.values())
+    h.close()
