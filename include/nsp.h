@@ -273,13 +273,15 @@ nsp_status nsp_launch_stats_get(nsp_handle *h, nsp_launch_stats out[3], int rese
 /* Launch shape used for a batch: workgroups per launch.  0 = automatic.
  * nsp_autotune times candidate shapes on the handle's own workspace (a
  * 40-iteration Poisson solve on a synthetic right-hand side): workgroup
- * counts and, where the CG phases use column tiles, tile depths of 8, 16 or
- * 32 planes and (NSP_MIXED) one or two rows per thread; it keeps the fastest
- * for (batch, prec) and reports it in *chosen_workgroups, *chosen_planes and
- * *chosen_items (0 for flat tiles; each may be NULL).  Results do not depend
- * on the choice: partial sums are kept per tile, or per block of rows and 8
- * planes.  It allocates and frees two batch-sized device arrays and
- * synchronises the stream. */
+ * counts and, where the CG phases use column tiles, tile depths from the
+ * grid's partial block (8 planes, or 4 where one slice has fewer 8-plane
+ * tiles than the GPU has workgroups) up to 32 planes and (NSP_MIXED) one or
+ * two rows per thread; it keeps the fastest for (batch, prec) and reports it
+ * in *chosen_workgroups, *chosen_planes and *chosen_items (0 for flat tiles;
+ * each may be NULL).  Results do not depend on the choice: partial sums are
+ * kept per tile, or per block of rows and 4 or 8 planes fixed for the grid.
+ * It allocates and frees two batch-sized device arrays and synchronises the
+ * stream. */
 nsp_status nsp_set_launch(nsp_handle *h, int workgroups);
 nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stream, int *chosen_workgroups,
                         int *chosen_planes, int *chosen_items);

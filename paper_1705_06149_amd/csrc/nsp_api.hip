@@ -34,7 +34,7 @@ struct LaunchRes {
 
 struct TuneEntry {
     int batch, prec, workgroups;
-    int depth;  // CG column-tile depth in units of kZSub planes (0: by rule)
+    int depth;  // CG column-tile depth in units of the grid's zsub planes (0: by rule)
     int items;  // CG column items per thread (0: by rule)
 };
 
@@ -44,8 +44,9 @@ struct nsp_handle {
     double lx = 1, ly = 1, lz = 1, re = 1;
     int max_batch = 0;
     int tile = 0, ntiles = 0;
-    int cby = 0, cbz = 0, cny = 0, cnz = 0, cgtiles = 0;  // CG column tiles (cby = 0: flat tiles), depth kZSub
+    int cby = 0, cbz = 0, cny = 0, cnz = 0, cgtiles = 0;  // CG column tiles (cby = 0: flat tiles), depth zsub
     int crb = 0, cnb = 0;  // rows per partial block (one workgroup-wide plane patch), blocks along y
+    int zsh = 3;           // log2 of the planes per partial block (zsub = 8, or 4: see nsp_create)
     int cgparts = 0;                                      // CG partials per slice
     long long ncells = 0, nu = 0, nv = 0, nw = 0;
     double nfluid = 0;
@@ -70,7 +71,7 @@ struct nsp_handle {
     int slip = 0;  // free-slip obstacle walls
     int max_wg = 0;
     int fixed_wg = 0;
-    int force_depth = 0;  // CG column-tile depth (units of kZSub) forced during autotuning
+    int force_depth = 0;  // CG column-tile depth (units of zsub) forced during autotuning
     int force_items = 0;  // CG column items per thread forced during autotuning
     std::vector<TuneEntry> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -257,6 +258,7 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.cny = h->cny;
     G.cnz = h->cnz;
     G.crb = h->crb;
+    G.zsh = h->zsh;
     G.cni = 1;
     G.cnb = h->cnb;
     G.cgtiles = h->cgtiles;
@@ -309,20 +311,21 @@ int auto_workgroups(nsp_handle *h, int batch, int prec, int total_tiles) {
 // number of plane steps one workgroup makes (tiles per workgroup x planes per
 // tile), a two-item plane step costing 1.75 one-item ones (measured on 96^3
 // and 128^3 batches); FP64 launches always use one item (two FP64 items would
-// not fit the LDS plane buffers).  Depth: `depth` x kZSub planes if depth > 0,
-// else the deepest of 1, 2, 4 x kZSub planes that leaves at least two CG
-// tiles per workgroup (deeper tiles refill the z pipeline less often).
-// Partial sums stay per crb rows and kZSub planes, so neither choice changes
-// a result.
+// not fit the LDS plane buffers).  Depth, in units of each grid's zsub
+// planes (at most 32 planes): `depth` if > 0, else the deepest of 8, 4, 2
+// units that leaves at least two CG tiles per workgroup, else 1 (deeper tiles
+// refill the z pipeline less often).  Partial sums stay per crb rows and zsub
+// planes, so neither choice changes a result.
 void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int fp32, int *ntiles, int *cgtiles,
                    int *cgparts) {
+    auto planes = [](const GroupDesc &X, int m) { return std::min(m << X.zsh, 32); };
     auto count = [&](int ni, int m) {
         long long t = 0;
         for (int g = 0; g < ngroups; ++g) {
             const GroupDesc &X = G[g];
             if (X.crb > 0) {
-                const int rows = ni * X.crb;
-                t += (long long)X.nslices * ((X.ny + rows - 1) / rows) * ((X.nz + m * kZSub - 1) / (m * kZSub));
+                const int rows = ni * X.crb, pl = planes(X, m);
+                t += (long long)X.nslices * ((X.ny + rows - 1) / rows) * ((X.nz + pl - 1) / pl);
             } else {
                 t += (long long)X.nslices * X.cgtiles;
             }
@@ -332,8 +335,10 @@ void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int 
     // estimated plane steps of the busiest workgroup, in quarters of a one-item step
     auto path = [&](int ni) {
         long long best = -1;
-        for (int m : {1, 2, 4}) {
-            const long long c = (count(ni, m) + wg - 1) / wg * m * (ni == 2 ? 7 : 4);
+        for (int m : {1, 2, 4, 8}) {
+            int pl = 0;
+            for (int g = 0; g < ngroups; ++g) pl = std::max(pl, G[g].crb > 0 ? planes(G[g], m) : 0);
+            const long long c = (count(ni, m) + wg - 1) / wg * std::max(pl, 1) * (ni == 2 ? 7 : 4);
             if (best < 0 || c < best) best = c;
         }
         return best;
@@ -343,7 +348,7 @@ void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int 
         if (G[g].crb > 0 && G[g].cnb < 2) two = false;
     if (!two) items = 1;
     if (items <= 0) items = path(2) < path(1) ? 2 : 1;
-    for (int m : {4, 2}) {
+    for (int m : {8, 4, 2}) {
         if (depth > 0) break;
         if (count(items, m) >= 2LL * wg) { depth = m; break; }
     }
@@ -356,7 +361,7 @@ void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int 
             X.cni = items;
             X.cby = std::min(items * X.crb, X.ny);
             X.cny = (X.ny + X.cby - 1) / X.cby;
-            X.cbz = depth * kZSub;
+            X.cbz = planes(X, depth);
             X.cnz = (X.nz + X.cbz - 1) / X.cbz;
             X.cgtiles = X.cny * X.cnz;
         }
@@ -723,15 +728,12 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     h->ntiles = (int)((h->ncells + h->tile - 1) / h->tile);
     // CG column tiles for grids of at least 64^3 cells where two x rows fit in
     // a workgroup (nx a multiple of 32, so halo rows are whole waves): cby rows
-    // (one workgroup-wide plane patch) by 8 planes
+    // (one workgroup-wide plane patch) by zsub planes (set below, once the
+    // workgroup count is known)
     if (2 * g->nx <= kBlock && g->nx % 32 == 0 && h->ncells >= (1LL << 18)) {
         h->cby = h->crb = std::min(kBlock / g->nx, g->ny);
         h->cnb = (g->ny + h->crb - 1) / h->crb;
-        h->cbz = kZSub;
         h->cny = (g->ny + h->cby - 1) / h->cby;
-        h->cnz = (g->nz + h->cbz - 1) / h->cbz;
-        h->cgtiles = h->cny * h->cnz;
-        h->cgparts = h->cgtiles;
     } else {
         h->cby = h->cbz = h->cny = h->cnz = h->crb = h->cnb = 0;
         h->cgtiles = h->ntiles;
@@ -788,6 +790,16 @@ nsp_status nsp_create(const nsp_grid *g, nsp_handle **out) {
     if ((e = hipEventCreate(&h->ev1)) != hipSuccess) return fail_create(e);
     if ((e = max_coresident_workgroups(h->device, &h->max_wg)) != hipSuccess) return fail_create(e);
     if (h->max_wg < 1) return fail_create(hipErrorInvalidValue);
+    if (h->crb > 0) {
+        // partial sums per 8 planes, or per 4 where one slice has fewer
+        // 8-plane tiles than workgroups (shallower tiles then keep more of the
+        // chip busy); fixed for the grid, so every launch sums alike
+        h->zsh = (long long)h->cnb * ((g->nz + 7) / 8) < h->max_wg ? 2 : 3;
+        h->cbz = 1 << h->zsh;
+        h->cnz = (g->nz + h->cbz - 1) / h->cbz;
+        h->cgtiles = h->cny * h->cnz;
+        h->cgparts = h->cgtiles;
+    }
     if (ensure_launch_res(h, g->max_batch, g->max_batch * std::max(h->ntiles, h->cgtiles)) != NSP_OK)
         return fail_create(hipErrorOutOfMemory);
     *out = h;
@@ -1123,9 +1135,9 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     nsp_state y{nullptr, nullptr, nullptr, p};
     fill_group(G, h, y, 0, batch, 0, 0, b);
     nsp_handle *hs[1] = {h};
-    // column-tile depths (units of kZSub planes); flat tiles have none
+    // column-tile depths (units of zsub planes, at most 32 planes); flat tiles have none
     std::vector<int> depths = {1}, itemss = {1};
-    if (h->crb > 0) depths = {1, 2, 4};
+    if (h->crb > 0) depths = h->zsh == 2 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1, 2, 4};
     if (h->crb > 0 && prec == NSP_MIXED && h->cnb >= 2) itemss = {1, 2};
     nsp_launch_stats keep_stats[3];
     for (int m = 0; m < 3; ++m) keep_stats[m] = h->stats[m];  // the trial launches are not counted
@@ -1169,7 +1181,7 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
         }
     if (!found) h->tuned.push_back(TuneEntry{batch, pr, best, keep_depth, keep_items});
     if (chosen) *chosen = best;
-    if (chosen_planes) *chosen_planes = keep_depth * kZSub;
+    if (chosen_planes) *chosen_planes = keep_depth << h->zsh;
     if (chosen_items) *chosen_items = keep_items;
     return NSP_OK;
 }

@@ -12,7 +12,6 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxGroups = 4;    // grids per launch (uneven batch)
 constexpr int kMaxSlices = 64;   // slices per launch
 constexpr int kNQ = 4;           // partial sums per tile
-constexpr int kZSub = 8;         // planes per CG partial sum of a column tile
 
 // Per-cell flag byte: which of the six faces of the pressure cell are open,
 // whether the cell is fluid, and whether the momentum stencil of the cell's
@@ -22,6 +21,8 @@ enum : uint8_t {
     FL_XM = 1, FL_XP = 2, FL_YM = 4, FL_YP = 8, FL_ZM = 16, FL_ZP = 32,
     FL_OPEN = 63, FL_FLUID = 64, FL_SLOW = 128
 };
+
+constexpr int kMaxBlk = 8;       // zsub-plane partial blocks per column tile (32 planes / 4)
 
 // One grid and the batch of slices it carries in a launch.
 struct GroupDesc {
@@ -34,15 +35,17 @@ struct GroupDesc {
     int slice0;            // first slice index of this grid in the launch
     int tile0;             // first tile index of this grid in the launch
     // CG tiles (phases of the CG loop).  Column tiles: full x rows, cby rows
-    // in y, cbz planes in z (a multiple of kZSub, chosen per launch); each
+    // in y, cbz planes in z (a multiple of zsub, chosen per launch); each
     // thread walks z carrying cni items (rows yy and yy + crb; cni = 2 only
     // in FP32 launches), so cby = cni * crb.  Partial sums are kept per crb
-    // rows and kZSub planes whatever cbz and cni are, so results depend on
+    // rows and zsub planes whatever cbz and cni are, so results depend on
     // neither.  cby == 0: the CG loop uses the flat tiles above (one partial
     // per tile).
     int cby, cbz;          // rows / planes per column tile
     int cny, cnz;          // column tiles along y / z
     int crb, cni, cnb;     // rows per partial block, items per thread, row blocks along y
+    int zsh;               // log2 of zsub, the planes per partial block (8, or 4 on grids whose
+                           // slice alone has fewer 8-plane column tiles than workgroups); fixed per grid
     int cgtiles;           // CG tiles per slice
     int cgtile0;           // first CG tile index of this grid in the launch
     int cgparts;           // CG partial sums per slice

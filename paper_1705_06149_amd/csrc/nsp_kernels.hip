@@ -280,6 +280,7 @@ struct Runner {
     LAS double *s_sum;         // [nslices][kNQ] reduced sums of the last barrier
     const LAS unsigned *s_nx;  // [kMaxXcd] workgroups of this launch on each XCD
     unsigned xcc;              // this workgroup's XCD
+    LAS double *s_blk;         // [kMaxBlk][kWaves][kNQ] wave partials of a column tile's plane blocks
     unsigned epoch = 0;        // barriers passed (uniform over the grid)
 
     __device__ __forceinline__ void locate(int t, int &gi, int &sl) const {
@@ -397,6 +398,27 @@ struct Runner {
     // all workgroups obtain bit-identical sums.  Lanes of wave 0 then run the
     // CG scalar logic, one slice each, on this workgroup's copy of the
     // control blocks.  Returns the OR of the slices' flags.
+    // one wave's lane sums of NQ quantities over partials t = lane, lane + 64,
+    // ... of one slice, in that order; the loads of four consecutive terms
+    // are issued together before they are added
+    template <int NQ>
+    __device__ __forceinline__ void lane_sums(const GAS double *pp, int nt, int lane, double (&v)[kNQ]) {
+        constexpr int kRB = 4;
+        for (int t0 = lane; t0 < nt; t0 += 64 * kRB) {
+            double a[kRB][NQ];
+#pragma unroll
+            for (int j = 0; j < kRB; ++j)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    a[j][q] = t0 + 64 * j < nt ? pp[(long)q * P.pstride + t0 + 64 * j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kRB; ++j)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (t0 + 64 * j < nt) v[q] += a[j][q];
+        }
+    }
+
     __device__ __forceinline__ int reduce_all(int rid, int buf) {
         __shared__ int s_any;
         const int nq = nq_of(rid);
@@ -406,10 +428,13 @@ struct Runner {
             const GAS double *pp = gp(P.part) + (long)(buf * kNQ) * P.pstride + s_pb[2 * s + cg];
             const int nt = s_pn[2 * s + cg];
             double v[kNQ] = {0.0, 0.0, 0.0, 0.0};
-            for (int t = lane; t < nt; t += 64)
-#pragma unroll
-                for (int q = 0; q < kNQ; ++q)
-                    if (q < nq) v[q] += pp[(long)q * P.pstride + t];
+            switch (nq) {
+            case 1: lane_sums<1>(pp, nt, lane, v); break;
+            case 2: lane_sums<2>(pp, nt, lane, v); break;
+            case 3: lane_sums<3>(pp, nt, lane, v); break;
+            case 4: lane_sums<4>(pp, nt, lane, v); break;
+            default: break;
+            }
 #pragma unroll
             for (int q = 0; q < kNQ; ++q)
                 if (q < nq) {
@@ -920,7 +945,7 @@ struct Runner {
     // faces are closed) and are filled from a valid cell.
     // A thread carries NI items of a column tile: rows yy and yy + crb (NI =
     // 2, FP32 launches with enough tiles) of the x position tid % nx.  Partial
-    // sums are kept per block of crb rows and kZSub planes whatever NI and
+    // sums are kept per block of crb rows and zsub planes whatever NI and
     // the tile depth are, so neither changes a result.
     template <int NI>
     struct ColPos {
@@ -959,31 +984,51 @@ struct Runner {
         T a[NI], b[NI], c[NI], ah, bh;
     };
 
-    // Partials of NI items (NQ quantities each), stored at t[u] where ok[u]
-    // (the last tile of a grid may carry a row block beyond the grid).
+    // Column-tile partials.  At the end of each zsub-plane block every wave
+    // sums its lanes' NI x NQ values (wave_sum) into the block's LDS slots;
+    // at the end of the tile one workgroup barrier, then each of the tile's
+    // blocks x NI x NQ sums is combined over the waves in the fixed tree of
+    // combine_waves and stored as partial pbase + (first block + b) * cnb +
+    // row block (rows beyond the grid in the last tile are not stored).  The
+    // next write to the slots follows at least one plane step, whose barrier
+    // every thread of the combine has passed.
     template <int NQ, int NI>
-    __device__ __forceinline__ void store_item_partials(double (&acc)[NI][NQ], const int (&t)[NI],
-                                                        const bool (&ok)[NI]) {
+    __device__ __forceinline__ void stage_block(double (&acc)[NI][NQ], int blk) {
         static_assert(NQ * NI <= kNQ, "wave partial slots");
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < NI; ++u)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const double v = wave_sum(acc[u][q]);
-                if (lane == 0) s_red[wv * kNQ + u * NQ + q] = v;
+                if (lane == 0) s_blk[(blk * kWaves + wv) * kNQ + u * NQ + q] = v;
+                acc[u][q] = 0.0;
             }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    template <int NQ, int NI>
+    __device__ __forceinline__ void flush_blocks(const GAS GroupDesc &G, int nblk, int z0, int pbase, int yb) {
         __syncthreads();
-        if (threadIdx.x < NQ * NI) {
-            const int u = threadIdx.x / NQ, q = threadIdx.x % NQ;
-            const double v = combine_waves(u * NQ + q);
-            if (ok[u]) gp(P.part)[(long)(((epoch + 1) & 1) * kNQ + q) * P.pstride + t[u]] = v;
+        for (int x = threadIdx.x; x < nblk * NI * NQ; x += kBlock) {
+            const int b = x / (NI * NQ), u = (x / NQ) % NI, q = x % NQ;
+            const LAS double *L = s_blk + b * kWaves * kNQ + u * NQ + q;
+            // the pairwise tree of combine_waves over the 16 waves, written out
+            static_assert(kWaves == 16, "wave tree");
+            auto l = [&](int i) { return L[i * kNQ]; };
+            const double v = (((l(0) + l(1)) + (l(2) + l(3))) + ((l(4) + l(5)) + (l(6) + l(7)))) +
+                             (((l(8) + l(9)) + (l(10) + l(11))) + ((l(12) + l(13)) + (l(14) + l(15))));
+            const int rb = yb * G.cni + u;
+            if (rb < G.cnb) {
+                const int t = pbase + ((z0 >> G.zsh) + b) * G.cnb + rb;
+                gp(P.part)[(long)(((epoch + 1) & 1) * kNQ + q) * P.pstride + t] = v;
+            }
         }
-        __syncthreads();
     }
 
     // phase A over one column tile; stores <d_new, A d_new> per crb rows and
-    // kZSub planes as partials pbase + (k / kZSub) * cnb + row block.  Loads
+    // zsub planes as partials pbase + (k / zsub) * cnb + row block.  Loads
     // run two planes ahead: two PlaneLoad sets alternate (the loop is
     // unrolled by two so that no register copy waits for a load in flight).
     template <class T, bool FIRST, bool WT, int NI>
@@ -1074,28 +1119,17 @@ struct Runner {
             }
             hc = hn;
             buf ^= 1;
-            if ((k + 1) % kZSub == 0 || k + 1 == z1) {
-                int t[NI];
-                bool ok[NI];
-#pragma unroll
-                for (int u = 0; u < NI; ++u) {
-                    const int rb = yb * G.cni + u;
-                    t[u] = pbase + (k / kZSub) * G.cnb + rb;
-                    ok[u] = rb < G.cnb;
-                }
-                store_item_partials<1, NI>(acc, t, ok);
-#pragma unroll
-                for (int u = 0; u < NI; ++u) acc[u][0] = 0.0;
-            }
+            if (((k + 1) & ((1 << G.zsh) - 1)) == 0 || k + 1 == z1) stage_block<1, NI>(acc, (k - z0) >> G.zsh);
         };
         for (int k = z0; k < z1; k += 2) {
             step(k, LA);
             if (k + 1 < z1) step(k + 1, LB);
         }
+        flush_blocks<1, NI>(G, (z1 - z0 + (1 << G.zsh) - 1) >> G.zsh, z0, pbase, yb);
     }
 
     // phase B over one column tile: q = A d from d's planes; x += alpha d,
-    // r -= alpha q; partials <r,z>, <r,r> per crb rows and kZSub planes as in
+    // r -= alpha q; partials <r,z>, <r,r> per crb rows and zsub planes as in
     // col_A.  Loads and halos as in col_A.
     template <class T, bool WT, int NI>
     __device__ void col_B(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ d,
@@ -1189,24 +1223,13 @@ struct Runner {
             }
             hc = hn;
             buf ^= 1;
-            if ((k + 1) % kZSub == 0 || k + 1 == z1) {
-                int t[NI];
-                bool ok[NI];
-#pragma unroll
-                for (int u = 0; u < NI; ++u) {
-                    const int rb = yb * G.cni + u;
-                    t[u] = pbase + (k / kZSub) * G.cnb + rb;
-                    ok[u] = rb < G.cnb;
-                }
-                store_item_partials<2, NI>(acc, t, ok);
-#pragma unroll
-                for (int u = 0; u < NI; ++u) acc[u][0] = acc[u][1] = 0.0;
-            }
+            if (((k + 1) & ((1 << G.zsh) - 1)) == 0 || k + 1 == z1) stage_block<2, NI>(acc, (k - z0) >> G.zsh);
         };
         for (int k = z0; k < z1; k += 2) {
             step(k, LA);
             if (k + 1 < z1) step(k + 1, LB);
         }
+        flush_blocks<2, NI>(G, (z1 - z0 + (1 << G.zsh) - 1) >> G.zsh, z0, pbase, yb);
     }
 
     template <class T, int NI>
@@ -1666,6 +1689,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
 k_persistent(const KParams *__restrict__ Pp) {
     const GAS KParams &P = *gp(Pp);
     __shared__ double s_red[kWaves * kNQ];
+    __shared__ double s_blk[kMaxBlk * kWaves * kNQ];
     __shared__ double s_plane[2 * 2 * kBlock];  // (cby + 2) * nx <= kBlock + 2 nx <= 2 kBlock
     __shared__ double s_idg[kMaxGroups * 64];
     __shared__ float s_idg32[kMaxGroups * 64];
@@ -1723,7 +1747,7 @@ k_persistent(const KParams *__restrict__ Pp) {
     Runner R{P, sched[0][0], sched[0][1], sched[0][2], sched[1][0], sched[1][1], sched[1][2], (LAS double *)s_red,
              (const LAS double *)s_idg, (const LAS float *)s_idg32, (LAS double *)s_plane, (LAS SliceCtl *)s_ctl,
              (const LAS double *)s_nf, (const LAS int *)s_pb, (const LAS int *)s_pn, (LAS double *)s_sum,
-             (const LAS unsigned *)s_nx, hw_xcc_id()};
+             (const LAS unsigned *)s_nx, hw_xcc_id(), (LAS double *)s_blk};
     if (R.startup((LAS unsigned *)s_nx)) R.run();
     // every workgroup holds the same control blocks: workgroup 0 returns them
     __syncthreads();

@@ -171,9 +171,11 @@ def test_batched_equals_unbatched(gpu):
 def test_column_depth_does_not_change_results(gpu, prec):
     """128 x ny x nz Poisson solves: a batch of 8 runs with deeper column
     tiles (and, in FP32 inner solves, two rows per thread), a batch of 1 with
-    8-plane tiles and one row per thread; partial sums are kept per row block
-    and 8 planes, so the slices must agree bitwise (with obstacles, a ragged
-    last row block, an odd number of row blocks, nz not a multiple of 16)."""
+    the shallowest tiles and one row per thread; partial sums are kept per row
+    block and 8 planes (128^3) or 4 planes (the two smaller grids, whose slice
+    has fewer 8-plane tiles than workgroups), so the slices must agree bitwise
+    (with obstacles, a ragged last row block, an odd number of row blocks, nz
+    not a multiple of 16)."""
     for shape, obst in [((128, 128, 128), False), ((128, 92, 112), True), ((128, 88, 120), False)]:
         nx, ny, nz = shape
         _say("column depth independence", shape, "obstacles", obst, "prec", prec)
@@ -215,7 +217,7 @@ def test_autotune_keeps_results(gpu, prec):
     h.poisson_solve(b, p0, opts)
     wg, planes, items = h.autotune(B, prec)
     _say("  chose", wg, "workgroups,", planes, "planes,", items, "rows per thread")
-    assert wg >= 1 and planes in (8, 16, 32) and items in ((1,) if prec == 0 else (1, 2))
+    assert wg >= 1 and planes in (4, 8, 16, 32) and items in ((1,) if prec == 0 else (1, 2))
     p1 = T(np.zeros((B, n, n, n)))
     h.poisson_solve(b, p1, opts)
     assert np.array_equal(N(p0), N(p1))
