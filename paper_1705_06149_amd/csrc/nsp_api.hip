@@ -34,7 +34,7 @@ struct LaunchRes {
 
 struct TuneEntry {
     int batch, prec, workgroups;
-    int depth;  // CG column-tile depth in units of the grid's zsub planes (0: by rule)
+    int depth;  // CG column-tile depth in planes (0: by rule)
     int items;  // CG column items per thread (0: by rule)
 };
 
@@ -71,7 +71,7 @@ struct nsp_handle {
     int slip = 0;  // free-slip obstacle walls
     int max_wg = 0;
     int fixed_wg = 0;
-    int force_depth = 0;  // CG column-tile depth (units of zsub) forced during autotuning
+    int force_depth = 0;  // CG column-tile depth in planes, forced during autotuning
     int force_items = 0;  // CG column items per thread forced during autotuning
     std::vector<TuneEntry> tuned;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -311,20 +311,21 @@ int auto_workgroups(nsp_handle *h, int batch, int prec, int total_tiles) {
 // number of plane steps one workgroup makes (tiles per workgroup x planes per
 // tile), a two-item plane step costing 1.75 one-item ones (measured on 96^3
 // and 128^3 batches); FP64 launches always use one item (two FP64 items would
-// not fit the LDS plane buffers).  Depth, in units of each grid's zsub
-// planes (at most 32 planes): `depth` if > 0, else the deepest of 8, 4, 2
-// units that leaves at least two CG tiles per workgroup, else 1 (deeper tiles
-// refill the z pipeline less often).  Partial sums stay per crb rows and zsub
-// planes, so neither choice changes a result.
+// not fit the LDS plane buffers).  Depth D in planes, the same for every
+// grid of the launch (a grid never goes below its zsub): `depth` if > 0,
+// else the deepest of 32 and 16 planes that leaves at least two CG tiles per
+// workgroup (deeper tiles refill the z pipeline less often), else 8 planes,
+// or 4 when even 8-plane tiles leave workgroups idle.  Partial sums stay per
+// crb rows and zsub planes, so neither choice changes a result.
 void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int fp32, int *ntiles, int *cgtiles,
                    int *cgparts) {
-    auto planes = [](const GroupDesc &X, int m) { return std::min(m << X.zsh, 32); };
-    auto count = [&](int ni, int m) {
+    auto planes = [](const GroupDesc &X, int D) { return std::max(D, 1 << X.zsh); };
+    auto count = [&](int ni, int D) {
         long long t = 0;
         for (int g = 0; g < ngroups; ++g) {
             const GroupDesc &X = G[g];
             if (X.crb > 0) {
-                const int rows = ni * X.crb, pl = planes(X, m);
+                const int rows = ni * X.crb, pl = planes(X, D);
                 t += (long long)X.nslices * ((X.ny + rows - 1) / rows) * ((X.nz + pl - 1) / pl);
             } else {
                 t += (long long)X.nslices * X.cgtiles;
@@ -335,24 +336,25 @@ void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int 
     // estimated plane steps of the busiest workgroup, in quarters of a one-item step
     auto path = [&](int ni) {
         long long best = -1;
-        for (int m : {1, 2, 4, 8}) {
-            int pl = 0;
-            for (int g = 0; g < ngroups; ++g) pl = std::max(pl, G[g].crb > 0 ? planes(G[g], m) : 0);
-            const long long c = (count(ni, m) + wg - 1) / wg * std::max(pl, 1) * (ni == 2 ? 7 : 4);
+        for (int D : {8, 16, 32}) {
+            const long long c = (count(ni, D) + wg - 1) / wg * D * (ni == 2 ? 7 : 4);
             if (best < 0 || c < best) best = c;
         }
         return best;
     };
-    bool two = fp32 != 0;
-    for (int g = 0; g < ngroups; ++g)
+    bool two = fp32 != 0, four = false;
+    for (int g = 0; g < ngroups; ++g) {
         if (G[g].crb > 0 && G[g].cnb < 2) two = false;
+        if (G[g].crb > 0 && G[g].zsh == 2) four = true;
+    }
     if (!two) items = 1;
     if (items <= 0) items = path(2) < path(1) ? 2 : 1;
-    for (int m : {8, 4, 2}) {
-        if (depth > 0) break;
-        if (count(items, m) >= 2LL * wg) { depth = m; break; }
+    if (depth <= 0) {
+        depth = 8;
+        for (int D : {32, 16})
+            if (count(items, D) >= 2LL * wg) { depth = D; break; }
+        if (depth == 8 && four && count(items, 8) < wg) depth = 4;
     }
-    if (depth <= 0) depth = 1;
     *ntiles = *cgtiles = *cgparts = 0;
     int slice0 = 0;
     for (int g = 0; g < ngroups; ++g) {
@@ -1135,9 +1137,9 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     nsp_state y{nullptr, nullptr, nullptr, p};
     fill_group(G, h, y, 0, batch, 0, 0, b);
     nsp_handle *hs[1] = {h};
-    // column-tile depths (units of zsub planes, at most 32 planes); flat tiles have none
+    // column-tile depths in planes (from the grid's zsub up to 32); flat tiles have none
     std::vector<int> depths = {1}, itemss = {1};
-    if (h->crb > 0) depths = h->zsh == 2 ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{1, 2, 4};
+    if (h->crb > 0) depths = h->zsh == 2 ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{8, 16, 32};
     if (h->crb > 0 && prec == NSP_MIXED && h->cnb >= 2) itemss = {1, 2};
     nsp_launch_stats keep_stats[3];
     for (int m = 0; m < 3; ++m) keep_stats[m] = h->stats[m];  // the trial launches are not counted
@@ -1181,7 +1183,7 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
         }
     if (!found) h->tuned.push_back(TuneEntry{batch, pr, best, keep_depth, keep_items});
     if (chosen) *chosen = best;
-    if (chosen_planes) *chosen_planes = keep_depth << h->zsh;
+    if (chosen_planes) *chosen_planes = keep_depth;
     if (chosen_items) *chosen_items = keep_items;
     return NSP_OK;
 }
