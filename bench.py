@@ -285,6 +285,9 @@ def bench_parareal(args):
     Fk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
     Gk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
     _sync()
+    h.launch_stats(reset=True)
+    if hc is not None:
+        hc.launch_stats(reset=True)
     t0 = time.perf_counter()
     if cgrid:
         h.parareal_start_cgrid(hc, Y, Gk, N, 0.0, T, DT, coarse)
@@ -311,10 +314,21 @@ def bench_parareal(args):
                            sum((ref[c] ** 2).sum() for c in range(3))))
     cells = n ** 3
     nf = int(round(T / dt))
+    kst = [h.launch_stats()["fine"]] + ([hc.launch_stats()["fine"]] if hc is not None else [])
+    kbytes = sum(_stats_bytes(x, BYTES_STEP_FIXED["fp64"]) for x in kst)
+    kms = sum(x["ms"] for x in kst)
+    klaunch = sum(x["launches"] for x in kst)
+    kach = kbytes / (kms * 1e-3) / 1e9
     out = {
         "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
         "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "roofline": {"bound": "hbm", "achieved": kach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": kach / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_persistent (batched fine sweeps and coarse steps of the Parareal run)",
+                     "avg_launch_ms": kms / max(klaunch, 1), "launches": klaunch,
+                     "algorithmic_bytes_per_launch": kbytes / max(klaunch, 1),
+                     "k_persistent_share_of_wall": kms * 1e-3 / par},
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
                    "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n],
                    "fine_poisson": "mixed, eta %g" % args.eta, "coarse_poisson": "fp64"},
@@ -364,6 +378,8 @@ def bench_obstacles(args):
     Fks = [tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in h.shapes()) for h in hs]
     Gks = [tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in h.shapes()) for h in hs]
     _sync()
+    for h in hs:
+        h.launch_stats(reset=True)
     t0 = time.perf_counter()
     nsp.group_parareal_start(hs, Ys, Gks, N, 0.0, T, DT, coarse)
     k, jumps, iter_s = 0, [], []
@@ -384,10 +400,22 @@ def bench_obstacles(args):
                                      sum((ref[c] ** 2).sum() for c in range(3)))))
     cells = sum(n ** 3 for n, _ in grids)
     nf = int(round(T / dt))
+    # grouped launches count on the first handle
+    kst = [h.launch_stats()["fine"] for h in hs]
+    kbytes = sum(_stats_bytes(x, BYTES_STEP_FIXED["fp64"]) for x in kst)
+    kms = sum(x["ms"] for x in kst)
+    klaunch = sum(x["launches"] for x in kst)
+    kach = kbytes / (kms * 1e-3) / 1e9
     out = {
         "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
         "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "roofline": {"bound": "hbm", "achieved": kach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": kach / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_persistent (grouped fine sweeps and coarse steps of the Parareal run)",
+                     "avg_launch_ms": kms / max(klaunch, 1), "launches": klaunch,
+                     "algorithmic_bytes_per_launch": kbytes / max(klaunch, 1),
+                     "k_persistent_share_of_wall": kms * 1e-3 / par},
         "config": {"workload": "obstacles_64_96_128", "grids": [n for n, _ in grids], "mask_seeds": [s for _, s in grids],
                    "slices_per_grid": N, "T": T, "dt": dt, "DT": DT, "jump_tol": tol,
                    "batch_cells": N * cells},
@@ -494,6 +522,16 @@ def bench_paper_sim(args, sim):
 BYTES_PROJECT_FIXED = 163.0  # adjoint projection launch: a fine step's fixed bytes without the predictor
 
 
+def _stats_bytes(st, fixed):
+    """Algorithmic bytes of the k_persistent launches summed in one entry of
+    the library's launch statistics: `fixed` bytes per cell and step, plus
+    per cell 66 B per FP64 PCG iteration, 34 B per FP32 inner iteration,
+    139 B per BiCGStab iteration and 65 B per mixed-precision sweep."""
+    return (st["cell_steps"] * fixed + st["cg64_cell_iters"] * BYTES_CG_ITER["fp64"] +
+            st["cg32_cell_iters"] * BYTES_CG_ITER["mixed"] + st["bicg_cell_iters"] * BYTES_BICG_ITER +
+            st["mixed_cell_sweeps"] * BYTES_MIXED_SWEEP)
+
+
 def bench_adjoint(args):
     """The adjoint workload: 96^3 cavity, Re 400, 100 fine steps of 1e-3,
     J = kinetic energy at T, gradients with respect to the initial velocity
@@ -536,8 +574,7 @@ def bench_adjoint(args):
     st = h.launch_stats()
     cells = n ** 3
     fine, proj = st["fine"], st["project"]
-    byts = (fine["cell_steps"] * BYTES_STEP_FIXED["fp64"] + fine["cg_cell_iters"] * BYTES_CG_ITER["fp64"] +
-            proj["cell_steps"] * BYTES_PROJECT_FIXED + proj["cg_cell_iters"] * BYTES_CG_ITER["fp64"])
+    byts = _stats_bytes(fine, BYTES_STEP_FIXED["fp64"]) + _stats_bytes(proj, BYTES_PROJECT_FIXED)
     kms = fine["ms"] + proj["ms"]
     launches = fine["launches"] + proj["launches"]
     achieved = byts / (kms * 1e-3) / 1e9

@@ -265,8 +265,12 @@ typedef struct {
     long long launches;
     double ms;             /* summed launch durations */
     double cell_steps;     /* sum over launches and slices of cells x steps (x 1 for solves) */
-    double cg_cell_iters;  /* sum over slices of cells x Krylov iterations (inner ones for mixed) */
+    double cg_cell_iters;  /* sum over slices of cells x Krylov iterations, all kinds */
     double cell_sweeps;    /* sum over slices of cells x defect-correction sweeps / restarts */
+    double cg64_cell_iters;   /* the part in FP64 PCG iterations */
+    double cg32_cell_iters;   /* the part in FP32 inner PCG iterations (mixed precision) */
+    double bicg_cell_iters;   /* the part in BiCGStab iterations */
+    double mixed_cell_sweeps; /* the part of cell_sweeps in mixed-precision launches */
 } nsp_launch_stats;
 nsp_status nsp_launch_stats_get(nsp_handle *h, nsp_launch_stats out[3], int reset);
 

@@ -476,10 +476,18 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     for (int g = 0, s = 0; g < ngroups; ++g)
         for (int k = 0; k < lg[g].nslices; ++k, ++s) {
             const SliceCtl &c = h->L.ctl_host[s];
-            const double cells = (double)lg[g].ncells;
+            const double cells = (double)lg[g].ncells, it = cells * c.tot_it;
             S.cell_steps += cells * (mode == MODE_FINE ? nsteps : 1);
-            S.cg_cell_iters += cells * c.tot_it;
+            S.cg_cell_iters += it;
             S.cell_sweeps += cells * c.tot_outer;
+            if (P.prec == 1) {
+                S.cg32_cell_iters += it;
+                S.mixed_cell_sweeps += cells * c.tot_outer;
+            } else if (P.solver == NSP_BICGSTAB) {
+                S.bicg_cell_iters += it;
+            } else {
+                S.cg64_cell_iters += it;
+            }
         }
     for (int s = 0; s < nslices; ++s) {
         const SliceCtl &c = h->L.ctl_host[s];

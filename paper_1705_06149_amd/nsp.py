@@ -53,7 +53,9 @@ class _Info(ctypes.Structure):
 
 class _LaunchStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong), ("ms", ctypes.c_double), ("cell_steps", ctypes.c_double),
-                ("cg_cell_iters", ctypes.c_double), ("cell_sweeps", ctypes.c_double)]
+                ("cg_cell_iters", ctypes.c_double), ("cell_sweeps", ctypes.c_double),
+                ("cg64_cell_iters", ctypes.c_double), ("cg32_cell_iters", ctypes.c_double),
+                ("bicg_cell_iters", ctypes.c_double), ("mixed_cell_sweeps", ctypes.c_double)]
 
 
 class _State(ctypes.Structure):

@@ -398,6 +398,16 @@ def test_launch_stats_count_what_ran(gpu):
     assert st["poisson"]["cell_steps"] == B * cells
     assert st["poisson"]["cg_cell_iters"] == cells * sum(x["iters"] for x in pinfo)
     assert st["fine"]["ms"] > 0 and st["poisson"]["ms"] > 0
+    assert st["fine"]["cg64_cell_iters"] == st["fine"]["cg_cell_iters"]
+    assert st["fine"]["cg32_cell_iters"] == 0 and st["fine"]["bicg_cell_iters"] == 0
     st = h.launch_stats()
     assert all(v["launches"] == 0 for v in st.values())
+    # mixed precision and BiCGStab land in their own fields
+    mi = h.poisson_solve(b, T(np.zeros((B, n, n, n))), gpu.PoissonOpts(prec=gpu.MIXED))
+    bi = h.poisson_solve(b, T(np.zeros((B, n, n, n))), gpu.PoissonOpts(solver=gpu.BICGSTAB))
+    st = h.launch_stats(reset=True)["poisson"]
+    assert st["cg32_cell_iters"] == cells * sum(x["iters"] for x in mi)
+    assert st["mixed_cell_sweeps"] == cells * sum(x["outer"] for x in mi)
+    assert st["bicg_cell_iters"] == cells * sum(x["iters"] for x in bi)
+    assert st["cg64_cell_iters"] == 0
     h.close()
