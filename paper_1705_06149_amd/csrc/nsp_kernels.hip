@@ -422,7 +422,7 @@ struct Runner {
     __device__ __forceinline__ int reduce_all(int rid, int buf) {
         __shared__ int s_any;
         const int nq = nq_of(rid);
-        const int cg = (rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32) ? 1 : 0;
+        const int cg = (rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32 || rid == R_BG1 || rid == R_BG2) ? 1 : 0;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int s = wv; s < P.nslices; s += kWaves) {
             const GAS double *pp = gp(P.part) + (long)(buf * kNQ) * P.pstride + s_pb[2 * s + cg];
@@ -1417,53 +1417,224 @@ struct Runner {
         return s_idg[group_index(G) * 64 + (f & FL_OPEN)];
     }
 
+    // The CG tiles of the launch: column tiles of a grid go to col(G, sl, gs,
+    // y0, y1, z0, z1, pbase, yb), which stores its own partials; flat tiles
+    // run body(G, sl, gs, c, acc) on each cell and store NQ partials at
+    // pbase + tile.
+    template <int NQ, class Skip, class Col, class Body>
+    __device__ __forceinline__ void cg_tiles(Skip skip, Col col, Body body) {
+        for (int t = cb; t < ce; t += cs) {
+            int gi, sl;
+            locate_cg(t, gi, sl);
+            const GAS GroupDesc &G = P.g[gi];
+            const int gs = G.slice0 + sl;
+            if (skip(G, gs)) continue;
+            const int lt = t - G.cgtile0 - sl * G.cgtiles;
+            const int pbase = G.cgpart0 + sl * G.cgparts;
+            if (G.cby > 0) {
+                int y0, y1, z0, z1, yb;
+                cg_tile_bounds(G, lt, y0, y1, z0, z1, yb);
+                col(G, sl, gs, y0, y1, z0, z1, pbase, yb);
+            } else {
+                double acc[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+                const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+                for (int c = base + (int)threadIdx.x; c < end; c += kBlock) body(G, sl, gs, c, acc);
+                store_partials<NQ>(acc, pbase + lt);
+            }
+        }
+    }
+
+    struct BGLoad {
+        uint8_t f, fh;
+        double a, b, c, e, ah, bh, ch;
+    };
+
+    // BiCGStab phases 1 and 2 over one column tile (FP64, one column per
+    // thread), on the plan of col_A: the value y = M^-1 w of each plane is
+    // staged in the LDS plane with its halo rows, z neighbours in registers.
+    //   MODE 1: w = p = r (first) or r + beta (p_old - omega v_old); stores
+    //           p and v = A y; r^ = r on the first iteration; partial <r^, v>.
+    //   MODE 2: w = s = r - alpha v; stores t = A y; partials <t, s>, <t, t>.
+    template <int MODE, bool WT>
+    __device__ void col_BG(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS double *__restrict__ r,
+                           const GAS double *__restrict__ b_in, const GAS double *__restrict__ c_in,
+                           GAS double *__restrict__ out0, GAS double *__restrict__ out1, GAS double *__restrict__ rh,
+                           bool first, double beta, double omega, double alpha, int y0, int y1, int z0, int z1,
+                           int pbase, int yb) {
+        constexpr int NQ = MODE == 1 ? 1 : 2;
+        const int gb = group_index(G) * 64;
+        const long sz = (long)G.nx * G.ny;
+        const int nx = G.nx, nz = G.nz;
+        const double hx = G.ih2[0], hy = G.ih2[1], hz = G.ih2[2];
+        const ColPos<1> P0 = col_pos<1>(G, y0, y1, z0);
+        LAS double *plane = reinterpret_cast<LAS double *>(s_plane);
+        const int pst = (G.cby + 2) * nx;
+        const bool useb = MODE == 2 || !first;
+        // w from the loaded values (a = r, b = p_old or v, c = v_old)
+        auto wv = [&](double a, double bb, double cc) -> double {
+            if (MODE == 1) return first ? a : a + beta * (bb - omega * cc);
+            return a - alpha * bb;
+        };
+        auto load = [&](int k, BGLoad &L) {
+            const long o = (long)(k % nz - z0) * sz;
+            const long c0 = P0.c0[0] + o;
+            L.f = fl[c0];
+            L.a = r[c0];
+            if (useb) L.b = b_in[c0];
+            if (MODE == 1 && !first) L.c = c_in[c0];
+            if (MODE == 1 && !first) L.e = rh[c0];
+            if (P0.halo) {
+                const long h0 = P0.h0 + o;
+                L.fh = fl[h0];
+                L.ah = r[h0];
+                if (useb) L.bh = b_in[h0];
+                if (MODE == 1 && !first) L.ch = c_in[h0];
+            }
+        };
+        BGLoad L0{}, LA{}, LB{};
+        load(z0, L0);
+        load(z0 + 1, LA);
+        load(z0 + 2, LB);
+        double ym, wc, yc;
+        uint8_t fc;
+        double ac = L0.a, ec = L0.e;
+        {
+            const long cm = z0 > 0 ? P0.c0[0] - sz : P0.c0[0] + (long)(nz - 1) * sz;
+            const uint8_t fm = fl[cm];
+            const double am = r[cm], bm = useb ? b_in[cm] : 0.0, cm_ = (MODE == 1 && !first) ? c_in[cm] : 0.0;
+            ym = idg_of<double>(gb, fm) * wv(am, bm, cm_);
+            wc = wv(L0.a, L0.b, L0.c);
+            yc = idg_of<double>(gb, L0.f) * wc;
+            fc = L0.f;
+        }
+        double hc = idg_of<double>(gb, L0.fh) * wv(L0.ah, L0.bh, L0.ch);
+        double acc[1][NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[0][q] = 0.0;
+        int buf = 0;
+        auto step = [&](int k, BGLoad &Lk1) {
+            const double wp = wv(Lk1.a, Lk1.b, Lk1.c);
+            const double yp = idg_of<double>(gb, Lk1.f) * wp;
+            const uint8_t fp = Lk1.f;
+            const double ap = Lk1.a, ep = Lk1.e;
+            const double hn = idg_of<double>(gb, Lk1.fh) * wv(Lk1.ah, Lk1.bh, Lk1.ch);
+            load(k + 3, Lk1);
+            LAS double *pl = plane + buf * pst;
+            if (P0.act[0]) pl[P0.slot[0]] = yc;
+            if (P0.halo) pl[P0.hslot] = hc;
+            __syncthreads();
+            const int sl = P0.slot[0];
+            const uint8_t f = fc;
+            double q = 0.0;
+            q = (f & FL_XM) ? fmaT(yc - pl[sl - 1], hx, q) : q;
+            q = (f & FL_XP) ? fmaT(yc - pl[sl + 1], hx, q) : q;
+            q = (f & FL_YM) ? fmaT(yc - pl[sl - nx], hy, q) : q;
+            q = (f & FL_YP) ? fmaT(yc - pl[sl + nx], hy, q) : q;
+            q = (f & FL_ZM) ? fmaT(yc - ym, hz, q) : q;
+            q = (f & FL_ZP) ? fmaT(yc - yp, hz, q) : q;
+            if (P0.act[0]) {
+                const long c = P0.c0[0] + (long)(k - z0) * sz;
+                if (MODE == 1) {
+                    st_out<WT>(&out0[c], wc);
+                    st_out<WT>(&out1[c], q);
+                    const double rhc = first ? ac : ec;
+                    if (first) st_out<WT>(&rh[c], ac);
+                    acc[0][0] = fmaT(rhc, q, acc[0][0]);
+                } else {
+                    st_out<WT>(&out0[c], q);
+                    acc[0][0] = fmaT(q, wc, acc[0][0]);
+                    acc[0][NQ - 1] = fmaT(q, q, acc[0][NQ - 1]);
+                }
+            }
+            ym = yc;
+            yc = yp;
+            wc = wp;
+            fc = fp;
+            ac = ap;
+            ec = ep;
+            hc = hn;
+            buf ^= 1;
+            if (((k + 1) & ((1 << G.zsh) - 1)) == 0 || k + 1 == z1) stage_block<NQ, 1>(acc, (k - z0) >> G.zsh);
+        };
+        for (int k = z0; k < z1; k += 2) {
+            step(k, LA);
+            if (k + 1 < z1) step(k + 1, LB);
+        }
+        flush_blocks<NQ, 1>(G, (z1 - z0 + (1 << G.zsh) - 1) >> G.zsh, z0, pbase, yb);
+    }
+
     __device__ __forceinline__ void phase_bg1(int par) {
-        tiles<1>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).active; },
-                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
-                     const LAS SliceCtl &cs = ctl(gs);
-                     const long off = (long)sl * G.ncells;
-                     const GAS uint8_t *fl = gp(G.flags);
-                     const double GAS *r = gp(G.r) + off;
-                     const double GAS *pold = gp(par ? G.d1 : G.d0) + off, *vold = gp(par ? G.bv1 : G.bv0) + off;
-                     double GAS *pnew = gp(par ? G.d0 : G.d1) + off, *vnew = gp(par ? G.bv0 : G.bv1) + off;
-                     double GAS *rh = gp(G.brh) + off;
-                     const bool first = cs.first;
-                     const double beta = cs.beta, omega = cs.omega;
-                     auto pval = [&](long n) {
-                         return first ? r[n] : r[n] + beta * (pold[n] - omega * vold[n]);
-                     };
-                     const uint8_t f = fl[c];
-                     const double pc = pval(c);
-                     const double yc = bg_idg(G, f) * pc;
-                     const double vc = apply_A<double>(G, c, f, yc, [&](long n) { return bg_idg(G, fl[n]) * pval(n); },
-                                                       G.ih2);
-                     pnew[c] = pc;
-                     vnew[c] = vc;
-                     double rhc;
-                     if (first) { rhc = r[c]; rh[c] = rhc; }
-                     else rhc = rh[c];
-                     acc[0] += rhc * vc;
-                 });
+        auto skip = [&](const GAS GroupDesc &, int gs) { return !ctl(gs).active; };
+        auto col = [&](const GAS GroupDesc &G, int sl, int gs, int y0, int y1, int z0, int z1, int pbase, int yb) {
+            const LAS SliceCtl &cs = ctl(gs);
+            const long off = (long)sl * G.ncells;
+            const double GAS *r = gp(G.r) + off;
+            const double GAS *pold = gp(par ? G.d1 : G.d0) + off, *vold = gp(par ? G.bv1 : G.bv0) + off;
+            double GAS *pnew = gp(par ? G.d0 : G.d1) + off, *vnew = gp(par ? G.bv0 : G.bv1) + off;
+            double GAS *rh = gp(G.brh) + off;
+            if (P.wt)
+                col_BG<1, true>(G, gp(G.flags), r, pold, vold, pnew, vnew, rh, cs.first, cs.beta, cs.omega, 0.0, y0,
+                                y1, z0, z1, pbase, yb);
+            else
+                col_BG<1, false>(G, gp(G.flags), r, pold, vold, pnew, vnew, rh, cs.first, cs.beta, cs.omega, 0.0, y0,
+                                 y1, z0, z1, pbase, yb);
+        };
+        cg_tiles<1>(skip, col, [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
+            const LAS SliceCtl &cs = ctl(gs);
+            const long off = (long)sl * G.ncells;
+            const GAS uint8_t *fl = gp(G.flags);
+            const double GAS *r = gp(G.r) + off;
+            const double GAS *pold = gp(par ? G.d1 : G.d0) + off, *vold = gp(par ? G.bv1 : G.bv0) + off;
+            double GAS *pnew = gp(par ? G.d0 : G.d1) + off, *vnew = gp(par ? G.bv0 : G.bv1) + off;
+            double GAS *rh = gp(G.brh) + off;
+            const bool first = cs.first;
+            const double beta = cs.beta, omega = cs.omega;
+            auto pval = [&](long n) { return first ? r[n] : r[n] + beta * (pold[n] - omega * vold[n]); };
+            const uint8_t f = fl[c];
+            const double pc = pval(c);
+            const double yc = bg_idg(G, f) * pc;
+            const double vc = apply_A<double>(G, c, f, yc, [&](long n) { return bg_idg(G, fl[n]) * pval(n); }, G.ih2);
+            pnew[c] = pc;
+            vnew[c] = vc;
+            double rhc;
+            if (first) { rhc = r[c]; rh[c] = rhc; }
+            else rhc = rh[c];
+            acc[0] += rhc * vc;
+        });
     }
 
     __device__ __forceinline__ void phase_bg2(int par) {
-        tiles<2>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).active; },
-                 [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
-                     const LAS SliceCtl &cs = ctl(gs);
-                     const long off = (long)sl * G.ncells;
-                     const GAS uint8_t *fl = gp(G.flags);
-                     const double GAS *r = gp(G.r) + off, *v = gp(par ? G.bv0 : G.bv1) + off;
-                     double GAS *t = gp(G.q) + off;
-                     const double alpha = cs.alpha;
-                     const uint8_t f = fl[c];
-                     const double sc = r[c] - alpha * v[c];
-                     const double zc = bg_idg(G, f) * sc;
-                     const double tc = apply_A<double>(
-                         G, c, f, zc, [&](long n) { return bg_idg(G, fl[n]) * (r[n] - alpha * v[n]); }, G.ih2);
-                     t[c] = tc;
-                     acc[0] += tc * sc;
-                     acc[1] += tc * tc;
-                 });
+        auto skip = [&](const GAS GroupDesc &, int gs) { return !ctl(gs).active; };
+        auto col = [&](const GAS GroupDesc &G, int sl, int gs, int y0, int y1, int z0, int z1, int pbase, int yb) {
+            const LAS SliceCtl &cs = ctl(gs);
+            const long off = (long)sl * G.ncells;
+            const double GAS *r = gp(G.r) + off, *v = gp(par ? G.bv0 : G.bv1) + off;
+            double GAS *t = gp(G.q) + off;
+            if (P.wt)
+                col_BG<2, true>(G, gp(G.flags), r, v, nullptr, t, nullptr, nullptr, false, 0.0, 0.0, cs.alpha, y0, y1,
+                                z0, z1, pbase, yb);
+            else
+                col_BG<2, false>(G, gp(G.flags), r, v, nullptr, t, nullptr, nullptr, false, 0.0, 0.0, cs.alpha, y0, y1,
+                                 z0, z1, pbase, yb);
+        };
+        cg_tiles<2>(skip, col, [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
+            const LAS SliceCtl &cs = ctl(gs);
+            const long off = (long)sl * G.ncells;
+            const GAS uint8_t *fl = gp(G.flags);
+            const double GAS *r = gp(G.r) + off, *v = gp(par ? G.bv0 : G.bv1) + off;
+            double GAS *t = gp(G.q) + off;
+            const double alpha = cs.alpha;
+            const uint8_t f = fl[c];
+            const double sc = r[c] - alpha * v[c];
+            const double zc = bg_idg(G, f) * sc;
+            const double tc =
+                apply_A<double>(G, c, f, zc, [&](long n) { return bg_idg(G, fl[n]) * (r[n] - alpha * v[n]); }, G.ih2);
+            t[c] = tc;
+            acc[0] += tc * sc;
+            acc[1] += tc * tc;
+        });
     }
 
     __device__ __forceinline__ void phase_bg3(int par) {

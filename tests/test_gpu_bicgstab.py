@@ -36,7 +36,8 @@ def mean_free(b, fluid):
 
 
 @pytest.mark.parametrize("shape,obst,periodic", [((24, 20, 16), False, False), ((16, 16, 16), True, False),
-                                                 ((20, 18, 12), False, True), ((64, 64, 64), False, False)])
+                                                 ((20, 18, 12), False, True), ((64, 64, 64), False, False),
+                                                 ((64, 64, 64), True, False), ((64, 64, 72), False, True)])
 def test_bicgstab_poisson_parity(gpu, oracle, shape, obst, periodic):
     nx, ny, nz = shape
     _say("bicgstab poisson", shape, "obstacles" if obst else "", "periodic" if periodic else "")
@@ -95,4 +96,23 @@ def test_bicgstab_is_fp64_only(gpu):
     with pytest.raises(gpu.NSPError) as ex:
         h.poisson_solve(b, p, gpu.PoissonOpts(prec=gpu.MIXED, solver=gpu.BICGSTAB))
     assert ex.value.status == gpu.NSP_ERR_UNSUPPORTED
+    h.close()
+
+
+def test_bicgstab_column_tiles_batch_equals_single(gpu):
+    """64^3 with obstacles (column tiles in the two matrix-vector phases):
+    three slices in one launch equal each slice alone, bitwise."""
+    n = 64
+    _say("bicgstab column tiles, batch == single", n)
+    solid = inputs.obstacle_mask(n, 6)
+    h = gpu.Handle(n, n, n, re=1000.0, solid=solid, max_batch=3)
+    sts = [inputs.random_state(n, n, n, seed=40 + b, scale=0.2, pscale=0.0) for b in range(3)]
+    opts = gpu.PoissonOpts(rtol=1e-10, solver=gpu.BICGSTAB)
+    y = tuple(T(np.stack([s[c] for s in sts])) for c in range(4))
+    h.fine_step(y, 0.0, 0.002, 1e-3, opts)
+    for b in range(3):
+        y1 = tuple(T(a[None]) for a in sts[b])
+        h.fine_step(y1, 0.0, 0.002, 1e-3, opts)
+        for c in range(4):
+            assert np.array_equal(N(y[c])[b], N(y1[c])[0]), (b, c)
     h.close()
