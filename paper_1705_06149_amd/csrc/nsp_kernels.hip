@@ -2006,11 +2006,17 @@ __global__ void k_transfer(TransferParams T) {
     }
 }
 
-__global__ void k_parareal_update(UpdateParams U) {
-    // grid-stride over all segments, one segment at a time
+// Eq. (6) on the segments: y <- f + (g - gold), gold <- g, and the max of
+// |y_new - y_old| per jump slot.  The max is taken over the block (wave
+// shuffles, then LDS) and only then merged into the slot with one 64-bit
+// atomic max of the non-negative bit pattern per block and slot (segments of
+// one slot are consecutive), so a launch issues a few hundred atomics, not
+// one per wave; the max does not depend on the order.
+__global__ void __launch_bounds__(kBlock) k_parareal_update(UpdateParams U) {
+    __shared__ double s_m[kWaves];
+    double m = 0.0;
     for (int si = 0; si < U.nseg; ++si) {
         const UpdateSeg &S = U.seg[si];
-        double m = 0.0;
         for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < S.n;
              x += (long long)gridDim.x * blockDim.x) {
             const double g = S.g[x];
@@ -2020,16 +2026,26 @@ __global__ void k_parareal_update(UpdateParams U) {
             S.y[x] = y;
             S.gold[x] = g;
         }
-        // reduce max over the wave, then one atomic per wave
+        const bool flush = si + 1 == U.nseg || U.group_of_seg[si + 1] != U.group_of_seg[si] ||
+                           U.seg[si + 1].jslot != S.jslot;
+        if (!flush) continue;
         for (int o = 32; o >= 1; o >>= 1) {
             const double t = __shfl_xor(m, o, 64);
             m = (t > m || t != t) ? t : m;
         }
-        if ((threadIdx.x & 63) == 0 && m != 0.0) {
-            unsigned long long bits = __double_as_longlong(m);
-            const int slot = 2 * U.group_of_seg[si] + S.jslot;
-            __hip_atomic_fetch_max(&U.jump[slot], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mm = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mm = (s_m[w] > mm || s_m[w] != s_m[w]) ? s_m[w] : mm;
+            if (mm != 0.0) {
+                const unsigned long long bits = __double_as_longlong(mm);
+                const int slot = 2 * U.group_of_seg[si] + S.jslot;
+                __hip_atomic_fetch_max(&U.jump[slot], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
+        __syncthreads();
+        m = 0.0;
     }
 }
 
@@ -2067,10 +2083,11 @@ hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream) {
 hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream) {
     long long nmax = 0;
     for (int i = 0; i < U.nseg; ++i) nmax = U.seg[i].n > nmax ? U.seg[i].n : nmax;
-    long long blocks = (nmax + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
+    // two 1024-thread blocks per CU stream the arrays at full rate
+    long long blocks = (nmax + kBlock - 1) / kBlock;
+    if (blocks > 512) blocks = 512;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_parareal_update, dim3((unsigned)blocks), dim3(256), 0, stream, U);
+    hipLaunchKernelGGL(k_parareal_update, dim3((unsigned)blocks), dim3(kBlock), 0, stream, U);
     return hipGetLastError();
 }
 
