@@ -428,6 +428,15 @@ def bench_obstacles(args):
     return out
 
 
+def paper_sim_config(sim):
+    """Parameters of the paper's test cases (Sec. 3, Table 1)."""
+    if sim == 1:
+        return {"domain": [1.0, 1.0, 0.1], "cells": [32, 32, 5], "T": 80.0, "coarse_dt": 1e-2, "fine_dt": 1e-3,
+                "re": 1000.0, "obstacles": 0}
+    return {"domain": [1.0, 1.0, 1.0], "cells": [32, 32, 32], "T": 24.0, "coarse_dt": 1e-2, "fine_dt": 1e-3,
+            "re": 1000.0, "obstacles": 49}
+
+
 def bench_paper_sim(args, sim):
     """The paper's test cases (Sec. 3, Table 1), periodic in z, Re 1000, lid
     u = 1, fine dt 1e-3, coarse dt 1e-2, FP64:
@@ -442,12 +451,10 @@ def bench_paper_sim(args, sim):
     import torch
     from paper_1705_06149_amd import inputs, nsp
 
-    if sim == 1:
-        nx, ny, nz, lz, solid, T_def = 32, 32, 5, 0.1, None, 80.0
-    else:
-        nx, ny, nz, lz, T_def = 32, 32, 32, 1.0, 24.0
-        solid = inputs.median_plane_cubes(32, seed=49)
-    re_, dt, DT = 1000.0, 1e-3, 1e-2
+    c = paper_sim_config(sim)
+    nx, ny, nz = c["cells"]
+    lz, T_def, re_, dt, DT = c["domain"][2], c["T"], c["re"], c["fine_dt"], c["coarse_dt"]
+    solid = inputs.median_plane_cubes(nx, seed=49, count=c["obstacles"]) if c["obstacles"] else None
     N = args.slices
     T = args.sim_t if args.sim_t is not None else T_def
     o64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
