@@ -324,7 +324,8 @@ def bench_parareal(args):
         "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "roofline": {"bound": "hbm", "achieved": kach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": kach / PEAK_HBM_GBS, "traffic": None,
+                     "frac": kach / PEAK_HBM_GBS,
+                     "traffic": None if cgrid else _traffic_from_profile("k_persistent_parareal96_pmc.txt"),
                      "kernel": "k_persistent (batched fine sweeps and coarse steps of the Parareal run)",
                      "avg_launch_ms": kms / max(klaunch, 1), "launches": klaunch,
                      "algorithmic_bytes_per_launch": kbytes / max(klaunch, 1),
@@ -480,6 +481,7 @@ def bench_paper_sim(args, sim):
         return dv, float((Y[3][1:] - ref[3][1:]).abs().max())
 
     _sync()
+    h.launch_stats(reset=True)
     t0 = time.perf_counter()
     h.parareal_start(Y, Gk, N, 0.0, T, DT, o64)
     defects = [defect()]
@@ -498,10 +500,19 @@ def bench_paper_sim(args, sim):
     _sync()
     par = time.perf_counter() - t0
     nf = int(round(T / dt))
+    kst = h.launch_stats()["fine"]
+    kbytes = _stats_bytes(kst, BYTES_STEP_FIXED["fp64"])
+    kach = kbytes / max(kst["ms"] * 1e-3, 1e-12) / 1e9
     out = {
         "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
         "steps": nf, "warmup": 0, "ms_per_step": 1e3 * par / nf, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "roofline": {"bound": "hbm", "achieved": kach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": kach / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_persistent (Parareal sweeps; a small grid, so latency-bound)",
+                     "avg_launch_ms": kst["ms"] / max(kst["launches"], 1), "launches": kst["launches"],
+                     "algorithmic_bytes_per_launch": kbytes / max(kst["launches"], 1),
+                     "k_persistent_share_of_wall": kst["ms"] * 1e-3 / par},
         "config": {"workload": "paper_sim%d" % sim, "grid": [nx, ny, nz], "domain": [1.0, 1.0, lz],
                    "periodic_z": True, "obstacles": "49 seeded cubes, median plane" if solid is not None else None,
                    "re": re_, "slices": N, "T": T, "dt": dt, "DT": DT},
@@ -598,7 +609,8 @@ def bench_adjoint(args):
         "forward_cg_iters_per_step": fine["cg_cell_iters"] / max(fine["cell_steps"], 1.0),
         "reverse_cg_iters_per_projection": proj["cg_cell_iters"] / max(proj["cell_steps"], 1.0),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": _traffic_from_profile("k_persistent_adjoint96_pmc.txt"),
                      "kernel": "k_persistent (forward segments and reverse projections)",
                      "avg_launch_ms": kms / max(launches, 1), "launches": launches,
                      "algorithmic_bytes_per_launch": byts / max(launches, 1)},
