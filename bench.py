@@ -178,6 +178,7 @@ def bench_fine(args):
                      "avg_launch_ms": 1e3 * avg_launch_s,
                      "algorithmic_bytes_per_launch": per_launch_bytes},
     }
+    out["hbm_measured_GB_per_s"] = traffic / avg_launch_s / 1e9 if traffic else None
     h.close()
     return out, host_state, t
 
@@ -245,6 +246,8 @@ def bench_poisson(args):
                      "kernel": "k_persistent (%d CG iterations on %d grids per launch)" % (its, B),
                      "avg_launch_ms": float(np.mean(ms)), "algorithmic_bytes_per_launch": per_launch},
     }
+    t = out["roofline"]["traffic"]
+    out["hbm_measured_GB_per_s"] = t / (np.mean(ms) * 1e-3) / 1e9 if t else None
     h.close()
     return out
 
@@ -335,6 +338,7 @@ def bench_parareal(args):
                    "fine_poisson": "mixed, eta %g" % args.eta, "coarse_poisson": "fp64"},
         "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
         "serial_equiv_cell_updates_per_s": cells * nf / par,
+        "executed_cell_updates_per_s": sum(x["cell_steps"] for x in kst) / par,
         "end_state_rel_l2_vs_serial_fp64": err,
         "bound_paper_eq8": N / k,
         "autotuned_launch": {"workgroups": tuned_wg, "cg_tile_planes": tuned_planes,
@@ -422,6 +426,7 @@ def bench_obstacles(args):
                    "batch_cells": N * cells},
         "parareal_iterations": k, "jumps_per_grid": jumps, "iteration_s": iter_s, "serial_fp64_s": serial,
         "parareal_s": par, "serial_equiv_cell_updates_per_s": cells * nf / par,
+        "executed_cell_updates_per_s": sum(x["cell_steps"] for x in kst) / par,
         "end_state_rel_l2_vs_serial_fp64": errs,
     }
     for h in hs:
@@ -517,6 +522,8 @@ def bench_paper_sim(args, sim):
                    "periodic_z": True, "obstacles": "49 seeded cubes, median plane" if solid is not None else None,
                    "re": re_, "slices": N, "T": T, "dt": dt, "DT": DT},
         "parareal_iterations": k, "serial_fp64_s": serial, "parareal_s": par,
+        "serial_equiv_cell_updates_per_s": nx * ny * nz * nf / par,
+        "executed_cell_updates_per_s": kst["cell_steps"] / par,
         "wall_s_after_iteration": iter_wall,
         "defect_vs_serial_uvw_per_iteration": [d[0] for d in defects],
         "defect_vs_serial_p_per_iteration": [d[1] for d in defects],
