@@ -706,7 +706,7 @@ def main():
     if args.warmup is None:
         args.warmup = 5
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (time slices would shard "
+        print("bench.py runs on one GPU only: there is no multi-GPU path (time slices would shard "
               "across GPUs with point-to-point sends of slice-end states; not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "fine":

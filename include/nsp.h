@@ -43,7 +43,7 @@ typedef enum {
     NSP_ERR_NOT_CONVERGED = 2, /* a Poisson solve hit maxit / max_outer */
     NSP_ERR_NONFINITE = 3,     /* a residual norm became NaN or Inf */
     NSP_ERR_HIP = 4,           /* a HIP runtime call failed */
-    NSP_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+    NSP_ERR_UNSUPPORTED = 5    /* valid request the library does not implement */
 } nsp_status;
 
 typedef enum {

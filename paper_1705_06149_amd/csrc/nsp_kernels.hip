@@ -41,9 +41,9 @@ enum Red : int {
     R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32, R_BG1, R_BG2, R_BG3
 };
 
-// a * b + c with one rounding.  The build does not contract expressions on
-// its own; the CG kernels fuse explicitly, so every instantiation computes
-// the same bits.
+// a * b + c with one rounding.  The library is compiled with
+// -ffp-contract=off, so the compiler fuses nothing on its own; the CG
+// kernels fuse explicitly, so every instantiation computes the same bits.
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 

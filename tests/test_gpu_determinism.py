@@ -1,4 +1,4 @@
-"""Repeatability on the GPU (the build's race detector: every reduction has a
+"""Repeatability on the GPU (the library's race detector: every reduction has a
 fixed order and no floating-point atomics feed a result): the same call on
 the same inputs twice gives bitwise the same outputs, for the FP64, mixed and
 BiCGStab solves and a projection step with obstacles; and a Parareal run
