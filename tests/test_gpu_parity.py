@@ -411,3 +411,48 @@ def test_launch_stats_count_what_ran(gpu):
     assert st["bicg_cell_iters"] == cells * sum(x["iters"] for x in bi)
     assert st["cg64_cell_iters"] == 0
     h.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", [(512, 16, 32), (32, 128, 64)])
+def test_column_tile_extreme_row_widths(gpu, oracle, shape, prec):
+    """Column tiles at the widest rows they take (nx = 512: two rows per tile,
+    every thread also computes a halo value) and the narrowest (nx = 32: 32
+    rows, one halo wave), 2^18 cells each: Poisson solves and projection
+    steps with obstacles against the oracle."""
+    nx, ny, nz = shape
+    _say("column tiles, row width", nx, "prec", prec)
+    from scipy import ndimage
+    rng = np.random.default_rng(8)
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    for _ in range(12):
+        sx, sy, sz = rng.integers(2, 5, 3)
+        x0, y0, z0 = rng.integers(1, nx - sx - 1), rng.integers(1, ny - sy - 2), rng.integers(1, nz - sz - 1)
+        solid[z0:z0 + sz, y0:y0 + sy, x0:x0 + sx] = 1
+    lab, _ = ndimage.label(solid == 0)
+    top = np.unique(lab[:, ny - 1, :])
+    solid[~np.isin(lab, top[top > 0])] = 1
+    ls = dict(lx=nx / 128.0, ly=ny / 128.0, lz=nz / 128.0)   # cubic cells, h = 1/128
+    g = oracle.Grid(nx, ny, nz, re=300.0, solid=solid, **ls)
+    fluid = g.fluid()
+    b = mean_free(rng.standard_normal((nz, ny, nx)), fluid)
+    h = gpu.Handle(nx, ny, nz, re=300.0, solid=solid, max_batch=1, **ls)
+    pt = T(np.zeros((1, nz, ny, nx)))
+    info = h.poisson_solve(T(b[None]), pt, gpu.PoissonOpts(rtol=1e-12, prec=prec))[0]
+    ref, oinfo = oracle.pcg(g, b, rtol=1e-12) if prec == 0 else oracle.pcg_mixed(g, b, rtol=1e-12)
+    assert oinfo["status"] == 0
+    e = np.linalg.norm(N(pt)[0] - ref) / np.linalg.norm(ref)
+    _say("  poisson rel err", e, "iters gpu", info["iters"], "oracle", oinfo["iters"])
+    assert e < 1e-9
+    assert info["status"] == 0 and info["rel_res_true"] <= 2e-12
+    if prec == 0:
+        assert abs(info["iters"] - oinfo["iters"]) <= 2
+    st = inputs.random_state(nx, ny, nz, seed=2, scale=0.2, pscale=0.0)
+    refs, _, _, s = oracle.fine_steps(g, st, 2, 1e-3, prec=prec, rtol=1e-11)
+    assert s == 0
+    y = tuple(T(a[None]) for a in st)
+    h.fine_step(y, 0.0, 0.002, 1e-3, gpu.PoissonOpts(rtol=1e-11, prec=prec))
+    e = rel_l2([N(a)[0] for a in y[:3]], refs[:3])
+    _say("  step velocity rel L2", e)
+    assert e <= (1e-10 if prec == 0 else 1e-8)
+    h.close()
