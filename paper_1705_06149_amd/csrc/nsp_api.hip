@@ -1128,9 +1128,16 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     // candidate shape runs the same 40 CG iterations from p = 0
     std::vector<double> hb((size_t)h->ncells);
     for (long long c = 0; c < h->ncells; ++c) hb[c] = std::sin(0.37 * (double)c) + std::cos(0.011 * (double)c);
-    double *b = nullptr, *p = nullptr;
-    HIPCHK(h, dalloc(&b, (size_t)batch * h->ncells));
-    HIPCHK(h, dalloc(&p, (size_t)batch * h->ncells));
+    struct TrialBuffers {  // freed on every return path
+        double *b = nullptr, *p = nullptr;
+        ~TrialBuffers() {
+            (void)hipFree(b);
+            (void)hipFree(p);
+        }
+    } tb;
+    HIPCHK(h, dalloc(&tb.b, (size_t)batch * h->ncells));
+    HIPCHK(h, dalloc(&tb.p, (size_t)batch * h->ncells));
+    double *const b = tb.b, *const p = tb.p;
     for (int i = 0; i < batch; ++i)
         HIPCHK(h, hipMemcpy(b + (long long)i * h->ncells, hb.data(), h->ncells * sizeof(double), hipMemcpyHostToDevice));
     nsp_poisson_opts o{0.0, 40, prec, 1e-30, 1};
@@ -1167,8 +1174,6 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
                 if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
                     h->force_depth = h->force_items = 0;
                     for (int m = 0; m < 3; ++m) h->stats[m] = keep_stats[m];
-                    (void)hipFree(b);
-                    (void)hipFree(p);
                     return st;
                 }
                 if (rep > 0) tot += h->last_ms;
@@ -1177,8 +1182,6 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
         }
     h->force_depth = h->force_items = 0;
     for (int m = 0; m < 3; ++m) h->stats[m] = keep_stats[m];
-    (void)hipFree(b);
-    (void)hipFree(p);
     const int pr = prec == NSP_MIXED ? 1 : 0;
     const int keep_depth = h->crb > 0 ? best_depth : 0, keep_items = h->crb > 0 ? best_items : 0;
     bool found = false;
