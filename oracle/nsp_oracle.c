@@ -33,7 +33,9 @@
  *     fluid cells, and the pressure gauge is mean_fluid(p) = 0;
  *   - PCG stops when ||r||_2 <= rtol ||b||_2 on the recursive residual; the
  *     true residual is then recomputed and, if above 2 rtol ||b||, CG is
- *     restarted from it.
+ *     restarted from it;
+ *   - a warm start with ||b - A x0|| > ||b|| is replaced by x0 = 0 (every
+ *     solver, before its first iteration).
  *
  * OpenMP is used only on loops whose iterations write disjoint outputs, so
  * results do not depend on the thread count.  Every reduction is a serial
@@ -381,6 +383,29 @@ static void subtract_mean(const og_grid *g, double *a) {
 
 /* ------------------------------------------------------ Jacobi-PCG (a3) */
 
+/* Cold start: a warm start worse than none is dropped.  When the squared
+ * norm of the starting residual b - A x exceeds that of b, x is set to 0
+ * (then r = b).  The relative stopping test ||r|| <= rtol ||b|| cannot be
+ * met from a starting residual far above ||b||: with b at the rounding
+ * level (a flow uniform to rounding along periodic z) Krylov iterations on
+ * rounding noise drift into A's null space and break down.  From x = 0
+ * the same systems converge in a few iterations.  Squared sums are
+ * compared, so x = 0 on entry (r = b exactly) is never a cold start.
+ * Returns 1 if x was reset. */
+static int cold_start_if_worse(const og_grid *g, const double *b, double *x, double *tmp) {
+    size_t n = ncells(g);
+    og_apply_A(g, x, tmp);
+    double rr = 0.0, bb = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        double d = b[i] - tmp[i];
+        rr += d * d;
+        bb += b[i] * b[i];
+    }
+    if (!(rr > bb)) return 0;
+    for (size_t i = 0; i < n; ++i) x[i] = 0.0;
+    return 1;
+}
+
 /* Solves A x = b for a mean-free b, x holding the initial guess on entry.
  * On exit x is gauge-fixed (mean_fluid(x) = 0). */
 int og_pcg(const og_grid *g, const double *b, double *x, double rtol, int maxit, og_info *info) {
@@ -398,6 +423,7 @@ int og_pcg(const og_grid *g, const double *b, double *x, double rtol, int maxit,
     }
     int it = 0, status = 0, restarts = 0;
     double rel_true = 0.0;
+    cold_start_if_worse(g, b, x, q);
     for (;;) {
         /* (re)start from the true residual */
         og_apply_A(g, x, q);
@@ -468,6 +494,7 @@ int og_bicgstab(const og_grid *g, const double *b, double *x, double rtol, int m
         for (size_t i = 0; i < n; ++i) x[i] = 0.0;
         goto done;
     }
+    cold_start_if_worse(g, b, x, t);
     for (;;) {
         og_apply_A(g, x, t);
         for (size_t i = 0; i < n; ++i) { r[i] = b[i] - t[i]; rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
@@ -598,6 +625,7 @@ int og_pcg_mixed(const og_grid *g, const double *b, double *x, double rtol, doub
     if (bnorm == 0.0) {
         for (size_t i = 0; i < n; ++i) x[i] = 0.0;
     } else {
+        cold_start_if_worse(g, b, x, r);
         for (;;) {
             og_apply_A(g, x, r);
             for (size_t i = 0; i < n; ++i) r[i] = b[i] - r[i];

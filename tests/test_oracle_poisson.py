@@ -123,3 +123,73 @@ def test_warm_start_and_status_codes(oracle):
     bn[2, 2, 2] = np.nan
     _, info6 = oracle.pcg(g, bn)
     assert info6["status"] == 3
+
+
+def _periodic_closed_form(b, h):
+    """Neumann in x, y and periodic in z: DCT-II in x, y and the DFT in z
+    diagonalise A; the mean-free solution of A p = b."""
+    nz, ny, nx = b.shape
+    lam = ((4 / h[0] ** 2) * np.sin(np.pi * np.arange(nx) / (2 * nx)) ** 2)[None, None, :] \
+        + ((4 / h[1] ** 2) * np.sin(np.pi * np.arange(ny) / (2 * ny)) ** 2)[None, :, None] \
+        + ((4 / h[2] ** 2) * np.sin(np.pi * np.arange(nz) / nz) ** 2)[:, None, None]
+    bh = np.fft.fft(fft.dctn(b, type=2, norm="ortho", axes=(1, 2)), axis=0)
+    lam[0, 0, 0] = 1.0
+    ph = bh / lam
+    ph[0, 0, 0] = 0.0
+    p = fft.idctn(np.fft.ifft(ph, axis=0).real, type=2, norm="ortho", axes=(1, 2))
+    return p - p.mean()
+
+
+@pytest.mark.parametrize("solver", ["pcg", "pcg_mixed", "bicgstab"])
+def test_cold_start_on_rounding_level_rhs(oracle, solver):
+    """A right-hand side at the rounding level (as after a step that left the
+    flow uniform along periodic z) with a warm start of order 30: the warm
+    start is worse than none (||b - A x0|| > ||b||), so the solve starts from
+    x0 = 0 and converges to the closed-form solution.  Iterating from the
+    warm start instead cannot meet ||r|| <= rtol ||b|| and breaks down."""
+    g = oracle.Grid(6, 6, 6, periodic_z=True)
+    rng = np.random.default_rng(21)
+    b = rng.standard_normal((6, 6, 6)) * 1e-13
+    b -= b.mean()
+    x0 = rng.standard_normal((6, 6, 6)) * 30.0
+    p, info = getattr(oracle, solver)(g, b, x0=x0, rtol=1e-10)
+    ref = _periodic_closed_form(b, g.h)
+    assert info["status"] == 0, info
+    assert np.linalg.norm(p - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_cold_start_keeps_a_good_warm_start(oracle):
+    """The rule fires only when the warm start is worse than none: a warm
+    start near the solution is kept and saves iterations."""
+    g = oracle.Grid(10, 10, 10)
+    rng = np.random.default_rng(22)
+    b = rng.standard_normal((10, 10, 10))
+    b -= b.mean()
+    ref = _dct_solve(b, g.h)
+    _, cold = oracle.pcg(g, b, rtol=1e-10)
+    near = ref + 1e-3 * np.abs(ref).max() * rng.standard_normal(b.shape)
+    p, warm = oracle.pcg(g, b, x0=near, rtol=1e-10)
+    assert warm["status"] == 0 and warm["iters"] < cold["iters"]
+    assert np.linalg.norm(p - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_periodic_column_decays_in_closed_form(oracle):
+    """A 1 x 1 x 4 column periodic in z: u and v sit on walls (zero), the
+    projection leaves w uniform along z, and then each step multiplies it
+    by 1 - 4 dt (1/hx^2 + 1/hy^2)/Re (no-slip images on the four side walls;
+    a uniform w has equal fluxes through every z face).  From the second
+    step on the right-hand side is rounding noise while the warm-started
+    pressure is not: every step must still converge."""
+    re, dt = 100.0, 1e-3
+    g = oracle.Grid(1, 1, 4, lx=0.25, ly=0.25, lz=1.0, re=re, periodic_z=True)
+    st = inputs.random_state(1, 1, 4, seed=3, scale=0.5, pscale=0.0)
+    st = (st[0], st[1], np.concatenate([st[2][:-1], st[2][:1]], axis=0), st[3])
+    hx, hy, _ = g.h
+    fac = 1.0 - 4.0 * dt * (1.0 / hx ** 2 + 1.0 / hy ** 2) / re
+    y1, _, _, s1 = oracle.fine_steps(g, st, 1, dt)
+    y4, iters, rel, s4 = oracle.fine_steps(g, y1, 3, dt)
+    assert s1 == 0 and s4 == 0
+    assert np.all(y4[0] == 0.0) and np.all(y4[1] == 0.0)
+    c1 = y1[2].mean()
+    assert np.max(np.abs(y4[2] - c1 * fac ** 3)) <= 1e-9 * abs(c1)
+    assert np.all(np.isfinite(y4[3]))
