@@ -1,0 +1,83 @@
+"""Write the serial FP64 reference of the 96^3 Parareal workload.
+
+The workload: lid-driven cavity on the unit cube, 96^3 cells, Re = 1000, lid
+u = 1, start from rest (Sec. 3), fine step dt = 5e-4 up to T = 0.64 (1280
+projection steps), Jacobi-PCG to ||r|| <= 1e-10 ||b||.  Parareal converges to
+the serial fine solution (Sec. 2.1.2, Eqs. (6)-(7)), so this serial run of the
+oracle is the reference the GPU's Parareal end state is checked against.
+
+Only the oracle runs here.  The file written holds, per component u, v, w, p:
+16384 flat indices drawn with a fixed seed and the end-state values there,
+the L2 and max norms of the whole component, and the CG iterations of every
+step.  Usage:
+
+    python tests/golden/make_c3_reference.py [--checkpoint FILE]
+
+With --checkpoint the state is saved every 40 steps and a rerun resumes from
+it.  A full run takes hours on a few CPU cores.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+
+N, RE, DT, T, RTOL = 96, 1000.0, 5e-4, 0.64, 1e-10
+NSTEPS = int(round(T / DT))
+NSAMPLE, SEED = 16384, 20170518
+OUT = os.path.join(HERE, "c3_cavity96_re1000_T064_fp64.npz")
+
+
+def sample_indices(shapes):
+    rng = np.random.default_rng(SEED)
+    return [np.sort(rng.choice(int(np.prod(s)), size=NSAMPLE, replace=False)).astype(np.int64) for s in shapes]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--checkpoint", default=None)
+    ap.add_argument("--chunk", type=int, default=40)
+    a = ap.parse_args()
+    g = O.Grid(N, N, N, re=RE)
+    state, step, iters = g.zeros_state(), 0, []
+    if a.checkpoint and os.path.exists(a.checkpoint):
+        z = np.load(a.checkpoint)
+        state = tuple(z[k] for k in ("u", "v", "w", "p"))
+        step, iters = int(z["step"]), list(z["iters"])
+        print("resumed at step %d" % step, flush=True)
+    t0 = time.time()
+    while step < NSTEPS:
+        n = min(a.chunk, NSTEPS - step)
+        state, it, rel, st = O.fine_steps(g, state, n, DT, rtol=RTOL)
+        if st != 0:
+            raise RuntimeError("oracle step failed with status %d at step %d" % (st, step))
+        step += n
+        iters += [int(x) for x in it]
+        print("step %d/%d  CG iterations of the last %d steps: %d  (%.0f s)"
+              % (step, NSTEPS, n, int(np.sum(it)), time.time() - t0), flush=True)
+        if a.checkpoint:
+            tmp = a.checkpoint + ".tmp.npz"
+            np.savez(tmp, u=state[0], v=state[1], w=state[2], p=state[3], step=step, iters=np.array(iters))
+            os.replace(tmp, a.checkpoint)
+    idx = sample_indices(g.shapes())
+    out = dict(n=N, re=RE, dt=DT, T=T, rtol=RTOL, nsteps=NSTEPS, seed=SEED, iters=np.array(iters, np.int32))
+    for name, arr, ix in zip("uvwp", state, idx):
+        out["idx_" + name] = ix
+        out["val_" + name] = arr.ravel()[ix]
+        out["l2_" + name] = float(np.sqrt(np.sum(arr * arr)))
+        out["max_" + name] = float(np.max(np.abs(arr)))
+    np.savez_compressed(OUT, **out)
+    print("wrote", OUT, os.path.getsize(OUT), "bytes", flush=True)
+
+
+if __name__ == "__main__":
+    main()

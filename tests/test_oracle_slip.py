@@ -116,3 +116,50 @@ def test_slip_adjoint_is_refused(oracle):
     g = oracle.Grid(6, 6, 6, solid=solid, slip_obstacles=True)
     with pytest.raises(NotImplementedError):
         oracle.adjoint_gradient(g, g.zeros_state(), 1, 1e-3)
+
+
+def _smart_hand(U, C, D):
+    # the NVD characteristic written out for the hand computation below
+    if D == U:
+        return C
+    ph = (C - U) / (D - U)
+    if 0 < ph < 1 / 6:
+        f = 3 * ph
+    elif 1 / 6 <= ph < 5 / 6:
+        f = 0.75 * ph + 0.375
+    elif 5 / 6 <= ph < 1:
+        f = 1.0
+    else:
+        f = ph
+    return U + f * (D - U)
+
+
+@pytest.mark.parametrize("slip", [True, False])
+def test_image_two_rows_above_an_obstacle_top_by_hand(oracle, slip):
+    """A solid slab fills row 2; u is uniform along x and z in every row and
+    v = V > 0 on the open v faces.  At the u face of row 4 the upwind triple
+    of the lower control-volume face is (row 2, row 3, row 4), and row 2 is
+    closed by the obstacle, half a cell beyond row 3: the image is u(row 3)
+    itself with a free-slip obstacle (zero tangential stress mirrors it) and
+    -u(row 3) with a no-slip one.  Hand value of F at that face."""
+    n, re, dt, V = 8, 10.0, 1e-3, 0.3
+    h = 1.0 / n
+    rows = [0.1, 0.15, 0.0, 0.25, 0.55, 0.6, 0.62, 0.64]
+    solid = np.zeros((n, n, n), np.uint8)
+    solid[:, 2, :] = 1
+    u = np.zeros((n, n, n + 1))
+    for j, a in enumerate(rows):
+        u[:, j, 1:n] = a
+    u[:, 2, :] = 0.0
+    v = np.zeros((n, n + 1, n))
+    v[:, 1:n, :] = V
+    v[:, 2:4, :] = 0.0
+    w = np.zeros((n + 1, n, n))
+    g = oracle.Grid(n, n, n, re=re, solid=solid, slip_obstacles=slip, lid=np.zeros((n, n + 1)))
+    Fu, _, _ = oracle.momentum(g, u, v, w, dt)
+    img = rows[3] if slip else -rows[3]
+    lap = (rows[5] - 2 * rows[4] + rows[3]) / h ** 2
+    fp = V * _smart_hand(rows[3], rows[4], rows[5])
+    fm = V * _smart_hand(img, rows[3], rows[4])
+    expect = rows[4] + dt * (lap / re - (fp - fm) / h)
+    assert Fu[4, 4, 4] == pytest.approx(expect, rel=1e-13)

@@ -184,3 +184,57 @@ def test_closed_faces_written_zero_and_ignored(oracle):
     b, _, _, _ = oracle.fine_steps(g, tuple(from_open), 2, 1e-3)
     for x, y in zip(a[:3], b[:3]):
         assert np.array_equal(x, y)
+
+
+def _layered_state(n, rows, V, solid_rows=()):
+    """u = rows[j] on every interior u face of row j (uniform in x and z),
+    v = V on every open v face, w = 0; rows listed in solid_rows are solid."""
+    u = np.zeros((n, n, n + 1))
+    for j, a in enumerate(rows):
+        u[:, j, 1:n] = a
+    v = np.zeros((n, n + 1, n))
+    v[:, 1:n, :] = V
+    for j in solid_rows:
+        u[:, j, :] = 0.0
+        v[:, j:j + 2, :] = 0.0
+    return u, v, np.zeros((n + 1, n, n))
+
+
+def _hand_F(a_m1, a_0, a_p1, a_p2, img_m2, V, h, dt, re):
+    """F at a u face with row values a(-1), a(0), a(+1), a(+2) along y and the
+    image img_m2 at offset -2, uniform along x and z (so only the y terms
+    act), transport V > 0 through both y control-volume faces."""
+    lap = (a_p1 - 2 * a_0 + a_m1) / h ** 2
+    fp = V * _smart_hand(a_m1, a_0, a_p1)     # upwind triple (f-1, f, f+1)
+    fm = V * _smart_hand(img_m2, a_m1, a_0)   # upwind triple (f-2, f-1, f)
+    return a_0 + dt * (lap / re - (fp - fm) / h)
+
+
+def test_tangential_no_slip_image_two_rows_above_the_bottom_wall(oracle):
+    """u face one row above the bottom row, flow upward: the upwind triple
+    of the lower control-volume face reaches two rows down, behind the
+    no-slip wall at y = 0, whose image is 2*0 - u(row 0) (the wall sits
+    half a cell below row 0, so row 0 is the mirror)."""
+    n, re, dt, V = 8, 10.0, 1e-3, 0.3
+    h = 1.0 / n
+    rows = [0.2, 0.5, 0.65, 0.7, 0.72, 0.74, 0.76, 0.78]
+    g = oracle.Grid(n, n, n, re=re, lid=np.zeros((n, n + 1)))
+    Fu, _, _ = oracle.momentum(g, *_layered_state(n, rows, V), dt)
+    expect = _hand_F(rows[0], rows[1], rows[2], None, -rows[0], V, h, dt, re)
+    assert Fu[4, 1, 4] == pytest.approx(expect, rel=1e-13)
+    # the image differs from the one a wall beside row 1 would give
+    assert abs(expect - _hand_F(rows[0], rows[1], rows[2], None, -rows[1], V, h, dt, re)) > 1e-6
+
+
+def test_tangential_no_slip_image_two_rows_above_an_obstacle_top(oracle):
+    """The same branch at an obstacle: a solid slab fills row 2; the u face
+    of row 4 looks two rows down at the closed row 2, image -u(row 3)."""
+    n, re, dt, V = 8, 10.0, 1e-3, 0.3
+    h = 1.0 / n
+    rows = [0.1, 0.15, 0.0, 0.25, 0.55, 0.6, 0.62, 0.64]
+    solid = np.zeros((n, n, n), np.uint8)
+    solid[:, 2, :] = 1
+    g = oracle.Grid(n, n, n, re=re, solid=solid, lid=np.zeros((n, n + 1)))
+    Fu, _, _ = oracle.momentum(g, *_layered_state(n, rows, V, solid_rows=(2,)), dt)
+    expect = _hand_F(rows[3], rows[4], rows[5], None, -rows[3], V, h, dt, re)
+    assert Fu[4, 4, 4] == pytest.approx(expect, rel=1e-13)
