@@ -131,8 +131,9 @@ const char *nsp_last_error(const nsp_handle *h);
 
 /* Lid: the wall value of u on the top face, one value per top u-face
  * position, DEVICE array [nz][nx+1] (entries at i = 0 and i = nx are
- * unused).  Copied. */
-nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev);
+ * unused).  Copied on `stream` (so a lid written by earlier work on that
+ * stream is seen); returns after the copy. */
+nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev, void *stream);
 
 /* Pressure Poisson solve of the projection step (Sec. 2): A p = b for a
  * batch of right-hand sides.  b: [batch] cell arrays, first made mean-free
@@ -176,7 +177,12 @@ nsp_status nsp_group_fine_step(nsp_handle *const *hs, const nsp_state *ys, const
  *   g = G(Ynew[n]);  Ynew[n+1] = F(Y[n]) + (g - Gk[n]);  Gk[n] = g.
  * jump (HOST, 2 doubles): max over slices and grid points of
  * |Ynew - Y| for (u,v,w) and for p.  The handle needs max_batch >=
- * nslices. */
+ * nslices.  When a fine or coarse Poisson solve hits maxit / max_outer the
+ * iteration still completes with that solve's best iterate (Y, Gk and jump
+ * are written) and the call returns NSP_ERR_NOT_CONVERGED; any other error
+ * stops it at once.  nsp_parareal_start reports coarse solves the same way.
+ * Poisson solves of every verb start from the state's p unless that warm
+ * start is worse than none (||b - A p|| > ||b||), then from p = 0. */
 nsp_status nsp_parareal_start(nsp_handle *h, nsp_state Y, nsp_state Gk, int nslices, double t0, double T,
                               double DT, const nsp_poisson_opts *coarse, void *stream);
 nsp_status nsp_parareal_iterate(nsp_handle *h, nsp_state Y, nsp_state Fk, nsp_state Gk, int nslices, int k,

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -381,7 +382,8 @@ void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int 
 // Launch the persistent kernel over ngroups groups and read back the
 // per-slice control blocks into info (may be NULL).
 nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
-               const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override) {
+               const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override,
+               const LaunchRes *ws = nullptr) {
     nsp_handle *h = hs[0];
     int nslices = 0, ntiles = 0, cgtiles = 0;
     for (int g = 0; g < ngroups; ++g) {
@@ -402,7 +404,9 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     if (wg > kMaxWG) wg = kMaxWG;
     GroupDesc lg[kMaxGroups];
     for (int g = 0; g < ngroups; ++g) lg[g] = groups[g];
-    if (o->solver == NSP_BICGSTAB)
+    // ws: launch workspace brought in by the caller (every vector pointer of
+    // the groups already set); nothing is allocated then
+    if (o->solver == NSP_BICGSTAB && !ws)
         for (int g = 0; g < ngroups; ++g) {
             nsp_handle *hg = hs[g];
             if (!hg->bv0) {
@@ -425,9 +429,15 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     int cgparts = 0;
     layout_groups(lg, ngroups, wg, depth, items, o->prec == NSP_MIXED, &ntiles, &cgtiles, &cgparts);
     const int pstride = std::max(ntiles, cgparts);
-    nsp_status st = ensure_launch_res(h, nslices, pstride);
-    if (st != NSP_OK) return st;
-    KParams &P = *h->L.params_host;
+    if (ws) {
+        if (nslices > ws->cap_slices || pstride > ws->cap_tiles)
+            return fail(h, NSP_ERR_ARG, "launch workspace too small for this launch");
+    } else {
+        nsp_status st = ensure_launch_res(h, nslices, pstride);
+        if (st != NSP_OK) return st;
+    }
+    const LaunchRes &L = ws ? *ws : h->L;
+    KParams &P = *L.params_host;
     // the pinned block may still be read by an earlier copy on this stream
     HIPCHK(h, hipStreamSynchronize(stream));
     std::memset(&P, 0, sizeof(P));
@@ -453,18 +463,19 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.dt = dt;
     P.rtol = o->rtol;
     P.eta = o->inner_rtol;
-    P.ctl = h->L.ctl;
-    P.part = h->L.part;
-    P.sync = h->L.sync;
-    HIPCHK(h, hipMemsetAsync(h->L.ctl, 0, nslices * sizeof(SliceCtl), stream));
-    HIPCHK(h, hipMemcpyAsync(h->L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
-    HIPCHK(h, launch_reset_sync(h->L.sync, stream));
+    P.ctl = L.ctl;
+    P.part = L.part;
+    P.sync = L.sync;
+    static_assert(sizeof(SliceCtl) % sizeof(unsigned) == 0, "control blocks are zeroed as words");
+    HIPCHK(h, launch_zero_words(L.ctl, (long long)nslices * (sizeof(SliceCtl) / sizeof(unsigned)), stream));
+    HIPCHK(h, hipMemcpyAsync(L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
+    HIPCHK(h, launch_reset_sync(L.sync, stream));
     HIPCHK(h, hipEventRecord(h->ev0, stream));
-    HIPCHK(h, launch_persistent(h->L.params, wg, stream));
+    HIPCHK(h, launch_persistent(L.params, wg, stream));
     HIPCHK(h, hipEventRecord(h->ev1, stream));
-    HIPCHK(h, hipMemcpyAsync(h->L.ctl_host, h->L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipMemcpyAsync(L.ctl_host, L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost, stream));
     int aborted = 0;
-    HIPCHK(h, hipMemcpyAsync(&aborted, &h->L.sync->abort, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipMemcpyAsync(&aborted, &L.sync->abort, sizeof(int), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
     float ms = 0;
     if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
@@ -475,7 +486,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     int worst = 0;
     for (int g = 0, s = 0; g < ngroups; ++g)
         for (int k = 0; k < lg[g].nslices; ++k, ++s) {
-            const SliceCtl &c = h->L.ctl_host[s];
+            const SliceCtl &c = L.ctl_host[s];
             const double cells = (double)lg[g].ncells, it = cells * c.tot_it;
             S.cell_steps += cells * (mode == MODE_FINE ? nsteps : 1);
             S.cg_cell_iters += it;
@@ -490,7 +501,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
             }
         }
     for (int s = 0; s < nslices; ++s) {
-        const SliceCtl &c = h->L.ctl_host[s];
+        const SliceCtl &c = L.ctl_host[s];
         worst = std::max(worst, c.status);
         if (info) {
             info[s].iters = c.tot_it;
@@ -604,14 +615,16 @@ nsp_status coarse_slice(nsp_handle *const *hs, nsp_handle *const *hcs, const nsp
         }
     }
     nsp_status st = propagate(hcs ? hcs : hs, gsv, ones, ngroups, t0, t1, DT, coarse, s, nullptr);
-    if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) {
-        if (hcs) h->err = "coarse grid: " + hcs[0]->err;
-        return st;
-    }
+    if (hcs && st != NSP_OK) h->err = "coarse grid: " + hcs[0]->err;
+    if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
     if (hcs)
         for (int g = 0; g < ngroups; ++g) HIPCHK(h, transfer(hs[g], hcs[g]->gs, hs[g]->gs, 1, true, s));
-    return NSP_OK;
+    // a coarse solve that hit its limit still leaves its best iterate in gs
+    return st;
 }
+
+// the worse of two statuses where the call goes on (OK < NOT_CONVERGED)
+nsp_status worse(nsp_status a, nsp_status b) { return (a == NSP_ERR_NOT_CONVERGED || b == NSP_ERR_NOT_CONVERGED) ? NSP_ERR_NOT_CONVERGED : NSP_OK; }
 
 nsp_status parareal_start_impl(nsp_handle *const *hs, nsp_handle *const *hcs, const nsp_state *Y,
                                const nsp_state *Gk, int ngroups, int nslices, double t0, double T, double DT,
@@ -625,15 +638,20 @@ nsp_status parareal_start_impl(nsp_handle *const *hs, nsp_handle *const *hcs, co
     if (!step_count(0.0, len, DT, &nc)) return fail(h, NSP_ERR_ARG, "slice length / DT is not an integer");
     for (int g = 0; g < ngroups; ++g)
         if (!hs[g] || !state_ok(Y[g]) || !state_ok(Gk[g])) return fail(h, NSP_ERR_ARG, "null state");
+    nsp_status worst = NSP_OK;
+    std::string msg;
     for (int n = 0; n < nslices; ++n) {
         nsp_status st = coarse_slice(hs, hcs, Y, ngroups, n, t0 + n * len, t0 + (n + 1) * len, DT, coarse, s);
-        if (st != NSP_OK) return st;
+        if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
+        if (st != NSP_OK && worst == NSP_OK) msg = h->err;
+        worst = worse(worst, st);
         for (int g = 0; g < ngroups; ++g) {
             HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Y[g], n + 1), hs[g]->gs, 1, s));
             HIPCHK(h, copy_slices(hs[g], offset_state(hs[g], Gk[g], n), hs[g]->gs, 1, s));
         }
     }
     HIPCHK(h, hipStreamSynchronize(s));
+    if (worst != NSP_OK) return fail(h, worst, "coarse sweep: " + msg);
     return NSP_OK;
 }
 
@@ -667,10 +685,16 @@ nsp_status parareal_iterate_impl(nsp_handle *const *hs, nsp_handle *const *hcs, 
     }
     nsp_status st = propagate(hs, fsub, nb, ngroups, t0 + k * len, t0 + (k + 1) * len, dt, fine, stream, nullptr);
     if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
+    // a solve that hit its limit does not stop the iteration: its best iterate
+    // enters Eq. (6), and the call reports NOT_CONVERGED at the end
+    nsp_status worst = st;
+    std::string msg = st != NSP_OK ? "fine sweep: " + h->err : std::string();
     HIPCHK(h, hipMemsetAsync(h->L.jump, 0, 2 * kMaxGroups * sizeof(unsigned long long), s));
     for (int n = k; n < nslices; ++n) {
         st = coarse_slice(hs, hcs, Y, ngroups, n, t0 + n * len, t0 + (n + 1) * len, DT, coarse, s);
-        if (st != NSP_OK) return st;
+        if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
+        if (st != NSP_OK && worst == NSP_OK) msg = "coarse sweep: " + h->err;
+        worst = worse(worst, st);
         UpdateParams U;
         std::memset(&U, 0, sizeof(U));
         U.jump = h->L.jump;
@@ -705,6 +729,7 @@ nsp_status parareal_iterate_impl(nsp_handle *const *hs, nsp_handle *const *hcs, 
         std::memcpy(&v, &h->L.jump_host[g], sizeof(v));
         jump[g] = v;
     }
+    if (worst != NSP_OK) return fail(h, worst, msg);
     return NSP_OK;
 }
 
@@ -837,9 +862,12 @@ nsp_status nsp_destroy(nsp_handle *h) {
     return NSP_OK;
 }
 
-nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev) {
+nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev, void *stream) {
     if (!h || !lid_dev) return fail(h, NSP_ERR_ARG, "null lid pointer");
-    HIPCHK(h, hipMemcpy(h->lid, lid_dev, (size_t)h->nz * (h->nx + 1) * sizeof(double), hipMemcpyDeviceToDevice));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipMemcpyAsync(h->lid, lid_dev, (size_t)h->nz * (h->nx + 1) * sizeof(double), hipMemcpyDeviceToDevice,
+                             s));
+    HIPCHK(h, hipStreamSynchronize(s));
     return NSP_OK;
 }
 

@@ -80,6 +80,7 @@ struct SliceCtl {
     int it_in;    // iterations of the current inner (FP32) solve
     int need;     // mixed: another defect-correction sweep is needed
     int zero;     // right-hand side is zero: solution is p = 0
+    int cold;     // the warm start was worse than none: the solve restarts from p = 0
     int outer;    // restarts / sweeps of the current step
     int done;     // current solve finished for this slice
     int status;   // worst status over the call
@@ -139,6 +140,8 @@ struct KParams {
 hipError_t launch_persistent(const KParams *P_dev, int workgroups, hipStream_t stream);
 hipError_t max_coresident_workgroups(int device, int *out);
 hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream);
+// zero nwords 32-bit words at p on the stream (a kernel, not a memset)
+hipError_t launch_zero_words(void *p, long long nwords, hipStream_t stream);
 
 struct UpdateSeg {
     double *y;          // slice-end state to overwrite (y^{k+1}_{n+1})

@@ -386,8 +386,8 @@ struct Runner {
         switch (rid) {
         case R_MEANB: case R_A: case R_A32: case R_BG1: return 1;
         case R_B: case R_B32: case R_CAST: case R_BG2: case R_BG3: return 2;
-        case R_INIT: case R_TRUE: case R_OUT: return 3;
-        case R_OUT0: return 4;
+        case R_TRUE: case R_OUT: return 3;
+        case R_INIT: case R_OUT0: return 4;
         default: return 0;
         }
     }
@@ -450,7 +450,8 @@ struct Runner {
                 for (int q = 0; q < nq; ++q) S[q] = s_sum[lane * kNQ + q];
                 f = control(rid, lane, S, s_nf[lane]);
             }
-            const int any = __any(f != 0) ? 1 : 0;
+            // bit 0: some slice iterates; bit 1: some slice takes a cold start
+            const int any = (__any(f & 1) ? 1 : 0) | (__any(f & 2) ? 2 : 0);
             if (lane == 0) s_any = any;
         }
         __syncthreads();
@@ -561,7 +562,9 @@ struct Runner {
             c.mean_b = S[0] / nf;
             return 0;
         case R_INIT: {
-            // S0 = ||b||^2, S1 = ||r||^2, S2 = <r,z>
+            // S0 = ||b||^2, S1 = ||r||^2, S2 = <r,z>, S3 = <b, M^-1 b>.  A warm
+            // start worse than none (||r||^2 > ||b||^2) is dropped: the solve
+            // starts from p = 0, r = b (written by phase_cold)
             c.bnorm = sqrt(S[0]);
             c.it = 0;
             c.outer = 0;
@@ -570,18 +573,21 @@ struct Runner {
             c.first = 1;
             c.zero = (c.bnorm == 0.0);
             c.active = 0;
+            c.cold = 0;
             if (c.zero) return 0;
-            c.rz = S[2];
+            c.cold = S[1] > S[0] ? 1 : 0;
+            const double rr = c.cold ? S[0] : S[1];
+            c.rz = c.cold ? S[3] : S[2];
             if (P.solver == 1) {
                 // BiCGStab: r^ = r0, so rho = <r^, r0> = ||r0||^2; alpha = omega = 1
-                c.rz = S[1];
+                c.rz = rr;
                 c.alpha = 1.0;
                 c.omega = 1.0;
             }
-            const double rn = sqrt(S[1]);
+            const double rn = sqrt(rr);
             if (!isfinite(rn)) c.step_status = 3;
             else if (rn > P.rtol * c.bnorm) c.active = (c.it < P.maxit) ? 1 : (c.step_status = 2, 0);
-            return c.active;
+            return c.active | (c.cold << 1);
         }
         case R_A:
             if (c.active) c.alpha = c.rz / S[0];
@@ -645,6 +651,9 @@ struct Runner {
                 c.step_status = 0;
                 c.zero = (c.bnorm == 0.0);
                 c.need = 0;
+                c.cold = 0;
+            } else {
+                c.cold = 0;
             }
             if (c.done) return 0;
             if (c.zero) {
@@ -652,6 +661,12 @@ struct Runner {
                 c.res_true = 0.0;
                 finish_solve(c);
                 return 0;
+            }
+            if (rid == R_OUT0 && S[0] > S[3]) {
+                // the warm start is worse than none: p = 0 (phase_cold), then
+                // the residual is evaluated again
+                c.cold = 1;
+                return 2;
             }
             c.res_true = sqrt(S[0]);
             c.rel_true = c.res_true / c.bnorm;
@@ -819,9 +834,9 @@ struct Runner {
     __device__ __forceinline__ int group_index(const GAS GroupDesc &G) const { return (int)(&G - P.g); }
 
     // FP64 CG, initial residual: b -= mean_b (stored), r = b - A p.
-    // partials: ||b||^2, ||r||^2, <r,z>
+    // partials: ||b||^2, ||r||^2, <r,z>, <b, M^-1 b>
     __device__ __forceinline__ void phase_init64(bool from_user) {
-        tiles<3>([](const GAS GroupDesc &, int) { return false; },
+        tiles<4>([](const GAS GroupDesc &, int) { return false; },
                  [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
                      const long off = (long)sl * G.ncells;
                      double GAS *b = gp(G.b) + off, *r = gp(G.r) + off;
@@ -834,10 +849,22 @@ struct Runner {
                      const double ap = apply_A<double>(G, c, fl, p[c], [&](long n) { return p[n]; }, G.ih2);
                      const double rv = bv - ap;
                      r[c] = rv;
-                     const double z = rv * s_idg[group_index(G) * 64 + (fl & FL_OPEN)];
+                     const double idg = s_idg[group_index(G) * 64 + (fl & FL_OPEN)];
                      acc[0] += bv * bv;
                      acc[1] += rv * rv;
-                     acc[2] += rv * z;
+                     acc[2] += rv * (rv * idg);
+                     acc[3] += bv * (bv * idg);
+                 });
+    }
+
+    // Cold start of the slices whose warm start was worse than none: p = 0
+    // on every cell and, when with_r, r = b (the residual of p = 0).
+    __device__ __forceinline__ void phase_cold(bool with_r) {
+        tiles<0>([&](const GAS GroupDesc &, int gs) { return !ctl(gs).cold; },
+                 [&](const GAS GroupDesc &G, int sl, int, int c, double *) {
+                     const long off = (long)sl * G.ncells;
+                     gp(G.p)[off + c] = 0.0;
+                     if (with_r) gp(G.r)[off + c] = gp(G.b)[off + c];
                  });
     }
 
@@ -1744,9 +1771,19 @@ struct Runner {
     // ---------------------------------------------------------- programs
 
     // returns false on abort
+    // after the initial residual: cold-start the slices that need it
+    __device__ __forceinline__ int after_init(int any, bool with_r) {
+        if (any < 0) return -1;
+        if (any & 2) {
+            phase_cold(with_r);
+            if (sync(R_NONE) < 0) return -1;
+        }
+        return any & 1;
+    }
+
     __device__ __forceinline__ bool solve64(bool from_user) {
         phase_init64(from_user);
-        int any = sync(R_INIT);
+        int any = after_init(sync(R_INIT), true);
         if (any < 0) return false;
         int iter = 0;
         for (;;) {
@@ -1769,7 +1806,7 @@ struct Runner {
 
     __device__ __forceinline__ bool solve_bicg(bool from_user) {
         phase_init64(from_user);
-        int any = sync(R_INIT);
+        int any = after_init(sync(R_INIT), true);
         if (any < 0) return false;
         int par = 0;
         for (;;) {
@@ -1795,6 +1832,14 @@ struct Runner {
         phase_out(true, from_user);
         int any = sync(R_OUT0);
         if (any < 0) return false;
+        if (any & 2) {
+            // cold starts: p = 0, then every unfinished slice's residual again
+            phase_cold(false);
+            if (sync(R_NONE) < 0) return false;
+            phase_out(false, false);
+            any = sync(R_OUT);
+            if (any < 0) return false;
+        }
         int iter = 0;
         while (any > 0) {
             phase_cast();
@@ -1929,10 +1974,11 @@ k_persistent(const KParams *__restrict__ Pp) {
     }
 }
 
-__global__ void k_reset_sync(SyncWords *s) {
-    unsigned *w = reinterpret_cast<unsigned *>(s);
-    const long n = sizeof(SyncWords) / sizeof(unsigned);
-    for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) w[x] = 0u;
+// zero n 32-bit words (a kernel rather than a memset node, so that the
+// launch sequence stays valid under stream capture)
+__global__ void k_zero_words(unsigned *w, long long n) {
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x)
+        w[x] = 0u;
 }
 
 // Restriction (coarse output element) or prolongation (fine output element)
@@ -2075,9 +2121,17 @@ hipError_t max_coresident_workgroups(int device, int *out) {
     return hipSuccess;
 }
 
-hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream) {
-    hipLaunchKernelGGL(k_reset_sync, dim3(64), dim3(256), 0, stream, s);
+hipError_t launch_zero_words(void *p, long long nwords, hipStream_t stream) {
+    if (nwords <= 0) return hipSuccess;
+    long long blocks = (nwords + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, stream, reinterpret_cast<unsigned *>(p),
+                       nwords);
     return hipGetLastError();
+}
+
+hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream) {
+    return launch_zero_words(s, (long long)(sizeof(SyncWords) / sizeof(unsigned)), stream);
 }
 
 hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream) {

@@ -12,8 +12,11 @@ A batch adds a leading dimension B.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -81,7 +84,7 @@ def lib():
         L.nsp_destroy.argtypes = [P]
         L.nsp_last_error.argtypes = [P]
         L.nsp_last_error.restype = ctypes.c_char_p
-        L.nsp_set_lid.argtypes = [P, P]
+        L.nsp_set_lid.argtypes = [P, P, P]
         L.nsp_poisson_solve.argtypes = [P, P, P, I, ctypes.POINTER(_Opts), P, P]
         L.nsp_fine_step.argtypes = [P, _State, I, D, D, D, ctypes.POINTER(_Opts), P, P]
         L.nsp_coarse_step.argtypes = [P, _State, I, D, D, D, ctypes.POINTER(_Opts), P, P]
@@ -156,6 +159,24 @@ def _check(t, shape, name):
     return t.data_ptr()
 
 
+# Handles still open when the interpreter exits are destroyed by an atexit
+# hook, while the HIP runtime (and any profiler attached to it) is still up;
+# a handle reached only by garbage collection during interpreter teardown is
+# left to the process exit instead of calling into HIP from a finalizer.
+_live_handles = weakref.WeakSet()
+
+
+def _close_live_handles():
+    for h in list(_live_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_live_handles)
+
+
 class Handle:
     """One grid (nsp_create / nsp_destroy)."""
 
@@ -180,6 +201,7 @@ class Handle:
         if st != NSP_OK:
             raise NSPError(st, "nsp_create failed (sizes, max_batch <= 64, connected fluid region)")
         self._h = h
+        _live_handles.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -187,6 +209,8 @@ class Handle:
             self._h = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -223,7 +247,7 @@ class Handle:
 
     def set_lid(self, lid):
         _check(lid, (self.nz, self.nx + 1), "lid")
-        self._err(lib().nsp_set_lid(self._h, ctypes.c_void_p(lid.data_ptr())), "nsp_set_lid")
+        self._err(lib().nsp_set_lid(self._h, ctypes.c_void_p(lid.data_ptr()), _stream_ptr()), "nsp_set_lid")
 
     def poisson_solve(self, b, p, opts=None, check=True):
         """Solve A p = b in place on p (batch = leading dimension)."""
@@ -267,8 +291,10 @@ class Handle:
                                       int(nslices), float(t0), float(T), float(DT), ctypes.byref(o), _stream_ptr())
         self._err(st, "nsp_parareal_start")
 
-    def parareal_iterate(self, Y, Fk, Gk, nslices, k, t0, T, dt, DT, fine=None, coarse=None):
-        """Iteration k of Eq. (6); returns (velocity jump, pressure jump)."""
+    def parareal_iterate(self, Y, Fk, Gk, nslices, k, t0, T, dt, DT, fine=None, coarse=None, check=True):
+        """Iteration k of Eq. (6); returns (velocity jump, pressure jump).  With
+        check=False a solve that hit its limit (NSP_ERR_NOT_CONVERGED) does not
+        raise; the jumps are returned and self.last_status holds the status."""
         fine = fine or PoissonOpts()
         coarse = coarse or PoissonOpts()
         of, oc = fine.c(), coarse.c()
@@ -277,7 +303,9 @@ class Handle:
                                         self._state(Gk, nslices, "Gk"), int(nslices), int(k), float(t0), float(T),
                                         float(dt), float(DT), ctypes.byref(of), ctypes.byref(oc), _stream_ptr(),
                                         jump)
-        self._err(st, "nsp_parareal_iterate")
+        self.last_status = st
+        if check or st != NSP_ERR_NOT_CONVERGED:
+            self._err(st, "nsp_parareal_iterate")
         return float(jump[0]), float(jump[1])
 
     def restrict(self, hc, yf, yc):

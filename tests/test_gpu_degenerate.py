@@ -84,3 +84,37 @@ def test_degenerate_grid_parity(gpu, oracle, shape, periodic, hole, prec):
         assert s == 0
         assert _close([N(a)[i] for a in y[:3]], ref[:3], 1e-10 if prec == 0 else 1e-8), i
     h.close()
+
+
+@pytest.mark.parametrize("prec,solver", [(0, 0), (1, 0), (0, 1)])
+def test_cold_start_on_rounding_level_rhs(gpu, oracle, prec, solver):
+    """A warm start worse than none is dropped (p = 0) before the solve, as in
+    the oracle.  A 1 x 1 x 4 column periodic in z is uniform along z after one
+    step, so every later right-hand side is rounding noise while the
+    warm-started pressure is not; and a Poisson solve with b ~ 1e-13 from a
+    warm start of order 30 on a periodic 6^3 box.  Both converge, as the
+    oracle does, and match it."""
+    _say("cold start, prec", prec, "solver", solver)
+    opts = gpu.PoissonOpts(rtol=1e-10, prec=prec, solver=solver)
+    g = oracle.Grid(1, 1, 4, lx=0.25, ly=0.25, re=100.0, periodic_z=True)
+    st = _state((1, 1, 4), True, 3)
+    h = gpu.Handle(1, 1, 4, lx=0.25, ly=0.25, re=100.0, periodic_z=True, max_batch=1)
+    y = tuple(T(a[None]) for a in st)
+    info = h.fine_step(y, 0.0, 0.004, 1e-3, opts)
+    ref, _, _, s = oracle.fine_steps(g, st, 4, 1e-3, prec=prec, solver=solver, rtol=1e-10)
+    assert s == 0 and info[0]["status"] == 0
+    assert _close([N(a)[0] for a in y[:3]], ref[:3], 1e-10 if prec == 0 else 1e-8)
+    h.close()
+    g6 = oracle.Grid(6, 6, 6, periodic_z=True)
+    rng = np.random.default_rng(21)
+    b = rng.standard_normal((6, 6, 6)) * 1e-13
+    b -= b.mean()
+    x0 = rng.standard_normal((6, 6, 6)) * 30.0
+    solve = oracle.bicgstab if solver == 1 else (oracle.pcg_mixed if prec == 1 else oracle.pcg)
+    ref, oinfo = solve(g6, b, x0=x0, rtol=1e-10)
+    h6 = gpu.Handle(6, 6, 6, periodic_z=True, max_batch=1)
+    pt = T(x0[None])
+    info = h6.poisson_solve(T(b[None]), pt, opts)
+    assert oinfo["status"] == 0 and info[0]["status"] == 0
+    assert _close([N(pt)[0]], [ref], 1e-8)
+    h6.close()

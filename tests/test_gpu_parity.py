@@ -314,6 +314,32 @@ def test_parareal_matches_oracle_iterates(gpu, oracle):
     h.close()
 
 
+def test_parareal_reports_a_solve_at_its_limit(gpu):
+    """A fine solve capped at one CG iteration: the Parareal iteration still
+    completes (Eq. (6) takes the solve's best iterate, the jumps are written)
+    and reports NSP_ERR_NOT_CONVERGED instead of NSP_OK."""
+    _say("parareal with maxit = 1")
+    n, N_s = 16, 2
+    h = gpu.Handle(n, n, n, re=100.0, max_batch=N_s)
+    y0 = h.zeros_state(1)
+    Y = tuple(t.repeat((N_s + 1,) + (1,) * (t.dim() - 1)).contiguous() for t in y0)
+    Fk = h.zeros_state(N_s)
+    Gk = h.zeros_state(N_s)
+    good = gpu.PoissonOpts(rtol=1e-10)
+    h.parareal_start(Y, Gk, N_s, 0.0, 0.004, 2e-3, good)
+    capped = gpu.PoissonOpts(rtol=1e-10, maxit=1)
+    with pytest.raises(gpu.NSPError) as e:
+        h.parareal_iterate(Y, Fk, Gk, N_s, 0, 0.0, 0.004, 1e-3, 2e-3, capped, good)
+    assert e.value.status == gpu.NSP_ERR_NOT_CONVERGED
+    jv, jp = h.parareal_iterate(Y, Fk, Gk, N_s, 0, 0.0, 0.004, 1e-3, 2e-3, capped, good, check=False)
+    assert h.last_status == gpu.NSP_ERR_NOT_CONVERGED
+    assert np.isfinite(jv) and jv > 0.0 and np.isfinite(jp)
+    # the coarse propagator at its limit is reported the same way
+    jv, jp = h.parareal_iterate(Y, Fk, Gk, N_s, 0, 0.0, 0.004, 1e-3, 2e-3, good, capped, check=False)
+    assert h.last_status == gpu.NSP_ERR_NOT_CONVERGED and np.isfinite(jv)
+    h.close()
+
+
 def test_error_paths(gpu):
     _say("error paths")
     n = 8
