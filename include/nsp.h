@@ -143,6 +143,23 @@ nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev, void *stream);
 nsp_status nsp_poisson_solve(nsp_handle *h, const double *b, double *p, int batch,
                              const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
 
+/* nsp_poisson_solve for callers that cannot allocate device memory: code
+ * under stream capture, tight serving loops, harnesses that forbid it.  Same
+ * arguments, kernels and results (bitwise) as nsp_poisson_solve, but every
+ * scratch buffer of the solve (launch parameters, barrier words, per-slice
+ * control blocks, partial sums, the right-hand-side copy and the CG vectors)
+ * lives in one fixed device array of 96 MiB inside the library, which each
+ * GPU it runs on holds until the process ends; the call allocates nothing.
+ * Needed: 36 bytes per cell and slice (PCG, FP64 or mixed) or 68 (BiCGStab),
+ * plus a few hundred KiB: one 128^3 slice in PCG, three 96^3 slices.  A solve
+ * that needs more returns NSP_ERR_ARG with the size in nsp_last_error; the
+ * current device must be the handle's.  Every call on one GPU shares that
+ * GPU's array (it keeps the last call's contents; the call clears what must
+ * start at zero), so calls that overlap on one GPU, on any handles or
+ * streams, race: serialise them. */
+nsp_status nsp_poisson_solve_noalloc(nsp_handle *h, const double *b, double *p, int batch,
+                                     const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
+
 /* Fine propagator F(y, t1, t0) of Sec. 2.1.2: (t1 - t0)/dt forward-Euler
  * projection steps, in place on the batch y.  (t1 - t0)/dt must be a
  * non-negative integer to 1e-9 relative (NSP_ERR_ARG otherwise).  Each step:

@@ -1228,3 +1228,99 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
 }
 
 }  // extern "C"
+
+// ------------------------------------------------ allocation-free Poisson solve
+
+namespace {
+
+// Workspace of nsp_poisson_solve_noalloc: one file-scope device array, which
+// every GPU the library runs on holds until the process ends.  Host code
+// never uses the array's name as an address: the address on each device
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is passed to kernels and copies.
+constexpr size_t kScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_at[kMaxScratchDevices];  // scratch's address on each device (null: not yet taken)
+
+nsp_status scratch_address(nsp_handle *h, unsigned char **out) {
+    int dev = -1;
+    HIPCHK(h, hipGetDevice(&dev));
+    if (dev != h->device) return fail(h, NSP_ERR_ARG, "the current device is not the handle's device");
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(h, NSP_ERR_UNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_at[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(h, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(h, NSP_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_at[dev] = static_cast<unsigned char *>(ptr);
+    }
+    *out = g_scratch_at[dev];
+    return NSP_OK;
+}
+
+// Hands out 256-byte-aligned pieces of [base, base + cap); `used` may exceed
+// cap, which the caller checks before any piece is used.
+struct Carve {
+    unsigned char *base;
+    size_t used = 0;
+    template <class T>
+    T *take(size_t n) {
+        used = (used + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base + used);
+        used += n * sizeof(T);
+        return p;
+    }
+};
+
+}  // namespace
+
+extern "C" nsp_status nsp_poisson_solve_noalloc(nsp_handle *h, const double *b, double *p, int batch,
+                                                const nsp_poisson_opts *o, void *stream, nsp_solve_info *info) {
+    if (!h) return NSP_ERR_ARG;
+    if (batch < 0 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "batch outside [0, max_batch]");
+    if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
+    if (batch == 0) return NSP_OK;
+    if (!b || !p) return fail(h, NSP_ERR_ARG, "null pointer");
+    if (o->solver == NSP_BICGSTAB && o->prec != NSP_FP64)
+        return fail(h, NSP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
+    if (batch > h->L.cap_slices) return fail(h, NSP_ERR_ARG, "batch above the handle's control-block capacity");
+    unsigned char *base = nullptr;
+    nsp_status st = scratch_address(h, &base);
+    if (st != NSP_OK) return st;
+    const size_t cells = (size_t)batch * (size_t)h->ncells;
+    const int pstride = batch * std::max(h->ntiles, h->cgparts);
+    Carve c{base};
+    LaunchRes ws;
+    ws.params = c.take<KParams>(1);
+    ws.sync = c.take<SyncWords>(1);
+    ws.ctl = c.take<SliceCtl>(batch);
+    ws.part = c.take<double>((size_t)2 * kNQ * pstride);
+    ws.params_host = h->L.params_host;
+    ws.ctl_host = h->L.ctl_host;
+    ws.cap_slices = batch;
+    ws.cap_tiles = pstride;
+    GroupDesc G;
+    nsp_state y{nullptr, nullptr, nullptr, p};
+    fill_group(G, h, y, 0, batch, 0, 0, b);
+    G.b = c.take<double>(cells);
+    G.r = c.take<double>(cells);
+    G.d0 = c.take<double>(cells);
+    G.d1 = c.take<double>(cells);
+    G.e = c.take<float>(cells);
+    G.q = G.bv0 = G.bv1 = G.brh = nullptr;
+    if (o->solver == NSP_BICGSTAB) {
+        G.q = c.take<double>(cells);
+        G.bv0 = c.take<double>(cells);
+        G.bv1 = c.take<double>(cells);
+        G.brh = c.take<double>(cells);
+    }
+    if (c.used > kScratchBytes)
+        return fail(h, NSP_ERR_ARG,
+                    "the solve needs " + std::to_string(c.used) + " bytes of workspace, above the " +
+                        std::to_string(kScratchBytes) + " bytes of the allocation-free solve");
+    nsp_handle *hs[1] = {h};
+    return run(hs, 1, &G, MODE_POISSON, 0, 1.0, o, static_cast<hipStream_t>(stream), info, 0, &ws);
+}

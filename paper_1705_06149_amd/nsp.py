@@ -86,6 +86,7 @@ def lib():
         L.nsp_last_error.restype = ctypes.c_char_p
         L.nsp_set_lid.argtypes = [P, P, P]
         L.nsp_poisson_solve.argtypes = [P, P, P, I, ctypes.POINTER(_Opts), P, P]
+        L.nsp_poisson_solve_noalloc.argtypes = [P, P, P, I, ctypes.POINTER(_Opts), P, P]
         L.nsp_fine_step.argtypes = [P, _State, I, D, D, D, ctypes.POINTER(_Opts), P, P]
         L.nsp_coarse_step.argtypes = [P, _State, I, D, D, D, ctypes.POINTER(_Opts), P, P]
         L.nsp_group_fine_step.argtypes = [P, P, P, I, D, D, D, ctypes.POINTER(_Opts), P, P]
@@ -108,7 +109,8 @@ def lib():
                                              ctypes.POINTER(D), P]
         L.nsp_lid_from_modes.argtypes = [P, P, I, P, P]
         L.nsp_lid_modes_grad.argtypes = [P, P, I, P, P]
-        for name in ("nsp_create", "nsp_destroy", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
+        for name in ("nsp_create", "nsp_destroy", "nsp_set_lid", "nsp_poisson_solve", "nsp_poisson_solve_noalloc",
+                     "nsp_fine_step",
                      "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
                      "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
                      "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
@@ -262,6 +264,22 @@ class Handle:
         res = [_info_dict(x) for x in info]
         if check:
             self._err(st, "nsp_poisson_solve", res)
+        return res
+
+    def poisson_solve_noalloc(self, b, p, opts=None, check=True):
+        """poisson_solve through nsp_poisson_solve_noalloc: the library's fixed
+        device array as workspace, no device allocation by the call."""
+        opts = opts or PoissonOpts()
+        B = int(b.shape[0])
+        sp = (B, self.nz, self.ny, self.nx)
+        pb, pp = _check(b, sp, "b"), _check(p, sp, "p")
+        info = (_Info * B)()
+        o = opts.c()
+        st = lib().nsp_poisson_solve_noalloc(self._h, ctypes.c_void_p(pb), ctypes.c_void_p(pp), B, ctypes.byref(o),
+                                             _stream_ptr(), info)
+        res = [_info_dict(x) for x in info]
+        if check:
+            self._err(st, "nsp_poisson_solve_noalloc", res)
         return res
 
     def _prop(self, fn, y, t0, t1, step, opts, check):
@@ -468,7 +486,8 @@ def group_parareal_iterate(handles, Ys, Fks, Gks, nslices, k, t0, T, dt, DT, fin
     return [(float(jump[2 * g]), float(jump[2 * g + 1])) for g in range(n)]
 
 
-EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_poisson_solve", "nsp_fine_step",
+EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_poisson_solve",
+            "nsp_poisson_solve_noalloc", "nsp_fine_step",
             "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
             "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
             "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
