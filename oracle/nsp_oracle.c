@@ -465,6 +465,84 @@ int og_pcg(const og_grid *g, const double *b, double *x, double rtol, int maxit,
     return status;
 }
 
+/* ------------------------------- single-reduction Jacobi-PCG (a3) */
+
+/* The same Krylov method as og_pcg with its two inner-product stages merged
+ * into one (Chronopoulos & Gear 1989).  Besides x and r it carries
+ * u = M^-1 r, w = A u, the search direction p and s = A p:
+ *   start:  u = M^-1 r,  w = A u,  gamma = <r,u>,  delta = <w,u>
+ *   step:   beta  = gamma / gamma_prev            (0 on the first step)
+ *           alpha = gamma / (delta - beta gamma / alpha_prev)
+ *                                                  (gamma / delta first)
+ *           p = u + beta p,   s = w + beta s
+ *           x = x + alpha p,  r = r - alpha s
+ *           u = M^-1 r,  w = A u,  then gamma, delta and ||r||^2 together
+ * The denominator is <p, A p>: expand p = u + beta p_prev, use that p_prev
+ * is A-conjugate to p, and that s_prev = (r_prev - r)/alpha_prev with
+ * <u, r_prev> = 0.  Stopping, true residual, restart and cold start as in
+ * og_pcg. */
+int og_pcg_sr(const og_grid *g, const double *b, double *x, double rtol, int maxit, og_info *info) {
+    size_t n = ncells(g);
+    double *r = malloc(n * sizeof(double)), *u = malloc(n * sizeof(double));
+    double *w = malloc(n * sizeof(double)), *p = malloc(n * sizeof(double));
+    double *sv = malloc(n * sizeof(double)), *dg = malloc(n * sizeof(double));
+    diag_A(g, dg);
+    memset(info, 0, sizeof(*info));
+    double bnorm = sqrt(dot(g, b, b));
+    if (bnorm == 0.0) {
+        for (size_t i = 0; i < n; ++i) x[i] = 0.0;
+        free(r); free(u); free(w); free(p); free(sv); free(dg);
+        return 0;
+    }
+    int it = 0, status = 0, restarts = 0;
+    double rel_true = 0.0;
+    cold_start_if_worse(g, b, x, w);
+    for (;;) {
+        og_apply_A(g, x, w);
+        for (size_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
+        for (size_t i = 0; i < n; ++i) u[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0;
+        og_apply_A(g, u, w);
+        double gamma = dot(g, r, u), delta = dot(g, w, u);
+        double rnorm = sqrt(dot(g, r, r));
+        double gamma_prev = 0.0, alpha = 0.0;
+        int first = 1;
+        for (;;) {
+            if (!isfinite(rnorm)) { status = 3; break; }
+            if (rnorm <= rtol * bnorm) break;
+            if (it >= maxit) { status = 2; break; }
+            double beta = first ? 0.0 : gamma / gamma_prev;
+            alpha = first ? gamma / delta : gamma / (delta - beta * gamma / alpha);
+            for (size_t i = 0; i < n; ++i) {
+                p[i] = first ? u[i] : u[i] + beta * p[i];
+                sv[i] = first ? w[i] : w[i] + beta * sv[i];
+            }
+            for (size_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+            for (size_t i = 0; i < n; ++i) r[i] -= alpha * sv[i];
+            for (size_t i = 0; i < n; ++i) u[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0;
+            og_apply_A(g, u, w);
+            gamma_prev = gamma;
+            gamma = dot(g, r, u);
+            delta = dot(g, w, u);
+            rnorm = sqrt(dot(g, r, r));
+            first = 0;
+            ++it;
+        }
+        og_apply_A(g, x, w);
+        for (size_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
+        rel_true = sqrt(dot(g, r, r)) / bnorm;
+        if (status != 0 || !isfinite(rel_true) || rel_true <= 2.0 * rtol || it >= maxit) break;
+        ++restarts;
+    }
+    if (status == 0 && !isfinite(rel_true)) status = 3;
+    subtract_mean(g, x);
+    info->iters = it;
+    info->outer = restarts;
+    info->status = status;
+    info->rel_res_true = rel_true;
+    free(r); free(u); free(w); free(p); free(sv); free(dg);
+    return status;
+}
+
 /* ---------------------------------------------- BiCGStab (Sec. 2) */
 
 /* The paper solves the pressure equation with BiCGStab (van der Vorst 1992).
@@ -697,7 +775,7 @@ int og_fine_steps(const og_grid *g, double *u, double *v, double *w, double *p, 
 }
 
 /* as og_fine_steps; solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed), 1: FP64
- * Jacobi-BiCGStab (prec ignored) */
+ * Jacobi-BiCGStab (prec ignored), 2: single-reduction Jacobi-PCG (FP64) */
 int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
                          int prec, int solver, double rtol, int maxit, double eta, int max_outer, int *iters,
                          double *rel_true) {
@@ -710,9 +788,10 @@ int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, doub
         og_momentum(g, u, v, w, dt, Fu, Fv, Fw);
         og_rhs(g, Fu, Fv, Fw, dt, b);
         og_info info;
-        int st = solver == 1 ? og_bicgstab(g, b, p, rtol, maxit, &info)
-                 : prec == 0 ? og_pcg(g, b, p, rtol, maxit, &info)
-                             : og_pcg_mixed(g, b, p, rtol, eta, maxit, max_outer, &info);
+        int st = solver == 1               ? og_bicgstab(g, b, p, rtol, maxit, &info)
+                 : solver == 2 && prec == 0 ? og_pcg_sr(g, b, p, rtol, maxit, &info)
+                 : prec == 0                ? og_pcg(g, b, p, rtol, maxit, &info)
+                                            : og_pcg_mixed(g, b, p, rtol, eta, maxit, max_outer, &info);
         if (st > worst) worst = st;
         if (iters) iters[s] = info.iters;
         if (rel_true) rel_true[s] = info.rel_res_true;

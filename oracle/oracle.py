@@ -77,6 +77,8 @@ def lib():
         _lib.og_fine_steps_solver.restype = I
         _lib.og_bicgstab.argtypes = [G, P, P, D, I, ctypes.POINTER(_Info)]
         _lib.og_bicgstab.restype = I
+        _lib.og_pcg_sr.argtypes = [G, P, P, D, I, ctypes.POINTER(_Info)]
+        _lib.og_pcg_sr.restype = I
         _lib.og_momentum_adjoint.argtypes = [G, P, P, P, D, P, P, P, P, P, P, P]
         _lib.og_stencil_form_value.argtypes = [G, I, P, I, I, I, I, I]
         _lib.og_stencil_form_value.restype = D
@@ -214,6 +216,19 @@ def bicgstab(g: Grid, b, x0=None, rtol=1e-10, maxit=100000):
     return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
 
 
+def pcg_sr(g: Grid, b, x0=None, rtol=1e-10, maxit=100000):
+    """FP64 Jacobi-PCG with one merged inner-product stage per iteration
+    (Chronopoulos & Gear): the same Krylov iterates as pcg in exact
+    arithmetic."""
+    sp = g.shapes()[3]
+    b = _chk(b, sp)
+    x = np.zeros(sp) if x0 is None else _chk(x0, sp).copy()
+    info = _Info()
+    gc = g.c()
+    lib().og_pcg_sr(ctypes.byref(gc), _p(b), _p(x), float(rtol), int(maxit), ctypes.byref(info))
+    return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
+
+
 def pcg_mixed(g: Grid, b, x0=None, rtol=1e-10, eta=1e-5, maxit=100000, max_outer=8):
     sp = g.shapes()[3]
     b = _chk(b, sp)
@@ -236,7 +251,8 @@ def correct(g: Grid, Fu, Fv, Fw, p, dt):
 
 def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta=1e-5, max_outer=8, solver=0):
     """nsteps projection steps of size dt; returns (new state, iters, rel_true, status).
-    solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed); 1: FP64 Jacobi-BiCGStab.
+    solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed); 1: FP64 Jacobi-BiCGStab;
+    2: single-reduction Jacobi-PCG (FP64).
 
     The input state tuple (u, v, w, p) is not modified."""
     su, sv, sw, sp = g.shapes()
