@@ -48,6 +48,31 @@ PEAK_HBM_GBS = 8000.0
 # cell flags; face arrays counted as one entry per cell and component).
 BYTES_CG_ITER = {"fp64": 66.0, "mixed": 34.0}   # one CG iteration
 BYTES_BICG_ITER = 139.0  # one BiCGStab iteration (FP64): phases of 49, 25 and 65 B
+BYTES_SR_ITER = 81.0     # one single-reduction CG iteration (FP64): reads r, w, s, p, x, flags; writes r, w, s, p, x
+BYTES_SR_START = 17.0    # the start of a single-reduction run: w = A M^-1 r (reads r, flags; writes w)
+# The byte model of the method itself (not of this kernel's phase layout):
+# per fine step 112 B per cell for momentum + right-hand side + correction,
+# and 80 B per cell per FP64 CG iteration (read r, d, write d, q; read x, d,
+# r, q, write x, r).
+MODEL_STEP_FIXED, MODEL_CG_ITER = 112.0, 80.0
+
+
+def _solver(args):
+    from paper_1705_06149_amd import nsp
+    return {"pcg": nsp.PCG, "bicgstab": nsp.BICGSTAB, "pcg_sr": nsp.PCG_SR}[args.solver]
+
+
+def _solver_name(args):
+    return {"pcg": "Jacobi-PCG", "bicgstab": "Jacobi-BiCGStab",
+            "pcg_sr": "Jacobi-PCG, single reduction"}[args.solver]
+
+
+def _bytes_per_iter(args):
+    if args.solver == "bicgstab":
+        return BYTES_BICG_ITER
+    if args.solver == "pcg_sr":
+        return BYTES_SR_ITER
+    return BYTES_CG_ITER[args.precision]
 BYTES_STEP_FIXED = {"fp64": 212.0, "mixed": 212.0}  # momentum, rhs, init/true, correction, gauge
 BYTES_MIXED_SWEEP = 65.0  # mixed: one FP64 residual + cast + update sweep
 
@@ -111,8 +136,8 @@ def bench_fine(args):
 
     n, re_, dt = 128, 1000.0, 5e-4
     prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
-    solver = nsp.BICGSTAB if args.solver == "bicgstab" else nsp.PCG
-    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=args.eta, max_outer=8, solver=solver)
+    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=args.eta, max_outer=8,
+                           solver=_solver(args))
     h = nsp.Handle(n, n, n, re=re_, max_batch=1, solid=_fine_solid(args), slip_obstacles=args.slip)
     y = h.zeros_state(1)
     t = 0.0
@@ -143,13 +168,16 @@ def bench_fine(args):
         h.fine_step(y64, t - K * dt, t, dt, o64)
         err_vs_fp64 = float(torch.sqrt(sum(((y[c] - y64[c]) ** 2).sum() for c in range(3)) /
                                        sum((y64[c] ** 2).sum() for c in range(3))))
-    per_iter = BYTES_BICG_ITER if args.solver == "bicgstab" else BYTES_CG_ITER[args.precision]
-    per_launch_bytes = cells * (BYTES_STEP_FIXED[args.precision] + per_iter * iters / K)
+    per_iter = _bytes_per_iter(args)
+    fixed = BYTES_STEP_FIXED[args.precision] + (BYTES_SR_START if args.solver == "pcg_sr" else 0.0)
+    per_launch_bytes = cells * (fixed + per_iter * iters / K)
     if args.precision == "mixed":
         per_launch_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     achieved = per_launch_bytes / avg_launch_s / 1e9
-    sfx = "_bicgstab" if args.solver == "bicgstab" else ""
+    # the method's own byte model (FP64 CG), independent of the kernel layout
+    model_bytes = cells * (MODEL_STEP_FIXED + MODEL_CG_ITER * iters / K)
+    sfx = "" if args.solver == "pcg" else "_" + args.solver
     traffic = (_traffic_from_profile("k_persistent_cavity128_%s%s_pmc.txt" % (args.precision, sfx))
                if not args.obstacles else None)
     out = {
@@ -167,7 +195,7 @@ def bench_fine(args):
         "data": "synthetic",
         "config": {"workload": _fine_workload(args), "grid": [n, n, n], "re": re_, "dt": dt,
                    "start": "rest, after %d warm-up steps" % args.warmup,
-                   "poisson": ("Jacobi-BiCGStab" if args.solver == "bicgstab" else "Jacobi-PCG") + " rtol 1e-10",
+                   "poisson": _solver_name(args) + " rtol 1e-10",
                    "precision": args.precision},
         "cg_iters_per_step": iters / K,
         "inner_rtol": args.eta if args.precision == "mixed" else None,
@@ -176,7 +204,9 @@ def bench_fine(args):
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_persistent (one fused fine step per launch)",
                      "avg_launch_ms": 1e3 * avg_launch_s,
-                     "algorithmic_bytes_per_launch": per_launch_bytes},
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "model_bytes_per_launch": model_bytes,
+                     "model_frac": model_bytes / avg_launch_s / 1e9 / PEAK_HBM_GBS},
     }
     out["hbm_measured_GB_per_s"] = traffic / avg_launch_s / 1e9 if traffic else None
     h.close()
@@ -213,8 +243,7 @@ def bench_poisson(args):
     g = torch.Generator(device="cuda").manual_seed(0)
     b = torch.randn((B, n, n, n), dtype=torch.float64, device="cuda", generator=g)
     p = torch.zeros_like(b)
-    solver = nsp.BICGSTAB if args.solver == "bicgstab" else nsp.PCG
-    opts = nsp.PoissonOpts(rtol=0.0, maxit=its, prec=prec, inner_rtol=1e-30, max_outer=1, solver=solver)
+    opts = nsp.PoissonOpts(rtol=0.0, maxit=its, prec=prec, inner_rtol=1e-30, max_outer=1, solver=_solver(args))
     for _ in range(args.warmup):
         p.zero_()
         h.poisson_solve(b, p, opts, check=False)
@@ -228,7 +257,7 @@ def bench_poisson(args):
     _sync()
     wall = time.perf_counter() - t0
     cells = B * n ** 3
-    per_launch = cells * (BYTES_BICG_ITER if args.solver == "bicgstab" else BYTES_CG_ITER[args.precision]) * its
+    per_launch = cells * _bytes_per_iter(args) * its
     if args.precision == "mixed":
         per_launch += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
     achieved = per_launch / (np.mean(ms) * 1e-3) / 1e9
@@ -242,7 +271,7 @@ def bench_poisson(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": _traffic_from_profile("k_persistent_poisson32x128_%s%s_pmc.txt" % (
-                         args.precision, "_bicgstab" if args.solver == "bicgstab" else "")),
+                         args.precision, "" if args.solver == "pcg" else "_" + args.solver)),
                      "kernel": "k_persistent (%d CG iterations on %d grids per launch)" % (its, B),
                      "avg_launch_ms": float(np.mean(ms)), "algorithmic_bytes_per_launch": per_launch},
     }
@@ -675,8 +704,9 @@ def main():
     ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "sim2", "adjoint", "copy"],
                     default="fine")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--solver", choices=["pcg", "bicgstab"], default="pcg",
-                    help="pressure solver: Jacobi-PCG, or the paper's BiCGStab (FP64)")
+    ap.add_argument("--solver", choices=["pcg", "bicgstab", "pcg_sr"], default="pcg",
+                    help="pressure solver: Jacobi-PCG, the paper's BiCGStab (FP64), or Jacobi-PCG with one "
+                         "merged reduction per iteration (FP64)")
     ap.add_argument("--max-iters", type=int, default=32)
     ap.add_argument("--slices", type=int, default=16, help="sim1/sim2 modes: time slices")
     ap.add_argument("--sim-t", type=float, default=None,

@@ -53,7 +53,10 @@ typedef enum {
 
 typedef enum {
     NSP_PCG = 0,      /* Jacobi-preconditioned CG (A is symmetric positive semi-definite) */
-    NSP_BICGSTAB = 1  /* Jacobi-preconditioned BiCGStab, the paper's solver (Sec. 2); FP64 only */
+    NSP_BICGSTAB = 1, /* Jacobi-preconditioned BiCGStab, the paper's solver (Sec. 2); FP64 only */
+    NSP_PCG_SR = 2    /* the same CG with its inner products merged into one stage per iteration
+                         (Chronopoulos & Gear): one grid-wide reduction per iteration instead of
+                         two, at 81 instead of 66 bytes per cell; FP64 only */
 } nsp_solver;
 
 typedef struct nsp_handle nsp_handle;
@@ -93,7 +96,12 @@ typedef struct {
  * NSP_ERR_UNSUPPORTED): right-preconditioned BiCGStab from the same warm
  * start, restarted from the true residual after a breakdown (at most 16
  * times); its workspace (three vectors per slice) is allocated on first use.
- * `iters` then counts BiCGStab iterations (two products with A each). */
+ * `iters` then counts BiCGStab iterations (two products with A each).
+ * solver NSP_PCG_SR (FP64 only, else NSP_ERR_UNSUPPORTED): the iterates of
+ * NSP_PCG in exact arithmetic, computed with one grid barrier per iteration
+ * (the faster choice when a launch is latency-bound, e.g. one slice of up to
+ * 128^3 cells); the same workspace as BiCGStab.  Results differ from
+ * NSP_PCG's at the solver tolerance, never bit for bit. */
 typedef struct {
     double rtol;
     int maxit;
@@ -150,7 +158,8 @@ nsp_status nsp_poisson_solve(nsp_handle *h, const double *b, double *p, int batc
  * control blocks, partial sums, the right-hand-side copy and the CG vectors)
  * lives in one fixed device array of 96 MiB inside the library, which each
  * GPU it runs on holds until the process ends; the call allocates nothing.
- * Needed: 36 bytes per cell and slice (PCG, FP64 or mixed) or 68 (BiCGStab),
+ * Needed: 36 bytes per cell and slice (PCG, FP64 or mixed) or 68 (BiCGStab,
+ * single-reduction PCG),
  * plus a few hundred KiB: one 128^3 slice in PCG, three 96^3 slices.  A solve
  * that needs more returns NSP_ERR_ARG with the size in nsp_last_error; the
  * current device must be the handle's.  Every call on one GPU shares that

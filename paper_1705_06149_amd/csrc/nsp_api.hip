@@ -227,7 +227,7 @@ nsp_status ensure_launch_res(nsp_handle *h, int nslices, int ntiles) {
 bool valid_opts(const nsp_poisson_opts *o) {
     return o && o->rtol >= 0 && o->maxit >= 0 && (o->prec == NSP_FP64 || o->prec == NSP_MIXED) &&
            (o->prec == NSP_FP64 || (o->inner_rtol > 0 && o->inner_rtol < 1 && o->max_outer >= 0)) &&
-           (o->solver == NSP_PCG || o->solver == NSP_BICGSTAB);
+           (o->solver == NSP_PCG || o->solver == NSP_BICGSTAB || o->solver == NSP_PCG_SR);
 }
 
 // number of steps (t1 - t0)/dt, which must be a non-negative integer
@@ -394,8 +394,8 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     if (nslices <= 0) return NSP_OK;
     if (nslices > kMaxSlices) return fail(h, NSP_ERR_ARG, "more than 64 slices in one launch");
     if (ngroups > kMaxGroups) return fail(h, NSP_ERR_ARG, "too many grids in one launch");
-    if (o->solver == NSP_BICGSTAB && o->prec != NSP_FP64)
-        return fail(h, NSP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
+    if (o->solver != NSP_PCG && o->prec != NSP_FP64)
+        return fail(h, NSP_ERR_UNSUPPORTED, "BiCGStab and single-reduction PCG run in FP64 only");
     // workgroups from the finest tiling, then the tile depth for that count
     const int units = std::max(ntiles, cgtiles);
     int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, units))
@@ -406,7 +406,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     for (int g = 0; g < ngroups; ++g) lg[g] = groups[g];
     // ws: launch workspace brought in by the caller (every vector pointer of
     // the groups already set); nothing is allocated then
-    if (o->solver == NSP_BICGSTAB && !ws)
+    if (o->solver != NSP_PCG && !ws)
         for (int g = 0; g < ngroups; ++g) {
             nsp_handle *hg = hs[g];
             if (!hg->bv0) {
@@ -1284,8 +1284,8 @@ extern "C" nsp_status nsp_poisson_solve_noalloc(nsp_handle *h, const double *b, 
     if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
     if (batch == 0) return NSP_OK;
     if (!b || !p) return fail(h, NSP_ERR_ARG, "null pointer");
-    if (o->solver == NSP_BICGSTAB && o->prec != NSP_FP64)
-        return fail(h, NSP_ERR_UNSUPPORTED, "BiCGStab runs in FP64 only");
+    if (o->solver != NSP_PCG && o->prec != NSP_FP64)
+        return fail(h, NSP_ERR_UNSUPPORTED, "BiCGStab and single-reduction PCG run in FP64 only");
     if (batch > h->L.cap_slices) return fail(h, NSP_ERR_ARG, "batch above the handle's control-block capacity");
     unsigned char *base = nullptr;
     nsp_status st = scratch_address(h, &base);
@@ -1311,7 +1311,7 @@ extern "C" nsp_status nsp_poisson_solve_noalloc(nsp_handle *h, const double *b, 
     G.d1 = c.take<double>(cells);
     G.e = c.take<float>(cells);
     G.q = G.bv0 = G.bv1 = G.brh = nullptr;
-    if (o->solver == NSP_BICGSTAB) {
+    if (o->solver != NSP_PCG) {
         G.q = c.take<double>(cells);
         G.bv0 = c.take<double>(cells);
         G.bv1 = c.take<double>(cells);

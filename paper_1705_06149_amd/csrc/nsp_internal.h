@@ -63,8 +63,10 @@ struct GroupDesc {
     const float *idiag32;  // [64]
     double *u, *v, *w, *p;         // state, slice 0 (slice stride nu/nv/nw/ncells)
     double *Fu, *Fv, *Fw, *b;      // predictor and right-hand side workspace
-    double *r, *d0, *d1, *q;       // CG vectors (FP32 view in mixed mode); BiCGStab: p in d0/d1, t in q
-    double *bv0, *bv1, *brh;       // BiCGStab: v (two buffers) and the shadow residual
+    double *r, *d0, *d1, *q;       // CG vectors (FP32 view in mixed mode); BiCGStab: p in d0/d1, t in q;
+                                   // single-reduction CG: s in d0/d1, p in q
+    double *bv0, *bv1, *brh;       // BiCGStab: v (two buffers) and the shadow residual; single-reduction
+                                   // CG: w (two buffers) and the second residual buffer
     float *e;                      // FP32 defect correction
     const double *bin;             // Poisson mode: caller's right-hand side
 };
@@ -126,7 +128,7 @@ struct KParams {
     int prec;              // 0 fp64, 1 mixed
     int maxit, max_outer;
     int xcd_remap;         // contiguous tile ranges per XCD
-    int solver;            // 0: Jacobi-PCG, 1: Jacobi-BiCGStab (FP64)
+    int solver;            // 0: Jacobi-PCG, 1: Jacobi-BiCGStab (FP64), 2: single-reduction Jacobi-PCG (FP64)
     int wt;                // CG outputs by write-through (device-scope) stores
     double dt;
     double rtol, eta;

@@ -38,7 +38,8 @@ template <class T>
 __device__ __forceinline__ const GAS T *gp(const T *p) { return (const GAS T *)p; }  // ~seconds: a wait this long means something is broken
 
 enum Red : int {
-    R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32, R_BG1, R_BG2, R_BG3
+    R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32, R_BG1, R_BG2, R_BG3,
+    R_SR0, R_SR
 };
 
 // a * b + c with one rounding.  The library is compiled with
@@ -386,7 +387,7 @@ struct Runner {
         switch (rid) {
         case R_MEANB: case R_A: case R_A32: case R_BG1: return 1;
         case R_B: case R_B32: case R_CAST: case R_BG2: case R_BG3: return 2;
-        case R_TRUE: case R_OUT: return 3;
+        case R_TRUE: case R_OUT: case R_SR0: case R_SR: return 3;
         case R_INIT: case R_OUT0: return 4;
         default: return 0;
         }
@@ -422,7 +423,8 @@ struct Runner {
     __device__ __forceinline__ int reduce_all(int rid, int buf) {
         __shared__ int s_any;
         const int nq = nq_of(rid);
-        const int cg = (rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32 || rid == R_BG1 || rid == R_BG2) ? 1 : 0;
+        const int cg = (rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32 || rid == R_BG1 || rid == R_BG2 ||
+                        rid == R_SR0 || rid == R_SR) ? 1 : 0;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int s = wv; s < P.nslices; s += kWaves) {
             const GAS double *pp = gp(P.part) + (long)(buf * kNQ) * P.pstride + s_pb[2 * s + cg];
@@ -728,6 +730,32 @@ struct Runner {
             if (c.it >= P.maxit) { c.step_status = 2; c.active = 0; return 0; }
             if (S[0] == 0.0 || c.omega == 0.0) { c.active = 0; return 0; }  // breakdown: restart
             c.beta = (S[0] / c.rz) * (c.alpha / c.omega);
+            c.rz = S[0];
+            return 1;
+        }
+        case R_SR0: {
+            // start of a single-reduction CG run: S0 = gamma = <r,u>,
+            // S1 = delta = <w,u>, S2 = ||r||^2; the first step has beta = 0
+            if (!c.active) return 0;
+            c.rz = S[0];
+            c.alpha = S[0] / S[1];
+            c.beta = 0.0;
+            c.first = 1;
+            return 1;
+        }
+        case R_SR: {
+            // after a single-reduction step: S0 = gamma, S1 = delta, S2 = ||r||^2
+            // of the new residual; the next step's beta and alpha
+            if (!c.active) return 0;
+            c.it += 1;
+            c.first = 0;
+            const double rn = sqrt(S[2]);
+            if (!isfinite(rn)) { c.step_status = 3; c.active = 0; return 0; }
+            if (rn <= P.rtol * c.bnorm) { c.active = 0; return 0; }
+            if (c.it >= P.maxit) { c.step_status = 2; c.active = 0; return 0; }
+            const double beta = S[0] / c.rz;
+            c.alpha = S[0] / (S[1] - beta * S[0] / c.alpha);
+            c.beta = beta;
             c.rz = S[0];
             return 1;
         }
@@ -1408,6 +1436,250 @@ struct Runner {
         }
     }
 
+    // --------------------------------------------- single-reduction CG
+    //
+    // Chronopoulos & Gear's CG: one phase and one grid barrier per
+    // iteration.  Besides x and r it carries u = M^-1 r, w = A u, the search
+    // direction p and s = A p.  Iteration i, with alpha and beta from the
+    // last barrier, in one pass over each column tile:
+    //   s = w + beta s_old,  p = u + beta p_old  (beta = 0 on the first step)
+    //   x += alpha p,  r_new = r - alpha s,  u_new = M^-1 r_new,  w_new = A u_new
+    //   partials <r_new, u_new>, <w_new, u_new>, ||r_new||^2
+    // w_new needs u_new at the six neighbours: each thread forms r_new of its
+    // own cell (and of one halo cell) from r, w, s_old and puts u_new into the
+    // LDS plane; z neighbours stay in registers, as in col_A.  r, w and s are
+    // read at neighbours while they are written, so they alternate between
+    // two buffers by iteration parity; p and x are pointwise and stay in
+    // place.  Start of a run (SR_W0): w = A M^-1 r and the same partials.
+    // Bytes per cell and iteration (FP64): reads r, w, s, p, x, flags; writes
+    // r, w, s, p, x: 81 B.
+    enum SrMode : int { SR_W0 = 0, SR_FIRST = 1, SR_NEXT = 2 };
+
+    template <class T>
+    struct SrLoad {
+        uint8_t f, fh;
+        T r, w, s, p, x, rh, wh, sh;
+    };
+
+    template <class T, int MODE, bool WT>
+    __device__ void col_SR(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl, const GAS T *__restrict__ r,
+                           const GAS T *__restrict__ w, const GAS T *__restrict__ sold, GAS T *__restrict__ pv,
+                           GAS T *__restrict__ x, GAS T *__restrict__ rout, GAS T *__restrict__ wout,
+                           GAS T *__restrict__ sout, T alpha, T beta, int y0, int y1, int z0, int z1, int pbase,
+                           int yb) {
+        const int gb = group_index(G) * 64;
+        const long sz = (long)G.nx * G.ny;
+        const int nx = G.nx, nz = G.nz;
+        const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
+        const ColPos<1> P0 = col_pos<1>(G, y0, y1, z0);
+        LAS T *plane = reinterpret_cast<LAS T *>(s_plane);
+        const int pst = (G.cby + 2) * nx;
+        // s_i and r_{i+1} from the loaded r_i, w_i and s_{i-1}
+        auto snew = [&](T wv, T sv) -> T { return MODE == SR_FIRST ? wv : fmaT(beta, sv, wv); };
+        auto rnew = [&](T rv, T wv, T sv) -> T {
+            if (MODE == SR_W0) return rv;
+            return fmaT(-alpha, snew(wv, sv), rv);
+        };
+        auto load = [&](int k, SrLoad<T> &L) {
+            const long o = (long)(k % nz - z0) * sz;
+            const long c0 = P0.c0[0] + o;
+            L.f = fl[c0];
+            L.r = r[c0];
+            if (MODE != SR_W0) {
+                L.w = w[c0];
+                L.x = x[c0];
+                if (MODE == SR_NEXT) {
+                    L.s = sold[c0];
+                    L.p = pv[c0];
+                }
+            }
+            if (P0.halo) {
+                const long h0 = P0.h0 + o;
+                L.fh = fl[h0];
+                L.rh = r[h0];
+                if (MODE != SR_W0) {
+                    L.wh = w[h0];
+                    if (MODE == SR_NEXT) L.sh = sold[h0];
+                }
+            }
+        };
+        SrLoad<T> L0{}, LA{}, LB{};
+        load(z0, L0);
+        load(z0 + 1, LA);
+        load(z0 + 2, LB);
+        // the centre plane's new values: u_new, r_new, s, p, x_new
+        T uc, rc, sc = T(0), pc = T(0), xc = T(0), um;
+        uint8_t fc;
+        auto centre = [&](const SrLoad<T> &L, T &u, T &rn, T &sv, T &pp, T &xn) {
+            rn = rnew(L.r, L.w, L.s);
+            u = rn * idg_of<T>(gb, L.f);
+            if (MODE != SR_W0) {
+                sv = snew(L.w, L.s);
+                const T uo = L.r * idg_of<T>(gb, L.f);
+                pp = MODE == SR_FIRST ? uo : fmaT(beta, L.p, uo);
+                xn = fmaT(alpha, pp, L.x);
+            }
+        };
+        {
+            const long cm = z0 > 0 ? P0.c0[0] - sz : P0.c0[0] + (long)(nz - 1) * sz;
+            const uint8_t fm = fl[cm];
+            const T rm = r[cm];
+            const T wm = MODE != SR_W0 ? w[cm] : T(0), sm = MODE == SR_NEXT ? sold[cm] : T(0);
+            um = rnew(rm, wm, sm) * idg_of<T>(gb, fm);
+            centre(L0, uc, rc, sc, pc, xc);
+            fc = L0.f;
+        }
+        T hc = rnew(L0.rh, L0.wh, L0.sh) * idg_of<T>(gb, L0.fh);
+        double acc[1][3] = {{0.0, 0.0, 0.0}};
+        int buf = 0;
+        auto step = [&](int k, SrLoad<T> &Lk1) {
+            T up, rp, sp = T(0), pp = T(0), xp = T(0);
+            centre(Lk1, up, rp, sp, pp, xp);
+            const uint8_t fp = Lk1.f;
+            const T hn = rnew(Lk1.rh, Lk1.wh, Lk1.sh) * idg_of<T>(gb, Lk1.fh);
+            load(k + 3, Lk1);
+            LAS T *pl = plane + buf * pst;
+            if (P0.act[0]) pl[P0.slot[0]] = uc;
+            if (P0.halo) pl[P0.hslot] = hc;
+            __syncthreads();
+            const int sl = P0.slot[0];
+            const uint8_t f = fc;
+            T q = T(0);
+            q = (f & FL_XM) ? fmaT(uc - pl[sl - 1], hx, q) : q;
+            q = (f & FL_XP) ? fmaT(uc - pl[sl + 1], hx, q) : q;
+            q = (f & FL_YM) ? fmaT(uc - pl[sl - nx], hy, q) : q;
+            q = (f & FL_YP) ? fmaT(uc - pl[sl + nx], hy, q) : q;
+            q = (f & FL_ZM) ? fmaT(uc - um, hz, q) : q;
+            q = (f & FL_ZP) ? fmaT(uc - up, hz, q) : q;
+            const bool live = P0.act[0] && (f & FL_FLUID);
+            if (live) {
+                const long c = P0.c0[0] + (long)(k - z0) * sz;
+                st_out<WT>(&wout[c], q);
+                if (MODE != SR_W0) {
+                    st_out<WT>(&rout[c], rc);
+                    st_out<WT>(&sout[c], sc);
+                    st_out<WT>(&pv[c], pc);
+                    st_out<WT>(&x[c], xc);
+                }
+            }
+            acc[0][0] = live ? fmaT((double)rc, (double)uc, acc[0][0]) : acc[0][0];
+            acc[0][1] = live ? fmaT((double)q, (double)uc, acc[0][1]) : acc[0][1];
+            acc[0][2] = live ? fmaT((double)rc, (double)rc, acc[0][2]) : acc[0][2];
+            um = uc;
+            uc = up;
+            rc = rp;
+            sc = sp;
+            pc = pp;
+            xc = xp;
+            fc = fp;
+            hc = hn;
+            buf ^= 1;
+            if (((k + 1) & ((1 << G.zsh) - 1)) == 0 || k + 1 == z1) stage_block<3, 1>(acc, (k - z0) >> G.zsh);
+        };
+        for (int k = z0; k < z1; k += 2) {
+            step(k, LA);
+            if (k + 1 < z1) step(k + 1, LB);
+        }
+        flush_blocks<3, 1>(G, (z1 - z0 + (1 << G.zsh) - 1) >> G.zsh, z0, pbase, yb);
+    }
+
+    // the single-reduction step over one flat tile (grids without column
+    // tiles): each thread forms u_new of its cell and of its six neighbours
+    // from their r, w and s_old; partials as col_SR
+    template <class T, int MODE, bool WT>
+    __device__ __forceinline__ void tile_SR(const GAS GroupDesc &G, const GAS uint8_t *__restrict__ fl,
+                                            const GAS T *__restrict__ r, const GAS T *__restrict__ w,
+                                            const GAS T *__restrict__ sold, GAS T *__restrict__ pv,
+                                            GAS T *__restrict__ x, GAS T *__restrict__ rout,
+                                            GAS T *__restrict__ wout, GAS T *__restrict__ sout, T alpha, T beta,
+                                            int base, int end, double (&acc)[3]) {
+        const int gb = group_index(G) * 64;
+        const long sy = G.nx, sz = (long)G.nx * G.ny;
+        const long last = G.ncells - 1;
+        const long off[6] = {-1, 1, -sy, sy, -sz, sz};
+        const T h2[3] = {ih2_of<T>(G, 0), ih2_of<T>(G, 1), ih2_of<T>(G, 2)};
+        auto snew = [&](T wv, T sv) -> T { return MODE == SR_FIRST ? wv : fmaT(beta, sv, wv); };
+        auto rnew_at = [&](long n) -> T {
+            const T rv = r[n];
+            if (MODE == SR_W0) return rv;
+            return fmaT(-alpha, snew(w[n], MODE == SR_NEXT ? sold[n] : T(0)), rv);
+        };
+        for (int c = base + (int)threadIdx.x; c < end; c += kBlock) {
+            const uint8_t f = fl[c];
+            const T rn = rnew_at(c);
+            const T u = rn * idg_of<T>(gb, f);
+            T q = T(0);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                if (!(f & (1 << k))) continue;
+                long n = c + off[k];
+                // wrap into the slice: z neighbours across a periodic seam
+                n = n < 0 ? n + last + 1 : (n > last ? n - last - 1 : n);
+                const T un = rnew_at(n) * idg_of<T>(gb, fl[n]);
+                q = fmaT(u - un, h2[k >> 1], q);
+            }
+            if (!(f & FL_FLUID)) continue;
+            st_out<WT>(&wout[c], q);
+            if (MODE != SR_W0) {
+                const T wv = w[c];
+                const T sv = snew(wv, MODE == SR_NEXT ? sold[c] : T(0));
+                const T uo = r[c] * idg_of<T>(gb, f);
+                const T pp = MODE == SR_FIRST ? uo : fmaT(beta, pv[c], uo);
+                st_out<WT>(&rout[c], rn);
+                st_out<WT>(&sout[c], sv);
+                st_out<WT>(&pv[c], pp);
+                st_out<WT>(&x[c], fmaT(alpha, pp, x[c]));
+            }
+            acc[0] = fmaT((double)rn, (double)u, acc[0]);
+            acc[1] = fmaT((double)q, (double)u, acc[1]);
+            acc[2] = fmaT((double)rn, (double)rn, acc[2]);
+        }
+    }
+
+    template <class T, int MODE>
+    __device__ __forceinline__ void sr_tile(const GAS GroupDesc &G, const LAS SliceCtl &cs, long off, int lt,
+                                            int pbase, int par) {
+        const GAS T *r = gp(reinterpret_cast<const T *>(par ? G.brh : G.r)) + off;
+        const GAS T *w = gp(reinterpret_cast<const T *>(par ? G.bv1 : G.bv0)) + off;
+        const GAS T *sold = gp(reinterpret_cast<const T *>(par ? G.d1 : G.d0)) + off;
+        GAS T *rout = gp(reinterpret_cast<T *>(par ? G.r : G.brh)) + off;
+        GAS T *wout = gp(reinterpret_cast<T *>(MODE == SR_W0 ? (par ? G.bv1 : G.bv0) : (par ? G.bv0 : G.bv1))) + off;
+        GAS T *sout = gp(reinterpret_cast<T *>(par ? G.d0 : G.d1)) + off;
+        GAS T *pv = gp(reinterpret_cast<T *>(G.q)) + off;
+        GAS T *x = gp(reinterpret_cast<T *>(G.p)) + off;
+        const T al = (T)cs.alpha, be = (T)cs.beta;
+        if (G.cby > 0) {
+            int y0, y1, z0, z1, yb;
+            cg_tile_bounds(G, lt, y0, y1, z0, z1, yb);
+            if (P.wt) col_SR<T, MODE, true>(G, gp(G.flags), r, w, sold, pv, x, rout, wout, sout, al, be, y0, y1, z0, z1, pbase, yb);
+            else col_SR<T, MODE, false>(G, gp(G.flags), r, w, sold, pv, x, rout, wout, sout, al, be, y0, y1, z0, z1, pbase, yb);
+        } else {
+            const int base = lt * G.tile, end = min(base + G.tile, G.ncells);
+            double acc[3] = {0.0, 0.0, 0.0};
+            if (P.wt) tile_SR<T, MODE, true>(G, gp(G.flags), r, w, sold, pv, x, rout, wout, sout, al, be, base, end, acc);
+            else tile_SR<T, MODE, false>(G, gp(G.flags), r, w, sold, pv, x, rout, wout, sout, al, be, base, end, acc);
+            store_partials<3>(acc, pbase + lt);
+        }
+    }
+
+    // one single-reduction phase over the active slices' CG tiles; w0: the
+    // start of a run (w = A M^-1 r), else an iteration with parity par
+    __device__ __forceinline__ void phase_SR(bool w0, int par) {
+        for (int t = cb; t < ce; t += cs) {
+            int gi, sl;
+            locate_cg(t, gi, sl);
+            const GAS GroupDesc &G = P.g[gi];
+            const LAS SliceCtl &cs_ = ctl(G.slice0 + sl);
+            if (!cs_.active) continue;
+            const long off = (long)sl * G.ncells;
+            const int lt = t - G.cgtile0 - sl * G.cgtiles;
+            const int pbase = G.cgpart0 + sl * G.cgparts;
+            if (w0) sr_tile<double, SR_W0>(G, cs_, off, lt, pbase, par);
+            else if (cs_.first) sr_tile<double, SR_FIRST>(G, cs_, off, lt, pbase, par);
+            else sr_tile<double, SR_NEXT>(G, cs_, off, lt, pbase, par);
+        }
+    }
+
     // FP64 true residual r = b - A p (stored for a restart).
     // partials ||r||^2, sum p, <r,z>
     __device__ __forceinline__ void phase_true64() {
@@ -1804,6 +2076,41 @@ struct Runner {
         return true;
     }
 
+    // single-reduction CG: each (re)start begins with w = A M^-1 r (R_SR0),
+    // then one phase and one barrier per iteration; r, w, s alternate
+    // between two buffers by iteration parity, starting from r in G.r
+    __device__ __forceinline__ bool solve_sr(bool from_user) {
+        phase_init64(from_user);
+        int any = after_init(sync(R_INIT), true);
+        if (any < 0) return false;
+        for (;;) {
+            if (any > 0) {
+                phase_SR(true, 0);
+                any = sync(R_SR0);
+                if (any < 0) return false;
+                int iter = 0;
+                while (any > 0) {
+                    phase_SR(false, iter & 1);
+                    any = sync(R_SR);
+                    if (any < 0) return false;
+                    ++iter;
+                }
+            }
+            phase_true64();
+            any = sync(R_TRUE);
+            if (any < 0) return false;
+            if (!any) break;
+        }
+        return true;
+    }
+
+    // the FP64 solve of the selected solver
+    __device__ __forceinline__ bool solve_fp64(bool from_user) {
+        if (P.solver == 1) return solve_bicg(from_user);
+        if (P.solver == 2) return solve_sr(from_user);
+        return solve64(from_user);
+    }
+
     __device__ __forceinline__ bool solve_bicg(bool from_user) {
         phase_init64(from_user);
         int any = after_init(sync(R_INIT), true);
@@ -1867,7 +2174,7 @@ struct Runner {
         if (P.mode == MODE_POISSON) {
             phase_meanb_user();
             if (sync(R_MEANB) < 0) return;
-            const bool ok = P.prec == 0 ? (P.solver == 1 ? solve_bicg(true) : solve64(true)) : solve_mixed(true);
+            const bool ok = P.prec == 0 ? solve_fp64(true) : solve_mixed(true);
             if (!ok) return;
             phase_gauge();
             return;
@@ -1875,7 +2182,7 @@ struct Runner {
         if (P.mode == MODE_PROJECT) {
             phase_rhs();
             if (sync(R_MEANB) < 0) return;
-            if (!solve64(false)) return;
+            if (!solve_fp64(false)) return;
             phase_corr();
             if (sync(R_NONE) < 0) return;
             phase_gauge();
@@ -1886,7 +2193,7 @@ struct Runner {
             if (sync(R_NONE) < 0) return;
             phase_rhs();
             if (sync(R_MEANB) < 0) return;
-            const bool ok = P.prec == 0 ? (P.solver == 1 ? solve_bicg(false) : solve64(false)) : solve_mixed(false);
+            const bool ok = P.prec == 0 ? solve_fp64(false) : solve_mixed(false);
             if (!ok) return;
             phase_corr();
             // the correction reads neighbouring pressures: no cell may be

@@ -24,7 +24,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnsp.so")
 
 NSP_OK, NSP_ERR_ARG, NSP_ERR_NOT_CONVERGED, NSP_ERR_NONFINITE, NSP_ERR_HIP, NSP_ERR_UNSUPPORTED = range(6)
-PCG, BICGSTAB = 0, 1
+PCG, BICGSTAB, PCG_SR = 0, 1, 2
 _STATUS = {0: "NSP_OK", 1: "NSP_ERR_ARG", 2: "NSP_ERR_NOT_CONVERGED", 3: "NSP_ERR_NONFINITE",
            4: "NSP_ERR_HIP", 5: "NSP_ERR_UNSUPPORTED"}
 FP64, MIXED = 0, 1
@@ -129,7 +129,7 @@ class PoissonOpts:
     prec: int = FP64
     inner_rtol: float = 1e-5
     max_outer: int = 8
-    solver: int = 0  # PCG or BICGSTAB
+    solver: int = 0  # PCG, BICGSTAB or PCG_SR
 
     def c(self):
         return _Opts(float(self.rtol), int(self.maxit), int(self.prec), float(self.inner_rtol), int(self.max_outer),

@@ -27,7 +27,7 @@ def N(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("prec,solver", [(0, 0), (1, 0), (0, 1)])
+@pytest.mark.parametrize("prec,solver", [(0, 0), (1, 0), (0, 1), (0, 2)])
 def test_repeat_runs_are_bitwise_equal(gpu, prec, solver):
     n = 64
     _say("repeat runs", n, "prec", prec, "solver", solver)
