@@ -158,9 +158,9 @@ nsp_status nsp_poisson_solve(nsp_handle *h, const double *b, double *p, int batc
  * control blocks, partial sums, the right-hand-side copy and the CG vectors)
  * lives in one fixed device array of 96 MiB inside the library, which each
  * GPU it runs on holds until the process ends; the call allocates nothing.
- * Needed: 36 bytes per cell and slice (PCG, FP64 or mixed) or 68 (BiCGStab,
- * single-reduction PCG),
- * plus a few hundred KiB: one 128^3 slice in PCG, three 96^3 slices.  A solve
+ * Needed: 44 bytes per cell and slice (PCG, FP64 or mixed) or 68 (BiCGStab,
+ * single-reduction PCG), plus a few hundred KiB: one 128^3 slice or two
+ * 96^3 slices in PCG.  A solve
  * that needs more returns NSP_ERR_ARG with the size in nsp_last_error; the
  * current device must be the handle's.  Every call on one GPU shares that
  * GPU's array (it keeps the last call's contents; the call clears what must
@@ -303,6 +303,8 @@ typedef struct {
     double cg32_cell_iters;   /* the part in FP32 inner PCG iterations (mixed precision) */
     double bicg_cell_iters;   /* the part in BiCGStab iterations */
     double mixed_cell_sweeps; /* the part of cell_sweeps in mixed-precision launches */
+    long long rr_launches;    /* launches whose CG vectors stayed in registers: every CG tile had its
+                                 own workgroup (results equal the streaming kernel's bit for bit) */
 } nsp_launch_stats;
 nsp_status nsp_launch_stats_get(nsp_handle *h, nsp_launch_stats out[3], int reset);
 

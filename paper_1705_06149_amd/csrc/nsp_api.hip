@@ -460,6 +460,19 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
         for (int g = 0; g < ngroups; ++g) cells += (long long)lg[g].nslices * lg[g].ncells;
         P.wt = cells <= (8LL << 20) ? 1 : 0;
     }
+    {
+        // registers hold the CG vectors when every CG tile has its own
+        // workgroup (PCG, FP64 or the FP32 inner solve)
+        bool rr = o->solver == NSP_PCG && cgtiles <= wg;
+        for (int g = 0; g < ngroups; ++g) {
+            const GroupDesc &X = lg[g];
+            rr = rr && X.cby > 0 && X.cni == 1 && X.cbz == (1 << X.zsh) && (X.cbz == 4 || X.cbz == 8) &&
+                 X.nz % X.cbz == 0;
+            // the loop publishes boundary values in d0, d1 and q
+            rr = rr && X.d0 && X.d1 && X.q && X.r && (o->prec == NSP_FP64 || X.e);
+        }
+        P.rr = rr ? 1 : 0;
+    }
     P.dt = dt;
     P.rtol = o->rtol;
     P.eta = o->inner_rtol;
@@ -471,7 +484,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     HIPCHK(h, hipMemcpyAsync(L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
     HIPCHK(h, launch_reset_sync(L.sync, stream));
     HIPCHK(h, hipEventRecord(h->ev0, stream));
-    HIPCHK(h, launch_persistent(L.params, wg, stream));
+    HIPCHK(h, launch_persistent(L.params, wg, P.rr != 0, stream));
     HIPCHK(h, hipEventRecord(h->ev1, stream));
     HIPCHK(h, hipMemcpyAsync(L.ctl_host, L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost, stream));
     int aborted = 0;
@@ -482,6 +495,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     if (aborted) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
     nsp_launch_stats &S = h->stats[mode];
     S.launches += 1;
+    S.rr_launches += P.rr;
     S.ms += ms;
     int worst = 0;
     for (int g = 0, s = 0; g < ngroups; ++g)
@@ -1310,9 +1324,9 @@ extern "C" nsp_status nsp_poisson_solve_noalloc(nsp_handle *h, const double *b, 
     G.d0 = c.take<double>(cells);
     G.d1 = c.take<double>(cells);
     G.e = c.take<float>(cells);
-    G.q = G.bv0 = G.bv1 = G.brh = nullptr;
+    G.q = c.take<double>(cells);
+    G.bv0 = G.bv1 = G.brh = nullptr;
     if (o->solver != NSP_PCG) {
-        G.q = c.take<double>(cells);
         G.bv0 = c.take<double>(cells);
         G.bv1 = c.take<double>(cells);
         G.brh = c.take<double>(cells);

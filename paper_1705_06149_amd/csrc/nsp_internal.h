@@ -130,6 +130,9 @@ struct KParams {
     int xcd_remap;         // contiguous tile ranges per XCD
     int solver;            // 0: Jacobi-PCG, 1: Jacobi-BiCGStab (FP64), 2: single-reduction Jacobi-PCG (FP64)
     int wt;                // CG outputs by write-through (device-scope) stores
+    int rr;                // CG vectors held in registers: every group has column tiles of 4 or 8
+                           // planes (one partial block deep, nz a multiple), one item per thread, and
+                           // the launch has no more CG tiles than workgroups
     double dt;
     double rtol, eta;
     SliceCtl *ctl;         // [nslices]
@@ -139,7 +142,8 @@ struct KParams {
 
 // Launchers implemented in nsp_kernels.hip.
 // P_dev: device copy of the parameters, valid until the launch completes
-hipError_t launch_persistent(const KParams *P_dev, int workgroups, hipStream_t stream);
+// rr: the instantiation that keeps the CG vectors in registers (KParams::rr)
+hipError_t launch_persistent(const KParams *P_dev, int workgroups, bool rr, hipStream_t stream);
 hipError_t max_coresident_workgroups(int device, int *out);
 hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream);
 // zero nwords 32-bit words at p on the stream (a kernel, not a memset)

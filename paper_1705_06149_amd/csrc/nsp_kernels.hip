@@ -266,6 +266,11 @@ __device__ __forceinline__ double predictor(const GAS GroupDesc &G, const GAS do
 
 // ------------------------------------------------------------ the runner
 
+// RR: the kernel instantiation for launches whose CG vectors stay in
+// registers (PCG only); the other holds the streaming CG, BiCGStab and the
+// single-reduction CG.  Two instantiations keep each one's register
+// allocation free of the other's code.
+template <bool RR>
 struct Runner {
     const GAS KParams &P;
     int tb, te, ts;        // my tiles: tb, tb + ts, ... < te
@@ -1397,6 +1402,223 @@ struct Runner {
         }
     }
 
+    // ------------------------------------------- register-resident CG
+    //
+    // When a launch has no more CG column tiles than workgroups, every
+    // workgroup owns at most one tile for the whole solve, and the tile's
+    // vectors x, r and d stay in registers across iterations (thread (x, y)
+    // holds its column's K planes).  Per iteration only tile-boundary values
+    // (rows y0 and y1 - 1, planes z0 and z1 - 1) go through memory: phase B
+    // publishes z = M^-1 r there, phase A publishes d (two buffers by
+    // iteration parity).  Phase A forms the halo d = z + beta d_prev from the
+    // neighbouring tiles' published z and previous d, phase B reads the halo
+    // d the neighbours published in phase A.  Every value is computed by the
+    // formulas of col_A and col_B from the same inputs (q is formed again in
+    // phase B, as col_B does) and the partials are kept per the same row and
+    // plane blocks, so the results equal the streaming phases' bit for bit.
+    // The loop writes x back when every slice of the launch is done.
+    template <class T, int K>
+    struct RRState {
+        T r[K], x[K], d[K];
+        unsigned long long f;  // flags of the column's K cells, byte k for plane k
+    };
+
+    template <class T, int K>
+    __device__ __forceinline__ uint8_t rr_flag(const RRState<T, K> &S, int k) const {
+        return (uint8_t)((S.f >> (8 * k)) & 0xFF);
+    }
+
+    // q = A d at plane k of the column: d of the plane and of the halo row
+    // through the LDS plane, z neighbours from registers; the order of col_A
+    template <class T, int K>
+    __device__ __forceinline__ T rr_q(const GAS GroupDesc &G, const ColPos<1> &P0, const RRState<T, K> &S, int k,
+                                      T dhk, T dzm, T dzp, T hx, T hy, T hz) {
+        LAS T *pl = reinterpret_cast<LAS T *>(s_plane) + (k & 1) * (G.cby + 2) * G.nx;
+        const int sl = P0.slot[0], nx = G.nx;
+        if (P0.act[0]) pl[sl] = S.d[k];
+        if (P0.halo) pl[P0.hslot] = dhk;
+        __syncthreads();
+        const uint8_t f = rr_flag(S, k);
+        const T d0 = S.d[k];
+        const T dm = k > 0 ? S.d[k > 0 ? k - 1 : 0] : dzm;
+        const T dp = k < K - 1 ? S.d[k < K - 1 ? k + 1 : 0] : dzp;
+        T q = T(0);
+        q = (f & FL_XM) ? fmaT(d0 - pl[sl - 1], hx, q) : q;
+        q = (f & FL_XP) ? fmaT(d0 - pl[sl + 1], hx, q) : q;
+        q = (f & FL_YM) ? fmaT(d0 - pl[sl - nx], hy, q) : q;
+        q = (f & FL_YP) ? fmaT(d0 - pl[sl + nx], hy, q) : q;
+        q = (f & FL_ZM) ? fmaT(d0 - dm, hz, q) : q;
+        q = (f & FL_ZP) ? fmaT(d0 - dp, hz, q) : q;
+        return q;
+    }
+
+    // cells below and above the column's planes (wrapped into the slice)
+    template <int K>
+    __device__ __forceinline__ void rr_zcells(const GAS GroupDesc &G, const ColPos<1> &P0, int z0, long &cm,
+                                              long &cp) const {
+        const long sz = (long)G.nx * G.ny;
+        cm = z0 > 0 ? P0.c0[0] - sz : P0.c0[0] + (long)(G.nz - 1) * sz;
+        cp = P0.c0[0] + (long)((z0 + K) % G.nz - z0) * sz;
+    }
+
+    // phase A: d = z + beta d (own cells and halo), publish the boundary d,
+    // q = A d, partial <d, q>
+    template <class T, int K, bool WT>
+    __device__ __forceinline__ void rr_phase_A(const GAS GroupDesc &G, const ColPos<1> &P0, RRState<T, K> &S,
+                                               bool first, T beta, const GAS T *__restrict__ rg,
+                                               const GAS T *__restrict__ pubz, const GAS T *__restrict__ dprev,
+                                               GAS T *__restrict__ dcur, bool edge, int z0, int pbase, int yb) {
+        const int gb = group_index(G) * 64;
+        const long sz = (long)G.nx * G.ny;
+        const GAS uint8_t *fl = gp(G.flags);
+        // a neighbouring tile's d: at a (re)start z formed from r as the
+        // streaming phase does, else beta d_prev + z from the published values
+        auto dat = [&](long c) -> T {
+            if (first) return rg[c] * idg_of<T>(gb, fl[c]);
+            return fmaT(beta, dprev[c], pubz[c]);
+        };
+        long cm, cp;
+        rr_zcells<K>(G, P0, z0, cm, cp);
+        const T dzm = dat(cm), dzp = dat(cp);
+        T dh[K];
+        if (P0.halo) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) dh[k] = dat(P0.h0 + (long)k * sz);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T z = S.r[k] * idg_of<T>(gb, rr_flag(S, k));
+            S.d[k] = first ? z : fmaT(beta, S.d[k], z);
+            if (P0.act[0] && (edge || k == 0 || k == K - 1)) st_out<WT>(&dcur[P0.c0[0] + (long)k * sz], S.d[k]);
+        }
+        const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
+        double acc[1][1] = {{0.0}};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T q = rr_q<T, K>(G, P0, S, k, P0.halo ? dh[k] : T(0), dzm, dzp, hx, hy, hz);
+            acc[0][0] = P0.act[0] ? fmaT((double)S.d[k], (double)q, acc[0][0]) : acc[0][0];
+        }
+        stage_block<1, 1>(acc, 0);
+        flush_blocks<1, 1>(G, 1, z0, pbase, yb);
+    }
+
+    // phase B: q = A d again (halo d as published in phase A), x += alpha d,
+    // r -= alpha q on live cells, partials <r,z>, ||r||^2; publish z of the
+    // tile's boundary cells
+    template <class T, int K, bool WT>
+    __device__ __forceinline__ void rr_phase_B(const GAS GroupDesc &G, const ColPos<1> &P0, RRState<T, K> &S,
+                                               T alpha, GAS T *__restrict__ pubz, const GAS T *__restrict__ dcur,
+                                               bool edge, int z0, int pbase, int yb) {
+        const int gb = group_index(G) * 64;
+        const long sz = (long)G.nx * G.ny;
+        long cm, cp;
+        rr_zcells<K>(G, P0, z0, cm, cp);
+        const T dzm = dcur[cm], dzp = dcur[cp];
+        T dh[K];
+        if (P0.halo) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) dh[k] = dcur[P0.h0 + (long)k * sz];
+        }
+        const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
+        double acc[1][2] = {{0.0, 0.0}};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T q = rr_q<T, K>(G, P0, S, k, P0.halo ? dh[k] : T(0), dzm, dzp, hx, hy, hz);
+            const uint8_t f = rr_flag(S, k);
+            const T xv = fmaT(alpha, S.d[k], S.x[k]);
+            const T rv = fmaT(-alpha, q, S.r[k]);
+            const T z = rv * idg_of<T>(gb, f);
+            const bool live = P0.act[0] && (f & FL_FLUID);
+            if (live) {
+                S.x[k] = xv;
+                S.r[k] = rv;
+            }
+            acc[0][0] = live ? fmaT((double)rv, (double)z, acc[0][0]) : acc[0][0];
+            acc[0][1] = live ? fmaT((double)rv, (double)rv, acc[0][1]) : acc[0][1];
+            if (P0.act[0] && (edge || k == 0 || k == K - 1))
+                st_out<WT>(&pubz[P0.c0[0] + (long)k * sz], S.r[k] * idg_of<T>(gb, f));
+        }
+        stage_block<2, 1>(acc, 0);
+        flush_blocks<2, 1>(G, 1, z0, pbase, yb);
+    }
+
+    // The CG loop of a launch whose CG tiles fit one per workgroup, with this
+    // workgroup's tile (if any) of K planes held in registers.  ra / rb: the
+    // reductions after phases A and B (FP64 or FP32 inner CG).  Published
+    // boundary values: z in d0; d in d1 and q by iteration parity.  x is
+    // written back after the loop, followed by a grid barrier.  Returns the
+    // control word after the loop, or -1 if the launch was abandoned.
+    template <class T, int K, bool WT>
+    __device__ __forceinline__ int rr_loop(int any, int ra, int rb) {
+        const bool has = cb < ce;
+        int gi = 0, sl = 0;
+        if (has) locate_cg(cb, gi, sl);
+        const GAS GroupDesc &G = P.g[gi];
+        const int gs = G.slice0 + sl;
+        const long off = (long)sl * G.ncells;
+        const int lt = has ? cb - G.cgtile0 - sl * G.cgtiles : 0;
+        int y0 = 0, y1 = 0, z0 = 0, z1 = 0, yb = 0;
+        cg_tile_bounds(G, lt, y0, y1, z0, z1, yb);
+        const int pbase = G.cgpart0 + sl * G.cgparts;
+        const ColPos<1> P0 = col_pos<1>(G, y0, y1, z0);
+        const int yrow = (int)((P0.c0[0] / G.nx) % G.ny);
+        const bool edge = yrow == y0 || yrow == y1 - 1;
+        const GAS T *rg = gp(reinterpret_cast<const T *>(G.r)) + off;
+        GAS T *xg = gp(sizeof(T) == 8 ? reinterpret_cast<T *>(G.p) : reinterpret_cast<T *>(G.e)) + off;
+        GAS T *pubz = gp(reinterpret_cast<T *>(G.d0)) + off;
+        GAS T *pubd[2] = {gp(reinterpret_cast<T *>(G.d1)) + off, gp(reinterpret_cast<T *>(G.q)) + off};
+        const long sz = (long)G.nx * G.ny;
+        RRState<T, K> S;
+        S.f = 0;
+        if (has) {
+            const GAS uint8_t *fl = gp(G.flags);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const long c = P0.c0[0] + (long)k * sz;
+                S.f |= (unsigned long long)fl[c] << (8 * k);
+                S.r[k] = rg[c];
+                S.x[k] = xg[c];
+            }
+        }
+        int iter = 0;
+        while (any > 0) {
+            const LAS SliceCtl &c = ctl(gs);
+            const bool run = has && c.active;
+            GAS T *dcur = pubd[iter & 1];
+            const GAS T *dprev = pubd[(iter + 1) & 1];
+            if (run)
+                rr_phase_A<T, K, WT>(G, P0, S, c.first, c.first ? T(0) : (T)c.beta, rg, pubz, dprev, dcur, edge, z0,
+                                     pbase, yb);
+            if (sync(ra) < 0) return -1;
+            if (run) rr_phase_B<T, K, WT>(G, P0, S, (T)c.alpha, pubz, dcur, edge, z0, pbase, yb);
+            any = sync(rb);
+            if (any < 0) return -1;
+            ++iter;
+        }
+        if (has) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (P0.act[0] && (rr_flag(S, k) & FL_FLUID)) xg[P0.c0[0] + (long)k * sz] = S.x[k];
+        }
+        // the phases after the loop read x at other tiles' cells: every
+        // workgroup's write-back must be done first
+        if (sync(R_NONE) < 0) return -1;
+        return any;
+    }
+
+    // register-resident CG loop: the tile's depth K is 4 or 8 planes
+    template <class T>
+    __device__ __forceinline__ int rr_cg(int any, int ra, int rb) {
+        int k8 = 0;
+        if (cb < ce) {
+            int gi, sl;
+            locate_cg(cb, gi, sl);
+            k8 = P.g[gi].cbz == 8;
+        }
+        if (P.wt) return k8 ? rr_loop<T, 8, true>(any, ra, rb) : rr_loop<T, 4, true>(any, ra, rb);
+        return k8 ? rr_loop<T, 8, false>(any, ra, rb) : rr_loop<T, 4, false>(any, ra, rb);
+    }
+
     // FP64: p += alpha d; r -= alpha A d.  partials <r,z>, ||r||^2
     // FP32 (inner solve of the mixed path): e += alpha d; r -= alpha A d.
     template <class T>
@@ -2059,14 +2281,19 @@ struct Runner {
         if (any < 0) return false;
         int iter = 0;
         for (;;) {
-            while (any > 0) {
-                const int par = iter & 1;
-                phase_A<double>(par);
-                if (sync(R_A) < 0) return false;
-                phase_B<double>(par);
-                any = sync(R_B);
+            if constexpr (RR) {
+                any = rr_cg<double>(any, R_A, R_B);
                 if (any < 0) return false;
-                ++iter;
+            } else {
+                while (any > 0) {
+                    const int par = iter & 1;
+                    phase_A<double>(par);
+                    if (sync(R_A) < 0) return false;
+                    phase_B<double>(par);
+                    any = sync(R_B);
+                    if (any < 0) return false;
+                    ++iter;
+                }
             }
             phase_true64();
             any = sync(R_TRUE);
@@ -2106,8 +2333,10 @@ struct Runner {
 
     // the FP64 solve of the selected solver
     __device__ __forceinline__ bool solve_fp64(bool from_user) {
-        if (P.solver == 1) return solve_bicg(from_user);
-        if (P.solver == 2) return solve_sr(from_user);
+        if constexpr (!RR) {
+            if (P.solver == 1) return solve_bicg(from_user);
+            if (P.solver == 2) return solve_sr(from_user);
+        }
         return solve64(from_user);
     }
 
@@ -2152,14 +2381,19 @@ struct Runner {
             phase_cast();
             int act = sync(R_CAST);
             if (act < 0) return false;
-            while (act > 0) {
-                const int par = iter & 1;
-                phase_A<float>(par);
-                if (sync(R_A32) < 0) return false;
-                phase_B<float>(par);
-                act = sync(R_B32);
+            if constexpr (RR) {
+                act = rr_cg<float>(act, R_A32, R_B32);
                 if (act < 0) return false;
-                ++iter;
+            } else {
+                while (act > 0) {
+                    const int par = iter & 1;
+                    phase_A<float>(par);
+                    if (sync(R_A32) < 0) return false;
+                    phase_B<float>(par);
+                    act = sync(R_B32);
+                    if (act < 0) return false;
+                    ++iter;
+                }
             }
             phase_update();
             if (sync(R_NONE) < 0) return false;
@@ -2208,6 +2442,7 @@ struct Runner {
 // by-value parameter block of this size would be copied to scratch.
 // At most 128 VGPRs (4 waves per SIMD): the CG phases need the occupancy;
 // the image-rule momentum path may spill instead.
+template <bool RR>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_persistent(const KParams *__restrict__ Pp) {
     const GAS KParams &P = *gp(Pp);
@@ -2267,7 +2502,7 @@ k_persistent(const KParams *__restrict__ Pp) {
     }
     __syncthreads();
     __shared__ unsigned s_nx[kMaxXcd];
-    Runner R{P, sched[0][0], sched[0][1], sched[0][2], sched[1][0], sched[1][1], sched[1][2], (LAS double *)s_red,
+    Runner<RR> R{P, sched[0][0], sched[0][1], sched[0][2], sched[1][0], sched[1][1], sched[1][2], (LAS double *)s_red,
              (const LAS double *)s_idg, (const LAS float *)s_idg32, (LAS double *)s_plane, (LAS SliceCtl *)s_ctl,
              (const LAS double *)s_nf, (const LAS int *)s_pb, (const LAS int *)s_pn, (LAS double *)s_sum,
              (const LAS unsigned *)s_nx, hw_xcc_id(), (LAS double *)s_blk};
@@ -2409,18 +2644,23 @@ __global__ void k_copy(double *__restrict__ dst, const double *__restrict__ src,
 
 }  // namespace
 
-hipError_t launch_persistent(const KParams *P_dev, int workgroups, hipStream_t stream) {
+hipError_t launch_persistent(const KParams *P_dev, int workgroups, bool rr, hipStream_t stream) {
     const KParams *arg = P_dev;
     void *args[] = {&arg};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_persistent), dim3(workgroups), dim3(kBlock),
-                                      args, 0, stream);
+    const void *fn = rr ? reinterpret_cast<const void *>(&k_persistent<true>)
+                        : reinterpret_cast<const void *>(&k_persistent<false>);
+    return hipLaunchCooperativeKernel(fn, dim3(workgroups), dim3(kBlock), args, 0, stream);
 }
 
 hipError_t max_coresident_workgroups(int device, int *out) {
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_persistent),
-                                                               kBlock, 0);
+    int per_cu = 0, per_cu_rr = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_persistent<false>), kBlock, 0);
     if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_rr, reinterpret_cast<const void *>(&k_persistent<true>),
+                                                     kBlock, 0);
+    if (e != hipSuccess) return e;
+    per_cu = per_cu < per_cu_rr ? per_cu : per_cu_rr;
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) return e;

@@ -58,7 +58,8 @@ class _LaunchStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_longlong), ("ms", ctypes.c_double), ("cell_steps", ctypes.c_double),
                 ("cg_cell_iters", ctypes.c_double), ("cell_sweeps", ctypes.c_double),
                 ("cg64_cell_iters", ctypes.c_double), ("cg32_cell_iters", ctypes.c_double),
-                ("bicg_cell_iters", ctypes.c_double), ("mixed_cell_sweeps", ctypes.c_double)]
+                ("bicg_cell_iters", ctypes.c_double), ("mixed_cell_sweeps", ctypes.c_double),
+                ("rr_launches", ctypes.c_longlong)]
 
 
 class _State(ctypes.Structure):
@@ -210,8 +211,8 @@ class Handle:
             lib().nsp_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()

@@ -47,7 +47,11 @@ def _case(gpu, h, batch, opts, seed):
 def test_noalloc_poisson_matches_the_allocating_solve(gpu):
     h = gpu.Handle(64, 64, 64, max_batch=2)
     _say("noalloc 64^3 batch 2 fp64")
+    h.launch_stats(reset=True)
     _case(gpu, h, 2, gpu.PoissonOpts(rtol=1e-10), 1)
+    # both launches (allocating and not) held the CG vectors in registers,
+    # whose boundary values go through the workspace's d0, d1 and q
+    assert h.launch_stats()["poisson"]["rr_launches"] == 2
     _say("noalloc 64^3 batch 1 mixed")
     _case(gpu, h, 1, gpu.PoissonOpts(rtol=1e-10, prec=gpu.MIXED), 2)
     h.close()
