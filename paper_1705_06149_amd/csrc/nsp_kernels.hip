@@ -1428,16 +1428,30 @@ struct Runner {
         return (uint8_t)((S.f >> (8 * k)) & 0xFF);
     }
 
-    // q = A d at plane k of the column: d of the plane and of the halo row
-    // through the LDS plane, z neighbours from registers; the order of col_A
+    // Stage d of the tile's K planes and of its halo rows (dh, halo threads)
+    // in the LDS, plane k at offset k (cby + 2) nx, then one workgroup
+    // barrier; the plane buffer of the register-resident instantiation holds
+    // all K planes.  The previous reads of the buffer are a grid barrier back.
+    template <class T, int K>
+    __device__ __forceinline__ void rr_stage(const GAS GroupDesc &G, const ColPos<1> &P0, const RRState<T, K> &S,
+                                             const T *dh) {
+        LAS T *pl = reinterpret_cast<LAS T *>(s_plane);
+        const int pst = (G.cby + 2) * G.nx;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (P0.act[0]) pl[k * pst + P0.slot[0]] = S.d[k];
+            if (P0.halo) pl[k * pst + P0.hslot] = dh[k];
+        }
+        __syncthreads();
+    }
+
+    // q = A d at plane k of the column from the staged planes, z neighbours
+    // from registers; the order of col_A
     template <class T, int K>
     __device__ __forceinline__ T rr_q(const GAS GroupDesc &G, const ColPos<1> &P0, const RRState<T, K> &S, int k,
-                                      T dhk, T dzm, T dzp, T hx, T hy, T hz) {
-        LAS T *pl = reinterpret_cast<LAS T *>(s_plane) + (k & 1) * (G.cby + 2) * G.nx;
+                                      T dzm, T dzp, T hx, T hy, T hz) const {
+        const LAS T *pl = reinterpret_cast<const LAS T *>(s_plane) + k * (G.cby + 2) * G.nx;
         const int sl = P0.slot[0], nx = G.nx;
-        if (P0.act[0]) pl[sl] = S.d[k];
-        if (P0.halo) pl[P0.hslot] = dhk;
-        __syncthreads();
         const uint8_t f = rr_flag(S, k);
         const T d0 = S.d[k];
         const T dm = k > 0 ? S.d[k > 0 ? k - 1 : 0] : dzm;
@@ -1492,10 +1506,11 @@ struct Runner {
             if (P0.act[0] && (edge || k == 0 || k == K - 1)) st_out<WT>(&dcur[P0.c0[0] + (long)k * sz], S.d[k]);
         }
         const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
+        rr_stage<T, K>(G, P0, S, dh);
         double acc[1][1] = {{0.0}};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const T q = rr_q<T, K>(G, P0, S, k, P0.halo ? dh[k] : T(0), dzm, dzp, hx, hy, hz);
+            const T q = rr_q<T, K>(G, P0, S, k, dzm, dzp, hx, hy, hz);
             acc[0][0] = P0.act[0] ? fmaT((double)S.d[k], (double)q, acc[0][0]) : acc[0][0];
         }
         stage_block<1, 1>(acc, 0);
@@ -1520,10 +1535,11 @@ struct Runner {
             for (int k = 0; k < K; ++k) dh[k] = dcur[P0.h0 + (long)k * sz];
         }
         const T hx = ih2_of<T>(G, 0), hy = ih2_of<T>(G, 1), hz = ih2_of<T>(G, 2);
+        rr_stage<T, K>(G, P0, S, dh);
         double acc[1][2] = {{0.0, 0.0}};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const T q = rr_q<T, K>(G, P0, S, k, P0.halo ? dh[k] : T(0), dzm, dzp, hx, hy, hz);
+            const T q = rr_q<T, K>(G, P0, S, k, dzm, dzp, hx, hy, hz);
             const uint8_t f = rr_flag(S, k);
             const T xv = fmaT(alpha, S.d[k], S.x[k]);
             const T rv = fmaT(-alpha, q, S.r[k]);
@@ -2448,7 +2464,9 @@ k_persistent(const KParams *__restrict__ Pp) {
     const GAS KParams &P = *gp(Pp);
     __shared__ double s_red[kWaves * kNQ];
     __shared__ double s_blk[kMaxBlk * kWaves * kNQ];
-    __shared__ double s_plane[2 * 2 * kBlock];  // (cby + 2) * nx <= kBlock + 2 nx <= 2 kBlock
+    // (cby + 2) * nx <= kBlock + 2 nx <= 2 kBlock: two planes streaming, K <= 8
+    // planes in the register-resident instantiation
+    __shared__ double s_plane[(RR ? 8 : 2) * 2 * kBlock];
     __shared__ double s_idg[kMaxGroups * 64];
     __shared__ float s_idg32[kMaxGroups * 64];
     for (int x = threadIdx.x; x < P.ngroups * 64; x += kBlock) {
