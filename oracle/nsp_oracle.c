@@ -728,6 +728,95 @@ int og_pcg_mixed(const og_grid *g, const double *b, double *x, double rtol, doub
     return status;
 }
 
+/* Mixed precision that keeps its Krylov space: FP32 Jacobi-PCG on the
+ * correction e of the FP64 iterate x, with reliable updates (Sleijpen & van
+ * der Vorst 1996).  The FP32 recursive residual drifts from b - A(x + e) by
+ * FP32 rounding; whenever it has fallen by the factor delta below its norm
+ * at the last update (or below rtol ||b||, or the iteration limit is hit),
+ * e is added to x in FP64, the FP64 residual b - A x is recomputed, tested
+ * against rtol ||b||, and its mean-free FP32 copy replaces the recursive
+ * residual.  The search direction d is kept across the update, so CG goes
+ * on in the same Krylov space instead of restarting:
+ *   start:   r = b - A x, rt = fp32(r - mean r), e = 0, z = M^-1 rt, d = z
+ *   step:    q = A d, alpha = <rt,z>/<d,q>, e += alpha d, rt -= alpha q,
+ *            z = M^-1 rt;  [update: x += e, e = 0, r = b - A x, stop if
+ *            ||r|| <= rtol ||b||, rt = fp32(r - mean r), z = M^-1 rt]
+ *            beta = <rt,z>_new / <rt,z>_old, d = z + beta d
+ * Inner products in FP64 from FP32 values (products exact), alpha and beta
+ * rounded to FP32 as in pcg32.  outer counts the updates (at most
+ * max_updates), iters the FP32 iterations. */
+int og_pcg_mixed_ru(const og_grid *g, const double *b, double *x, double rtol, double delta, int maxit,
+                    int max_updates, og_info *info) {
+    size_t n = ncells(g);
+    double *r = malloc(n * sizeof(double)), *dg = malloc(n * sizeof(double));
+    float *dg32 = malloc(n * sizeof(float)), *rt = malloc(n * sizeof(float)), *e = malloc(n * sizeof(float));
+    float *z = malloc(n * sizeof(float)), *d = malloc(n * sizeof(float)), *q = malloc(n * sizeof(float));
+    diag_A(g, dg);
+    for (size_t i = 0; i < n; ++i) dg32[i] = (float)dg[i];
+    memset(info, 0, sizeof(*info));
+    double bnorm = sqrt(dot(g, b, b));
+    int status = 0, it = 0, updates = 0;
+    double rel = 0.0;
+    if (bnorm == 0.0) {
+        for (size_t i = 0; i < n; ++i) x[i] = 0.0;
+        goto done;
+    }
+    cold_start_if_worse(g, b, x, r);
+    /* FP64 residual of x; 1 when it meets the tolerance */
+    og_apply_A(g, x, r);
+    for (size_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    double rnorm = sqrt(dot(g, r, r));
+    rel = rnorm / bnorm;
+    if (!isfinite(rnorm)) { status = 3; goto fold; }
+    if (rnorm <= rtol * bnorm) goto fold;
+    for (size_t i = 0; i < n; ++i) e[i] = 0.0f;
+    double m = mean_fluid(g, r);
+    for (size_t i = 0; i < n; ++i) rt[i] = is_fluid_id(g, i) ? (float)(r[i] - m) : 0.0f;
+    for (size_t i = 0; i < n; ++i) { z[i] = dg32[i] > 0.0f ? rt[i] / dg32[i] : 0.0f; d[i] = z[i]; }
+    double rho = dot32(g, rt, z);
+    double rlast = sqrt(dot32(g, rt, rt));
+    for (;;) {
+        apply_A32(g, d, q);
+        float alpha = (float)(rho / dot32(g, d, q));
+        for (size_t i = 0; i < n; ++i) e[i] += alpha * d[i];
+        for (size_t i = 0; i < n; ++i) rt[i] -= alpha * q[i];
+        for (size_t i = 0; i < n; ++i) z[i] = dg32[i] > 0.0f ? rt[i] / dg32[i] : 0.0f;
+        double rho_new = dot32(g, rt, z);
+        double rn = sqrt(dot32(g, rt, rt));
+        ++it;
+        if (rn <= delta * rlast || rn <= rtol * bnorm || it >= maxit || !isfinite(rn)) {
+            /* reliable update */
+            for (size_t i = 0; i < n; ++i) x[i] += (double)e[i];
+            for (size_t i = 0; i < n; ++i) e[i] = 0.0f;
+            ++updates;
+            og_apply_A(g, x, r);
+            for (size_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+            rnorm = sqrt(dot(g, r, r));
+            rel = rnorm / bnorm;
+            if (!isfinite(rnorm)) { status = 3; break; }
+            if (rnorm <= rtol * bnorm) break;
+            if (updates >= max_updates || it >= maxit) { status = 2; break; }
+            m = mean_fluid(g, r);
+            for (size_t i = 0; i < n; ++i) rt[i] = is_fluid_id(g, i) ? (float)(r[i] - m) : 0.0f;
+            for (size_t i = 0; i < n; ++i) z[i] = dg32[i] > 0.0f ? rt[i] / dg32[i] : 0.0f;
+            rho_new = dot32(g, rt, z);
+            rlast = sqrt(dot32(g, rt, rt));
+        }
+        float beta = (float)(rho_new / rho);
+        rho = rho_new;
+        for (size_t i = 0; i < n; ++i) d[i] = z[i] + beta * d[i];
+    }
+fold:
+    subtract_mean(g, x);
+done:
+    info->iters = it;
+    info->outer = updates;
+    info->status = status;
+    info->rel_res_true = rel;
+    free(r); free(dg); free(dg32); free(rt); free(e); free(z); free(d); free(q);
+    return status;
+}
+
 /* ------------------------------------------------- correction and step */
 
 /* u = F - dt G p on open faces, 0 on closed faces. */
@@ -762,7 +851,9 @@ void og_rhs(const og_grid *g, const double *Fu, const double *Fv, const double *
 }
 
 /* nsteps forward-Euler projection steps of size dt, in place on (u,v,w,p).
- * prec 0: FP64 PCG; prec 1: FP32 inner PCG with FP64 defect correction.
+ * prec 0: FP64 PCG; prec 1: FP32 inner PCG with FP64 defect correction;
+ * prec 2: FP32 PCG with reliable updates (eta is delta, max_outer the
+ * update limit).
  * iters (optional, nsteps entries) receives the CG iterations per step.
  * Returns the worst status over the steps. */
 int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
@@ -791,6 +882,7 @@ int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, doub
         int st = solver == 1               ? og_bicgstab(g, b, p, rtol, maxit, &info)
                  : solver == 2 && prec == 0 ? og_pcg_sr(g, b, p, rtol, maxit, &info)
                  : prec == 0                ? og_pcg(g, b, p, rtol, maxit, &info)
+                 : prec == 2                ? og_pcg_mixed_ru(g, b, p, rtol, eta, maxit, max_outer, &info)
                                             : og_pcg_mixed(g, b, p, rtol, eta, maxit, max_outer, &info);
         if (st > worst) worst = st;
         if (iters) iters[s] = info.iters;

@@ -79,6 +79,8 @@ def lib():
         _lib.og_bicgstab.restype = I
         _lib.og_pcg_sr.argtypes = [G, P, P, D, I, ctypes.POINTER(_Info)]
         _lib.og_pcg_sr.restype = I
+        _lib.og_pcg_mixed_ru.argtypes = [G, P, P, D, D, I, I, ctypes.POINTER(_Info)]
+        _lib.og_pcg_mixed_ru.restype = I
         _lib.og_momentum_adjoint.argtypes = [G, P, P, P, D, P, P, P, P, P, P, P]
         _lib.og_stencil_form_value.argtypes = [G, I, P, I, I, I, I, I]
         _lib.og_stencil_form_value.restype = D
@@ -240,6 +242,20 @@ def pcg_mixed(g: Grid, b, x0=None, rtol=1e-10, eta=1e-5, maxit=100000, max_outer
     return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
 
 
+def pcg_mixed_ru(g: Grid, b, x0=None, rtol=1e-10, delta=0.1, maxit=100000, max_updates=64):
+    """FP32 Jacobi-PCG on the correction with reliable updates: the FP64
+    residual replaces the FP32 one whenever it has fallen by `delta`, and the
+    search direction is kept.  outer = number of updates."""
+    sp = g.shapes()[3]
+    b = _chk(b, sp)
+    x = np.zeros(sp) if x0 is None else _chk(x0, sp).copy()
+    info = _Info()
+    gc = g.c()
+    lib().og_pcg_mixed_ru(ctypes.byref(gc), _p(b), _p(x), float(rtol), float(delta), int(maxit), int(max_updates),
+                          ctypes.byref(info))
+    return x, dict(iters=info.iters, outer=info.outer, status=info.status, rel_res_true=info.rel_res_true)
+
+
 def correct(g: Grid, Fu, Fv, Fw, p, dt):
     su, sv, sw, sp = g.shapes()
     u, v, w = np.empty(su), np.empty(sv), np.empty(sw)
@@ -251,8 +267,9 @@ def correct(g: Grid, Fu, Fv, Fw, p, dt):
 
 def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta=1e-5, max_outer=8, solver=0):
     """nsteps projection steps of size dt; returns (new state, iters, rel_true, status).
-    solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed); 1: FP64 Jacobi-BiCGStab;
-    2: single-reduction Jacobi-PCG (FP64).
+    solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed restarts, 2 mixed reliable
+    updates with eta = delta and max_outer = update limit); 1: FP64
+    Jacobi-BiCGStab; 2: single-reduction Jacobi-PCG (FP64).
 
     The input state tuple (u, v, w, p) is not modified."""
     su, sv, sw, sp = g.shapes()
