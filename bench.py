@@ -46,7 +46,7 @@ PEAK_HBM_GBS = 8000.0
 
 # Algorithmic bytes per cell of the kernels' phases (FP64 state, 1-byte
 # cell flags; face arrays counted as one entry per cell and component).
-BYTES_CG_ITER = {"fp64": 66.0, "mixed": 34.0}   # one CG iteration
+BYTES_CG_ITER = {"fp64": 66.0, "mixed": 34.0, "mixed_ru": 34.0}   # one CG iteration
 BYTES_BICG_ITER = 139.0  # one BiCGStab iteration (FP64): phases of 49, 25 and 65 B
 BYTES_SR_ITER = 81.0     # one single-reduction CG iteration (FP64): reads r, w, s, p, x, flags; writes r, w, s, p, x
 BYTES_SR_START = 17.0    # the start of a single-reduction run: w = A M^-1 r (reads r, flags; writes w)
@@ -55,6 +55,30 @@ BYTES_SR_START = 17.0    # the start of a single-reduction run: w = A M^-1 r (re
 # and 80 B per cell per FP64 CG iteration (read r, d, write d, q; read x, d,
 # r, q, write x, r).
 MODEL_STEP_FIXED, MODEL_CG_ITER = 112.0, 80.0
+
+
+def _prec(args):
+    from paper_1705_06149_amd import nsp
+    return {"fp64": nsp.FP64, "mixed": nsp.MIXED, "mixed_ru": nsp.MIXED_RU}[args.precision]
+
+
+def _eta(args):
+    """inner tolerance (restarted mixed solves) or update factor (reliable updates)"""
+    if args.eta is not None:
+        return args.eta
+    return 0.01 if args.precision == "mixed_ru" else 1e-5
+
+
+def _max_outer(args):
+    return 64 if args.precision == "mixed_ru" else 8
+
+
+def _parareal_fine_opts(args, nsp):
+    """Poisson options of the batched fine sweeps of the Parareal modes"""
+    prec = {"fp64": nsp.FP64, "mixed": nsp.MIXED, "mixed_ru": nsp.MIXED_RU}[args.parareal_fine]
+    eta = args.eta if args.eta is not None else (0.01 if args.parareal_fine == "mixed_ru" else 1e-5)
+    return nsp.PoissonOpts(rtol=1e-10, prec=prec, inner_rtol=eta, max_outer=64 if args.parareal_fine == "mixed_ru"
+                           else 8)
 
 
 def _solver(args):
@@ -73,7 +97,7 @@ def _bytes_per_iter(args):
     if args.solver == "pcg_sr":
         return BYTES_SR_ITER
     return BYTES_CG_ITER[args.precision]
-BYTES_STEP_FIXED = {"fp64": 212.0, "mixed": 212.0}  # momentum, rhs, init/true, correction, gauge
+BYTES_STEP_FIXED = {"fp64": 212.0, "mixed": 212.0, "mixed_ru": 212.0}  # momentum, rhs, init/true, correction, gauge
 BYTES_MIXED_SWEEP = 65.0  # mixed: one FP64 residual + cast + update sweep
 
 
@@ -135,9 +159,9 @@ def bench_fine(args):
     from paper_1705_06149_amd import nsp
 
     n, re_, dt = 128, 1000.0, 5e-4
-    prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
-    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=args.eta, max_outer=8,
-                           solver=_solver(args))
+    prec = _prec(args)
+    opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=_eta(args),
+                           max_outer=_max_outer(args), solver=_solver(args))
     h = nsp.Handle(n, n, n, re=re_, max_batch=1, solid=_fine_solid(args), slip_obstacles=args.slip)
     y = h.zeros_state(1)
     t = 0.0
@@ -160,7 +184,7 @@ def bench_fine(args):
     K = args.steps
     value = cells * K / wall
     err_vs_fp64 = None
-    if args.precision == "mixed" and args.compare_fp64:
+    if args.precision != "fp64" and args.compare_fp64:
         # the same K steps in FP64 from the same warmed state
         import torch
         y64 = tuple(torch.from_numpy(a[None].copy()).cuda() for a in host_state)
@@ -171,7 +195,7 @@ def bench_fine(args):
     per_iter = _bytes_per_iter(args)
     fixed = BYTES_STEP_FIXED[args.precision] + (BYTES_SR_START if args.solver == "pcg_sr" else 0.0)
     per_launch_bytes = cells * (fixed + per_iter * iters / K)
-    if args.precision == "mixed":
+    if args.precision != "fp64":
         per_launch_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     achieved = per_launch_bytes / avg_launch_s / 1e9
@@ -198,7 +222,7 @@ def bench_fine(args):
                    "poisson": _solver_name(args) + " rtol 1e-10",
                    "precision": args.precision},
         "cg_iters_per_step": iters / K,
-        "inner_rtol": args.eta if args.precision == "mixed" else None,
+        "inner_rtol": _eta(args) if args.precision != "fp64" else None,
         "velocity_rel_l2_vs_fp64": err_vs_fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
@@ -221,10 +245,11 @@ def cpu_baseline_fine(args, host_state, t):
     O.build()
     n = 128
     g = O.Grid(n, n, n, re=1000.0, solid=_fine_solid(args), slip_obstacles=args.slip)
-    prec = 1 if args.precision == "mixed" else 0
+    prec = {"fp64": 0, "mixed": 1, "mixed_ru": 2}[args.precision]
     nsteps = 2
     t0 = time.perf_counter()
-    _, iters, _, st = O.fine_steps(g, host_state, nsteps, 5e-4, prec=prec, rtol=1e-10)
+    _, iters, _, st = O.fine_steps(g, host_state, nsteps, 5e-4, prec=prec, rtol=1e-10, eta=_eta(args),
+                                   max_outer=_max_outer(args))
     wall = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": nsteps * n ** 3 / wall, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
@@ -237,7 +262,7 @@ def bench_poisson(args):
     from paper_1705_06149_amd import nsp
 
     n, B = 128, 32
-    prec = nsp.MIXED if args.precision == "mixed" else nsp.FP64
+    prec = nsp.MIXED if args.precision != "fp64" else nsp.FP64
     its = 100
     h = nsp.Handle(n, n, n, re=1000.0, max_batch=B)
     g = torch.Generator(device="cuda").manual_seed(0)
@@ -292,7 +317,7 @@ def bench_parareal(args):
     DT = args.coarse_dt if args.coarse_dt is not None else (1e-2 if cgrid else 5e-3)
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
-    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=args.eta)
+    mixed = _parareal_fine_opts(args, nsp)
     # the serial coarse sweep is a batch of one, latency-bound: FP32 saves no
     # time there and each defect-correction restart adds iterations, so G
     # solves in FP64 (measured at 96^3: 2.0 s per sweep vs 2.8 s mixed)
@@ -311,7 +336,7 @@ def bench_parareal(args):
     serial = time.perf_counter() - t0
     ref = tuple(a[0].clone() for a in y)
     # batched mixed-precision Parareal, launch shape autotuned for the full batch
-    tuned_wg, tuned_planes, tuned_items = h.autotune(N, nsp.MIXED)
+    tuned_wg, tuned_planes, tuned_items = h.autotune(N, mixed.prec)
     shapes = h.shapes()
     Y = tuple(torch.zeros((N + 1,) + s, dtype=torch.float64, device="cuda") for s in shapes)
     Fk = tuple(torch.zeros((N,) + s, dtype=torch.float64, device="cuda") for s in shapes)
@@ -364,7 +389,7 @@ def bench_parareal(args):
                      "k_persistent_share_of_wall": kms * 1e-3 / par},
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
                    "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n],
-                   "fine_poisson": "mixed, eta %g" % args.eta, "coarse_poisson": "fp64"},
+                   "fine_poisson": "%s, inner %g" % (args.parareal_fine, mixed.inner_rtol), "coarse_poisson": "fp64"},
         "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
         "serial_equiv_cell_updates_per_s": cells * nf / par,
         "executed_cell_updates_per_s": sum(x["cell_steps"] for x in kst) / par,
@@ -390,7 +415,7 @@ def bench_obstacles(args):
     DT = args.coarse_dt if args.coarse_dt is not None else 2.5e-3
     tol = 1e-6
     fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
-    mixed = nsp.PoissonOpts(rtol=1e-10, prec=nsp.MIXED, inner_rtol=args.eta)
+    mixed = _parareal_fine_opts(args, nsp)
     # the serial coarse sweep is a batch of one, latency-bound: FP32 saves no
     # time there and each defect-correction restart adds iterations, so G
     # solves in FP64 (measured at 96^3: 2.0 s per sweep vs 2.8 s mixed)
@@ -703,7 +728,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 5; adjoint mode: 1)")
     ap.add_argument("--mode", choices=["fine", "poisson", "parareal", "obstacles", "sim1", "sim2", "adjoint", "copy"],
                     default="fine")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_ru"], default="fp64",
+                    help="Poisson precision: FP64, FP32 inner solves restarted at each FP64 correction, or one "
+                         "FP32 solve with reliable updates")
     ap.add_argument("--solver", choices=["pcg", "bicgstab", "pcg_sr"], default="pcg",
                     help="pressure solver: Jacobi-PCG, the paper's BiCGStab (FP64), or Jacobi-PCG with one "
                          "merged reduction per iteration (FP64)")
@@ -726,7 +753,10 @@ def main():
     ap.add_argument("--obstacles", action="store_true",
                     help="fine mode: the 128^3 cavity with the seeded cuboid obstacles of the obstacle batch")
     ap.add_argument("--slip", action="store_true", help="with --obstacles: free-slip obstacle walls")
-    ap.add_argument("--eta", type=float, default=1e-5, help="inner FP32 tolerance of the mixed Poisson solve")
+    ap.add_argument("--parareal-fine", choices=["fp64", "mixed", "mixed_ru"], default="mixed_ru",
+                    help="Parareal modes: Poisson precision of the batched fine sweeps")
+    ap.add_argument("--eta", type=float, default=None,
+                    help="mixed: inner FP32 tolerance (default 1e-5); mixed_ru: update factor (default 0.01)")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="mixed fine mode: also run the timed steps in FP64 and report the velocity difference")
     args = ap.parse_args()

@@ -47,8 +47,12 @@ typedef enum {
 } nsp_status;
 
 typedef enum {
-    NSP_FP64 = 0,  /* Jacobi-PCG in FP64 */
-    NSP_MIXED = 1  /* FP32 Jacobi-PCG inner solves, FP64 defect correction */
+    NSP_FP64 = 0,     /* Jacobi-PCG in FP64 */
+    NSP_MIXED = 1,    /* FP32 Jacobi-PCG inner solves, FP64 defect correction (each inner solve
+                         restarts CG from the new residual) */
+    NSP_MIXED_RU = 2  /* one FP32 Jacobi-PCG run with reliable updates: the FP64 residual replaces
+                         the FP32 one whenever it has fallen by inner_rtol, keeping the search
+                         direction, so the Krylov space survives the corrections */
 } nsp_precision;
 
 typedef enum {
@@ -92,7 +96,13 @@ typedef struct {
  * Neumann Laplacian, stops when ||b - A p||_2 <= rtol ||b||_2 (recursive
  * residual for FP64, recomputed FP64 residual for mixed).  Mixed: each inner
  * FP32 solve stops at relative residual inner_rtol or maxit iterations; at
- * most max_outer inner solves.  solver NSP_BICGSTAB (FP64 only, else
+ * most max_outer inner solves.  Mixed with reliable updates: an update
+ * (e folded into p in FP64, FP64 residual recomputed and tested, its FP32
+ * copy replacing the recursive residual) whenever the FP32 residual has
+ * fallen by inner_rtol since the last one (0.01 is a good value), below
+ * rtol ||b||, or at maxit; at most max_outer updates (count them in the
+ * dozens: about one per factor inner_rtol of residual reduction); `outer`
+ * reports the updates, `iters` the FP32 iterations.  solver NSP_BICGSTAB (FP64 only, else
  * NSP_ERR_UNSUPPORTED): right-preconditioned BiCGStab from the same warm
  * start, restarted from the true residual after a breakdown (at most 16
  * times); its workspace (three vectors per slice) is allocated on first use.

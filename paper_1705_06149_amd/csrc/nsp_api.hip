@@ -225,7 +225,8 @@ nsp_status ensure_launch_res(nsp_handle *h, int nslices, int ntiles) {
 }
 
 bool valid_opts(const nsp_poisson_opts *o) {
-    return o && o->rtol >= 0 && o->maxit >= 0 && (o->prec == NSP_FP64 || o->prec == NSP_MIXED) &&
+    return o && o->rtol >= 0 && o->maxit >= 0 &&
+           (o->prec == NSP_FP64 || o->prec == NSP_MIXED || o->prec == NSP_MIXED_RU) &&
            (o->prec == NSP_FP64 || (o->inner_rtol > 0 && o->inner_rtol < 1 && o->max_outer >= 0)) &&
            (o->solver == NSP_PCG || o->solver == NSP_BICGSTAB || o->solver == NSP_PCG_SR);
 }
@@ -399,7 +400,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     // workgroups from the finest tiling, then the tile depth for that count
     const int units = std::max(ntiles, cgtiles);
     int wg = workgroups_override > 0 ? std::min(workgroups_override, std::min(h->max_wg, units))
-                                     : auto_workgroups(h, nslices, o->prec == NSP_MIXED ? 1 : 0, units);
+                                     : auto_workgroups(h, nslices, o->prec != NSP_FP64 ? 1 : 0, units);
     if (wg < 1) wg = 1;
     if (wg > kMaxWG) wg = kMaxWG;
     GroupDesc lg[kMaxGroups];
@@ -422,12 +423,12 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     int depth = h->force_depth, items = h->force_items;
     if (depth <= 0 && items <= 0)
         for (const TuneEntry &t : h->tuned)
-            if (t.batch == nslices && t.prec == (o->prec == NSP_MIXED ? 1 : 0)) {
+            if (t.batch == nslices && t.prec == (o->prec != NSP_FP64 ? 1 : 0)) {
                 depth = t.depth;
                 items = t.items;
             }
     int cgparts = 0;
-    layout_groups(lg, ngroups, wg, depth, items, o->prec == NSP_MIXED, &ntiles, &cgtiles, &cgparts);
+    layout_groups(lg, ngroups, wg, depth, items, o->prec != NSP_FP64, &ntiles, &cgtiles, &cgparts);
     const int pstride = std::max(ntiles, cgparts);
     if (ws) {
         if (nslices > ws->cap_slices || pstride > ws->cap_tiles)
@@ -449,7 +450,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.pstride = pstride;
     P.mode = mode;
     P.nsteps = nsteps;
-    P.prec = o->prec == NSP_MIXED ? 1 : 0;
+    P.prec = o->prec == NSP_MIXED ? 1 : (o->prec == NSP_MIXED_RU ? 2 : 0);
     P.maxit = o->maxit;
     P.max_outer = o->max_outer;
     P.xcd_remap = 1;
@@ -463,7 +464,8 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     {
         // registers hold the CG vectors when every CG tile has its own
         // workgroup (PCG, FP64 or the FP32 inner solve)
-        bool rr = o->solver == NSP_PCG && cgtiles <= wg;
+        // (the reliable-update mixed solve runs in the streaming phases)
+        bool rr = o->solver == NSP_PCG && o->prec != NSP_MIXED_RU && cgtiles <= wg;
         for (int g = 0; g < ngroups; ++g) {
             const GroupDesc &X = lg[g];
             rr = rr && X.cby > 0 && X.cni == 1 && X.cbz == (1 << X.zsh) && (X.cbz == 4 || X.cbz == 8) &&
@@ -505,7 +507,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
             S.cell_steps += cells * (mode == MODE_FINE ? nsteps : 1);
             S.cg_cell_iters += it;
             S.cell_sweeps += cells * c.tot_outer;
-            if (P.prec == 1) {
+            if (P.prec != 0) {
                 S.cg32_cell_iters += it;
                 S.mixed_cell_sweeps += cells * c.tot_outer;
             } else if (P.solver == NSP_BICGSTAB) {
@@ -1197,7 +1199,7 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
     // column-tile depths in planes (from the grid's zsub up to 32); flat tiles have none
     std::vector<int> depths = {1}, itemss = {1};
     if (h->crb > 0) depths = h->zsh == 2 ? std::vector<int>{4, 8, 16, 32} : std::vector<int>{8, 16, 32};
-    if (h->crb > 0 && prec == NSP_MIXED && h->cnb >= 2) itemss = {1, 2};
+    if (h->crb > 0 && prec != NSP_FP64 && h->cnb >= 2) itemss = {1, 2};
     nsp_launch_stats keep_stats[3];
     for (int m = 0; m < 3; ++m) keep_stats[m] = h->stats[m];  // the trial launches are not counted
     int best = cands[0], best_depth = depths[0], best_items = itemss[0];
@@ -1224,7 +1226,7 @@ nsp_status nsp_autotune(nsp_handle *h, int batch, nsp_precision prec, void *stre
         }
     h->force_depth = h->force_items = 0;
     for (int m = 0; m < 3; ++m) h->stats[m] = keep_stats[m];
-    const int pr = prec == NSP_MIXED ? 1 : 0;
+    const int pr = prec != NSP_FP64 ? 1 : 0;
     const int keep_depth = h->crb > 0 ? best_depth : 0, keep_items = h->crb > 0 ? best_items : 0;
     bool found = false;
     for (TuneEntry &t : h->tuned)

@@ -125,7 +125,7 @@ struct KParams {
     int pstride;           // max(flat tiles, CG partials): stride of the partial-sum rows
     int mode;
     int nsteps;
-    int prec;              // 0 fp64, 1 mixed
+    int prec;              // 0 fp64, 1 mixed (restarted FP32 solves), 2 mixed with reliable updates
     int maxit, max_outer;
     int xcd_remap;         // contiguous tile ranges per XCD
     int solver;            // 0: Jacobi-PCG, 1: Jacobi-BiCGStab (FP64), 2: single-reduction Jacobi-PCG (FP64)

@@ -39,7 +39,7 @@ __device__ __forceinline__ const GAS T *gp(const T *p) { return (const GAS T *)p
 
 enum Red : int {
     R_NONE = 0, R_MEANB, R_INIT, R_A, R_B, R_TRUE, R_OUT0, R_OUT, R_CAST, R_A32, R_B32, R_BG1, R_BG2, R_BG3,
-    R_SR0, R_SR
+    R_SR0, R_SR, R_CAST0RU, R_B32RU, R_OUTRU, R_CASTRU
 };
 
 // a * b + c with one rounding.  The library is compiled with
@@ -391,7 +391,9 @@ struct Runner {
     __device__ __forceinline__ static int nq_of(int rid) {
         switch (rid) {
         case R_MEANB: case R_A: case R_A32: case R_BG1: return 1;
-        case R_B: case R_B32: case R_CAST: case R_BG2: case R_BG3: return 2;
+        case R_B: case R_B32: case R_CAST: case R_BG2: case R_BG3: case R_CAST0RU: case R_B32RU: case R_CASTRU:
+            return 2;
+        case R_OUTRU: return 3;
         case R_TRUE: case R_OUT: case R_SR0: case R_SR: return 3;
         case R_INIT: case R_OUT0: return 4;
         default: return 0;
@@ -429,7 +431,7 @@ struct Runner {
         __shared__ int s_any;
         const int nq = nq_of(rid);
         const int cg = (rid == R_A || rid == R_B || rid == R_A32 || rid == R_B32 || rid == R_BG1 || rid == R_BG2 ||
-                        rid == R_SR0 || rid == R_SR) ? 1 : 0;
+                        rid == R_SR0 || rid == R_SR || rid == R_B32RU) ? 1 : 0;
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         for (int s = wv; s < P.nslices; s += kWaves) {
             const GAS double *pp = gp(P.part) + (long)(buf * kNQ) * P.pstride + s_pb[2 * s + cg];
@@ -736,6 +738,71 @@ struct Runner {
             if (S[0] == 0.0 || c.omega == 0.0) { c.active = 0; return 0; }  // breakdown: restart
             c.beta = (S[0] / c.rz) * (c.alpha / c.omega);
             c.rz = S[0];
+            return 1;
+        }
+        case R_CAST0RU: {
+            // reliable updates, first FP32 residual: S0 = ||rt||^2, S1 = <rt, z>
+            if (!c.need) return 0;
+            c.need = 0;
+            c.r0 = sqrt(S[0]);
+            c.rz = S[1];
+            c.it_in = 0;
+            c.first = 1;
+            c.active = (isfinite(c.r0) && c.r0 > 0.0 && P.maxit > 0) ? 1 : 0;
+            if (!c.active) {
+                // nothing to iterate on: the FP64 residual decides at once
+                c.step_status = (P.maxit > 0 && isfinite(c.r0)) ? c.step_status : 2;
+                finish_solve(c);
+            }
+            return c.active;
+        }
+        case R_B32RU: {
+            // after an FP32 step: S0 = <rt, z>, S1 = ||rt||^2.  A reliable
+            // update is due when the residual has fallen by eta since the last
+            // one, below the tolerance, or at the iteration limit
+            if (!c.active) return 0;
+            c.it_in += 1;
+            c.it += 1;
+            const double rn = sqrt(S[1]);
+            if (rn <= P.eta * c.r0 || rn <= P.rtol * c.bnorm || c.it >= P.maxit || !isfinite(rn)) {
+                c.need = 1;
+                return 3;
+            }
+            c.beta = S[0] / c.rz;
+            c.rz = S[0];
+            c.first = 0;
+            return 1;
+        }
+        case R_OUTRU: {
+            // FP64 residual after a reliable update: S0 = ||r||^2, S1 = sum r,
+            // S2 = sum p
+            if (!c.need) return c.active ? 1 : 0;
+            c.outer += 1;
+            c.res_true = sqrt(S[0]);
+            c.rel_true = c.res_true / c.bnorm;
+            c.mean_p = S[2] / nf;
+            int stop = 0;
+            if (!isfinite(c.res_true)) { c.step_status = 3; stop = 1; }
+            else if (c.res_true <= P.rtol * c.bnorm) stop = 1;
+            else if (c.outer >= P.max_outer || c.it >= P.maxit) { c.step_status = 2; stop = 1; }
+            if (stop) {
+                c.need = 0;
+                c.active = 0;
+                finish_solve(c);
+                return 0;
+            }
+            c.mean_r = S[1] / nf;
+            return 3;
+        }
+        case R_CASTRU: {
+            // the new FP32 residual: S0 = ||rt||^2, S1 = <rt, z>; the search
+            // direction is kept, beta from the new <rt, z>
+            if (!c.need) return c.active ? 1 : 0;
+            c.need = 0;
+            c.r0 = sqrt(S[0]);
+            c.beta = S[1] / c.rz;
+            c.rz = S[1];
+            c.first = 0;
             return 1;
         }
         case R_SR0: {
@@ -2194,9 +2261,13 @@ struct Runner {
     }
 
     // Mixed: FP64 residual r = b - A p.  First sweep also makes b mean-free.
-    // partials ||r||^2, sum r, sum p, ||b||^2
-    __device__ __forceinline__ void phase_out(bool first, bool from_user) {
-        tiles<4>([&](const GAS GroupDesc &, int gs) { return !first && (ctl(gs).done || ctl(gs).zero); },
+    // partials ||r||^2, sum r, sum p, ||b||^2.  need_only: the slices with a
+    // reliable update pending.
+    __device__ __forceinline__ void phase_out(bool first, bool from_user, bool need_only = false) {
+        tiles<4>([&](const GAS GroupDesc &, int gs) {
+                     if (need_only) return !ctl(gs).need;
+                     return !first && (ctl(gs).done || ctl(gs).zero);
+                 },
                  [&](const GAS GroupDesc &G, int sl, int gs, int c, double *acc) {
                      const long off = (long)sl * G.ncells;
                      double GAS *b = gp(G.b) + off;
@@ -2420,11 +2491,62 @@ struct Runner {
         return true;
     }
 
+    // Mixed precision with reliable updates: one FP32 CG run per solve whose
+    // search direction survives the updates (FP64 residual, fold of e into
+    // p, new FP32 residual), in the streaming phases
+    __device__ __forceinline__ bool solve_mixed_ru(bool from_user) {
+        phase_out(true, from_user);
+        int any = sync(R_OUT0);
+        if (any < 0) return false;
+        if (any & 2) {
+            phase_cold(false);
+            if (sync(R_NONE) < 0) return false;
+            phase_out(false, false);
+            any = sync(R_OUT);
+            if (any < 0) return false;
+        }
+        if (!(any & 1)) return true;
+        phase_cast();
+        int act = sync(R_CAST0RU);
+        if (act < 0) return false;
+        int iter = 0;
+        while (act > 0) {
+            const int par = iter & 1;
+            phase_A<float>(par);
+            if (sync(R_A32) < 0) return false;
+            phase_B<float>(par);
+            act = sync(R_B32RU);
+            if (act < 0) return false;
+            ++iter;
+            if (act & 2) {
+                phase_update();
+                if (sync(R_NONE) < 0) return false;
+                phase_out(false, false, true);
+                act = sync(R_OUTRU);
+                if (act < 0) return false;
+                if (act & 2) {
+                    phase_cast();
+                    act = sync(R_CASTRU);
+                    if (act < 0) return false;
+                }
+            }
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ bool solve_prec(bool from_user) {
+        if (P.prec == 0) return solve_fp64(from_user);
+        if constexpr (!RR) {
+            if (P.prec == 2) return solve_mixed_ru(from_user);
+        }
+        return solve_mixed(from_user);
+    }
+
     __device__ __forceinline__ void run() {
         if (P.mode == MODE_POISSON) {
             phase_meanb_user();
             if (sync(R_MEANB) < 0) return;
-            const bool ok = P.prec == 0 ? solve_fp64(true) : solve_mixed(true);
+            const bool ok = solve_prec(true);
             if (!ok) return;
             phase_gauge();
             return;
@@ -2443,7 +2565,7 @@ struct Runner {
             if (sync(R_NONE) < 0) return;
             phase_rhs();
             if (sync(R_MEANB) < 0) return;
-            const bool ok = P.prec == 0 ? solve_fp64(false) : solve_mixed(false);
+            const bool ok = solve_prec(false);
             if (!ok) return;
             phase_corr();
             // the correction reads neighbouring pressures: no cell may be

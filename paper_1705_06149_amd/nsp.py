@@ -27,7 +27,7 @@ NSP_OK, NSP_ERR_ARG, NSP_ERR_NOT_CONVERGED, NSP_ERR_NONFINITE, NSP_ERR_HIP, NSP_
 PCG, BICGSTAB, PCG_SR = 0, 1, 2
 _STATUS = {0: "NSP_OK", 1: "NSP_ERR_ARG", 2: "NSP_ERR_NOT_CONVERGED", 3: "NSP_ERR_NONFINITE",
            4: "NSP_ERR_HIP", 5: "NSP_ERR_UNSUPPORTED"}
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_RU = 0, 1, 2
 
 
 class NSPError(RuntimeError):

@@ -27,14 +27,15 @@ def N(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("prec,solver", [(0, 0), (1, 0), (0, 1), (0, 2)])
+@pytest.mark.parametrize("prec,solver", [(0, 0), (1, 0), (0, 1), (0, 2), (2, 0)])
 def test_repeat_runs_are_bitwise_equal(gpu, prec, solver):
     n = 64
     _say("repeat runs", n, "prec", prec, "solver", solver)
     solid = inputs.obstacle_mask(n, 5)
     h = gpu.Handle(n, n, n, re=1000.0, solid=solid, max_batch=2)
     st = inputs.random_state(n, n, n, seed=2, scale=0.2, pscale=0.0)
-    opts = gpu.PoissonOpts(rtol=1e-10, prec=prec, solver=solver)
+    opts = gpu.PoissonOpts(rtol=1e-10, prec=prec, solver=solver, inner_rtol=0.01 if prec == 2 else 1e-5,
+                           max_outer=64 if prec == 2 else 8)
     outs = []
     for rep in range(2):
         y = tuple(T(np.stack([a, a[::-1].copy()])) for a in st)
