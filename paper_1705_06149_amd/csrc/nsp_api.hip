@@ -464,8 +464,7 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     {
         // registers hold the CG vectors when every CG tile has its own
         // workgroup (PCG, FP64 or the FP32 inner solve)
-        // (the reliable-update mixed solve runs in the streaming phases)
-        bool rr = o->solver == NSP_PCG && o->prec != NSP_MIXED_RU && cgtiles <= wg;
+        bool rr = o->solver == NSP_PCG && cgtiles <= wg;
         for (int g = 0; g < ngroups; ++g) {
             const GroupDesc &X = lg[g];
             rr = rr && X.cby > 0 && X.cni == 1 && X.cbz == (1 << X.zsh) && (X.cbz == 4 || X.cbz == 8) &&

@@ -83,6 +83,7 @@ struct SliceCtl {
     int need;     // mixed: another defect-correction sweep is needed
     int zero;     // right-hand side is zero: solution is p = 0
     int cold;     // the warm start was worse than none: the solve restarts from p = 0
+    int fresh;    // reliable update: the FP32 residual was just replaced (until the next phase A)
     int outer;    // restarts / sweeps of the current step
     int done;     // current solve finished for this slice
     int status;   // worst status over the call

@@ -701,6 +701,7 @@ struct Runner {
         }
         case R_A32:
             if (c.active) c.alpha = c.rz / S[0];
+            c.fresh = 0;
             return 0;
         case R_B32: {
             if (!c.active) return 0;
@@ -799,6 +800,7 @@ struct Runner {
             // direction is kept, beta from the new <rt, z>
             if (!c.need) return c.active ? 1 : 0;
             c.need = 0;
+            c.fresh = 1;
             c.r0 = sqrt(S[0]);
             c.beta = S[1] / c.rz;
             c.rz = S[1];
@@ -1546,7 +1548,7 @@ struct Runner {
     // q = A d, partial <d, q>
     template <class T, int K, bool WT>
     __device__ __forceinline__ void rr_phase_A(const GAS GroupDesc &G, const ColPos<1> &P0, RRState<T, K> &S,
-                                               bool first, T beta, const GAS T *__restrict__ rg,
+                                               bool first, bool fresh, T beta, const GAS T *__restrict__ rg,
                                                const GAS T *__restrict__ pubz, const GAS T *__restrict__ dprev,
                                                GAS T *__restrict__ dcur, bool edge, int z0, int pbase, int yb) {
         const int gb = group_index(G) * 64;
@@ -1554,9 +1556,10 @@ struct Runner {
         const GAS uint8_t *fl = gp(G.flags);
         // a neighbouring tile's d: at a (re)start z formed from r as the
         // streaming phase does, else beta d_prev + z from the published values
+        // (z from r in memory right after a reliable update replaced r)
         auto dat = [&](long c) -> T {
             if (first) return rg[c] * idg_of<T>(gb, fl[c]);
-            return fmaT(beta, dprev[c], pubz[c]);
+            return fmaT(beta, dprev[c], fresh ? rg[c] * idg_of<T>(gb, fl[c]) : pubz[c]);
         };
         long cm, cp;
         rr_zcells<K>(G, P0, z0, cm, cp);
@@ -1670,13 +1673,41 @@ struct Runner {
             GAS T *dcur = pubd[iter & 1];
             const GAS T *dprev = pubd[(iter + 1) & 1];
             if (run)
-                rr_phase_A<T, K, WT>(G, P0, S, c.first, c.first ? T(0) : (T)c.beta, rg, pubz, dprev, dcur, edge, z0,
-                                     pbase, yb);
+                rr_phase_A<T, K, WT>(G, P0, S, c.first, c.fresh, c.first ? T(0) : (T)c.beta, rg, pubz, dprev, dcur,
+                                     edge, z0, pbase, yb);
             if (sync(ra) < 0) return -1;
             if (run) rr_phase_B<T, K, WT>(G, P0, S, (T)c.alpha, pubz, dcur, edge, z0, pbase, yb);
             any = sync(rb);
             if (any < 0) return -1;
             ++iter;
+            if (rb == R_B32RU && (any & 2)) {
+                // reliable update of the slices that asked for one: their e to
+                // memory, the FP64 phases, then the new FP32 residual into the
+                // registers; d stays
+                if (has && c.need) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if (P0.act[0] && (rr_flag(S, k) & FL_FLUID)) xg[P0.c0[0] + (long)k * sz] = S.x[k];
+                }
+                if (sync(R_NONE) < 0) return -1;
+                phase_update();
+                if (sync(R_NONE) < 0) return -1;
+                phase_out(false, false, true);
+                any = sync(R_OUTRU);
+                if (any < 0) return -1;
+                if (any & 2) {
+                    phase_cast();
+                    any = sync(R_CASTRU);
+                    if (any < 0) return -1;
+                }
+                if (has && c.fresh) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        S.r[k] = rg[P0.c0[0] + (long)k * sz];
+                        S.x[k] = T(0);
+                    }
+                }
+            }
         }
         if (has) {
 #pragma unroll
@@ -2509,36 +2540,38 @@ struct Runner {
         phase_cast();
         int act = sync(R_CAST0RU);
         if (act < 0) return false;
-        int iter = 0;
-        while (act > 0) {
-            const int par = iter & 1;
-            phase_A<float>(par);
-            if (sync(R_A32) < 0) return false;
-            phase_B<float>(par);
-            act = sync(R_B32RU);
-            if (act < 0) return false;
-            ++iter;
-            if (act & 2) {
-                phase_update();
-                if (sync(R_NONE) < 0) return false;
-                phase_out(false, false, true);
-                act = sync(R_OUTRU);
+        if constexpr (RR) {
+            return rr_cg<float>(act, R_A32, R_B32RU) >= 0;
+        } else {
+            int iter = 0;
+            while (act > 0) {
+                const int par = iter & 1;
+                phase_A<float>(par);
+                if (sync(R_A32) < 0) return false;
+                phase_B<float>(par);
+                act = sync(R_B32RU);
                 if (act < 0) return false;
+                ++iter;
                 if (act & 2) {
-                    phase_cast();
-                    act = sync(R_CASTRU);
+                    phase_update();
+                    if (sync(R_NONE) < 0) return false;
+                    phase_out(false, false, true);
+                    act = sync(R_OUTRU);
                     if (act < 0) return false;
+                    if (act & 2) {
+                        phase_cast();
+                        act = sync(R_CASTRU);
+                        if (act < 0) return false;
+                    }
                 }
             }
+            return true;
         }
-        return true;
     }
 
     __device__ __forceinline__ bool solve_prec(bool from_user) {
         if (P.prec == 0) return solve_fp64(from_user);
-        if constexpr (!RR) {
-            if (P.prec == 2) return solve_mixed_ru(from_user);
-        }
+        if (P.prec == 2) return solve_mixed_ru(from_user);
         return solve_mixed(from_user);
     }
 
