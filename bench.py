@@ -81,6 +81,13 @@ def _parareal_fine_opts(args, nsp):
                            else 8)
 
 
+def _model_bytes(args, cells, iters_per_step, sweeps_per_launch):
+    """The method's algorithmic bytes of one fine-step launch"""
+    if args.precision == "fp64":
+        return cells * (MODEL_STEP_FIXED + MODEL_CG_ITER * iters_per_step)
+    return cells * (MODEL_STEP_FIXED + 0.5 * MODEL_CG_ITER * iters_per_step) + cells * 40.0 * sweeps_per_launch
+
+
 def _solver(args):
     from paper_1705_06149_amd import nsp
     return {"pcg": nsp.PCG, "bicgstab": nsp.BICGSTAB, "pcg_sr": nsp.PCG_SR}[args.solver]
@@ -192,15 +199,19 @@ def bench_fine(args):
         h.fine_step(y64, t - K * dt, t, dt, o64)
         err_vs_fp64 = float(torch.sqrt(sum(((y[c] - y64[c]) ** 2).sum() for c in range(3)) /
                                        sum((y64[c] ** 2).sum() for c in range(3))))
+    # bytes by the kernels' own phase layout
     per_iter = _bytes_per_iter(args)
     fixed = BYTES_STEP_FIXED[args.precision] + (BYTES_SR_START if args.solver == "pcg_sr" else 0.0)
-    per_launch_bytes = cells * (fixed + per_iter * iters / K)
+    layout_bytes = cells * (fixed + per_iter * iters / K)
     if args.precision != "fp64":
-        per_launch_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
+        layout_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
-    achieved = per_launch_bytes / avg_launch_s / 1e9
-    # the method's own byte model (FP64 CG), independent of the kernel layout
-    model_bytes = cells * (MODEL_STEP_FIXED + MODEL_CG_ITER * iters / K)
+    # the roofline's algorithmic bytes: the method's byte model per cell and
+    # step, 112 B plus 80 B per FP64 CG iteration (mixed: 40 B per FP32
+    # iteration and 40 B per FP64 correction sweep), independent of how the
+    # kernels lay the phases out or keep vectors on chip
+    model_bytes = _model_bytes(args, cells, iters / K, info[0]["outer"])
+    achieved = model_bytes / avg_launch_s / 1e9
     sfx = "" if args.solver == "pcg" else "_" + args.solver
     traffic = (_traffic_from_profile("k_persistent_cavity128_%s%s_pmc.txt" % (args.precision, sfx))
                if not args.obstacles else None)
@@ -228,9 +239,10 @@ def bench_fine(args):
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_persistent (one fused fine step per launch)",
                      "avg_launch_ms": 1e3 * avg_launch_s,
-                     "algorithmic_bytes_per_launch": per_launch_bytes,
-                     "model_bytes_per_launch": model_bytes,
-                     "model_frac": model_bytes / avg_launch_s / 1e9 / PEAK_HBM_GBS},
+                     "algorithmic_bytes_per_launch": model_bytes,
+                     "byte_model": "112 + 80 I B per cell and step (mixed: 112 + 40 I32 + 40 per sweep)",
+                     "kernel_layout_bytes_per_launch": layout_bytes,
+                     "kernel_layout_frac": layout_bytes / avg_launch_s / 1e9 / PEAK_HBM_GBS},
     }
     out["hbm_measured_GB_per_s"] = traffic / avg_launch_s / 1e9 if traffic else None
     h.close()
@@ -246,15 +258,33 @@ def cpu_baseline_fine(args, host_state, t):
     n = 128
     g = O.Grid(n, n, n, re=1000.0, solid=_fine_solid(args), slip_obstacles=args.slip)
     prec = {"fp64": 0, "mixed": 1, "mixed_ru": 2}[args.precision]
-    nsteps = 2
-    t0 = time.perf_counter()
-    _, iters, _, st = O.fine_steps(g, host_state, nsteps, 5e-4, prec=prec, rtol=1e-10, eta=_eta(args),
-                                   max_outer=_max_outer(args))
-    wall = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nsteps * n ** 3 / wall, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+    threads = O.num_threads()
+    runs = {}
+    for label, nthr, nsteps in (("all", threads, 2), ("one", 1, 1)):
+        O.set_num_threads(nthr)
+        t0 = time.perf_counter()
+        _, iters, _, st = O.fine_steps(g, host_state, nsteps, 5e-4, prec=prec, rtol=1e-10, eta=_eta(args),
+                                       max_outer=_max_outer(args))
+        runs[label] = (nsteps, time.perf_counter() - t0, int(iters.sum()))
+    O.set_num_threads(threads)
+    (ns, wall, it), (n1, wall1, it1) = runs["all"], runs["one"]
+    return {"value": ns * n ** 3 / wall, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": "%d fine steps of the 128^3 cavity from the benchmark's warmed state "
-                      "(%d CG iterations, %.1f s)" % (nsteps, int(iters.sum()), wall)}
+                      "(%d CG iterations, %.1f s, %d threads)" % (ns, it, wall, threads),
+            "one_core": {"value": n1 * n ** 3 / wall1, "cores": 1,
+                         "sample": "%d fine step from the same state (%d CG iterations, %.1f s)" % (n1, it1, wall1)},
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_poisson(args):
@@ -283,9 +313,12 @@ def bench_poisson(args):
     wall = time.perf_counter() - t0
     cells = B * n ** 3
     per_launch = cells * _bytes_per_iter(args) * its
-    if args.precision == "mixed":
+    if args.precision != "fp64":
         per_launch += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
     achieved = per_launch / (np.mean(ms) * 1e-3) / 1e9
+    # the method's byte model: 80 B per cell and CG iteration (FP32: 40 B)
+    model = cells * its * (MODEL_CG_ITER if args.precision == "fp64" else 0.5 * MODEL_CG_ITER)
+    model_achieved = model / (np.mean(ms) * 1e-3) / 1e9
     out = {
         "metric": "Poisson HBM GB/s", "value": achieved, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
@@ -293,12 +326,15 @@ def bench_poisson(args):
         "data": "synthetic",
         "config": {"workload": "poisson_32x128cube", "batch": B, "grid": [n, n, n], "iterations": its,
                    "solver": args.solver, "precision": args.precision},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS,
+        "roofline": {"bound": "hbm", "achieved": model_achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": model_achieved / PEAK_HBM_GBS,
                      "traffic": _traffic_from_profile("k_persistent_poisson32x128_%s%s_pmc.txt" % (
                          args.precision, "" if args.solver == "pcg" else "_" + args.solver)),
                      "kernel": "k_persistent (%d CG iterations on %d grids per launch)" % (its, B),
-                     "avg_launch_ms": float(np.mean(ms)), "algorithmic_bytes_per_launch": per_launch},
+                     "avg_launch_ms": float(np.mean(ms)), "algorithmic_bytes_per_launch": model,
+                     "byte_model": "80 B per cell and CG iteration (FP32 inner: 40 B)",
+                     "kernel_layout_bytes_per_launch": per_launch,
+                     "kernel_layout_frac": achieved / PEAK_HBM_GBS},
     }
     t = out["roofline"]["traffic"]
     out["hbm_measured_GB_per_s"] = t / (np.mean(ms) * 1e-3) / 1e9 if t else None
@@ -372,7 +408,20 @@ def bench_parareal(args):
     cells = n ** 3
     nf = int(round(T / dt))
     kst = [h.launch_stats()["fine"]] + ([hc.launch_stats()["fine"]] if hc is not None else [])
-    kbytes = sum(_stats_bytes(x, BYTES_STEP_FIXED["fp64"]) for x in kst)
+    # one batched fine sweep (every slice over one slice length) from the
+    # Parareal slice starts, in FP64 and in the run's fine precision
+    sweep = {}
+    for name, o in (("fp64", fine64), (args.parareal_fine, mixed)):
+        ys = tuple(Y[c][:N].clone() for c in range(4))
+        _sync()
+        t1 = time.perf_counter()
+        inf = h.fine_step(ys, 0.0, T / N, dt, o)
+        _sync()
+        sweep[name] = {"s": time.perf_counter() - t1,
+                       "cg_iters_per_slice_step": sum(x["iters"] for x in inf) / float(nf)}
+        _log("batched fine sweep %s: %.2f s" % (name, sweep[name]["s"]))
+    klayout = sum(_stats_bytes(x, BYTES_STEP_FIXED["fp64"]) for x in kst)
+    kbytes = sum(_stats_model_bytes(x) for x in kst)
     kms = sum(x["ms"] for x in kst)
     klaunch = sum(x["launches"] for x in kst)
     kach = kbytes / (kms * 1e-3) / 1e9
@@ -386,11 +435,14 @@ def bench_parareal(args):
                      "kernel": "k_persistent (batched fine sweeps and coarse steps of the Parareal run)",
                      "avg_launch_ms": kms / max(klaunch, 1), "launches": klaunch,
                      "algorithmic_bytes_per_launch": kbytes / max(klaunch, 1),
+                     "kernel_layout_bytes_per_launch": klayout / max(klaunch, 1),
+                     "kernel_layout_frac": klayout / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                      "k_persistent_share_of_wall": kms * 1e-3 / par},
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
                    "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n],
                    "fine_poisson": "%s, inner %g" % (args.parareal_fine, mixed.inner_rtol), "coarse_poisson": "fp64"},
         "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
+        "batched_fine_sweep": sweep,
         "serial_equiv_cell_updates_per_s": cells * nf / par,
         "executed_cell_updates_per_s": sum(x["cell_steps"] for x in kst) / par,
         "end_state_rel_l2_vs_serial_fp64": err,
@@ -461,7 +513,8 @@ def bench_obstacles(args):
     nf = int(round(T / dt))
     # grouped launches count on the first handle
     kst = [h.launch_stats()["fine"] for h in hs]
-    kbytes = sum(_stats_bytes(x, BYTES_STEP_FIXED["fp64"]) for x in kst)
+    klayout = sum(_stats_bytes(x, BYTES_STEP_FIXED["fp64"]) for x in kst)
+    kbytes = sum(_stats_model_bytes(x) for x in kst)
     kms = sum(x["ms"] for x in kst)
     klaunch = sum(x["launches"] for x in kst)
     kach = kbytes / (kms * 1e-3) / 1e9
@@ -474,6 +527,8 @@ def bench_obstacles(args):
                      "kernel": "k_persistent (grouped fine sweeps and coarse steps of the Parareal run)",
                      "avg_launch_ms": kms / max(klaunch, 1), "launches": klaunch,
                      "algorithmic_bytes_per_launch": kbytes / max(klaunch, 1),
+                     "kernel_layout_bytes_per_launch": klayout / max(klaunch, 1),
+                     "kernel_layout_frac": klayout / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                      "k_persistent_share_of_wall": kms * 1e-3 / par},
         "config": {"workload": "obstacles_64_96_128", "grids": [n for n, _ in grids], "mask_seeds": [s for _, s in grids],
                    "slices_per_grid": N, "T": T, "dt": dt, "DT": DT, "jump_tol": tol,
@@ -560,7 +615,8 @@ def bench_paper_sim(args, sim):
     par = time.perf_counter() - t0
     nf = int(round(T / dt))
     kst = h.launch_stats()["fine"]
-    kbytes = _stats_bytes(kst, BYTES_STEP_FIXED["fp64"])
+    klayout = _stats_bytes(kst, BYTES_STEP_FIXED["fp64"])
+    kbytes = _stats_model_bytes(kst)
     kach = kbytes / max(kst["ms"] * 1e-3, 1e-12) / 1e9
     out = {
         "metric": "Parareal speedup vs serial fine", "value": serial / par, "unit": "x", "n_gpus": 1,
@@ -571,6 +627,7 @@ def bench_paper_sim(args, sim):
                      "kernel": "k_persistent (Parareal sweeps; a small grid, so latency-bound)",
                      "avg_launch_ms": kst["ms"] / max(kst["launches"], 1), "launches": kst["launches"],
                      "algorithmic_bytes_per_launch": kbytes / max(kst["launches"], 1),
+                     "kernel_layout_bytes_per_launch": klayout / max(kst["launches"], 1),
                      "k_persistent_share_of_wall": kst["ms"] * 1e-3 / par},
         "config": {"workload": "paper_sim%d" % sim, "grid": [nx, ny, nz], "domain": [1.0, 1.0, lz],
                    "periodic_z": True, "obstacles": "49 seeded cubes, median plane" if solid is not None else None,
@@ -599,6 +656,16 @@ def bench_paper_sim(args, sim):
 
 
 BYTES_PROJECT_FIXED = 163.0  # adjoint projection launch: a fine step's fixed bytes without the predictor
+
+
+def _stats_model_bytes(st):
+    """The method's algorithmic bytes of the launches in one entry of the
+    launch statistics: 112 B per cell and step, 80 B per FP64 CG iteration,
+    40 B per FP32 iteration and per mixed-precision sweep (BiCGStab, which
+    the byte model does not list, at its kernel's 139 B)."""
+    return (st["cell_steps"] * MODEL_STEP_FIXED + st["cg64_cell_iters"] * MODEL_CG_ITER +
+            st["cg32_cell_iters"] * 0.5 * MODEL_CG_ITER + st["bicg_cell_iters"] * BYTES_BICG_ITER +
+            st["mixed_cell_sweeps"] * 40.0)
 
 
 def _stats_bytes(st, fixed):

@@ -81,6 +81,8 @@ def lib():
         _lib.og_pcg_sr.restype = I
         _lib.og_pcg_mixed_ru.argtypes = [G, P, P, D, D, I, I, ctypes.POINTER(_Info)]
         _lib.og_pcg_mixed_ru.restype = I
+        _lib.og_num_threads.restype = I
+        _lib.og_set_num_threads.argtypes = [I]
         _lib.og_momentum_adjoint.argtypes = [G, P, P, P, D, P, P, P, P, P, P, P]
         _lib.og_stencil_form_value.argtypes = [G, I, P, I, I, I, I, I]
         _lib.og_stencil_form_value.restype = D
@@ -147,6 +149,15 @@ def _chk(a, shape, dtype=np.float64):
     a = np.ascontiguousarray(a, dtype=dtype)
     assert a.shape == tuple(shape), (a.shape, shape)
     return a
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().og_num_threads())
+
+
+def set_num_threads(n):
+    lib().og_set_num_threads(int(n))
 
 
 def smart(U, C, D):
