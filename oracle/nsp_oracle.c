@@ -74,6 +74,8 @@ typedef struct {
     const double *lid;    /* nz*(nx+1): wall value of u on the top face (y = Ly) */
     int periodic_z;       /* 1: periodic in z (the paper's runs), 0: walls at z = 0, Lz */
     int slip_obstacles;   /* 1: free-slip on obstacle surfaces, 0: no-slip (the paper's) */
+    int upwind;           /* 1: first-order upwind (donor-cell) convective face values instead
+                             of SMART: a coarse-propagator variant */
 } og_grid;
 
 typedef struct {
@@ -247,6 +249,8 @@ static double conv_flux(const og_grid *g, int c, const double *vel[3], const int
     if (abar == 0.0) return 0.0;
     double phi0 = phi[fidx(g, c, f)];
     double U, C, D;
+    /* donor cell: the face carries the value of the node on its upwind side,
+     * the C of the SMART triple below */
     if (s > 0) {
         if (abar > 0.0) { U = stencil_val(g, c, phi, f, d, -1); C = phi0; D = stencil_val(g, c, phi, f, d, 1); }
         else { U = stencil_val(g, c, phi, f, d, 2); C = stencil_val(g, c, phi, f, d, 1); D = phi0; }
@@ -254,6 +258,7 @@ static double conv_flux(const og_grid *g, int c, const double *vel[3], const int
         if (abar > 0.0) { U = stencil_val(g, c, phi, f, d, -2); C = stencil_val(g, c, phi, f, d, -1); D = phi0; }
         else { U = stencil_val(g, c, phi, f, d, 1); C = phi0; D = stencil_val(g, c, phi, f, d, -1); }
     }
+    if (g->upwind) return abar * C;
     return abar * og_smart(U, C, D);
 }
 

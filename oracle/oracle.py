@@ -40,7 +40,7 @@ class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
                 ("re", ctypes.c_double), ("solid", ctypes.c_void_p), ("lid", ctypes.c_void_p),
-                ("periodic_z", ctypes.c_int), ("slip_obstacles", ctypes.c_int)]
+                ("periodic_z", ctypes.c_int), ("slip_obstacles", ctypes.c_int), ("upwind", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -105,6 +105,7 @@ class Grid:
     lid: np.ndarray | None = None
     periodic_z: bool = False
     slip_obstacles: bool = False
+    upwind: bool = False  # first-order upwind (donor-cell) convection instead of SMART
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -124,7 +125,7 @@ class Grid:
         hx, hy, hz = self.h
         g = _Grid(self.nx, self.ny, self.nz, hx, hy, hz, float(self.re),
                   self.solid.ctypes.data if self.solid is not None else None, self.lid.ctypes.data,
-                  1 if self.periodic_z else 0, 1 if self.slip_obstacles else 0)
+                  1 if self.periodic_z else 0, 1 if self.slip_obstacles else 0, 1 if self.upwind else 0)
         return g
 
     def shapes(self):
@@ -444,6 +445,8 @@ def stencil_value(g: Grid, c, phi, f, d, m, as_form=False):
 
 
 def _no_periodic(g: Grid):
+    if g.upwind:
+        raise NotImplementedError("the adjoint differentiates the SMART fine propagator")
     if g.periodic_z:
         raise NotImplementedError("the adjoint is implemented for walls in z only")
     if g.slip_obstacles:
