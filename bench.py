@@ -360,6 +360,8 @@ def bench_parareal(args):
     coarse = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     h = nsp.Handle(n, n, n, re=re_, max_batch=N)
     hc = nsp.Handle(n // 2, n // 2, n // 2, re=re_, max_batch=1) if cgrid else None
+    if args.coarse_upwind:
+        (hc if cgrid else h).set_coarse_convection(nsp.CONV_UPWIND)
     # serial FP64 fine solve, batch 1, over [0, T]
     y = h.zeros_state(1)
     _sync()
@@ -440,6 +442,7 @@ def bench_parareal(args):
                      "k_persistent_share_of_wall": kms * 1e-3 / par},
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
                    "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n],
+                   "coarse_convection": "upwind" if args.coarse_upwind else "smart",
                    "fine_poisson": "%s, inner %g" % (args.parareal_fine, mixed.inner_rtol), "coarse_poisson": "fp64"},
         "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
         "batched_fine_sweep": sweep,
@@ -473,6 +476,9 @@ def bench_obstacles(args):
     # solves in FP64 (measured at 96^3: 2.0 s per sweep vs 2.8 s mixed)
     coarse = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
     hs = [nsp.Handle(n, n, n, re=re_, solid=inputs.obstacle_mask(n, seed), max_batch=N) for n, seed in grids]
+    if args.coarse_upwind:
+        for h in hs:
+            h.set_coarse_convection(nsp.CONV_UPWIND)
     # serial FP64 fine solve of each grid, batch 1
     refs, serial = [], 0.0
     for (n, _), h in zip(grids, hs):
@@ -813,6 +819,8 @@ def main():
     # defaults are 5e-3 for the 96^3 Parareal run (about 0.76) and 2.5e-3 for
     # the obstacle batch, whose 128^3 grid needs dt < ~4.4e-3.
     ap.add_argument("--coarse-dt", type=float, default=None)
+    ap.add_argument("--coarse-upwind", action="store_true",
+                    help="Parareal modes: donor-cell (first-order upwind) convection in the coarse propagator")
     ap.add_argument("--coarse-grid", action="store_true",
                     help="parareal mode: coarse propagator on a grid with half the cells per direction "
                          "(restriction, coarse steps, prolongation); coarse dt defaults to 1e-2")

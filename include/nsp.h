@@ -188,9 +188,21 @@ nsp_status nsp_fine_step(nsp_handle *h, nsp_state y, int batch, double t0, doubl
                          const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
 
 /* Coarse propagator G(y, t1, t0): the same scheme with the coarse step DT
- * (Sec. 2.1.2: forward Euler for both, larger step for G). */
+ * (Sec. 2.1.2: forward Euler for both, larger step for G), with the
+ * convection chosen by nsp_set_coarse_convection. */
 nsp_status nsp_coarse_step(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double DT,
                            const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
+
+/* Convection of the coarse propagator: the fine scheme's SMART (default) or
+ * first-order upwind (donor cell: a convective face carries the value at the
+ * node on its upwind side).  The paper runs G with the fine scheme and
+ * leaves other coarse propagators to future work (Sec. 2.1.2); a
+ * first-order G damps where SMART's forward-Euler steps amplify.  Applies to
+ * nsp_coarse_step and to the coarse sweeps of the Parareal calls made with
+ * this handle (for nsp_parareal_*_cgrid: the coarse handle's setting);
+ * fine steps always use SMART.  NSP_ERR_ARG for another value. */
+typedef enum { NSP_CONV_SMART = 0, NSP_CONV_UPWIND = 1 } nsp_convection;
+nsp_status nsp_set_coarse_convection(nsp_handle *h, nsp_convection scheme);
 
 /* Uneven batch: F over several grids in ONE launch.  hs[g] is the handle of
  * grid g, ys[g] its batch of batches[g] slices (groups with batches[g] = 0

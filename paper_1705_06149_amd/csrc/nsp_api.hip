@@ -70,6 +70,7 @@ struct nsp_handle {
     double *adj_lam = nullptr, *adj_mu = nullptr, *adj_p = nullptr, *adj_glid = nullptr, *adj_part = nullptr;
     int pz = 0;    // periodic in z
     int slip = 0;  // free-slip obstacle walls
+    int coarse_upwind = 0;  // the coarse propagator's convection: donor cell instead of SMART
     int max_wg = 0;
     int fixed_wg = 0;
     int force_depth = 0;  // CG column-tile depth in planes, forced during autotuning
@@ -270,6 +271,7 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.nfluid = h->nfluid;
     G.pz = h->pz;
     G.slip = h->slip;
+    G.upwind = 0;
     const double hh[3] = {h->lx / h->nx, h->ly / h->ny, h->lz / h->nz};
     for (int d = 0; d < 3; ++d) {
         G.ih[d] = 1.0 / hh[d];
@@ -551,8 +553,10 @@ hipError_t copy_slices(nsp_handle *h, nsp_state dst, nsp_state src, long long n,
     return launch_copy_state(dst.p, src.p, n * h->ncells, s);
 }
 
+// coarse: the steps of a coarse propagator (each handle's coarse convection)
 nsp_status propagate(nsp_handle *const *hs, const nsp_state *ys, const int *batches, int ngroups, double t0,
-                     double t1, double step, const nsp_poisson_opts *o, void *stream, nsp_solve_info *info) {
+                     double t1, double step, const nsp_poisson_opts *o, void *stream, nsp_solve_info *info,
+                     bool coarse = false) {
     if (!hs || !ys || !batches || ngroups < 1 || ngroups > kMaxGroups || !hs[0])
         return fail(hs ? hs[0] : nullptr, NSP_ERR_ARG, "bad group arguments");
     nsp_handle *h = hs[0];
@@ -569,6 +573,7 @@ nsp_status propagate(nsp_handle *const *hs, const nsp_state *ys, const int *batc
         if (batches[g] == 0) continue;
         if (!state_ok(ys[g])) return fail(h, NSP_ERR_ARG, "null state pointer");
         fill_group(G[ng], hs[g], ys[g], 0, batches[g], slice0, tile0, nullptr, cgtile0);
+        G[ng].upwind = coarse ? hs[g]->coarse_upwind : 0;
         used[ng++] = hs[g];
         slice0 += batches[g];
         tile0 += batches[g] * hs[g]->ntiles;
@@ -629,7 +634,7 @@ nsp_status coarse_slice(nsp_handle *const *hs, nsp_handle *const *hcs, const nsp
             gsv[g] = hs[g]->gs;
         }
     }
-    nsp_status st = propagate(hcs ? hcs : hs, gsv, ones, ngroups, t0, t1, DT, coarse, s, nullptr);
+    nsp_status st = propagate(hcs ? hcs : hs, gsv, ones, ngroups, t0, t1, DT, coarse, s, nullptr, true);
     if (hcs && st != NSP_OK) h->err = "coarse grid: " + hcs[0]->err;
     if (st != NSP_OK && st != NSP_ERR_NOT_CONVERGED) return st;
     if (hcs)
@@ -911,7 +916,14 @@ nsp_status nsp_coarse_step(nsp_handle *h, nsp_state y, int batch, double t0, dou
                            const nsp_poisson_opts *o, void *stream, nsp_solve_info *info) {
     if (!h) return NSP_ERR_ARG;
     nsp_handle *hs[1] = {h};
-    return propagate(hs, &y, &batch, 1, t0, t1, DT, o, stream, info);
+    return propagate(hs, &y, &batch, 1, t0, t1, DT, o, stream, info, true);
+}
+
+nsp_status nsp_set_coarse_convection(nsp_handle *h, nsp_convection scheme) {
+    if (!h) return NSP_ERR_ARG;
+    if (scheme != NSP_CONV_SMART && scheme != NSP_CONV_UPWIND) return fail(h, NSP_ERR_ARG, "unknown convection");
+    h->coarse_upwind = scheme == NSP_CONV_UPWIND ? 1 : 0;
+    return NSP_OK;
 }
 
 nsp_status nsp_group_fine_step(nsp_handle *const *hs, const nsp_state *ys, const int *batches, int ngroups, double t0,

@@ -54,6 +54,7 @@ struct GroupDesc {
     int pz;                // periodic in z: cell k = 0 neighbours k = nz - 1; the w plane at
                            // z = Lz repeats z = 0 (written equal)
     int slip;              // free-slip obstacle walls (domain walls stay no-slip)
+    int upwind;            // donor-cell convective face values instead of SMART (coarse propagator)
     double ih[3], ih2[3];  // 1/h, 1/h^2 per direction
     float ih2f[3];
     double inv_re;

@@ -245,9 +245,16 @@ __device__ __forceinline__ void dir_terms(const GAS GroupDesc &G, const GAS doub
                     real_face<FAST, D>(G, vel[D], i + di, j + dj, k + dk));
         am = 0.5 * (real_face<FAST, D>(G, vel[D], i - ci, j - cj, k - ck) + real_face<FAST, D>(G, vel[D], i, j, k));
     }
+    // face values: SMART of the upwind triple, or (donor cell) its central
+    // node, the node on the face's upwind side
     double fp = 0.0, fm = 0.0;
-    if (ap != 0.0) fp = ap * (ap > 0.0 ? smart_face(vm1, phi0, vp1) : smart_face(vp2, vp1, phi0));
-    if (am != 0.0) fm = am * (am > 0.0 ? smart_face(vm2, vm1, phi0) : smart_face(vp1, phi0, vm1));
+    if (G.upwind) {
+        if (ap != 0.0) fp = ap * (ap > 0.0 ? phi0 : vp1);
+        if (am != 0.0) fm = am * (am > 0.0 ? vm1 : phi0);
+    } else {
+        if (ap != 0.0) fp = ap * (ap > 0.0 ? smart_face(vm1, phi0, vp1) : smart_face(vp2, vp1, phi0));
+        if (am != 0.0) fm = am * (am > 0.0 ? smart_face(vm2, vm1, phi0) : smart_face(vp1, phi0, vm1));
+    }
     conv += (fp - fm) * G.ih[D];
     lap += ((vp1 - 2.0 * phi0) + vm1) * G.ih2[D];
 }

@@ -28,6 +28,7 @@ PCG, BICGSTAB, PCG_SR = 0, 1, 2
 _STATUS = {0: "NSP_OK", 1: "NSP_ERR_ARG", 2: "NSP_ERR_NOT_CONVERGED", 3: "NSP_ERR_NONFINITE",
            4: "NSP_ERR_HIP", 5: "NSP_ERR_UNSUPPORTED"}
 FP64, MIXED, MIXED_RU = 0, 1, 2
+CONV_SMART, CONV_UPWIND = 0, 1
 
 
 class NSPError(RuntimeError):
@@ -104,6 +105,7 @@ def lib():
                                                  ctypes.POINTER(_Opts), ctypes.POINTER(_Opts), P, P]
         L.nsp_launch_stats_get.argtypes = [P, P, I]
         L.nsp_set_launch.argtypes = [P, I]
+        L.nsp_set_coarse_convection.argtypes = [P, I]
         L.nsp_autotune.argtypes = [P, I, I, P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
         L.nsp_last_launch_ms.argtypes = [P, ctypes.POINTER(D)]
         L.nsp_fine_solve_adjoint.argtypes = [P, _State, I, D, I, ctypes.POINTER(_Opts), _State, P,
@@ -116,7 +118,7 @@ def lib():
                      "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
                      "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
                      "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
-                     "nsp_launch_stats_get"):
+                     "nsp_launch_stats_get", "nsp_set_coarse_convection"):
             getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -369,6 +371,11 @@ class Handle:
         return {k: {f: getattr(x, f) for f, _ in _LaunchStats._fields_}
                 for k, x in zip(("fine", "poisson", "project"), arr)}
 
+    def set_coarse_convection(self, scheme):
+        """CONV_SMART (the fine scheme) or CONV_UPWIND (donor cell) for the
+        coarse propagator of this handle."""
+        self._err(lib().nsp_set_coarse_convection(self._h, int(scheme)), "nsp_set_coarse_convection")
+
     def set_launch(self, workgroups):
         self._err(lib().nsp_set_launch(self._h, int(workgroups)), "nsp_set_launch")
 
@@ -493,4 +500,4 @@ EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_p
             "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
             "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
             "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
-            "nsp_launch_stats_get")
+            "nsp_launch_stats_get", "nsp_set_coarse_convection")
