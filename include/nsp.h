@@ -292,13 +292,35 @@ nsp_status nsp_parareal_iterate_cgrid(nsp_handle *h, nsp_handle *hc, nsp_state Y
  * mu + dt (dR/du)^T mu with the SMART slopes of the branch the forward step
  * took.  Forward states are stored every ckpt_every steps (0: only the
  * initial state) and recomputed segment by segment.  y0 is not modified.
- * The momentum adjoint accumulates with atomic adds, so results may differ
- * between runs in the last bits.  Workspace (checkpoints, one segment) is
- * allocated on first use and kept by the handle.  NSP_ERR_UNSUPPORTED on a
- * grid periodic in z. */
+ * The momentum adjoint is a gather (each face sums the transposed
+ * contributions of the flux interfaces that read it, in a fixed order), so
+ * repeated calls give bitwise equal gradients.  Workspace (checkpoints, one
+ * segment) is allocated on first use and kept by the handle.
+ * NSP_ERR_UNSUPPORTED on a grid periodic in z or with free-slip obstacles.
+ * Equivalent to nsp_fine_solve_record followed by nsp_fine_solve_reverse. */
 nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
                                   const nsp_poisson_opts *opts, nsp_state grad, double *g_lid, double *J,
                                   void *stream);
+
+/* The two halves of nsp_fine_solve_adjoint, for callers (an autograd
+ * function) whose forward pass runs before they know whether a gradient is
+ * wanted.  nsp_fine_solve_record runs the forward sweep from y0 and writes
+ * *J (HOST).  With tape non-NULL it also keeps on the handle the checkpoints,
+ * dJ/du at the end, nsteps, dt, ckpt_every and a copy of *opts, and writes
+ * a nonzero id of this record to *tape (HOST); with tape NULL nothing is
+ * kept and only J is computed.  A record replaces the previous one.
+ * nsp_fine_solve_reverse runs the reverse sweep of the record `tape` and
+ * writes grad (DEVICE face arrays, required) and, if non-NULL, g_lid
+ * (DEVICE [nz][nx+1]); the record stays valid, so it may be reversed again.
+ * It returns NSP_ERR_ARG without touching the outputs when the record is
+ * stale: another record was made on the handle, or nsp_set_lid was called
+ * after it.  nsp_fine_solve_tape_valid returns 1 when `tape` may be
+ * reversed, else 0 (also for a NULL handle). */
+nsp_status nsp_fine_solve_record(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
+                                 const nsp_poisson_opts *opts, double *J, unsigned long long *tape, void *stream);
+nsp_status nsp_fine_solve_reverse(nsp_handle *h, unsigned long long tape, nsp_state grad, double *g_lid,
+                                  void *stream);
+int nsp_fine_solve_tape_valid(const nsp_handle *h, unsigned long long tape);
 
 /* Lid profile from sine modes: lid(x, z) = 1 + sum_{m,n=1..M} c[m-1][n-1]
  * sin(m pi x/lx) sin(n pi z/lz) at the top u-face positions x = i hx,

@@ -4,9 +4,12 @@
     J.backward()          # u0.grad, v0.grad, w0.grad, lid.grad
 
 The forward pass runs the fine propagator (nsteps projection steps, Sec. 2
-of Croce, Ruprecht & Krause) and returns J = 1/2 hx hy hz sum u_T^2; the
-backward pass calls nsp_fine_solve_adjoint (forward recomputed from
-checkpoints, adjoint projection and adjoint momentum kernels).  Lid
+of Croce, Ruprecht & Krause), returns J = 1/2 hx hy hz sum u_T^2 and leaves
+its checkpoints on the handle (nsp_fine_solve_record); the backward pass
+reverses that record (nsp_fine_solve_reverse: segments recomputed from the
+checkpoints, adjoint projection and adjoint momentum kernels), so the
+forward sweep runs once.  If the record went stale in between (another
+record on the handle, or a new lid), backward records again first.  Lid
 profiles parameterised by sine modes go through LidFromModes.  All
 arithmetic runs in libnsp's kernels.
 """
@@ -37,22 +40,28 @@ class NSFineSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, v0, w0, lid, handle, nsteps, dt, ckpt_every, opts):
         handle.set_lid(lid.detach().contiguous())
-        p0 = torch.zeros((1, handle.nz, handle.ny, handle.nx), dtype=torch.float64, device=u0.device)
-        y0 = (u0.detach().contiguous()[None], v0.detach().contiguous()[None], w0.detach().contiguous()[None], p0)
-        J, _, _ = handle.fine_solve_adjoint(y0, nsteps, dt, ckpt_every, opts, grad=False)
+        keep = any(ctx.needs_input_grad[:4])  # no record when no gradient can be asked for
+        J, tape = handle.fine_solve_record(_y0(handle, u0, v0, w0), nsteps, dt, ckpt_every, opts, keep=keep)
         ctx.save_for_backward(u0, v0, w0, lid)
         ctx.args = (handle, nsteps, dt, ckpt_every, opts)
+        ctx.tape = tape
         return torch.tensor(J, dtype=torch.float64, device=u0.device)
 
     @staticmethod
     def backward(ctx, gJ):
         u0, v0, w0, lid = ctx.saved_tensors
         handle, nsteps, dt, ckpt_every, opts = ctx.args
-        handle.set_lid(lid.detach().contiguous())
-        p0 = torch.zeros((1, handle.nz, handle.ny, handle.nx), dtype=torch.float64, device=u0.device)
-        y0 = (u0.detach().contiguous()[None], v0.detach().contiguous()[None], w0.detach().contiguous()[None], p0)
-        _, g, gl = handle.fine_solve_adjoint(y0, nsteps, dt, ckpt_every, opts, grad=True)
+        tape = ctx.tape
+        if not handle.tape_valid(tape):
+            handle.set_lid(lid.detach().contiguous())
+            _, tape = handle.fine_solve_record(_y0(handle, u0, v0, w0), nsteps, dt, ckpt_every, opts, keep=True)
+        g, gl = handle.fine_solve_reverse(tape, device=u0.device)
         return gJ * g[0][0], gJ * g[1][0], gJ * g[2][0], gJ * gl, None, None, None, None, None
+
+
+def _y0(handle, u0, v0, w0):
+    p0 = torch.zeros((1, handle.nz, handle.ny, handle.nx), dtype=torch.float64, device=u0.device)
+    return (u0.detach().contiguous()[None], v0.detach().contiguous()[None], w0.detach().contiguous()[None], p0)
 
 
 def kinetic_energy(handle, u0, v0, w0, lid, nsteps, dt, ckpt_every=10, opts=None):

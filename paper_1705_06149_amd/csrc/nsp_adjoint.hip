@@ -8,26 +8,17 @@
 // Croce, Ruprecht & Krause).  Its adjoint: mu = P lam' (P symmetric; done by
 // the persistent kernel in projection mode), then
 //     lam = mu + dt (dR/du)^T mu,   g_lid += dt (dR/dlid)^T mu,
-// which k_mom_adjoint computes by scattering each open face's local
-// Jacobian-transpose contributions with FP64 atomic adds.  SMART is
-// piecewise linear in (U, C, D): the adjoint uses the slopes of the branch
-// the forward step took; a zero transport velocity gives a zero flux and no
+// which k_mom_adjoint gathers face by face: every face sums, in a fixed
+// order, the transposed contributions of the interfaces whose fluxes read
+// it, so the result has no atomics and repeats bitwise.  SMART is piecewise
+// linear in (U, C, D): the adjoint uses the slopes of the branch the forward
+// step took; a zero transport velocity gives a zero flux and no
 // contribution.
 #include "nsp_internal.h"
 
 namespace nsp {
 
 namespace {
-
-// A stencil value as a linear form in face values of one component plus a
-// multiple of one lid value.
-struct Form {
-    int n;
-    long idx[4];
-    double coef[4];
-    double lcoef;
-    long lidx;
-};
 
 struct AdjGrid {
     int nx, ny, nz;
@@ -42,178 +33,290 @@ __device__ __forceinline__ int ext(const AdjGrid &G, int c, int d) {
     return n + (c == d ? 1 : 0);
 }
 
-__device__ __forceinline__ long face_index(const AdjGrid &G, int c, const int p[3]) {
-    return ((long)p[2] * ext(G, c, 1) + p[1]) * ext(G, c, 0) + p[0];
-}
-
-// open face of component c at p: both adjacent cells fluid (the cell's own
-// "minus" open bit); outside the array or on the high boundary: closed
-__device__ __forceinline__ bool open_face(const AdjGrid &G, int c, const int p[3]) {
-    if (p[0] < 0 || p[1] < 0 || p[2] < 0 || p[0] >= G.nx || p[1] >= G.ny || p[2] >= G.nz) return false;
+// open face of component c at (i,j,k): both adjacent cells fluid (the
+// cell's own "minus" open bit); outside the array or on the high boundary:
+// closed
+__device__ __forceinline__ bool open_face(const AdjGrid &G, int c, int i, int j, int k) {
+    if (i < 0 || j < 0 || k < 0 || i >= G.nx || j >= G.ny || k >= G.nz) return false;
     const uint8_t bit = c == 0 ? FL_XM : (c == 1 ? FL_YM : FL_ZM);
-    return (G.flags[((long)p[2] * G.ny + p[1]) * G.nx + p[0]] & bit) != 0;
+    return (G.flags[((long)k * G.ny + j) * G.nx + i] & bit) != 0;
 }
 
-__device__ __forceinline__ bool lid_wall(const AdjGrid &G, int c, const int p[3], int d, int s) {
-    return c == 0 && d == 1 && s > 0 && p[1] == G.ny - 1;
+template <int C>
+__device__ __forceinline__ long fid(const AdjGrid &G, int i, int j, int k) {
+    return ((long)k * ext(G, C, 1) + j) * ext(G, C, 0) + i;
 }
 
-__device__ __forceinline__ void add_term(Form &F, long idx, double coef) {
-    F.idx[F.n] = idx;
-    F.coef[F.n] = coef;
-    ++F.n;
+// distance in the array of component C between neighbours along D
+template <int C, int D>
+__device__ __forceinline__ long fstride(const AdjGrid &G) {
+    return D == 0 ? 1 : (D == 1 ? (long)ext(G, C, 0) : (long)ext(G, C, 0) * ext(G, C, 1));
 }
 
-// value at offset +-1 (one = true) or +-2 along d, sense s, of the stencil
-// of open face f: own axis -> closed face 0, next position -phi0; across ->
-// wall half a cell away, image 2*wall - mirror (mirror resolved first)
-__device__ void form_of(const AdjGrid &G, int c, const int f[3], int d, int s, bool one, Form &F) {
-    int f1[3] = {f[0], f[1], f[2]}, f2[3] = {f[0], f[1], f[2]};
-    f1[d] += s;
-    f2[d] += 2 * s;
-    const long i0 = face_index(G, c, f);
-    F.n = 0;
-    F.lcoef = 0.0;
-    F.lidx = (long)f[2] * (G.nx + 1) + f[0];
-    const bool o1 = open_face(G, c, f1);
-    if (c == d) {
-        if (!o1) { if (!one) add_term(F, i0, -1.0); return; }
-        if (one) { add_term(F, face_index(G, c, f1), 1.0); return; }
-        if (open_face(G, c, f2)) add_term(F, face_index(G, c, f2), 1.0);
-        return;
-    }
-    if (!o1) {
-        if (lid_wall(G, c, f, d, s)) F.lcoef += 2.0;
-        if (one) { add_term(F, i0, -1.0); return; }
-        // 2 wall - (value at offset 1 on the other side)
-        int g1[3] = {f[0], f[1], f[2]};
-        g1[d] -= s;
-        if (open_face(G, c, g1)) {
-            add_term(F, face_index(G, c, g1), -1.0);
+// ------------------------------------------------------------ interfaces
+//
+// The momentum right-hand side of an open face is a sum over the six
+// interfaces around it (one per side and direction) of a diffusive flux
+// (the difference of the two values across the interface) and a convective
+// flux (transport velocity times the SMART value upwind of the
+// interface).  Between two open faces both of them see the same flux, with
+// the same image values, so the step is conservative and its transpose can
+// be taken interface by interface:
+//     R(L) += nu/h^2 Delta - Phi/h,   R(L + e) += -nu/h^2 Delta + Phi/h
+// for the interface between face L of a component and the next face L + e
+// along a direction.  An interface with only one open side enters that
+// side alone.  Its values at L - e, L, L + e, L + 2e, after the image rule
+// (a closed face of the component's own axis holds 0 and the next position
+// its odd reflection; across, a closed neighbour is a wall half a cell away
+// with image 2 wall - mirror; the lid is the wall above the top row of u),
+// are X[0..3]; Delta = X2 - X1; Phi = a (a > 0: SMART(X0, X1, X2), else
+// SMART(X3, X2, X1)), a the mean of the two faces of the transport component
+// that straddle the interface (own axis: of X1 and X2).
+
+struct Line {
+    bool oL, oU, om, o2;   // open: L, L + e, L - e, L + 2e
+    bool lidL, lidU;       // the lid is the wall above L / above L + e
+    double X[4];
+};
+
+// image-resolved values of the line of interface (C, D, L = (i,j,k));
+// false when neither L nor L + e is open
+template <int C, int D>
+__device__ __forceinline__ bool line_of(const AdjGrid &G, const double *__restrict__ phi, int i, int j, int k,
+                                        Line &Ln) {
+    constexpr int di = D == 0, dj = D == 1, dk = D == 2;
+    Ln.oL = open_face(G, C, i, j, k);
+    Ln.oU = open_face(G, C, i + di, j + dj, k + dk);
+    if (!Ln.oL && !Ln.oU) return false;
+    Ln.om = open_face(G, C, i - di, j - dj, k - dk);
+    Ln.o2 = open_face(G, C, i + 2 * di, j + 2 * dj, k + 2 * dk);
+    Ln.lidL = C == 0 && D == 1 && j == G.ny - 1;
+    Ln.lidU = C == 0 && D == 1 && j + 1 == G.ny - 1;
+    const double lv = (Ln.lidL || Ln.lidU) ? G.lid[(long)k * (G.nx + 1) + i] : 0.0;
+    const double wL = Ln.lidL ? lv : 0.0, wU = Ln.lidU ? lv : 0.0;
+    const long id = fid<C>(G, i, j, k), s = fstride<C, D>(G);
+    if (Ln.oL) {
+        const double P0 = phi[id];
+        Ln.X[1] = P0;
+        if (C == D) {
+            Ln.X[0] = Ln.om ? phi[id - s] : 0.0;
+            Ln.X[2] = Ln.oU ? phi[id + s] : 0.0;
+            Ln.X[3] = !Ln.oU ? -P0 : (Ln.o2 ? phi[id + 2 * s] : 0.0);
         } else {
-            if (lid_wall(G, c, f, d, -s)) F.lcoef -= 2.0;
-            add_term(F, i0, 1.0);
+            Ln.X[0] = Ln.om ? phi[id - s] : 2.0 * 0.0 - P0;
+            Ln.X[2] = Ln.oU ? phi[id + s] : 2.0 * wL - P0;
+            Ln.X[3] = !Ln.oU ? 2.0 * wL - Ln.X[0] : (Ln.o2 ? phi[id + 2 * s] : 2.0 * wU - Ln.X[2]);
         }
-        return;
+    } else {
+        const double P1 = phi[id + s];
+        Ln.X[2] = P1;
+        if (C == D) {
+            Ln.X[1] = 0.0;
+            Ln.X[0] = -P1;
+            Ln.X[3] = Ln.o2 ? phi[id + 2 * s] : 0.0;
+        } else {
+            Ln.X[1] = 2.0 * 0.0 - P1;
+            Ln.X[3] = Ln.o2 ? phi[id + 2 * s] : 2.0 * wU - P1;
+            Ln.X[0] = 2.0 * 0.0 - Ln.X[3];
+        }
     }
-    if (one) { add_term(F, face_index(G, c, f1), 1.0); return; }
-    if (!open_face(G, c, f2)) {
-        if (lid_wall(G, c, f1, d, s)) F.lcoef += 2.0;
-        add_term(F, face_index(G, c, f1), -1.0);
-        return;
+    return true;
+}
+
+// derivatives of X[0..3] with respect to the value at position L + (POS-1) e
+// (cx) and to the lid beside L (lx)
+template <int C, int D, int POS>
+__device__ __forceinline__ void coefs_of(const Line &Ln, double cx[4], double lx[4]) {
+    const double p0 = POS == 0, p1 = POS == 1, p2 = POS == 2, p3 = POS == 3;
+    lx[0] = lx[1] = lx[2] = lx[3] = 0.0;
+    if (Ln.oL) {
+        cx[1] = p1;
+        if (C == D) {
+            cx[0] = Ln.om ? p0 : 0.0;
+            cx[2] = Ln.oU ? p2 : 0.0;
+            cx[3] = !Ln.oU ? -p1 : (Ln.o2 ? p3 : 0.0);
+        } else {
+            cx[0] = Ln.om ? p0 : -p1;
+            cx[2] = Ln.oU ? p2 : -p1;
+            cx[3] = !Ln.oU ? -cx[0] : (Ln.o2 ? p3 : -cx[2]);
+            lx[2] = (!Ln.oU && Ln.lidL) ? 2.0 : 0.0;
+            lx[3] = !Ln.oU ? (Ln.lidL ? 2.0 : 0.0) : ((!Ln.o2 && Ln.lidU) ? 2.0 : 0.0);
+        }
+    } else {
+        cx[2] = p2;
+        if (C == D) {
+            cx[1] = 0.0;
+            cx[0] = -p2;
+            cx[3] = Ln.o2 ? p3 : 0.0;
+        } else {
+            cx[1] = -p2;
+            cx[3] = Ln.o2 ? p3 : -p2;
+            cx[0] = -cx[3];
+            lx[3] = (!Ln.o2 && Ln.lidU) ? 2.0 : 0.0;
+            lx[0] = -lx[3];
+        }
     }
-    add_term(F, face_index(G, c, f2), 1.0);
 }
 
-__device__ __forceinline__ double form_value(const Form &F, const double *phi, const double *lid) {
-    double v = 0.0;
-    for (int q = 0; q < F.n; ++q) v += F.coef[q] * phi[F.idx[q]];
-    return v + F.lcoef * lid[F.lidx];
+// value of the transport component D at its face (i,j,k); closed: 0
+template <int D>
+__device__ __forceinline__ double real_face(const AdjGrid &G, const double *__restrict__ a, int i, int j, int k) {
+    return open_face(G, D, i, j, k) ? a[fid<D>(G, i, j, k)] : 0.0;
 }
 
-__device__ __forceinline__ void scatter(const Form &F, double wgt, double *lam, double *glid) {
-    for (int q = 0; q < F.n; ++q) atomicAdd(&lam[F.idx[q]], wgt * F.coef[q]);
-    if (F.lcoef != 0.0) atomicAdd(&glid[F.lidx], wgt * F.lcoef);
-}
-
-// SMART face value and its slopes with respect to U, C, D on the branch taken
-__device__ __forceinline__ double smart_and_slopes(double U, double C, double D, double s[3]) {
+// SMART (normalised variable, Gaskell & Lau) face value of the upwind
+// triple (U, C, D) and its slopes on the branch taken
+__device__ __forceinline__ double smart_slopes(double U, double C, double D, double &sU, double &sC, double &sD) {
     const double delta = D - U;
-    s[0] = 0.0; s[1] = 1.0; s[2] = 0.0;
+    sU = 0.0; sC = 1.0; sD = 0.0;
     if (delta == 0.0) return C;
     const double ph = (C - U) / delta;
     double pf;
-    if (ph > 0.0 && ph < 1.0 / 6.0) { pf = 3.0 * ph; s[0] = -2.0; s[1] = 3.0; }
-    else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0) { pf = 0.75 * ph + 0.375; s[0] = -0.125; s[1] = 0.75; s[2] = 0.375; }
-    else if (ph >= 5.0 / 6.0 && ph < 1.0) { pf = 1.0; s[1] = 0.0; s[2] = 1.0; }
+    if (ph > 0.0 && ph < 1.0 / 6.0) { pf = 3.0 * ph; sU = -2.0; sC = 3.0; }
+    else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0) { pf = 0.75 * ph + 0.375; sU = -0.125; sC = 0.75; sD = 0.375; }
+    else if (ph >= 5.0 / 6.0 && ph < 1.0) { pf = 1.0; sC = 0.0; sD = 1.0; }
     else pf = ph;
     return U + pf * delta;
 }
 
-// lam = masked mu (closed faces 0); one thread per face of component c
-__global__ void k_adj_init(AdjGrid G, int c, const double *__restrict__ mu, double *__restrict__ lam, long n) {
-    for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) {
-        const int e0 = ext(G, c, 0), e1 = ext(G, c, 1);
-        const int p[3] = {(int)(x % e0), (int)((x / e0) % e1), (int)(x / ((long)e0 * e1))};
-        lam[x] = open_face(G, c, p) ? mu[x] : 0.0;
-    }
+// The linearised fluxes of interface (C, D, L = (i,j,k)) with their adjoint
+// weights: wphi = dt/h (mu(L+e) - mu(L)), wdel = dt nu/h^2 (mu(L) - mu(L+e)),
+// closed faces taking mu = 0.
+struct Flux {
+    double wphi, wdel;
+    double a;              // transport velocity
+    double S, sU, sC, sD;  // SMART value and slopes (a != 0)
+};
+
+template <int C, int D>
+__device__ __forceinline__ bool flux_of(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
+                                        int j, int k, Line &Ln, Flux &Fx) {
+    constexpr int di = D == 0, dj = D == 1, dk = D == 2;
+    constexpr int ci = C == 0, cj = C == 1, ck = C == 2;
+    if (!line_of<C, D>(G, vel[C], i, j, k, Ln)) return false;
+    const long id = fid<C>(G, i, j, k), s = fstride<C, D>(G);
+    const double mL = Ln.oL ? mu[C][id] : 0.0, mU = Ln.oU ? mu[C][id + s] : 0.0;
+    if (mL == mU) return false;  // both weights vanish
+    Fx.wphi = G.dt * G.ih[D] * (mU - mL);
+    Fx.wdel = G.dt * G.inv_re * G.ih2[D] * (mL - mU);
+    if (C == D) Fx.a = 0.5 * (Ln.X[1] + Ln.X[2]);
+    else
+        Fx.a = 0.5 * (real_face<D>(G, vel[D], i - ci + di, j - cj + dj, k - ck + dk) +
+                      real_face<D>(G, vel[D], i + di, j + dj, k + dk));
+    Fx.S = 0.0;
+    if (Fx.a > 0.0) Fx.S = smart_slopes(Ln.X[0], Ln.X[1], Ln.X[2], Fx.sU, Fx.sC, Fx.sD);
+    else if (Fx.a < 0.0) Fx.S = smart_slopes(Ln.X[3], Ln.X[2], Ln.X[1], Fx.sU, Fx.sC, Fx.sD);
+    return true;
 }
 
-// dt (dR/du)^T mu and dt (dR/dlid)^T mu for the open faces of component c
-__global__ void k_mom_adjoint(AdjGrid G, int c, const double *__restrict__ u, const double *__restrict__ v,
-                              const double *__restrict__ w, const double *__restrict__ muc, double *lu, double *lv,
-                              double *lw, double *glid, long n) {
-    const double *vel[3] = {u, v, w};
-    double *lam[3] = {lu, lv, lw};
-    for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) {
-        const int e0 = ext(G, c, 0), e1 = ext(G, c, 1);
-        const int f[3] = {(int)(x % e0), (int)((x / e0) % e1), (int)(x / ((long)e0 * e1))};
-        if (!open_face(G, c, f)) continue;
-        const double m0 = muc[x];
-        if (m0 == 0.0) continue;
-        const double *phi = vel[c];
-        for (int d = 0; d < 3; ++d) {
-            Form Vm2, Vm1, Vp1, Vp2, Self;
-            form_of(G, c, f, d, -1, false, Vm2);
-            form_of(G, c, f, d, -1, true, Vm1);
-            form_of(G, c, f, d, +1, true, Vp1);
-            form_of(G, c, f, d, +1, false, Vp2);
-            Self.n = 0;
-            Self.lcoef = 0.0;
-            Self.lidx = 0;
-            add_term(Self, x, 1.0);
-            // diffusion
-            const double wd = G.dt * m0 * G.inv_re * G.ih2[d];
-            scatter(Vp1, wd, lam[c], glid);
-            scatter(Vm1, wd, lam[c], glid);
-            atomicAdd(&lam[c][x], -2.0 * wd);
-            // convection: -(flux(+) - flux(-)) / h
-            for (int s = -1; s <= 1; s += 2) {
-                int ac;
-                long ai[2];
-                bool ao[2];
-                if (d == c) {
-                    int f1[3] = {f[0], f[1], f[2]};
-                    f1[d] += s;
-                    ac = c;
-                    ai[0] = x;
-                    ao[0] = true;
-                    ao[1] = open_face(G, c, f1);
-                    ai[1] = ao[1] ? face_index(G, c, f1) : 0;
-                } else {
-                    int q1[3] = {f[0], f[1], f[2]}, q2[3] = {f[0], f[1], f[2]};
-                    if (s > 0) { q1[d] += 1; q2[d] += 1; }
-                    q1[c] -= 1;
-                    ac = d;
-                    ao[0] = open_face(G, d, q1);
-                    ao[1] = open_face(G, d, q2);
-                    ai[0] = ao[0] ? face_index(G, d, q1) : 0;
-                    ai[1] = ao[1] ? face_index(G, d, q2) : 0;
-                }
-                const double a1 = ao[0] ? vel[ac][ai[0]] : 0.0;
-                const double a2 = ao[1] ? vel[ac][ai[1]] : 0.0;
-                const double abar = 0.5 * (a1 + a2);
-                if (abar == 0.0) continue;
-                const Form *U, *C, *D;
-                if (s > 0) {
-                    if (abar > 0.0) { U = &Vm1; C = &Self; D = &Vp1; }
-                    else { U = &Vp2; C = &Vp1; D = &Self; }
-                } else {
-                    if (abar > 0.0) { U = &Vm2; C = &Vm1; D = &Self; }
-                    else { U = &Vp1; C = &Self; D = &Vm1; }
-                }
-                double sl[3];
-                const double phis = smart_and_slopes(form_value(*U, phi, G.lid), form_value(*C, phi, G.lid),
-                                                     form_value(*D, phi, G.lid), sl);
-                const double wc = -(double)s * G.dt * m0 * G.ih[d];
-                if (ao[0]) atomicAdd(&lam[ac][ai[0]], wc * 0.5 * phis);
-                if (ao[1]) atomicAdd(&lam[ac][ai[1]], wc * 0.5 * phis);
-                scatter(*U, wc * abar * sl[0], lam[c], glid);
-                scatter(*C, wc * abar * sl[1], lam[c], glid);
-                scatter(*D, wc * abar * sl[2], lam[c], glid);
-            }
+// transposed contribution of interface (C, D, L) to the value of component
+// C at L + (POS-1) e; with LID also its contribution to the lid beside L
+template <int C, int D, int POS, bool LID>
+__device__ __forceinline__ double line_adj(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
+                                           int j, int k, double &glid) {
+    Line Ln;
+    Flux Fx;
+    if (!flux_of<C, D>(G, vel, mu, i, j, k, Ln, Fx)) return 0.0;
+    double cx[4], lx[4];
+    coefs_of<C, D, POS>(Ln, cx, lx);
+    double r = Fx.wdel * (cx[2] - cx[1]);
+    if (LID) glid += Fx.wdel * (lx[2] - lx[1]);
+    if (Fx.a != 0.0) {
+        const double wa = Fx.wphi * Fx.a;
+        if (Fx.a > 0.0) {
+            r += wa * ((Fx.sU * cx[0] + Fx.sC * cx[1]) + Fx.sD * cx[2]);
+            if (LID) glid += wa * ((Fx.sU * lx[0] + Fx.sC * lx[1]) + Fx.sD * lx[2]);
+        } else {
+            r += wa * ((Fx.sU * cx[3] + Fx.sC * cx[2]) + Fx.sD * cx[1]);
+            if (LID) glid += wa * ((Fx.sU * lx[3] + Fx.sC * lx[2]) + Fx.sD * lx[1]);
         }
+        if (C == D) r += Fx.wphi * 0.5 * Fx.S * (cx[1] + cx[2]);
     }
+    return r;
+}
+
+// transposed contribution of interface (C, D, L), C != D, to one of the two
+// faces of component D that carry its transport velocity
+template <int C, int D>
+__device__ __forceinline__ double transport_adj(const AdjGrid &G, const double *const *vel, const double *const *mu,
+                                                int i, int j, int k) {
+    Line Ln;
+    Flux Fx;
+    if (!flux_of<C, D>(G, vel, mu, i, j, k, Ln, Fx)) return 0.0;
+    return Fx.a != 0.0 ? Fx.wphi * 0.5 * Fx.S : 0.0;
+}
+
+// the four interfaces along D whose lines hold the face t = (i,j,k) of
+// component C: L = t - 2e .. t + e (t at position 3 .. 0 of their lines)
+template <int C, int D, bool LID>
+__device__ __forceinline__ double along(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
+                                        int j, int k, double &glid) {
+    constexpr int di = D == 0, dj = D == 1, dk = D == 2;
+    double r = line_adj<C, D, 3, false>(G, vel, mu, i - 2 * di, j - 2 * dj, k - 2 * dk, glid);
+    r += line_adj<C, D, 2, LID>(G, vel, mu, i - di, j - dj, k - dk, glid);
+    r += line_adj<C, D, 1, LID>(G, vel, mu, i, j, k, glid);
+    r += line_adj<C, D, 0, false>(G, vel, mu, i + di, j + dj, k + dk, glid);
+    return r;
+}
+
+// the interfaces of component C along T whose transport velocity averages
+// the face t = (i,j,k) of component T: L = t - e_T and t - e_T + e_C
+template <int C, int T>
+__device__ __forceinline__ double carried(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
+                                          int j, int k) {
+    constexpr int ti = T == 0, tj = T == 1, tk = T == 2;
+    constexpr int ci = C == 0, cj = C == 1, ck = C == 2;
+    return transport_adj<C, T>(G, vel, mu, i - ti, j - tj, k - tk) +
+           transport_adj<C, T>(G, vel, mu, i - ti + ci, j - tj + cj, k - tk + ck);
+}
+
+// lam = mu + dt (dR/du)^T mu at face x of component T, gathered in a fixed
+// order; for the top row of u also g_lid += dt (dR/dlid)^T mu beside it
+template <int T>
+__device__ __forceinline__ void gather_face(const AdjGrid &G, const double *const *vel, const double *const *mu,
+                                            double *__restrict__ lam, double *__restrict__ glid, long x) {
+    const int e0 = ext(G, T, 0), e1 = ext(G, T, 1);
+    const int i = (int)(x % e0), j = (int)((x / e0) % e1), k = (int)(x / ((long)e0 * e1));
+    if (!open_face(G, T, i, j, k)) {
+        lam[x] = 0.0;
+        return;
+    }
+    double gl = 0.0;
+    double r = mu[T][x];
+    if (T == 0 && j == G.ny - 1) {
+        r += along<T, 0, false>(G, vel, mu, i, j, k, gl);
+        r += along<T, 1, true>(G, vel, mu, i, j, k, gl);
+    } else {
+        r += along<T, 0, false>(G, vel, mu, i, j, k, gl);
+        r += along<T, 1, false>(G, vel, mu, i, j, k, gl);
+    }
+    r += along<T, 2, false>(G, vel, mu, i, j, k, gl);
+    if (T != 0) r += carried<0, T>(G, vel, mu, i, j, k);
+    if (T != 1) r += carried<1, T>(G, vel, mu, i, j, k);
+    if (T != 2) r += carried<2, T>(G, vel, mu, i, j, k);
+    lam[x] = r;
+    if (T == 0 && j == G.ny - 1) glid[(long)k * (G.nx + 1) + i] += gl;
+}
+
+struct AdjVecs {
+    const double *vel[3];
+    const double *mu[3];
+    double *lam[3];
+    long n[3];       // faces per component
+    unsigned b[3];   // blocks per component
+};
+
+// one thread per face of the three components; the blocks of each component
+// are contiguous, so a block never mixes components
+__global__ __launch_bounds__(256) void k_mom_adjoint(AdjGrid G, AdjVecs V, double *__restrict__ glid) {
+    unsigned b = blockIdx.x;
+    int t = 0;
+    if (b >= V.b[0]) { b -= V.b[0]; t = 1; if (b >= V.b[1]) { b -= V.b[1]; t = 2; } }
+    const long x = (long)b * blockDim.x + threadIdx.x;
+    if (x >= V.n[t]) return;
+    if (t == 0) gather_face<0>(G, V.vel, V.mu, V.lam[0], glid, x);
+    else if (t == 1) gather_face<1>(G, V.vel, V.mu, V.lam[1], glid, x);
+    else gather_face<2>(G, V.vel, V.mu, V.lam[2], glid, x);
 }
 
 // out = scale * a on open faces of component c, 0 on closed faces
@@ -221,8 +324,8 @@ __global__ void k_scale_open(AdjGrid G, int c, const double *__restrict__ a, dou
                              long n) {
     for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) {
         const int e0 = ext(G, c, 0), e1 = ext(G, c, 1);
-        const int p[3] = {(int)(x % e0), (int)((x / e0) % e1), (int)(x / ((long)e0 * e1))};
-        out[x] = open_face(G, c, p) ? scale * a[x] : 0.0;
+        const int i = (int)(x % e0), j = (int)((x / e0) % e1), k = (int)(x / ((long)e0 * e1));
+        out[x] = open_face(G, c, i, j, k) ? scale * a[x] : 0.0;
     }
 }
 
@@ -233,8 +336,8 @@ __global__ void k_sumsq_open(AdjGrid G, int c, const double *__restrict__ a, lon
     double acc = 0.0;
     for (long x = (long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long)gridDim.x * blockDim.x) {
         const int e0 = ext(G, c, 0), e1 = ext(G, c, 1);
-        const int p[3] = {(int)(x % e0), (int)((x / e0) % e1), (int)(x / ((long)e0 * e1))};
-        if (open_face(G, c, p)) acc += a[x] * a[x];
+        const int i = (int)(x % e0), j = (int)((x / e0) % e1), k = (int)(x / ((long)e0 * e1));
+        if (open_face(G, c, i, j, k)) acc += a[x] * a[x];
     }
     for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
@@ -308,12 +411,19 @@ AdjGrid adj_grid(const AdjParams &A) {
 hipError_t launch_momentum_adjoint(const AdjParams &A, const double *const vel[3], const double *const mu[3],
                                    double *const lam[3], double *glid, hipStream_t s) {
     const AdjGrid G = adj_grid(A);
-    const long nf[3] = {(long)(A.nx + 1) * A.ny * A.nz, (long)A.nx * (A.ny + 1) * A.nz, (long)A.nx * A.ny * (A.nz + 1)};
-    for (int c = 0; c < 3; ++c)
-        hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(nf[c])), dim3(256), 0, s, G, c, mu[c], lam[c], nf[c]);
-    for (int c = 0; c < 3; ++c)
-        hipLaunchKernelGGL(k_mom_adjoint, dim3(blocks_for(nf[c])), dim3(256), 0, s, G, c, vel[0], vel[1], vel[2],
-                           mu[c], lam[0], lam[1], lam[2], glid, nf[c]);
+    AdjVecs V;
+    V.n[0] = (long)(A.nx + 1) * A.ny * A.nz;
+    V.n[1] = (long)A.nx * (A.ny + 1) * A.nz;
+    V.n[2] = (long)A.nx * A.ny * (A.nz + 1);
+    unsigned nb = 0;
+    for (int c = 0; c < 3; ++c) {
+        V.vel[c] = vel[c];
+        V.mu[c] = mu[c];
+        V.lam[c] = lam[c];
+        V.b[c] = (unsigned)((V.n[c] + 255) / 256);
+        nb += V.b[c];
+    }
+    hipLaunchKernelGGL(k_mom_adjoint, dim3(nb), dim3(256), 0, s, G, V, glid);
     return hipGetLastError();
 }
 

@@ -68,6 +68,13 @@ struct nsp_handle {
     double *adj_segu = nullptr;  // velocities of one segment: adj_seg states
     double *adj_y = nullptr;     // working state
     double *adj_lam = nullptr, *adj_mu = nullptr, *adj_p = nullptr, *adj_glid = nullptr, *adj_part = nullptr;
+    double *adj_fin = nullptr;   // dJ/du at the end of the recorded run
+    // the recorded forward run (tape) the reverse sweep starts from
+    unsigned long long tape = 0, tape_seq = 0;
+    unsigned long long lid_version = 0, tape_lid_version = 0;
+    int tape_nsteps = 0, tape_ck = 1, tape_nseg = 0;
+    double tape_dt = 0.0;
+    nsp_poisson_opts tape_opts{};
     int pz = 0;    // periodic in z
     int slip = 0;  // free-slip obstacle walls
     int coarse_upwind = 0;  // the coarse propagator's convection: donor cell instead of SMART
@@ -870,6 +877,7 @@ nsp_status nsp_destroy(nsp_handle *h) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     void *aptrs[] = {h->adj_ck, h->adj_segu, h->adj_y, h->adj_lam, h->adj_mu, h->adj_p, h->adj_glid, h->adj_part,
+                     h->adj_fin,
                      h->bv0, h->bv1, h->brh};
     for (void *p : aptrs)
         if (p) (void)hipFree(p);
@@ -885,6 +893,7 @@ nsp_status nsp_destroy(nsp_handle *h) {
 nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev, void *stream) {
     if (!h || !lid_dev) return fail(h, NSP_ERR_ARG, "null lid pointer");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    ++h->lid_version;  // a recorded run used the previous lid
     HIPCHK(h, hipMemcpyAsync(h->lid, lid_dev, (size_t)h->nz * (h->nx + 1) * sizeof(double), hipMemcpyDeviceToDevice,
                              s));
     HIPCHK(h, hipStreamSynchronize(s));
@@ -1037,6 +1046,7 @@ nsp_status ensure_adj(nsp_handle *h, int nck, int seg) {
         HIPCHK(h, dalloc(&h->adj_p, h->ncells));
         HIPCHK(h, dalloc(&h->adj_glid, (size_t)h->nz * (h->nx + 1)));
         HIPCHK(h, dalloc(&h->adj_part, 3 * kSumBlocks + 1));
+        HIPCHK(h, dalloc(&h->adj_fin, h->nu + h->nv + h->nw));
     }
     if (nck > h->adj_nck) {
         if (h->adj_ck) (void)hipFree(h->adj_ck);
@@ -1057,28 +1067,29 @@ nsp_status ensure_adj(nsp_handle *h, int nck, int seg) {
 
 extern "C" {
 
-nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
-                                  const nsp_poisson_opts *o, nsp_state grad, double *g_lid, double *J, void *stream) {
+nsp_status nsp_fine_solve_record(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
+                                 const nsp_poisson_opts *o, double *J, unsigned long long *tape, void *stream) {
     if (!h) return NSP_ERR_ARG;
     if (h->pz) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for walls in z only");
     if (h->slip) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for no-slip obstacles only");
     if (!state_ok(y0) || nsteps < 0 || !(dt > 0) || !J) return fail(h, NSP_ERR_ARG, "bad adjoint arguments");
     if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
-    const bool want_grad = grad.u && grad.v && grad.w;
+    const bool keep = tape != nullptr;
+    if (keep) *tape = 0;
+    h->tape = 0;  // the workspace is about to be overwritten
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int ck = ckpt_every > 0 ? std::min(ckpt_every, std::max(nsteps, 1)) : std::max(nsteps, 1);
     const int nseg = nsteps > 0 ? (nsteps + ck - 1) / ck : 0;
-    nsp_status st = ensure_adj(h, want_grad ? nseg : 0, want_grad ? ck : 0);
+    nsp_status st = ensure_adj(h, keep ? nseg : 0, keep ? ck : 0);
     if (st != NSP_OK) return st;
     const long long L = state_len(h);
-    const long long F3 = h->nu + h->nv + h->nw;
     nsp_state y = packed_state(h, h->adj_y);
     HIPCHK(h, copy_slices(h, y, y0, 1, s));
     nsp_handle *hs[1] = {h};
     int one = 1;
     // forward sweep, storing the state at the start of every segment
     for (int sg = 0; sg < nseg; ++sg) {
-        if (want_grad) HIPCHK(h, launch_copy_state(h->adj_ck + (long long)sg * L, h->adj_y, L, s));
+        if (keep) HIPCHK(h, launch_copy_state(h->adj_ck + (long long)sg * L, h->adj_y, L, s));
         const int len = std::min(ck, nsteps - sg * ck);
         st = propagate(hs, &y, &one, 1, 0.0, len * dt, dt, o, stream, nullptr);
         if (st != NSP_OK) return st;
@@ -1088,17 +1099,53 @@ nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, doubl
     HIPCHK(h, launch_sumsq_open(A, vel, h->adj_part, h->adj_part + 3 * kSumBlocks, s));
     double ss = 0.0;
     HIPCHK(h, hipMemcpyAsync(&ss, h->adj_part + 3 * kSumBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
     const double vol = A.h[0] * A.h[1] * A.h[2];
+    if (keep) {
+        // dJ/du_T = vol * u_T on open faces, the reverse sweep's start
+        double *fin[3] = {h->adj_fin, h->adj_fin + h->nu, h->adj_fin + h->nu + h->nv};
+        HIPCHK(h, launch_scale_open(A, vel, vol, fin, s));
+    }
+    HIPCHK(h, hipStreamSynchronize(s));
     *J = 0.5 * vol * ss;
-    if (!want_grad) return NSP_OK;
-    // lam = dJ/du_T = vol * u_T on open faces
+    if (keep) {
+        h->tape = *tape = ++h->tape_seq;
+        h->tape_lid_version = h->lid_version;
+        h->tape_nsteps = nsteps;
+        h->tape_ck = ck;
+        h->tape_nseg = nseg;
+        h->tape_dt = dt;
+        h->tape_opts = *o;
+    }
+    return NSP_OK;
+}
+
+int nsp_fine_solve_tape_valid(const nsp_handle *h, unsigned long long tape) {
+    return h && tape != 0 && tape == h->tape && h->tape_lid_version == h->lid_version ? 1 : 0;
+}
+
+nsp_status nsp_fine_solve_reverse(nsp_handle *h, unsigned long long tape, nsp_state grad, double *g_lid,
+                                  void *stream) {
+    if (!h) return NSP_ERR_ARG;
+    if (!(grad.u && grad.v && grad.w)) return fail(h, NSP_ERR_ARG, "null gradient arrays");
+    if (!nsp_fine_solve_tape_valid(h, tape))
+        return fail(h, NSP_ERR_ARG, "stale tape: another run was recorded or the lid changed since");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const long long L = state_len(h);
+    const long long F3 = h->nu + h->nv + h->nw;
+    const int nsteps = h->tape_nsteps, ck = h->tape_ck, nseg = h->tape_nseg;
+    const double dt = h->tape_dt;
+    const nsp_poisson_opts o = h->tape_opts;
+    nsp_state y = packed_state(h, h->adj_y);
+    nsp_handle *hs[1] = {h};
+    int one = 1;
+    nsp_status st;
+    const AdjParams A = adj_params(h, dt);
     double *lam[3] = {h->adj_lam, h->adj_lam + h->nu, h->adj_lam + h->nu + h->nv};
     double *mu[3] = {h->adj_mu, h->adj_mu + h->nu, h->adj_mu + h->nu + h->nv};
-    HIPCHK(h, launch_scale_open(A, vel, vol, lam, s));
-    HIPCHK(h, hipMemsetAsync(h->adj_glid, 0, (size_t)h->nz * (h->nx + 1) * sizeof(double), s));
-    HIPCHK(h, hipMemsetAsync(h->adj_p, 0, h->ncells * sizeof(double), s));
-    nsp_poisson_opts po = *o;
+    HIPCHK(h, launch_copy_state(h->adj_lam, h->adj_fin, F3, s));
+    HIPCHK(h, launch_zero_words(h->adj_glid, 2LL * h->nz * (h->nx + 1), s));
+    HIPCHK(h, launch_zero_words(h->adj_p, 2LL * h->ncells, s));
+    nsp_poisson_opts po = o;
     po.prec = NSP_FP64;  // the adjoint differentiates the exact projection
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int len = std::min(ck, nsteps - sg * ck);
@@ -1107,7 +1154,7 @@ nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, doubl
         for (int m = 0; m < len; ++m) {
             HIPCHK(h, launch_copy_state(h->adj_segu + (long long)m * F3, h->adj_y, F3, s));
             if (m + 1 < len) {
-                st = propagate(hs, &y, &one, 1, 0.0, dt, dt, o, stream, nullptr);
+                st = propagate(hs, &y, &one, 1, 0.0, dt, dt, &o, stream, nullptr);
                 if (st != NSP_OK) return st;
             }
         }
@@ -1134,6 +1181,16 @@ nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, doubl
     if (g_lid) HIPCHK(h, launch_copy_state(g_lid, h->adj_glid, (long long)h->nz * (h->nx + 1), s));
     HIPCHK(h, hipStreamSynchronize(s));
     return NSP_OK;
+}
+
+nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
+                                  const nsp_poisson_opts *o, nsp_state grad, double *g_lid, double *J, void *stream) {
+    if (!h) return NSP_ERR_ARG;
+    const bool want_grad = grad.u && grad.v && grad.w;
+    unsigned long long tape = 0;
+    nsp_status st = nsp_fine_solve_record(h, y0, nsteps, dt, ckpt_every, o, J, want_grad ? &tape : nullptr, stream);
+    if (st != NSP_OK || !want_grad) return st;
+    return nsp_fine_solve_reverse(h, tape, grad, g_lid, stream);
 }
 
 nsp_status nsp_lid_from_modes(nsp_handle *h, const double *coef, int nmodes, double *lid_dev, void *stream) {

@@ -110,6 +110,11 @@ def lib():
         L.nsp_last_launch_ms.argtypes = [P, ctypes.POINTER(D)]
         L.nsp_fine_solve_adjoint.argtypes = [P, _State, I, D, I, ctypes.POINTER(_Opts), _State, P,
                                              ctypes.POINTER(D), P]
+        L.nsp_fine_solve_record.argtypes = [P, _State, I, D, I, ctypes.POINTER(_Opts), ctypes.POINTER(D),
+                                            ctypes.POINTER(ctypes.c_ulonglong), P]
+        L.nsp_fine_solve_reverse.argtypes = [P, ctypes.c_ulonglong, _State, P, P]
+        L.nsp_fine_solve_tape_valid.argtypes = [P, ctypes.c_ulonglong]
+        L.nsp_fine_solve_tape_valid.restype = I
         L.nsp_lid_from_modes.argtypes = [P, P, I, P, P]
         L.nsp_lid_modes_grad.argtypes = [P, P, I, P, P]
         for name in ("nsp_create", "nsp_destroy", "nsp_set_lid", "nsp_poisson_solve", "nsp_poisson_solve_noalloc",
@@ -118,7 +123,8 @@ def lib():
                      "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
                      "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
                      "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
-                     "nsp_launch_stats_get", "nsp_set_coarse_convection"):
+                     "nsp_launch_stats_get", "nsp_set_coarse_convection", "nsp_fine_solve_record",
+                     "nsp_fine_solve_reverse"):
             getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -410,6 +416,36 @@ class Handle:
         self._err(st, "nsp_fine_solve_adjoint")
         return J.value, g, gl
 
+    def fine_solve_record(self, y0, nsteps, dt, ckpt_every=10, opts=None, keep=True):
+        """Forward half of fine_solve_adjoint: J after nsteps steps from y0
+        (batch 1) and, if keep, the id of the record the handle now holds for
+        fine_solve_reverse (else 0).  Returns (J, tape)."""
+        opts = opts or PoissonOpts(rtol=1e-12)
+        s = self._state(y0, 1, "y0")
+        o = opts.c()
+        J = ctypes.c_double()
+        tape = ctypes.c_ulonglong(0)
+        st = lib().nsp_fine_solve_record(self._h, s, int(nsteps), float(dt), int(ckpt_every), ctypes.byref(o),
+                                         ctypes.byref(J), ctypes.byref(tape) if keep else None, _stream_ptr())
+        self._err(st, "nsp_fine_solve_record")
+        return J.value, tape.value
+
+    def tape_valid(self, tape):
+        """True while the record `tape` may still be reversed."""
+        return bool(lib().nsp_fine_solve_tape_valid(self._h, ctypes.c_ulonglong(int(tape))))
+
+    def fine_solve_reverse(self, tape, device=None):
+        """Reverse sweep of the record `tape`: ((gu, gv, gw), g_lid)."""
+        torch = _torch()
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        g = tuple(torch.zeros(sh, dtype=torch.float64, device=dev) for sh in self.shapes(1)[:3])
+        gl = torch.zeros((self.nz, self.nx + 1), dtype=torch.float64, device=dev)
+        gs = _State(g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(), None)
+        st = lib().nsp_fine_solve_reverse(self._h, ctypes.c_ulonglong(int(tape)), gs, ctypes.c_void_p(gl.data_ptr()),
+                                          _stream_ptr())
+        self._err(st, "nsp_fine_solve_reverse")
+        return g, gl
+
     def lid_from_modes(self, coef):
         """lid = 1 + sum c[m,n] sin(m pi x) sin(n pi z) at the top u-faces."""
         torch = _torch()
@@ -500,4 +536,5 @@ EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_p
             "nsp_group_parareal_start", "nsp_group_parareal_iterate", "nsp_set_launch", "nsp_autotune",
             "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
             "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
-            "nsp_launch_stats_get", "nsp_set_coarse_convection")
+            "nsp_launch_stats_get", "nsp_set_coarse_convection", "nsp_fine_solve_record",
+            "nsp_fine_solve_reverse", "nsp_fine_solve_tape_valid")

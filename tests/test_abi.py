@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     hdr = open(os.path.join(ROOT, "include", "nsp.h")).read()
-    return sorted(set(re.findall(r"^(?:nsp_status|const char \*)\s*(nsp_\w+)\s*\(", hdr, re.M)))
+    return sorted(set(re.findall(r"^(?:nsp_status|const char \*|int)\s*(nsp_\w+)\s*\(", hdr, re.M)))
 
 
 def test_header_symbols_exported():

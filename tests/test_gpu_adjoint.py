@@ -53,6 +53,85 @@ def test_adjoint_matches_oracle(gpu, oracle):
     h.close()
 
 
+def _small_case(gpu, n=14):
+    solid = np.zeros((n, n, n), np.uint8)
+    solid[4:7, 3:5, 5:8] = 1
+    solid[2, n - 2, 3] = 1  # an obstacle under the lid
+    lid = 1.0 + 0.1 * np.random.default_rng(2).standard_normal((n, n + 1))
+    h = gpu.Handle(n, n, n, re=400.0, solid=solid, max_batch=1)
+    h.set_lid(T(lid))
+    u0 = inputs.div_free_perturbation(n, n, n, seed=5, sigma=1e-1)
+    y0 = tuple(T(a[None]) for a in (u0[0], u0[1], u0[2], np.zeros((n, n, n))))
+    return h, y0, lid
+
+
+def test_record_and_reverse(gpu):
+    """nsp_fine_solve_record + nsp_fine_solve_reverse give the one-call
+    gradient bitwise; a record can be reversed twice; set_lid or a newer
+    record makes it stale (NSP_ERR_ARG, outputs untouched)."""
+    steps, dt = 6, 1e-3
+    _say("record/reverse", steps)
+    h, y0, lid = _small_case(gpu)
+    opts = gpu.PoissonOpts(rtol=1e-12)
+    J1, g1, gl1 = h.fine_solve_adjoint(y0, steps, dt, ckpt_every=3, opts=opts)
+    J2, tape = h.fine_solve_record(y0, steps, dt, ckpt_every=3, opts=opts)
+    assert J2 == J1 and tape != 0 and h.tape_valid(tape)
+    g2, gl2 = h.fine_solve_reverse(tape)
+    g3, gl3 = h.fine_solve_reverse(tape)
+    for a, b, c in zip(g1 + (gl1,), g2 + (gl2,), g3 + (gl3,)):
+        assert np.array_equal(N(a), N(b)) and np.array_equal(N(a), N(c))
+    assert float(gl1.abs().max()) > 0.0
+    # J only: nothing is kept, the old record goes stale all the same
+    J3, t0 = h.fine_solve_record(y0, steps, dt, ckpt_every=3, opts=opts, keep=False)
+    assert J3 == J1 and t0 == 0 and not h.tape_valid(tape) and not h.tape_valid(0)
+    _, tape = h.fine_solve_record(y0, steps, dt, ckpt_every=3, opts=opts)
+    h.set_lid(T(lid))
+    assert not h.tape_valid(tape)
+    with pytest.raises(gpu.NSPError) as e:
+        h.fine_solve_reverse(tape)
+    assert e.value.status == gpu.NSP_ERR_ARG
+    h.close()
+
+
+def test_autograd_backward_reuses_the_forward_record(gpu):
+    """J.backward() reverses the record its forward made: the fine steps run
+    in backward are only the segment recomputations (nseg (ck - 1) steps),
+    not another forward sweep; a stale record is recorded again."""
+    import torch
+    from paper_1705_06149_amd.autograd import kinetic_energy
+
+    n, steps, dt, ck = 14, 6, 1e-3, 3
+    _say("autograd record reuse", steps)
+    h, y0, lid = _small_case(gpu, n)
+    opts = gpu.PoissonOpts(rtol=1e-12)
+    ref = h.fine_solve_adjoint(y0, steps, dt, ckpt_every=ck, opts=opts)
+    cells = n ** 3
+
+    def run(stale):
+        u = [y0[c][0].clone().requires_grad_() for c in range(3)]
+        lid_t = T(lid).requires_grad_()
+        J = kinetic_energy(h, u[0], u[1], u[2], lid_t, steps, dt, ckpt_every=ck, opts=opts)
+        if stale:
+            h.fine_solve_record(y0, steps, dt, ckpt_every=ck, opts=opts)
+        h.launch_stats(reset=True)
+        J.backward()
+        st = h.launch_stats()
+        return float(J.detach()), u, lid_t, st["fine"]["cell_steps"], st["project"]["launches"]
+
+    J, u, lid_t, fine_cells, nproj = run(False)
+    assert J == ref[0]
+    assert fine_cells == (steps // ck) * (ck - 1) * cells
+    assert nproj == steps
+    for a, b in zip(u, ref[1]):
+        assert np.array_equal(N(a.grad), N(b[0]))
+    assert np.array_equal(N(lid_t.grad), N(ref[2]))
+    J, u, lid_t, fine_cells, nproj = run(True)
+    assert fine_cells == (steps + (steps // ck) * (ck - 1)) * cells
+    for a, b in zip(u, ref[1]):
+        assert np.array_equal(N(a.grad), N(b[0]))
+    h.close()
+
+
 def test_lid_modes_are_transposes(gpu):
     n, M = 20, 16
     h = gpu.Handle(n, n, n, max_batch=1)

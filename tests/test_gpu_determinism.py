@@ -1,7 +1,8 @@
 """Repeatability on the GPU (the library's race detector: every reduction has a
 fixed order and no floating-point atomics feed a result): the same call on
 the same inputs twice gives bitwise the same outputs, for the FP64, mixed and
-BiCGStab solves and a projection step with obstacles; and a Parareal run
+BiCGStab solves, a projection step with obstacles and the adjoint gradient;
+and a Parareal run
 saved after iteration k (Y, Gk and k through torch.save) and resumed in a new
 handle finishes bitwise like the uninterrupted run."""
 import io
@@ -44,6 +45,26 @@ def test_repeat_runs_are_bitwise_equal(gpu, prec, solver):
     for c in range(4):
         assert np.array_equal(outs[0][0][c], outs[1][0][c]), c
     assert outs[0][1] == outs[1][1]
+    h.close()
+
+
+def test_adjoint_gradients_repeat_bitwise(gpu):
+    """The momentum adjoint is a gather without atomics: two gradient
+    computations from the same state give bitwise equal J, dJ/du0 and
+    dJ/dlid."""
+    n, steps, dt = 64, 4, 1e-3
+    _say("adjoint repeat", n, steps)
+    solid = inputs.obstacle_mask(n, 5)
+    h = gpu.Handle(n, n, n, re=400.0, solid=solid, max_batch=1)
+    lid = 1.0 + 0.1 * np.random.default_rng(4).standard_normal((n, n + 1))
+    h.set_lid(T(lid))
+    st = inputs.random_state(n, n, n, seed=3, scale=0.2, pscale=0.0)
+    y0 = tuple(T(a[None]) for a in st)
+    outs = [h.fine_solve_adjoint(y0, steps, dt, ckpt_every=2, opts=gpu.PoissonOpts(rtol=1e-12)) for _ in range(2)]
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1] + (outs[0][2],), outs[1][1] + (outs[1][2],)):
+        assert np.array_equal(N(a), N(b))
+    assert float(outs[0][2].abs().max()) > 0.0
     h.close()
 
 
