@@ -55,6 +55,9 @@ BYTES_SR_START = 17.0    # the start of a single-reduction run: w = A M^-1 r (re
 # and 80 B per cell per FP64 CG iteration (read r, d, write d, q; read x, d,
 # r, q, write x, r).
 MODEL_STEP_FIXED, MODEL_CG_ITER = 112.0, 80.0
+# a projection of the adjoint sweep: the step without its momentum predictor
+# (read u, v, w, write F: 48 B per cell)
+MODEL_PROJECT_FIXED = MODEL_STEP_FIXED - 48.0
 
 
 def _prec(args):
@@ -664,12 +667,12 @@ def bench_paper_sim(args, sim):
 BYTES_PROJECT_FIXED = 163.0  # adjoint projection launch: a fine step's fixed bytes without the predictor
 
 
-def _stats_model_bytes(st):
+def _stats_model_bytes(st, fixed=MODEL_STEP_FIXED):
     """The method's algorithmic bytes of the launches in one entry of the
-    launch statistics: 112 B per cell and step, 80 B per FP64 CG iteration,
-    40 B per FP32 iteration and per mixed-precision sweep (BiCGStab, which
-    the byte model does not list, at its kernel's 139 B)."""
-    return (st["cell_steps"] * MODEL_STEP_FIXED + st["cg64_cell_iters"] * MODEL_CG_ITER +
+    launch statistics: `fixed` (112) B per cell and step, 80 B per FP64 CG
+    iteration, 40 B per FP32 iteration and per mixed-precision sweep
+    (BiCGStab, which the byte model does not list, at its kernel's 139 B)."""
+    return (st["cell_steps"] * fixed + st["cg64_cell_iters"] * MODEL_CG_ITER +
             st["cg32_cell_iters"] * 0.5 * MODEL_CG_ITER + st["bicg_cell_iters"] * BYTES_BICG_ITER +
             st["mixed_cell_sweeps"] * 40.0)
 
@@ -684,38 +687,71 @@ def _stats_bytes(st, fixed):
             st["mixed_cell_sweeps"] * BYTES_MIXED_SWEEP)
 
 
+def _time_momentum_adjoint(h, y, nsp, dt, reps=20):
+    """Average duration of one nsp_momentum_adjoint launch (k_mom_adjoint) at
+    the state y, with seeded adjoint weights, from HIP events on the stream it
+    runs on (torch's current stream)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(17)
+    mu = tuple(torch.randn(a.shape, dtype=torch.float64, device="cuda", generator=g) for a in y[:3])
+    lam = tuple(torch.empty_like(a) for a in y[:3])
+    glid = torch.zeros((h.nz, h.nx + 1), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        h.momentum_adjoint(y[:3], mu, lam, dt, glid)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        h.momentum_adjoint(y[:3], mu, lam, dt, glid)
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def bench_adjoint(args):
     """The adjoint workload: 96^3 cavity, Re 400, 100 fine steps of 1e-3,
     J = kinetic energy at T, gradients with respect to the initial velocity
     (a seeded divergence-free N(0, 1e-2) perturbation) and the 16 x 16 lid
     sine coefficients, checkpoints every 10 steps, FP64.  A "step" is one
-    whole gradient evaluation (forward sweep, recomputation from the
-    checkpoints, reverse sweep); value = cells x fine steps / wall time per
-    gradient.  The roofline is that of k_persistent over every launch inside
-    the evaluations (forward segments and the reverse projections), from the
-    library's launch statistics (HIP events on the launch stream)."""
+    whole gradient through the autograd path (J = kinetic_energy(...) then
+    J.backward(): the forward sweep records its checkpoints, backward
+    recomputes the segments from them and runs the reverse sweep); value =
+    cells x fine steps / wall time per gradient.  The roofline is that of
+    k_persistent over every launch inside the evaluations (forward segments,
+    recomputation and the reverse projections), from the library's launch
+    statistics (HIP events on the launch stream); k_mom_adjoint, the
+    transposed momentum step, is timed on its own beside it."""
     import torch
     from paper_1705_06149_amd import inputs, nsp
+    from paper_1705_06149_amd.autograd import LidFromModes, kinetic_energy
 
     n, re_, dt, nsteps, ck, M = 96, 400.0, 1e-3, 100, 10, 16
     K = args.steps if args.steps_given else 2
     W = args.warmup if args.warmup_given else 1
     h = nsp.Handle(n, n, n, re=re_, max_batch=1)
-    u0 = inputs.div_free_perturbation(n, n, n, seed=5, sigma=1e-2)
-    y0 = tuple(torch.from_numpy(np.ascontiguousarray(a[None])).cuda() for a in u0) + (
-        torch.zeros((1, n, n, n), dtype=torch.float64, device="cuda"),)
+    u0 = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+          for a in inputs.div_free_perturbation(n, n, n, seed=5, sigma=1e-2)]
     g = torch.Generator(device="cuda").manual_seed(16)
     coef = 1e-2 * torch.randn((M, M), dtype=torch.float64, device="cuda", generator=g)
-    h.set_lid(h.lid_from_modes(coef))
     opts = nsp.PoissonOpts(rtol=1e-12)
+    split = {"forward_s": 0.0, "backward_s": 0.0}
 
     def gradient():
-        J, gu, glid = h.fine_solve_adjoint(y0, nsteps, dt, ckpt_every=ck, opts=opts)
-        return J, gu, h.lid_modes_grad(glid, M)
+        us = [a.clone().requires_grad_() for a in u0]
+        c = coef.clone().requires_grad_()
+        t0 = time.perf_counter()
+        J = kinetic_energy(h, us[0], us[1], us[2], LidFromModes.apply(c, h), nsteps, dt, ckpt_every=ck, opts=opts)
+        _sync()
+        t1 = time.perf_counter()
+        J.backward()
+        _sync()
+        split["forward_s"] += t1 - t0
+        split["backward_s"] += time.perf_counter() - t1
+        return float(J.detach()), [a.grad for a in us], c.grad
 
     for _ in range(W):
         gradient()
     _sync()
+    split["forward_s"] = split["backward_s"] = 0.0
     h.launch_stats(reset=True)
     t0 = time.perf_counter()
     for i in range(K):
@@ -726,28 +762,44 @@ def bench_adjoint(args):
     st = h.launch_stats()
     cells = n ** 3
     fine, proj = st["fine"], st["project"]
-    byts = _stats_bytes(fine, BYTES_STEP_FIXED["fp64"]) + _stats_bytes(proj, BYTES_PROJECT_FIXED)
+    byts = _stats_model_bytes(fine) + _stats_model_bytes(proj, MODEL_PROJECT_FIXED)
+    klayout = _stats_bytes(fine, BYTES_STEP_FIXED["fp64"]) + _stats_bytes(proj, BYTES_PROJECT_FIXED)
     kms = fine["ms"] + proj["ms"]
     launches = fine["launches"] + proj["launches"]
     achieved = byts / (kms * 1e-3) / 1e9
+    # k_mom_adjoint alone, at the 96^3 state after the forward sweep
+    y = h.zeros_state(1)
+    h.fine_step(y, 0.0, 0.01, dt, opts)
+    ma_ms = _time_momentum_adjoint(h, y, nsp, dt)
+    nfaces = (n + 1) * n * n * 3
+    ma_bytes = 24.0 * nfaces + cells + 24.0 * n * (n + 1)
+    ma_gbs = ma_bytes / (ma_ms * 1e-3) / 1e9
     out = {
         "metric": "adjoint cell-updates/s", "value": cells * nsteps * K / wall, "unit": "cell-updates/s",
         "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * wall / K, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "adjoint96_re400", "grid": [n, n, n], "re": re_, "dt": dt, "fine_steps": nsteps,
                    "checkpoint_every": ck, "lid_modes": [M, M], "poisson": "Jacobi-PCG rtol 1e-12",
-                   "step": "one gradient of J (forward, recomputation, reverse)"},
+                   "step": "one gradient of J through autograd (forward sweep with checkpoints, then "
+                           "recomputation and reverse sweep)"},
         "J": J, "grad_u0_l2": float(torch.sqrt(sum((a ** 2).sum() for a in gu))),
         "grad_lid_coef_l2": float(torch.linalg.norm(gc)),
+        "forward_s_per_gradient": split["forward_s"] / K, "backward_s_per_gradient": split["backward_s"] / K,
         "k_persistent_share_of_wall": kms * 1e-3 / wall,
         "forward_cg_iters_per_step": fine["cg_cell_iters"] / max(fine["cell_steps"], 1.0),
         "reverse_cg_iters_per_projection": proj["cg_cell_iters"] / max(proj["cell_steps"], 1.0),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": _traffic_from_profile("k_persistent_adjoint96_pmc.txt"),
-                     "kernel": "k_persistent (forward segments and reverse projections)",
+                     "kernel": "k_persistent (forward segments, recomputation and reverse projections)",
                      "avg_launch_ms": kms / max(launches, 1), "launches": launches,
-                     "algorithmic_bytes_per_launch": byts / max(launches, 1)},
+                     "algorithmic_bytes_per_launch": byts / max(launches, 1),
+                     "kernel_layout_bytes_per_launch": klayout / max(launches, 1),
+                     "kernel_layout_frac": klayout / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "k_mom_adjoint": {"avg_launch_ms": ma_ms, "algorithmic_bytes_per_launch": ma_bytes,
+                          "bytes_model": "read u, v, w and mu (3 face arrays each), write lam, flags, lid and "
+                                         "g_lid: 24 B per face + 1 B per cell + 24 B per lid value",
+                          "achieved": ma_gbs, "unit": "GB/s", "frac": ma_gbs / PEAK_HBM_GBS},
     }
     h.close()
     return out

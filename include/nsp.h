@@ -302,6 +302,22 @@ nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, doubl
                                   const nsp_poisson_opts *opts, nsp_state grad, double *g_lid, double *J,
                                   void *stream);
 
+/* One reverse momentum step of the adjoint above, on its own:
+ *     lam = mu + dt (dR/du)^T mu   on open faces (0 on closed faces),
+ *     g_lid += dt (dR/dlid)^T mu   (if g_lid is non-NULL),
+ * R the momentum right-hand side of the fine step (Sec. 2: central
+ * diffusion, SMART convection with the slopes of the branch taken at vel,
+ * image rule at walls and obstacles, the lid above the top row of u) at the
+ * velocity vel, with the handle's Reynolds number, obstacles and lid.  vel,
+ * mu, lam: DEVICE face arrays of one slice (the p pointers are ignored);
+ * g_lid: DEVICE [nz][nx+1], accumulated.  lam must not alias vel or mu
+ * (NSP_ERR_ARG).  Asynchronous on `stream`; nothing is allocated.  Each face
+ * gathers its contributions in a fixed order (no atomics), so results repeat
+ * bitwise.  NSP_ERR_UNSUPPORTED on a grid periodic in z or with free-slip
+ * obstacles. */
+nsp_status nsp_momentum_adjoint(nsp_handle *h, nsp_state vel, nsp_state mu, nsp_state lam, double *g_lid, double dt,
+                                void *stream);
+
 /* The two halves of nsp_fine_solve_adjoint, for callers (an autograd
  * function) whose forward pass runs before they know whether a gradient is
  * wanted.  nsp_fine_solve_record runs the forward sweep from y0 and writes

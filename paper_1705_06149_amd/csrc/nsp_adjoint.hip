@@ -295,7 +295,7 @@ __device__ __forceinline__ void gather_face(const AdjGrid &G, const double *cons
     if (T != 1) r += carried<1, T>(G, vel, mu, i, j, k);
     if (T != 2) r += carried<2, T>(G, vel, mu, i, j, k);
     lam[x] = r;
-    if (T == 0 && j == G.ny - 1) glid[(long)k * (G.nx + 1) + i] += gl;
+    if (T == 0 && j == G.ny - 1 && glid) glid[(long)k * (G.nx + 1) + i] += gl;
 }
 
 struct AdjVecs {

@@ -1183,6 +1183,22 @@ nsp_status nsp_fine_solve_reverse(nsp_handle *h, unsigned long long tape, nsp_st
     return NSP_OK;
 }
 
+nsp_status nsp_momentum_adjoint(nsp_handle *h, nsp_state vel, nsp_state mu, nsp_state lam, double *g_lid, double dt,
+                                void *stream) {
+    if (!h) return NSP_ERR_ARG;
+    if (h->pz) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for walls in z only");
+    if (h->slip) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for no-slip obstacles only");
+    if (!(vel.u && vel.v && vel.w && mu.u && mu.v && mu.w && lam.u && lam.v && lam.w) || !(dt > 0))
+        return fail(h, NSP_ERR_ARG, "bad momentum-adjoint arguments");
+    const double *vp[3] = {vel.u, vel.v, vel.w}, *mp[3] = {mu.u, mu.v, mu.w};
+    double *lp[3] = {lam.u, lam.v, lam.w};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (lp[a] == mp[b] || lp[a] == vp[b]) return fail(h, NSP_ERR_ARG, "lam must not alias vel or mu");
+    HIPCHK(h, launch_momentum_adjoint(adj_params(h, dt), vp, mp, lp, g_lid, static_cast<hipStream_t>(stream)));
+    return NSP_OK;
+}
+
 nsp_status nsp_fine_solve_adjoint(nsp_handle *h, nsp_state y0, int nsteps, double dt, int ckpt_every,
                                   const nsp_poisson_opts *o, nsp_state grad, double *g_lid, double *J, void *stream) {
     if (!h) return NSP_ERR_ARG;

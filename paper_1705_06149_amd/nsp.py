@@ -114,6 +114,7 @@ def lib():
                                             ctypes.POINTER(ctypes.c_ulonglong), P]
         L.nsp_fine_solve_reverse.argtypes = [P, ctypes.c_ulonglong, _State, P, P]
         L.nsp_fine_solve_tape_valid.argtypes = [P, ctypes.c_ulonglong]
+        L.nsp_momentum_adjoint.argtypes = [P, _State, _State, _State, P, D, P]
         L.nsp_fine_solve_tape_valid.restype = I
         L.nsp_lid_from_modes.argtypes = [P, P, I, P, P]
         L.nsp_lid_modes_grad.argtypes = [P, P, I, P, P]
@@ -124,7 +125,7 @@ def lib():
                      "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
                      "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
                      "nsp_launch_stats_get", "nsp_set_coarse_convection", "nsp_fine_solve_record",
-                     "nsp_fine_solve_reverse"):
+                     "nsp_fine_solve_reverse", "nsp_momentum_adjoint"):
             getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -430,6 +431,23 @@ class Handle:
         self._err(st, "nsp_fine_solve_record")
         return J.value, tape.value
 
+    def momentum_adjoint(self, vel, mu, lam, dt, g_lid=None):
+        """lam = mu + dt (dR/du)^T mu at the velocity vel; g_lid += dt
+        (dR/dlid)^T mu if given.  vel, mu, lam: (u, v, w) of one slice, with or
+        without a batch dimension of 1.  Asynchronous on the current stream."""
+        shp = self.shapes(1)[:3]
+
+        def st(t, name):
+            ptrs = [_check(a if a.dim() == 4 else a[None], s, "%s[%d]" % (name, i))
+                    for i, (a, s) in enumerate(zip(t, shp))]
+            return _State(ptrs[0], ptrs[1], ptrs[2], None)
+
+        gl = None
+        if g_lid is not None:
+            gl = _check(g_lid, (self.nz, self.nx + 1), "g_lid")
+        self._err(lib().nsp_momentum_adjoint(self._h, st(vel, "vel"), st(mu, "mu"), st(lam, "lam"), gl, float(dt),
+                                             _stream_ptr()), "nsp_momentum_adjoint")
+
     def tape_valid(self, tape):
         """True while the record `tape` may still be reversed."""
         return bool(lib().nsp_fine_solve_tape_valid(self._h, ctypes.c_ulonglong(int(tape))))
@@ -537,4 +555,4 @@ EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_p
             "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
             "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
             "nsp_launch_stats_get", "nsp_set_coarse_convection", "nsp_fine_solve_record",
-            "nsp_fine_solve_reverse", "nsp_fine_solve_tape_valid")
+            "nsp_fine_solve_reverse", "nsp_fine_solve_tape_valid", "nsp_momentum_adjoint")

@@ -132,6 +132,55 @@ def test_autograd_backward_reuses_the_forward_record(gpu):
     h.close()
 
 
+def test_momentum_adjoint_entry_matches_oracle(gpu, oracle):
+    """nsp_momentum_adjoint alone against the oracle's momentum_adjoint on a
+    non-cubic grid with obstacles (one under the lid), a random lid, random
+    velocities (every SMART branch and both transport signs) and random
+    adjoint weights, closed faces holding garbage on input: lam to 1e-12 of
+    its max norm, g_lid accumulated onto a nonzero start, bitwise repeat,
+    and lam aliasing mu refused."""
+    import torch
+    nx, ny, nz, dt = 13, 11, 12, 1e-2
+    _say("momentum adjoint entry", nx, ny, nz)
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[3:6, 2:5, 4:7] = 1
+    solid[7, ny - 2, 2] = 1
+    solid[2, 5, nx - 2] = 1
+    rng = np.random.default_rng(11)
+    lid = 1.0 + 0.3 * rng.standard_normal((nz, nx + 1))
+    g = oracle.Grid(nx, ny, nz, re=50.0, solid=solid, lid=lid)
+    su, sv, sw, _ = g.shapes()
+    vel = [0.5 * rng.standard_normal(s) for s in (su, sv, sw)]
+    mu = [rng.standard_normal(s) for s in (su, sv, sw)]
+    lam_ref, glid_ref = oracle.momentum_adjoint(g, *vel, dt, mu)
+    h = gpu.Handle(nx, ny, nz, re=50.0, solid=solid, max_batch=1)
+    h.set_lid(T(lid))
+    g0 = rng.standard_normal((nz, nx + 1))
+    outs = []
+    for _ in range(2):
+        lam = tuple(torch.full((1,) + s, 7.0, dtype=torch.float64, device="cuda") for s in (su, sv, sw))
+        gl = T(g0)
+        h.momentum_adjoint(tuple(T(a) for a in vel), tuple(T(a) for a in mu), lam, dt, gl)
+        torch.cuda.synchronize()
+        outs.append(([N(a)[0] for a in lam], N(gl)))
+    for c in range(3):
+        scale = np.abs(lam_ref[c]).max()
+        err = np.abs(outs[0][0][c] - lam_ref[c]).max()
+        _say("  lam", c, err, scale)
+        assert err <= 1e-12 * scale, c
+        assert np.array_equal(outs[0][0][c], outs[1][0][c])
+    gerr = np.abs(outs[0][1] - (g0 + glid_ref)).max()
+    _say("  g_lid", gerr, np.abs(glid_ref).max())
+    assert np.abs(glid_ref).max() > 0.0
+    assert gerr <= 1e-12 * np.abs(glid_ref).max() + 1e-15 * np.abs(g0).max()
+    assert np.array_equal(outs[0][1], outs[1][1])
+    m = tuple(T(a) for a in mu)
+    with pytest.raises(gpu.NSPError) as e:
+        h.momentum_adjoint(tuple(T(a) for a in vel), m, m, dt)
+    assert e.value.status == gpu.NSP_ERR_ARG
+    h.close()
+
+
 def test_lid_modes_are_transposes(gpu):
     n, M = 20, 16
     h = gpu.Handle(n, n, n, max_batch=1)
