@@ -10,7 +10,8 @@
 //     lam = mu + dt (dR/du)^T mu,   g_lid += dt (dR/dlid)^T mu,
 // which k_mom_adjoint gathers face by face: every face sums, in a fixed
 // order, the transposed contributions of the interfaces whose fluxes read
-// it, so the result has no atomics and repeats bitwise.  SMART is piecewise
+// it (each interface evaluated once per tile, in LDS), so the result has no
+// atomics and repeats bitwise.  SMART is piecewise
 // linear in (U, C, D): the adjoint uses the slopes of the branch the forward
 // step took; a zero transport velocity gives a zero flux and no
 // contribution.
@@ -22,6 +23,7 @@ namespace {
 
 struct AdjGrid {
     int nx, ny, nz;
+    int ex[3][3];  // faces of component c along direction d
     double ih[3], ih2[3];
     double inv_re, dt;
     const uint8_t *flags;
@@ -47,10 +49,15 @@ __device__ __forceinline__ long fid(const AdjGrid &G, int i, int j, int k) {
     return ((long)k * ext(G, C, 1) + j) * ext(G, C, 0) + i;
 }
 
-// distance in the array of component C between neighbours along D
+// 32-bit index and neighbour distance along D in the array of component C
+// (the launcher refuses arrays of 2^31 or more faces)
+template <int C>
+__device__ __forceinline__ int fid32(const AdjGrid &G, int i, int j, int k) {
+    return (k * G.ex[C][1] + j) * G.ex[C][0] + i;
+}
 template <int C, int D>
-__device__ __forceinline__ long fstride(const AdjGrid &G) {
-    return D == 0 ? 1 : (D == 1 ? (long)ext(G, C, 0) : (long)ext(G, C, 0) * ext(G, C, 1));
+__device__ __forceinline__ int fstride32(const AdjGrid &G) {
+    return D == 0 ? 1 : (D == 1 ? G.ex[C][0] : G.ex[C][0] * G.ex[C][1]);
 }
 
 // ------------------------------------------------------------ interfaces
@@ -69,254 +76,321 @@ __device__ __forceinline__ long fstride(const AdjGrid &G) {
 // (a closed face of the component's own axis holds 0 and the next position
 // its odd reflection; across, a closed neighbour is a wall half a cell away
 // with image 2 wall - mirror; the lid is the wall above the top row of u),
-// are X[0..3]; Delta = X2 - X1; Phi = a (a > 0: SMART(X0, X1, X2), else
+// are X0..X3; Delta = X2 - X1; Phi = a (a > 0: SMART(X0, X1, X2), else
 // SMART(X3, X2, X1)), a the mean of the two faces of the transport component
 // that straddle the interface (own axis: of X1 and X2).
 
-struct Line {
-    bool oL, oU, om, o2;   // open: L, L + e, L - e, L + 2e
-    bool lidL, lidU;       // the lid is the wall above L / above L + e
-    double X[4];
-};
-
-// image-resolved values of the line of interface (C, D, L = (i,j,k));
-// false when neither L nor L + e is open
-template <int C, int D>
-__device__ __forceinline__ bool line_of(const AdjGrid &G, const double *__restrict__ phi, int i, int j, int k,
-                                        Line &Ln) {
-    constexpr int di = D == 0, dj = D == 1, dk = D == 2;
-    Ln.oL = open_face(G, C, i, j, k);
-    Ln.oU = open_face(G, C, i + di, j + dj, k + dk);
-    if (!Ln.oL && !Ln.oU) return false;
-    Ln.om = open_face(G, C, i - di, j - dj, k - dk);
-    Ln.o2 = open_face(G, C, i + 2 * di, j + 2 * dj, k + 2 * dk);
-    Ln.lidL = C == 0 && D == 1 && j == G.ny - 1;
-    Ln.lidU = C == 0 && D == 1 && j + 1 == G.ny - 1;
-    const double lv = (Ln.lidL || Ln.lidU) ? G.lid[(long)k * (G.nx + 1) + i] : 0.0;
-    const double wL = Ln.lidL ? lv : 0.0, wU = Ln.lidU ? lv : 0.0;
-    const long id = fid<C>(G, i, j, k), s = fstride<C, D>(G);
-    if (Ln.oL) {
-        const double P0 = phi[id];
-        Ln.X[1] = P0;
-        if (C == D) {
-            Ln.X[0] = Ln.om ? phi[id - s] : 0.0;
-            Ln.X[2] = Ln.oU ? phi[id + s] : 0.0;
-            Ln.X[3] = !Ln.oU ? -P0 : (Ln.o2 ? phi[id + 2 * s] : 0.0);
-        } else {
-            Ln.X[0] = Ln.om ? phi[id - s] : 2.0 * 0.0 - P0;
-            Ln.X[2] = Ln.oU ? phi[id + s] : 2.0 * wL - P0;
-            Ln.X[3] = !Ln.oU ? 2.0 * wL - Ln.X[0] : (Ln.o2 ? phi[id + 2 * s] : 2.0 * wU - Ln.X[2]);
-        }
-    } else {
-        const double P1 = phi[id + s];
-        Ln.X[2] = P1;
-        if (C == D) {
-            Ln.X[1] = 0.0;
-            Ln.X[0] = -P1;
-            Ln.X[3] = Ln.o2 ? phi[id + 2 * s] : 0.0;
-        } else {
-            Ln.X[1] = 2.0 * 0.0 - P1;
-            Ln.X[3] = Ln.o2 ? phi[id + 2 * s] : 2.0 * wU - P1;
-            Ln.X[0] = 2.0 * 0.0 - Ln.X[3];
-        }
-    }
-    return true;
-}
-
-// derivatives of X[0..3] with respect to the value at position L + (POS-1) e
-// (cx) and to the lid beside L (lx)
-template <int C, int D, int POS>
-__device__ __forceinline__ void coefs_of(const Line &Ln, double cx[4], double lx[4]) {
-    const double p0 = POS == 0, p1 = POS == 1, p2 = POS == 2, p3 = POS == 3;
-    lx[0] = lx[1] = lx[2] = lx[3] = 0.0;
-    if (Ln.oL) {
-        cx[1] = p1;
-        if (C == D) {
-            cx[0] = Ln.om ? p0 : 0.0;
-            cx[2] = Ln.oU ? p2 : 0.0;
-            cx[3] = !Ln.oU ? -p1 : (Ln.o2 ? p3 : 0.0);
-        } else {
-            cx[0] = Ln.om ? p0 : -p1;
-            cx[2] = Ln.oU ? p2 : -p1;
-            cx[3] = !Ln.oU ? -cx[0] : (Ln.o2 ? p3 : -cx[2]);
-            lx[2] = (!Ln.oU && Ln.lidL) ? 2.0 : 0.0;
-            lx[3] = !Ln.oU ? (Ln.lidL ? 2.0 : 0.0) : ((!Ln.o2 && Ln.lidU) ? 2.0 : 0.0);
-        }
-    } else {
-        cx[2] = p2;
-        if (C == D) {
-            cx[1] = 0.0;
-            cx[0] = -p2;
-            cx[3] = Ln.o2 ? p3 : 0.0;
-        } else {
-            cx[1] = -p2;
-            cx[3] = Ln.o2 ? p3 : -p2;
-            cx[0] = -cx[3];
-            lx[3] = (!Ln.o2 && Ln.lidU) ? 2.0 : 0.0;
-            lx[0] = -lx[3];
-        }
-    }
-}
-
-// value of the transport component D at its face (i,j,k); closed: 0
-template <int D>
-__device__ __forceinline__ double real_face(const AdjGrid &G, const double *__restrict__ a, int i, int j, int k) {
-    return open_face(G, D, i, j, k) ? a[fid<D>(G, i, j, k)] : 0.0;
-}
-
 // SMART (normalised variable, Gaskell & Lau) face value of the upwind
-// triple (U, C, D) and its slopes on the branch taken
-__device__ __forceinline__ double smart_slopes(double U, double C, double D, double &sU, double &sC, double &sD) {
+// triple (U, C, D) and its slopes on the branch taken, without branches
+__device__ __forceinline__ double smart_lin(double U, double C, double D, double &sU, double &sC, double &sD) {
     const double delta = D - U;
-    sU = 0.0; sC = 1.0; sD = 0.0;
-    if (delta == 0.0) return C;
-    const double ph = (C - U) / delta;
-    double pf;
-    if (ph > 0.0 && ph < 1.0 / 6.0) { pf = 3.0 * ph; sU = -2.0; sC = 3.0; }
-    else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0) { pf = 0.75 * ph + 0.375; sU = -0.125; sC = 0.75; sD = 0.375; }
-    else if (ph >= 5.0 / 6.0 && ph < 1.0) { pf = 1.0; sC = 0.0; sD = 1.0; }
-    else pf = ph;
-    return U + pf * delta;
+    const bool z = delta == 0.0;
+    const double ph = (C - U) / (z ? 1.0 : delta);
+    const bool b1 = ph > 0.0 && ph < 1.0 / 6.0;
+    const bool b2 = ph >= 1.0 / 6.0 && ph < 5.0 / 6.0;
+    const bool b3 = ph >= 5.0 / 6.0 && ph < 1.0;
+    const double pf = b1 ? 3.0 * ph : (b2 ? 0.75 * ph + 0.375 : (b3 ? 1.0 : ph));
+    sU = z ? 0.0 : (b1 ? -2.0 : (b2 ? -0.125 : 0.0));
+    sC = z ? 1.0 : (b1 ? 3.0 : (b2 ? 0.75 : (b3 ? 0.0 : 1.0)));
+    sD = z ? 0.0 : (b2 ? 0.375 : (b3 ? 1.0 : 0.0));
+    return z ? C : U + pf * delta;
 }
 
-// The linearised fluxes of interface (C, D, L = (i,j,k)) with their adjoint
-// weights: wphi = dt/h (mu(L+e) - mu(L)), wdel = dt nu/h^2 (mu(L) - mu(L+e)),
-// closed faces taking mu = 0.
-struct Flux {
-    double wphi, wdel;
-    double a;              // transport velocity
-    double S, sU, sC, sD;  // SMART value and slopes (a != 0)
+// A block gathers lam for a tile of TX x TY x TZ faces of component T.
+// Phase 1 evaluates, once each, the interfaces the tile's faces read into
+// LDS: those of component T along x, y and z whose lines hold a face of the
+// tile (lower faces from 2 before the tile to 1 past it), and those of the
+// two other components along T whose transport velocity averages a face of
+// the tile.  Phase 2 sums each face's records in a fixed order.
+constexpr int TX = 8, TY = 8, TZ = 4, kTile = TX * TY * TZ;
+constexpr int kAdjThreads = kTile;
+constexpr int NFX = (TX + 3) * TY * TZ, NFY = TX * (TY + 3) * TZ, NFZ = TX * TY * (TZ + 3);
+constexpr int NKMAX = (TX + 1) * TY * TZ > TX * TY * (TZ + 1) ? (TX + 1) * TY * TZ : TX * TY * (TZ + 1);
+
+// The cell flags of a tile and 3 cells around it, staged in LDS (cells
+// outside the domain: 0, so their faces read as closed); every face an
+// interface of the tile touches lies in this box.
+constexpr int FBX = TX + 6, FBY = TY + 6, FBZ = TZ + 6;
+struct FlagBox {
+    const uint8_t *f;  // LDS, [FBZ][FBY][FBX]
+    int ox, oy, oz;    // global cell of element 0
+    __device__ __forceinline__ int index(int i, int j, int k) const {
+        return ((k - oz) * FBY + (j - oy)) * FBX + (i - ox);
+    }
+    __device__ __forceinline__ bool open(int c, int i, int j, int k) const {
+        const uint8_t bit = c == 0 ? FL_XM : (c == 1 ? FL_YM : FL_ZM);
+        return (f[index(i, j, k)] & bit) != 0;
+    }
 };
 
+// The transpose of interface (C, D, L = (i,j,k)) applied to its adjoint
+// weights wphi = dt/h (mu(L+e) - mu(L)), wdel = dt nu/h^2 (mu(L) - mu(L+e))
+// (closed faces: mu = 0): r[0..3] to the faces of component C at L - e, L,
+// L + e, L + 2e; rl to the lid beside L; tw to each of the two faces of
+// component D that carry the transport velocity (C != D).
 template <int C, int D>
-__device__ __forceinline__ bool flux_of(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
-                                        int j, int k, Line &Ln, Flux &Fx) {
+__device__ __forceinline__ void iface(const AdjGrid &G, const FlagBox &FB, const double *const *vel,
+                                      const double *const *mu, int i, int j, int k, double r[4], double &rl,
+                                      double &tw) {
     constexpr int di = D == 0, dj = D == 1, dk = D == 2;
-    constexpr int ci = C == 0, cj = C == 1, ck = C == 2;
-    if (!line_of<C, D>(G, vel[C], i, j, k, Ln)) return false;
-    const long id = fid<C>(G, i, j, k), s = fstride<C, D>(G);
-    const double mL = Ln.oL ? mu[C][id] : 0.0, mU = Ln.oU ? mu[C][id + s] : 0.0;
-    if (mL == mU) return false;  // both weights vanish
-    Fx.wphi = G.dt * G.ih[D] * (mU - mL);
-    Fx.wdel = G.dt * G.inv_re * G.ih2[D] * (mL - mU);
-    if (C == D) Fx.a = 0.5 * (Ln.X[1] + Ln.X[2]);
-    else
-        Fx.a = 0.5 * (real_face<D>(G, vel[D], i - ci + di, j - cj + dj, k - ck + dk) +
-                      real_face<D>(G, vel[D], i + di, j + dj, k + dk));
-    Fx.S = 0.0;
-    if (Fx.a > 0.0) Fx.S = smart_slopes(Ln.X[0], Ln.X[1], Ln.X[2], Fx.sU, Fx.sC, Fx.sD);
-    else if (Fx.a < 0.0) Fx.S = smart_slopes(Ln.X[3], Ln.X[2], Ln.X[1], Fx.sU, Fx.sC, Fx.sD);
-    return true;
-}
-
-// transposed contribution of interface (C, D, L) to the value of component
-// C at L + (POS-1) e; with LID also its contribution to the lid beside L
-template <int C, int D, int POS, bool LID>
-__device__ __forceinline__ double line_adj(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
-                                           int j, int k, double &glid) {
-    Line Ln;
-    Flux Fx;
-    if (!flux_of<C, D>(G, vel, mu, i, j, k, Ln, Fx)) return 0.0;
-    double cx[4], lx[4];
-    coefs_of<C, D, POS>(Ln, cx, lx);
-    double r = Fx.wdel * (cx[2] - cx[1]);
-    if (LID) glid += Fx.wdel * (lx[2] - lx[1]);
-    if (Fx.a != 0.0) {
-        const double wa = Fx.wphi * Fx.a;
-        if (Fx.a > 0.0) {
-            r += wa * ((Fx.sU * cx[0] + Fx.sC * cx[1]) + Fx.sD * cx[2]);
-            if (LID) glid += wa * ((Fx.sU * lx[0] + Fx.sC * lx[1]) + Fx.sD * lx[2]);
-        } else {
-            r += wa * ((Fx.sU * cx[3] + Fx.sC * cx[2]) + Fx.sD * cx[1]);
-            if (LID) glid += wa * ((Fx.sU * lx[3] + Fx.sC * lx[2]) + Fx.sD * lx[1]);
-        }
-        if (C == D) r += Fx.wphi * 0.5 * Fx.S * (cx[1] + cx[2]);
+    constexpr int fd = D == 0 ? 1 : (D == 1 ? FBX : FBX * FBY);  // flag-box strides along D and C
+    constexpr int fc = C == 0 ? 1 : (C == 1 ? FBX : FBX * FBY);
+    constexpr uint8_t bc = C == 0 ? FL_XM : (C == 1 ? FL_YM : FL_ZM), bd = D == 0 ? FL_XM : (D == 1 ? FL_YM : FL_ZM);
+    // open bits from LDS first; the global loads then depend on them only
+    const int b = FB.index(i, j, k);
+    const bool oL = (FB.f[b] & bc) != 0, oU = (FB.f[b + fd] & bc) != 0;
+    const bool om = (FB.f[b - fd] & bc) != 0, o2 = (FB.f[b + 2 * fd] & bc) != 0;
+    const bool t0 = C != D && (FB.f[b - fc + fd] & bd) != 0, t1 = C != D && (FB.f[b + fd] & bd) != 0;
+    r[0] = r[1] = r[2] = r[3] = 0.0;
+    rl = tw = 0.0;
+    if (!oL && !oU) return;
+    const double *phi = vel[C];
+    const int id = fid32<C>(G, i, j, k), s = fstride32<C, D>(G);
+    double a0 = 0.0, a1 = 0.0;
+    if (C != D) {
+        // the two faces of component D at L + e_D - e_C and L + e_D
+        const int jd = fid32<D>(G, i + di, j + dj, k + dk);
+        a1 = t1 ? vel[D][jd] : 0.0;
+        a0 = t0 ? vel[D][jd - fstride32<D, C>(G)] : 0.0;
     }
-    return r;
+    const bool isL = C == 0 && D == 1 && j == G.ny - 1, isU = C == 0 && D == 1 && j + 1 == G.ny - 1;
+    // interior: the four positions are open faces and no lid is near, so
+    // the image rule is the identity
+    const bool inner = oL && oU && om && o2 && !isL && !isU;
+    double X0, X1, X2, X3, mL, mU;
+    if (inner) {
+        X0 = phi[id - s];
+        X1 = phi[id];
+        X2 = phi[id + s];
+        X3 = phi[id + 2 * s];
+        mL = mu[C][id];
+        mU = mu[C][id + s];
+    } else {
+        const double Pm = om ? phi[id - s] : 0.0, P0 = oL ? phi[id] : 0.0;
+        const double P1 = oU ? phi[id + s] : 0.0, P2 = o2 ? phi[id + 2 * s] : 0.0;
+        mL = oL ? mu[C][id] : 0.0;
+        mU = oU ? mu[C][id + s] : 0.0;
+        const double lv = (isL || isU) ? G.lid[k * (G.nx + 1) + i] : 0.0;
+        const double wL = isL ? lv : 0.0, wU = isU ? lv : 0.0;
+        // image-resolved values
+        if (C == D) {
+            X1 = oL ? P0 : 0.0;
+            X2 = P1;
+            X0 = oL ? Pm : -P1;
+            X3 = oL ? (!oU ? -P0 : P2) : P2;
+        } else {
+            if (oL) {
+                X1 = P0;
+                X0 = om ? Pm : 2.0 * 0.0 - P0;
+                X2 = oU ? P1 : 2.0 * wL - P0;
+                X3 = !oU ? 2.0 * wL - X0 : (o2 ? P2 : 2.0 * wU - X2);
+            } else {
+                X2 = P1;
+                X1 = 2.0 * 0.0 - P1;
+                X3 = o2 ? P2 : 2.0 * wU - P1;
+                X0 = 2.0 * 0.0 - X3;
+            }
+        }
+    }
+    const double wphi = G.dt * G.ih[D] * (mU - mL);
+    const double wdel = G.dt * G.inv_re * G.ih2[D] * (mL - mU);
+    const double a = C == D ? 0.5 * (X1 + X2) : 0.5 * (a0 + a1);
+    const bool pos = a > 0.0;
+    double sU, sC, sD;
+    const double S = smart_lin(pos ? X0 : X3, pos ? X1 : X2, pos ? X2 : X1, sU, sC, sD);
+    // weights of X0..X3
+    const double wa = a != 0.0 ? wphi * a : 0.0;
+    const double ws = a != 0.0 ? wphi * 0.5 * S : 0.0;
+    double w0 = pos ? wa * sU : 0.0;
+    double w1 = (pos ? wa * sC : wa * sD) - wdel;
+    double w2 = (pos ? wa * sD : wa * sC) + wdel;
+    double w3 = pos ? 0.0 : wa * sU;
+    if (C == D) {
+        w1 += ws;
+        w2 += ws;
+    } else {
+        tw = ws;
+    }
+    // through the transpose of the image rule onto the real values
+    if (inner) {
+        r[0] = w0;
+        r[1] = w1;
+        r[2] = w2;
+        r[3] = w3;
+    } else if (C == D) {
+        if (oL) {
+            r[0] = om ? w0 : 0.0;
+            r[1] = w1 - (oU ? 0.0 : w3);
+            r[2] = oU ? w2 : 0.0;
+            r[3] = (oU && o2) ? w3 : 0.0;
+        } else {
+            r[2] = w2 - w0;
+            r[3] = o2 ? w3 : 0.0;
+        }
+    } else {
+        if (oL) {
+            // X3
+            if (!oU) {
+                w0 -= w3;
+                rl += isL ? 2.0 * w3 : 0.0;
+            } else if (o2) {
+                r[3] = w3;
+            } else {
+                r[2] = -w3;
+                rl += isU ? 2.0 * w3 : 0.0;
+            }
+            // X2
+            if (oU) r[2] += w2;
+            else {
+                r[1] -= w2;
+                rl += isL ? 2.0 * w2 : 0.0;
+            }
+            r[1] += w1;
+            // X0
+            if (om) r[0] = w0;
+            else r[1] -= w0;
+        } else {
+            const double w3x = w3 - w0;  // X0 = -X3
+            if (o2) r[3] = w3x;
+            else {
+                r[2] = -w3x;
+                rl = isU ? 2.0 * w3x : 0.0;
+            }
+            r[2] += w2 - w1;
+        }
+    }
 }
 
-// transposed contribution of interface (C, D, L), C != D, to one of the two
-// faces of component D that carry its transport velocity
-template <int C, int D>
-__device__ __forceinline__ double transport_adj(const AdjGrid &G, const double *const *vel, const double *const *mu,
-                                                int i, int j, int k) {
-    Line Ln;
-    Flux Fx;
-    if (!flux_of<C, D>(G, vel, mu, i, j, k, Ln, Fx)) return 0.0;
-    return Fx.a != 0.0 ? Fx.wphi * 0.5 * Fx.S : 0.0;
+struct AdjLds {
+    double fx[4][NFX], fy[4][NFY], fz[4][NFZ];  // r[pos][record]
+    double fl[NFY];                             // lid part of the y interfaces (u only)
+    double k1[NKMAX], k2[NKMAX];                // transport weights of the carried interfaces
+    uint8_t flg[FBX * FBY * FBZ];               // cell flags of the tile and 3 cells around it
+};
+
+// local box of a record family: base offset from the tile origin, extents
+struct Box {
+    int bx, by, bz, ex, ey, ez;
+    __device__ int size() const { return ex * ey * ez; }
+    __device__ void at(int q, int &a, int &b, int &c) const {
+        a = q % ex;
+        b = (q / ex) % ey;
+        c = q / (ex * ey);
+    }
+};
+
+template <int T, int C>
+__device__ __forceinline__ Box carried_box() {
+    // L = t - e_T + {0, e_C}
+    return Box{-(T == 0), -(T == 1), -(T == 2), TX + (C == 0), TY + (C == 1), TZ + (C == 2)};
 }
 
-// the four interfaces along D whose lines hold the face t = (i,j,k) of
-// component C: L = t - 2e .. t + e (t at position 3 .. 0 of their lines)
-template <int C, int D, bool LID>
-__device__ __forceinline__ double along(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
-                                        int j, int k, double &glid) {
-    constexpr int di = D == 0, dj = D == 1, dk = D == 2;
-    double r = line_adj<C, D, 3, false>(G, vel, mu, i - 2 * di, j - 2 * dj, k - 2 * dk, glid);
-    r += line_adj<C, D, 2, LID>(G, vel, mu, i - di, j - dj, k - dk, glid);
-    r += line_adj<C, D, 1, LID>(G, vel, mu, i, j, k, glid);
-    r += line_adj<C, D, 0, false>(G, vel, mu, i + di, j + dj, k + dk, glid);
-    return r;
-}
-
-// the interfaces of component C along T whose transport velocity averages
-// the face t = (i,j,k) of component T: L = t - e_T and t - e_T + e_C
-template <int C, int T>
-__device__ __forceinline__ double carried(const AdjGrid &G, const double *const *vel, const double *const *mu, int i,
-                                          int j, int k) {
-    constexpr int ti = T == 0, tj = T == 1, tk = T == 2;
-    constexpr int ci = C == 0, cj = C == 1, ck = C == 2;
-    return transport_adj<C, T>(G, vel, mu, i - ti, j - tj, k - tk) +
-           transport_adj<C, T>(G, vel, mu, i - ti + ci, j - tj + cj, k - tk + ck);
-}
-
-// lam = mu + dt (dR/du)^T mu at face x of component T, gathered in a fixed
-// order; for the top row of u also g_lid += dt (dR/dlid)^T mu beside it
 template <int T>
-__device__ __forceinline__ void gather_face(const AdjGrid &G, const double *const *vel, const double *const *mu,
-                                            double *__restrict__ lam, double *__restrict__ glid, long x) {
-    const int e0 = ext(G, T, 0), e1 = ext(G, T, 1);
-    const int i = (int)(x % e0), j = (int)((x / e0) % e1), k = (int)(x / ((long)e0 * e1));
-    if (!open_face(G, T, i, j, k)) {
+__device__ void adj_tile(const AdjGrid &G, const double *const *vel, const double *const *mu, double *__restrict__ lam,
+                         double *__restrict__ glid, int x0, int y0, int z0, AdjLds &S) {
+    constexpr int C1 = T == 0 ? 1 : 0, C2 = T == 2 ? 1 : 2;  // the other two components
+    const Box BX{-2, 0, 0, TX + 3, TY, TZ}, BY{0, -2, 0, TX, TY + 3, TZ}, BZ{0, 0, -2, TX, TY, TZ + 3};
+    const Box K1 = carried_box<T, C1>(), K2 = carried_box<T, C2>();
+    const int n1 = NFX, n2 = n1 + NFY, n3 = n2 + NFZ, n4 = n3 + K1.size(), n5 = n4 + K2.size();
+    const FlagBox FB{S.flg, x0 - 3, y0 - 3, z0 - 3};
+    for (int q = threadIdx.x; q < FBX * FBY * FBZ; q += kAdjThreads) {
+        const int i = FB.ox + q % FBX, j = FB.oy + (q / FBX) % FBY, k = FB.oz + q / (FBX * FBY);
+        const bool in = (unsigned)i < (unsigned)G.nx && (unsigned)j < (unsigned)G.ny && (unsigned)k < (unsigned)G.nz;
+        S.flg[q] = in ? G.flags[((long)k * G.ny + j) * G.nx + i] : (uint8_t)0;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n5; q += kAdjThreads) {
+        double r[4], rl, tw;
+        int a, b, c;
+        if (q < n1) {
+            BX.at(q, a, b, c);
+            iface<T, 0>(G, FB, vel, mu, x0 + BX.bx + a, y0 + BX.by + b, z0 + BX.bz + c, r, rl, tw);
+            for (int m = 0; m < 4; ++m) S.fx[m][q] = r[m];
+        } else if (q < n2) {
+            const int qq = q - n1;
+            BY.at(qq, a, b, c);
+            iface<T, 1>(G, FB, vel, mu, x0 + BY.bx + a, y0 + BY.by + b, z0 + BY.bz + c, r, rl, tw);
+            for (int m = 0; m < 4; ++m) S.fy[m][qq] = r[m];
+            S.fl[qq] = rl;
+        } else if (q < n3) {
+            const int qq = q - n2;
+            BZ.at(qq, a, b, c);
+            iface<T, 2>(G, FB, vel, mu, x0 + BZ.bx + a, y0 + BZ.by + b, z0 + BZ.bz + c, r, rl, tw);
+            for (int m = 0; m < 4; ++m) S.fz[m][qq] = r[m];
+        } else if (q < n4) {
+            const int qq = q - n3;
+            K1.at(qq, a, b, c);
+            iface<C1, T>(G, FB, vel, mu, x0 + K1.bx + a, y0 + K1.by + b, z0 + K1.bz + c, r, rl, tw);
+            S.k1[qq] = tw;
+        } else {
+            const int qq = q - n4;
+            K2.at(qq, a, b, c);
+            iface<C2, T>(G, FB, vel, mu, x0 + K2.bx + a, y0 + K2.by + b, z0 + K2.bz + c, r, rl, tw);
+            S.k2[qq] = tw;
+        }
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
+    if (i >= ext(G, T, 0) || j >= ext(G, T, 1) || k >= ext(G, T, 2)) return;
+    const long x = fid<T>(G, i, j, k);
+    if (T == 0 && j == G.ny - 1) {
+        // lid beside the top row of u: the y interfaces below and above it
+        const int q0 = ((tz * (TY + 3) + ty + 1) * TX + tx);
+        glid[(long)k * (G.nx + 1) + i] += S.fl[q0] + S.fl[q0 + TX];
+    }
+    if (!FB.open(T, i, j, k)) {
         lam[x] = 0.0;
         return;
     }
-    double gl = 0.0;
-    double r = mu[T][x];
-    if (T == 0 && j == G.ny - 1) {
-        r += along<T, 0, false>(G, vel, mu, i, j, k, gl);
-        r += along<T, 1, true>(G, vel, mu, i, j, k, gl);
-    } else {
-        r += along<T, 0, false>(G, vel, mu, i, j, k, gl);
-        r += along<T, 1, false>(G, vel, mu, i, j, k, gl);
+    double acc = mu[T][x];
+    // own interfaces along x, y, z: lower faces t - 2e .. t + e hold t at
+    // positions 3 .. 0 of their lines
+    {
+        const int q = (tz * TY + ty) * (TX + 3) + tx;
+        acc += ((S.fx[3][q] + S.fx[2][q + 1]) + (S.fx[1][q + 2] + S.fx[0][q + 3]));
     }
-    r += along<T, 2, false>(G, vel, mu, i, j, k, gl);
-    if (T != 0) r += carried<0, T>(G, vel, mu, i, j, k);
-    if (T != 1) r += carried<1, T>(G, vel, mu, i, j, k);
-    if (T != 2) r += carried<2, T>(G, vel, mu, i, j, k);
-    lam[x] = r;
-    if (T == 0 && j == G.ny - 1 && glid) glid[(long)k * (G.nx + 1) + i] += gl;
+    {
+        const int q = (tz * (TY + 3) + ty) * TX + tx;
+        acc += ((S.fy[3][q] + S.fy[2][q + TX]) + (S.fy[1][q + 2 * TX] + S.fy[0][q + 3 * TX]));
+    }
+    {
+        const int q = (tz * TY + ty) * TX + tx;
+        constexpr int P = TX * TY;
+        acc += ((S.fz[3][q] + S.fz[2][q + P]) + (S.fz[1][q + 2 * P] + S.fz[0][q + 3 * P]));
+    }
+    // carried interfaces: L = t - e_T and t - e_T + e_C
+    {
+        const int q = (tz * K1.ey + ty) * K1.ex + tx;
+        const int st = C1 == 0 ? 1 : (C1 == 1 ? K1.ex : K1.ex * K1.ey);
+        acc += S.k1[q] + S.k1[q + st];
+    }
+    {
+        const int q = (tz * K2.ey + ty) * K2.ex + tx;
+        const int st = C2 == 0 ? 1 : (C2 == 1 ? K2.ex : K2.ex * K2.ey);
+        acc += S.k2[q] + S.k2[q + st];
+    }
+    lam[x] = acc;
 }
 
 struct AdjVecs {
     const double *vel[3];
     const double *mu[3];
     double *lam[3];
-    long n[3];       // faces per component
-    unsigned b[3];   // blocks per component
+    int tiles[3][3];  // tiles of each component along x, y, z
+    unsigned b[3];    // blocks of each component
 };
 
-// one thread per face of the three components; the blocks of each component
-// are contiguous, so a block never mixes components
-__global__ __launch_bounds__(256) void k_mom_adjoint(AdjGrid G, AdjVecs V, double *__restrict__ glid) {
+// one block per tile; the blocks of each component are contiguous
+__global__ __launch_bounds__(kAdjThreads) void k_mom_adjoint(AdjGrid G, AdjVecs V, double *__restrict__ glid) {
+    __shared__ AdjLds S;
     unsigned b = blockIdx.x;
     int t = 0;
     if (b >= V.b[0]) { b -= V.b[0]; t = 1; if (b >= V.b[1]) { b -= V.b[1]; t = 2; } }
-    const long x = (long)b * blockDim.x + threadIdx.x;
-    if (x >= V.n[t]) return;
-    if (t == 0) gather_face<0>(G, V.vel, V.mu, V.lam[0], glid, x);
-    else if (t == 1) gather_face<1>(G, V.vel, V.mu, V.lam[1], glid, x);
-    else gather_face<2>(G, V.vel, V.mu, V.lam[2], glid, x);
+    const int bx = b % V.tiles[t][0], by = (b / V.tiles[t][0]) % V.tiles[t][1], bz = b / (V.tiles[t][0] * V.tiles[t][1]);
+    if (t == 0) adj_tile<0>(G, V.vel, V.mu, V.lam[0], glid, bx * TX, by * TY, bz * TZ, S);
+    else if (t == 1) adj_tile<1>(G, V.vel, V.mu, V.lam[1], glid, bx * TX, by * TY, bz * TZ, S);
+    else adj_tile<2>(G, V.vel, V.mu, V.lam[2], glid, bx * TX, by * TY, bz * TZ, S);
 }
 
 // out = scale * a on open faces of component c, 0 on closed faces
@@ -395,6 +469,9 @@ AdjGrid adj_grid(const AdjParams &A) {
     G.nx = A.nx;
     G.ny = A.ny;
     G.nz = A.nz;
+    const int n[3] = {A.nx, A.ny, A.nz};
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) G.ex[c][d] = n[d] + (c == d);
     for (int d = 0; d < 3; ++d) {
         G.ih[d] = A.ih[d];
         G.ih2[d] = A.ih2[d];
@@ -411,19 +488,24 @@ AdjGrid adj_grid(const AdjParams &A) {
 hipError_t launch_momentum_adjoint(const AdjParams &A, const double *const vel[3], const double *const mu[3],
                                    double *const lam[3], double *glid, hipStream_t s) {
     const AdjGrid G = adj_grid(A);
+    // 32-bit face indices
+    if ((long long)(A.nx + 1) * (A.ny + 1) * (A.nz + 1) >= (1LL << 31)) return hipErrorInvalidValue;
     AdjVecs V;
-    V.n[0] = (long)(A.nx + 1) * A.ny * A.nz;
-    V.n[1] = (long)A.nx * (A.ny + 1) * A.nz;
-    V.n[2] = (long)A.nx * A.ny * (A.nz + 1);
+    const int n[3] = {A.nx, A.ny, A.nz}, tile[3] = {TX, TY, TZ};
     unsigned nb = 0;
     for (int c = 0; c < 3; ++c) {
         V.vel[c] = vel[c];
         V.mu[c] = mu[c];
         V.lam[c] = lam[c];
-        V.b[c] = (unsigned)((V.n[c] + 255) / 256);
-        nb += V.b[c];
+        unsigned cnt = 1;
+        for (int d = 0; d < 3; ++d) {
+            V.tiles[c][d] = (n[d] + (c == d) + tile[d] - 1) / tile[d];
+            cnt *= (unsigned)V.tiles[c][d];
+        }
+        V.b[c] = cnt;
+        nb += cnt;
     }
-    hipLaunchKernelGGL(k_mom_adjoint, dim3(nb), dim3(256), 0, s, G, V, glid);
+    hipLaunchKernelGGL(k_mom_adjoint, dim3(nb), dim3(kAdjThreads), 0, s, G, V, glid);
     return hipGetLastError();
 }
 
