@@ -14,11 +14,15 @@
 // tile writes its own partial sums (fixed-order wave64 butterflies, then a
 // fixed combination of the four waves), so every reduction result depends
 // only on the grid, never on the launch shape or on the batch it shares.
-// Between phases all workgroups meet at a grid barrier built from plain
-// flag stores: one reducer workgroup per slice waits for every arrival, sums
-// that slice's tile partials in a fixed order, runs the CG scalar logic
-// (alpha, beta, convergence) and flags itself done; every workgroup waits
-// for the reducers and ORs the slices' control flags.
+// Between phases all workgroups meet at a grid barrier whose arrivals are
+// combined per XCD (one L2 write-back per XCD and barrier, see SyncWords).
+// After it every workgroup reads all the slices' partials and sums them
+// itself, one wave per slice, in the same fixed order, then runs the CG
+// scalar logic (alpha, beta, convergence, cold start) on its own LDS copy of
+// each slice's state; identical inputs and order give every workgroup the
+// same result, so no reducer workgroup and no second barrier are needed.
+// Launches whose CG tiles fit one per workgroup keep x, r and the search
+// direction in registers across the whole solve (the RR instantiation).
 #include "nsp_internal.h"
 
 namespace nsp {
