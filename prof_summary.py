@@ -7,7 +7,8 @@ kept under profiles/.
            DIR holds `rocprofv3 --kernel-trace --stats --output-format csv
            -o run` output; the summary lists the per-kernel statistics and the
            mean duration of the last K dispatches of the kernel (bench.py's
-           timed launches) beside bench.py's own HIP-event figure.
+           timed launches) beside bench.py's own HIP-event figure
+           (--bench-field, default roofline.avg_launch_ms).
 
   traffic: python prof_summary.py traffic --fetch DIR --write DIR
                --copy-fetch DIR --copy-write DIR --kernel k_persistent --last K
@@ -60,6 +61,15 @@ def _counter(dirpath, counter, kernel):
     return [float(r["Counter_Value"]) for r in rows if _short(r["Kernel_Name"]) == kernel]
 
 
+def _field(d, path):
+    """d["a"]["b"] for path "a.b"; "n/a" when absent"""
+    for k in path.split("."):
+        if not isinstance(d, dict) or k not in d:
+            return "n/a"
+        d = d[k]
+    return d
+
+
 def cmd_trace(a):
     stats = _csv(a.dir, "kernel_stats.csv")
     trace = _csv(a.dir, "kernel_trace.csv")
@@ -81,7 +91,7 @@ def cmd_trace(a):
             "dispatches=%d" % len(dur),
             "timed_dispatches=%d" % len(last),
             "trace_avg_ms_timed=%.4f" % (sum(last) / max(len(last), 1)),
-            "bench_avg_launch_ms=%s" % bench.get("roofline", {}).get("avg_launch_ms", "n/a"),
+            "bench_avg_launch_ms=%s" % _field(bench, a.bench_field),
             "bench_value=%s %s" % (bench["value"], bench["unit"])]
     for k in ("cg_iters_per_step",):
         if k in bench:
@@ -143,6 +153,8 @@ def main():
     t.add_argument("--bench-json", required=True)
     t.add_argument("--cmd", required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--bench-field", default="roofline.avg_launch_ms",
+                   help="the bench.py JSON field with the kernel's own HIP-event launch time")
     p = sub.add_parser("traffic")
     for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--bench-json", "--copy-json", "--hash", "--cmd",
               "--out"):

@@ -1,17 +1,20 @@
-"""Write the serial FP64 reference of the 96^3 Parareal workload.
+"""Write the oracle's serial FP64 reference of a full-size cavity workload.
 
-The workload: lid-driven cavity on the unit cube, 96^3 cells, Re = 1000, lid
-u = 1, start from rest (Sec. 3), fine step dt = 5e-4 up to T = 0.64 (1280
-projection steps), Jacobi-PCG to ||r|| <= 1e-10 ||b||.  Parareal converges to
-the serial fine solution (Sec. 2.1.2, Eqs. (6)-(7)), so this serial run of the
-oracle is the reference the GPU's Parareal end state is checked against.
+Cases (lid-driven cavity on the unit cube, Re = 1000, lid u = 1, start from
+rest as in Sec. 3, fine step dt = 5e-4, Jacobi-PCG to ||r|| <= 1e-10 ||b||):
 
-Only the oracle runs here.  The file written holds, per component u, v, w, p:
-16384 flat indices drawn with a fixed seed and the end-state values there,
-the L2 and max norms of the whole component, and the CG iterations of every
-step.  Usage:
+  c3: 96^3 up to T = 0.64 (1280 projection steps), the Parareal workload.
+      Parareal converges to the serial fine solution (Sec. 2.1.2, Eqs.
+      (6)-(7)), so this run is what the GPU's Parareal end state is checked
+      against.
+  c2: 128^3 up to T = 0.1 (200 steps), the FP64 / mixed-precision workload.
 
-    python tests/golden/make_c3_reference.py [--checkpoint FILE]
+Only the oracle runs here.  The file written holds, per component u, v, w,
+p: 16384 flat indices drawn with a fixed seed and the end-state values
+there, the L2 and max norms of the whole component, and the CG iterations of
+every step.  Usage:
+
+    python tests/golden/make_cavity_reference.py --case c3|c2 [--checkpoint FILE]
 
 With --checkpoint the state is saved every 40 steps and a rerun resumes from
 it.  A full run takes hours on a few CPU cores.
@@ -31,10 +34,12 @@ sys.path.insert(0, ROOT)
 
 from oracle import oracle as O  # noqa: E402
 
-N, RE, DT, T, RTOL = 96, 1000.0, 5e-4, 0.64, 1e-10
-NSTEPS = int(round(T / DT))
+CASES = {
+    "c3": (96, 1000.0, 5e-4, 0.64, "c3_cavity96_re1000_T064_fp64.npz"),
+    "c2": (128, 1000.0, 5e-4, 0.1, "c2_cavity128_re1000_T01_fp64.npz"),
+}
+RTOL = 1e-10
 NSAMPLE, SEED = 16384, 20170518
-OUT = os.path.join(HERE, "c3_cavity96_re1000_T064_fp64.npz")
 
 
 def sample_indices(shapes):
@@ -44,9 +49,13 @@ def sample_indices(shapes):
 
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--case", choices=sorted(CASES), default="c3")
     ap.add_argument("--checkpoint", default=None)
     ap.add_argument("--chunk", type=int, default=40)
     a = ap.parse_args()
+    N, RE, DT, T, name = CASES[a.case]
+    NSTEPS = int(round(T / DT))
+    OUT = os.path.join(HERE, name)
     g = O.Grid(N, N, N, re=RE)
     state, step, iters = g.zeros_state(), 0, []
     if a.checkpoint and os.path.exists(a.checkpoint):

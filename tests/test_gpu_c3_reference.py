@@ -1,7 +1,7 @@
 """The 96^3 Parareal workload at full size against the oracle's serial FP64
 run: lid-driven cavity, Re 1000, from rest, fine step 5e-4 to T = 0.64 (1280
 steps), Jacobi-PCG to 1e-10.  The reference (tests/golden/
-c3_cavity96_re1000_T064_fp64.npz, written by make_c3_reference.py with the
+c3_cavity96_re1000_T064_fp64.npz, written by make_cavity_reference.py with the
 oracle alone) holds 16384 seeded sample points per component and the L2 and
 max norms of the whole end state.
 
