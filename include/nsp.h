@@ -161,8 +161,10 @@ nsp_status nsp_set_lid(nsp_handle *h, const double *lid_dev, void *stream);
 nsp_status nsp_poisson_solve(nsp_handle *h, const double *b, double *p, int batch,
                              const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
 
-/* nsp_poisson_solve for callers that cannot allocate device memory: code
- * under stream capture, tight serving loops, harnesses that forbid it.  Same
+/* nsp_poisson_solve for callers that cannot allocate device memory: tight
+ * serving loops and harnesses that forbid allocation (like every call it
+ * synchronises `stream` to read the solve's status, so it cannot itself be
+ * recorded into a graph).  Same
  * arguments, kernels and results (bitwise) as nsp_poisson_solve, but every
  * scratch buffer of the solve (launch parameters, barrier words, per-slice
  * control blocks, partial sums, the right-hand-side copy and the CG vectors)
