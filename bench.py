@@ -182,16 +182,35 @@ def bench_fine(args):
     _sync()
     iters = 0
     launch_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = h.fine_step(y, t, t + dt, dt, opts)
-        t += dt
-        iters += info[0]["iters"]
-        launch_ms.append(h.last_launch_ms())
-    _sync()
-    wall = time.perf_counter() - t0
-    cells = n ** 3
     K = args.steps
+    outer_per_launch = None
+    if args.graph:
+        # one step recorded as a HIP graph; K replays enqueued back to back,
+        # read back once
+        g = h.fine_step_graph(y, t, t + dt, dt, opts)
+        _sync()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            g.launch()
+        info = g.finish()
+        _sync()
+        wall = time.perf_counter() - t0
+        t += K * dt
+        iters = info[0]["iters"]
+        launch_ms = [h.last_launch_ms() / K]
+        outer_per_launch = info[0]["outer"] / K
+        g.close()
+    else:
+        t0 = time.perf_counter()
+        for _ in range(K):
+            info = h.fine_step(y, t, t + dt, dt, opts)
+            t += dt
+            iters += info[0]["iters"]
+            launch_ms.append(h.last_launch_ms())
+        _sync()
+        wall = time.perf_counter() - t0
+        outer_per_launch = info[0]["outer"]
+    cells = n ** 3
     value = cells * K / wall
     err_vs_fp64 = None
     if args.precision != "fp64" and args.compare_fp64:
@@ -207,13 +226,13 @@ def bench_fine(args):
     fixed = BYTES_STEP_FIXED[args.precision] + (BYTES_SR_START if args.solver == "pcg_sr" else 0.0)
     layout_bytes = cells * (fixed + per_iter * iters / K)
     if args.precision != "fp64":
-        layout_bytes += cells * BYTES_MIXED_SWEEP * info[0]["outer"]
+        layout_bytes += cells * BYTES_MIXED_SWEEP * outer_per_launch
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     # the roofline's algorithmic bytes: the method's byte model per cell and
     # step, 112 B plus 80 B per FP64 CG iteration (mixed: 40 B per FP32
     # iteration and 40 B per FP64 correction sweep), independent of how the
     # kernels lay the phases out or keep vectors on chip
-    model_bytes = _model_bytes(args, cells, iters / K, info[0]["outer"])
+    model_bytes = _model_bytes(args, cells, iters / K, outer_per_launch)
     achieved = model_bytes / avg_launch_s / 1e9
     sfx = "" if args.solver == "pcg" else "_" + args.solver
     traffic = (_traffic_from_profile("k_persistent_cavity128_%s%s_pmc.txt" % (args.precision, sfx))
@@ -235,6 +254,7 @@ def bench_fine(args):
                    "start": "rest, after %d warm-up steps" % args.warmup,
                    "poisson": _solver_name(args) + " rtol 1e-10",
                    "precision": args.precision},
+        "launch": "one HIP graph replayed per step, read back once" if args.graph else "one call per step",
         "cg_iters_per_step": iters / K,
         "inner_rtol": _eta(args) if args.precision != "fp64" else None,
         "velocity_rel_l2_vs_fp64": err_vs_fp64,
@@ -870,6 +890,8 @@ def main():
     # 0.96 + 0.55 on the 96^3 grid and the coarse propagator blows up; the
     # defaults are 5e-3 for the 96^3 Parareal run (about 0.76) and 2.5e-3 for
     # the obstacle batch, whose 128^3 grid needs dt < ~4.4e-3.
+    ap.add_argument("--graph", action="store_true",
+                    help="fine mode: record the step as a HIP graph and replay it (nsp_fine_step_graph_create)")
     ap.add_argument("--coarse-dt", type=float, default=None)
     ap.add_argument("--coarse-upwind", action="store_true",
                     help="Parareal modes: donor-cell (first-order upwind) convection in the coarse propagator")

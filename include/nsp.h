@@ -189,6 +189,38 @@ nsp_status nsp_poisson_solve_noalloc(nsp_handle *h, const double *b, double *p, 
 nsp_status nsp_fine_step(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double dt,
                          const nsp_poisson_opts *opts, void *stream, nsp_solve_info *info);
 
+/* The fine propagator as a replayable HIP graph: the batched fine sweep of
+ * Sec. 2.1.2 (all slices of y in one persistent launch) recorded once and
+ * replayed without host synchronisation.  nsp_fine_step_graph_create
+ * records what nsp_fine_step(h, y, batch, t0, t1, dt, opts) would launch:
+ * the graph holds the kernels that clear its control blocks and barrier
+ * words, the persistent kernel (a cooperative node) and a kernel that folds
+ * each replay's per-slice results into words the graph keeps.  The state
+ * pointers y, the batch, the step count (t1 - t0)/dt (a positive integer,
+ * else NSP_ERR_ARG), dt and *opts are fixed at creation; the launch shape
+ * is the one nsp_fine_step would pick (nsp_autotune results included).  The
+ * graph owns its parameter block, control blocks, partial sums and barrier
+ * words, and shares the handle's workspace vectors, so eager calls on the
+ * handle may run between replays on the same stream.  Creation is
+ * synchronous and allocates; *out receives the graph.
+ * nsp_graph_launch enqueues one replay on `stream` (asynchronous: y advances
+ * by (t1 - t0)/dt steps when it runs; nothing is read back).
+ * nsp_graph_finish synchronises `stream` and reports every replay since the
+ * previous finish: info (HOST, `batch` entries, or NULL) gets per slice the
+ * summed CG iterations and sweeps, the most iterations of one step, the
+ * worst status and the last replay's true residual; the return value is the
+ * worst status (NSP_ERR_NOT_CONVERGED, NSP_ERR_NONFINITE, or NSP_ERR_HIP if
+ * a replay abandoned a barrier wait).  Replays run the same kernels on the
+ * same inputs as nsp_fine_step and give bitwise its results.
+ * nsp_graph_destroy waits for the device and frees the graph; destroy a
+ * graph before its handle. */
+typedef struct nsp_graph nsp_graph;
+nsp_status nsp_fine_step_graph_create(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double dt,
+                                      const nsp_poisson_opts *opts, nsp_graph **out);
+nsp_status nsp_graph_launch(nsp_graph *g, void *stream);
+nsp_status nsp_graph_finish(nsp_graph *g, void *stream, nsp_solve_info *info);
+nsp_status nsp_graph_destroy(nsp_graph *g);
+
 /* Coarse propagator G(y, t1, t0): the same scheme with the coarse step DT
  * (Sec. 2.1.2: forward Euler for both, larger step for G), with the
  * convection chosen by nsp_set_coarse_convection. */

@@ -391,9 +391,16 @@ void layout_groups(GroupDesc *G, int ngroups, int wg, int depth, int items, int 
 
 // Launch the persistent kernel over ngroups groups and read back the
 // per-slice control blocks into info (may be NULL).
-nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
-               const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override,
-               const LaunchRes *ws = nullptr) {
+// The launch shape and parameter block of one persistent launch (resource
+// pointers not yet set); no device work.
+struct LaunchPlan {
+    GroupDesc lg[kMaxGroups];
+    int ngroups = 0, nslices = 0, wg = 0, pstride = 0;
+    KParams P;
+};
+
+nsp_status plan_launch(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
+                       const nsp_poisson_opts *o, int workgroups_override, bool caller_ws, LaunchPlan &pl) {
     nsp_handle *h = hs[0];
     int nslices = 0, ntiles = 0, cgtiles = 0;
     for (int g = 0; g < ngroups; ++g) {
@@ -401,6 +408,8 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
         ntiles += groups[g].nslices * groups[g].ntiles;
         cgtiles += groups[g].nslices * groups[g].cgtiles;
     }
+    pl.nslices = nslices;
+    pl.ngroups = ngroups;
     if (nslices <= 0) return NSP_OK;
     if (nslices > kMaxSlices) return fail(h, NSP_ERR_ARG, "more than 64 slices in one launch");
     if (ngroups > kMaxGroups) return fail(h, NSP_ERR_ARG, "too many grids in one launch");
@@ -412,11 +421,11 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
                                      : auto_workgroups(h, nslices, o->prec != NSP_FP64 ? 1 : 0, units);
     if (wg < 1) wg = 1;
     if (wg > kMaxWG) wg = kMaxWG;
-    GroupDesc lg[kMaxGroups];
+    GroupDesc *lg = pl.lg;
     for (int g = 0; g < ngroups; ++g) lg[g] = groups[g];
-    // ws: launch workspace brought in by the caller (every vector pointer of
-    // the groups already set); nothing is allocated then
-    if (o->solver != NSP_PCG && !ws)
+    // caller_ws: launch workspace brought in by the caller (every vector
+    // pointer of the groups already set); nothing is allocated then
+    if (o->solver != NSP_PCG && !caller_ws)
         for (int g = 0; g < ngroups; ++g) {
             nsp_handle *hg = hs[g];
             if (!hg->bv0) {
@@ -439,17 +448,9 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     int cgparts = 0;
     layout_groups(lg, ngroups, wg, depth, items, o->prec != NSP_FP64, &ntiles, &cgtiles, &cgparts);
     const int pstride = std::max(ntiles, cgparts);
-    if (ws) {
-        if (nslices > ws->cap_slices || pstride > ws->cap_tiles)
-            return fail(h, NSP_ERR_ARG, "launch workspace too small for this launch");
-    } else {
-        nsp_status st = ensure_launch_res(h, nslices, pstride);
-        if (st != NSP_OK) return st;
-    }
-    const LaunchRes &L = ws ? *ws : h->L;
-    KParams &P = *L.params_host;
-    // the pinned block may still be read by an earlier copy on this stream
-    HIPCHK(h, hipStreamSynchronize(stream));
+    pl.wg = wg;
+    pl.pstride = pstride;
+    KParams &P = pl.P;
     std::memset(&P, 0, sizeof(P));
     for (int g = 0; g < ngroups; ++g) P.g[g] = lg[g];
     P.ngroups = ngroups;
@@ -486,33 +487,25 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
     P.dt = dt;
     P.rtol = o->rtol;
     P.eta = o->inner_rtol;
-    P.ctl = L.ctl;
-    P.part = L.part;
-    P.sync = L.sync;
-    static_assert(sizeof(SliceCtl) % sizeof(unsigned) == 0, "control blocks are zeroed as words");
-    HIPCHK(h, launch_zero_words(L.ctl, (long long)nslices * (sizeof(SliceCtl) / sizeof(unsigned)), stream));
-    HIPCHK(h, hipMemcpyAsync(L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
-    HIPCHK(h, launch_reset_sync(L.sync, stream));
-    HIPCHK(h, hipEventRecord(h->ev0, stream));
-    HIPCHK(h, launch_persistent(L.params, wg, P.rr != 0, stream));
-    HIPCHK(h, hipEventRecord(h->ev1, stream));
-    HIPCHK(h, hipMemcpyAsync(L.ctl_host, L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost, stream));
-    int aborted = 0;
-    HIPCHK(h, hipMemcpyAsync(&aborted, &L.sync->abort, sizeof(int), hipMemcpyDeviceToHost, stream));
-    HIPCHK(h, hipStreamSynchronize(stream));
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
-    if (aborted) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
+    return NSP_OK;
+}
+
+// Per-slice results of a finished launch (control blocks copied to the
+// host): launch statistics, info, and the status; `worst` is the worst
+// slice status to report (the launch's own, or one kept across replays).
+nsp_status collect_status(nsp_handle *h, const LaunchPlan &pl, const SliceCtl *ctl_host, float ms, int worst,
+                          nsp_solve_info *info, int launches = 1) {
+    const KParams &P = pl.P;
+    const int mode = P.mode;
     nsp_launch_stats &S = h->stats[mode];
-    S.launches += 1;
-    S.rr_launches += P.rr;
+    S.launches += launches;
+    S.rr_launches += (long long)P.rr * launches;
     S.ms += ms;
-    int worst = 0;
-    for (int g = 0, s = 0; g < ngroups; ++g)
-        for (int k = 0; k < lg[g].nslices; ++k, ++s) {
-            const SliceCtl &c = L.ctl_host[s];
-            const double cells = (double)lg[g].ncells, it = cells * c.tot_it;
-            S.cell_steps += cells * (mode == MODE_FINE ? nsteps : 1);
+    for (int g = 0, s = 0; g < pl.ngroups; ++g)
+        for (int k = 0; k < pl.lg[g].nslices; ++k, ++s) {
+            const SliceCtl &c = ctl_host[s];
+            const double cells = (double)pl.lg[g].ncells, it = cells * c.tot_it;
+            S.cell_steps += cells * (mode == MODE_FINE ? P.nsteps : 1) * launches;
             S.cg_cell_iters += it;
             S.cell_sweeps += cells * c.tot_outer;
             if (P.prec != 0) {
@@ -524,21 +517,62 @@ nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int 
                 S.cg64_cell_iters += it;
             }
         }
-    for (int s = 0; s < nslices; ++s) {
-        const SliceCtl &c = L.ctl_host[s];
-        worst = std::max(worst, c.status);
+    for (int s = 0; s < pl.nslices; ++s) {
+        const SliceCtl &c = ctl_host[s];
         if (info) {
             info[s].iters = c.tot_it;
             info[s].max_iters = c.max_it;
             info[s].outer = c.tot_outer;
             info[s].status = c.status;
             info[s].rel_res_true = c.rel_true;
-            info[s].div_l2 = mode == MODE_FINE ? dt * c.res_true : 0.0;
+            info[s].div_l2 = mode == MODE_FINE ? P.dt * c.res_true : 0.0;
         }
     }
     if (worst == 2) return fail(h, NSP_ERR_NOT_CONVERGED, "Poisson solve reached its iteration limit");
     if (worst == 3) return fail(h, NSP_ERR_NONFINITE, "non-finite residual in the Poisson solve");
     return NSP_OK;
+}
+
+nsp_status run(nsp_handle *const *hs, int ngroups, const GroupDesc *groups, int mode, int nsteps, double dt,
+               const nsp_poisson_opts *o, hipStream_t stream, nsp_solve_info *info, int workgroups_override,
+               const LaunchRes *ws = nullptr) {
+    nsp_handle *h = hs[0];
+    LaunchPlan pl;
+    nsp_status st = plan_launch(hs, ngroups, groups, mode, nsteps, dt, o, workgroups_override, ws != nullptr, pl);
+    if (st != NSP_OK || pl.nslices <= 0) return st;
+    const int nslices = pl.nslices;
+    if (ws) {
+        if (nslices > ws->cap_slices || pl.pstride > ws->cap_tiles)
+            return fail(h, NSP_ERR_ARG, "launch workspace too small for this launch");
+    } else {
+        st = ensure_launch_res(h, nslices, pl.pstride);
+        if (st != NSP_OK) return st;
+    }
+    const LaunchRes &L = ws ? *ws : h->L;
+    KParams &P = *L.params_host;
+    // the pinned block may still be read by an earlier copy on this stream
+    HIPCHK(h, hipStreamSynchronize(stream));
+    P = pl.P;
+    P.ctl = L.ctl;
+    P.part = L.part;
+    P.sync = L.sync;
+    static_assert(sizeof(SliceCtl) % sizeof(unsigned) == 0, "control blocks are zeroed as words");
+    HIPCHK(h, launch_zero_words(L.ctl, (long long)nslices * (sizeof(SliceCtl) / sizeof(unsigned)), stream));
+    HIPCHK(h, hipMemcpyAsync(L.params, &P, sizeof(KParams), hipMemcpyHostToDevice, stream));
+    HIPCHK(h, launch_reset_sync(L.sync, stream));
+    HIPCHK(h, hipEventRecord(h->ev0, stream));
+    HIPCHK(h, launch_persistent(L.params, pl.wg, P.rr != 0, stream));
+    HIPCHK(h, hipEventRecord(h->ev1, stream));
+    HIPCHK(h, hipMemcpyAsync(L.ctl_host, L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost, stream));
+    int aborted = 0;
+    HIPCHK(h, hipMemcpyAsync(&aborted, &L.sync->abort, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
+    if (aborted) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
+    int worst = 0;
+    for (int s = 0; s < nslices; ++s) worst = std::max(worst, L.ctl_host[s].status);
+    return collect_status(h, pl, L.ctl_host, ms, worst, info);
 }
 
 bool state_ok(const nsp_state &y) { return y.u && y.v && y.w && y.p; }
@@ -762,6 +796,40 @@ nsp_status parareal_iterate_impl(nsp_handle *const *hs, nsp_handle *const *hcs, 
 
 }  // namespace
 
+// A recorded fine step (nsp_fine_step_graph_create): a HIP graph of one
+// persistent launch with launch resources of its own (parameter block,
+// control blocks, partial sums, barrier words), so eager calls on the same
+// handle between replays leave it intact.
+struct nsp_graph {
+    nsp_handle *h = nullptr;
+    LaunchPlan pl;
+    LaunchRes L;                   // params, ctl, ctl_host, part, sync
+    GraphFold *fold = nullptr;     // device
+    GraphFold *fold_host = nullptr;  // pinned
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int replays = 0;  // since the last nsp_graph_finish
+};
+
+namespace {
+
+void free_graph(nsp_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    void *dev[] = {g->L.params, g->L.ctl, g->L.part, g->L.sync, g->fold};
+    for (void *q : dev)
+        if (q) (void)hipFree(q);
+    if (g->L.ctl_host) (void)hipHostFree(g->L.ctl_host);
+    if (g->fold_host) (void)hipHostFree(g->fold_host);
+    if (g->ev0) (void)hipEventDestroy(g->ev0);
+    if (g->ev1) (void)hipEventDestroy(g->ev1);
+    delete g;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *nsp_last_error(const nsp_handle *h) { return h ? h->err.c_str() : "null handle"; }
@@ -919,6 +987,108 @@ nsp_status nsp_fine_step(nsp_handle *h, nsp_state y, int batch, double t0, doubl
     if (!h) return NSP_ERR_ARG;
     nsp_handle *hs[1] = {h};
     return propagate(hs, &y, &batch, 1, t0, t1, dt, o, stream, info);
+}
+
+nsp_status nsp_fine_step_graph_create(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double dt,
+                                      const nsp_poisson_opts *o, nsp_graph **out) {
+    if (!h || !out) return fail(h, NSP_ERR_ARG, "null handle or output pointer");
+    *out = nullptr;
+    if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
+    int nsteps = 0;
+    if (!step_count(t0, t1, dt, &nsteps) || nsteps == 0)
+        return fail(h, NSP_ERR_ARG, "(t1 - t0)/dt is not a positive integer");
+    if (!state_ok(y) || batch < 1 || batch > h->max_batch) return fail(h, NSP_ERR_ARG, "bad state or batch");
+    GroupDesc G;
+    fill_group(G, h, y, 0, batch, 0, 0, nullptr, 0);
+    G.upwind = 0;
+    nsp_handle *hs[1] = {h};
+    nsp_graph *g = new nsp_graph;
+    g->h = h;
+#define GCHK(call)                                                                                         \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess) {                                                                            \
+            free_graph(g);                                                                                 \
+            return fail(h, NSP_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));                \
+        }                                                                                                  \
+    } while (0)
+    nsp_status st = plan_launch(hs, 1, &G, MODE_FINE, nsteps, dt, o, 0, false, g->pl);
+    if (st != NSP_OK) {
+        free_graph(g);
+        return st;
+    }
+    const int nslices = g->pl.nslices;
+    GCHK(dalloc(&g->L.params, 1));
+    GCHK(dalloc(&g->L.ctl, nslices));
+    GCHK(hipHostMalloc(reinterpret_cast<void **>(&g->L.ctl_host), nslices * sizeof(SliceCtl)));
+    GCHK(dalloc(&g->L.part, (size_t)2 * kNQ * g->pl.pstride));
+    GCHK(dalloc(&g->L.sync, 1));
+    GCHK(dalloc(&g->fold, 1));
+    GCHK(hipHostMalloc(reinterpret_cast<void **>(&g->fold_host), sizeof(GraphFold)));
+    GCHK(hipEventCreate(&g->ev0));
+    GCHK(hipEventCreate(&g->ev1));
+    GCHK(launch_zero_words(g->fold, (long long)(sizeof(GraphFold) / sizeof(unsigned)), nullptr));
+    KParams P = g->pl.P;
+    P.ctl = g->L.ctl;
+    P.part = g->L.part;
+    P.sync = g->L.sync;
+    GCHK(hipMemcpy(g->L.params, &P, sizeof(KParams), hipMemcpyHostToDevice));
+    GCHK(hipDeviceSynchronize());
+    GCHK(hipGraphCreate(&g->graph, 0));
+    GCHK(add_persistent_graph_nodes(g->graph, g->L.params, g->pl.wg, P.rr != 0, g->L.ctl, nslices, g->L.sync,
+                                    g->fold));
+    GCHK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+#undef GCHK
+    *out = g;
+    return NSP_OK;
+}
+
+nsp_status nsp_graph_launch(nsp_graph *g, void *stream) {
+    if (!g) return NSP_ERR_ARG;
+    nsp_handle *h = g->h;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g->replays == 0) HIPCHK(h, hipEventRecord(g->ev0, s));
+    HIPCHK(h, hipGraphLaunch(g->exec, s));
+    HIPCHK(h, hipEventRecord(g->ev1, s));
+    ++g->replays;
+    return NSP_OK;
+}
+
+nsp_status nsp_graph_finish(nsp_graph *g, void *stream, nsp_solve_info *info) {
+    if (!g) return NSP_ERR_ARG;
+    nsp_handle *h = g->h;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIPCHK(h, hipStreamSynchronize(s));
+    const int n = g->replays;
+    if (n == 0) return NSP_OK;
+    const int nslices = g->pl.nslices;
+    HIPCHK(h, hipMemcpy(g->L.ctl_host, g->L.ctl, nslices * sizeof(SliceCtl), hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(g->fold_host, g->fold, sizeof(GraphFold), hipMemcpyDeviceToHost));
+    HIPCHK(h, launch_zero_words(g->fold, (long long)(sizeof(GraphFold) / sizeof(unsigned)), s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    g->replays = 0;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, g->ev0, g->ev1) == hipSuccess) h->last_ms = ms;
+    const GraphFold &F = *g->fold_host;
+    if (F.abort) return fail(h, NSP_ERR_HIP, "grid barrier wait exceeded its limit; launch abandoned");
+    // every replay's iterations and the worst status; the rest from the last
+    int worst = 0;
+    for (int k = 0; k < nslices; ++k) {
+        SliceCtl &c = g->L.ctl_host[k];
+        c.tot_it = (int)F.it[k];
+        c.tot_outer = (int)F.outer[k];
+        c.max_it = F.max_it[k];
+        c.status = F.status[k];
+        worst = std::max(worst, F.status[k]);
+    }
+    return collect_status(h, g->pl, g->L.ctl_host, ms, worst, info, n);
+}
+
+nsp_status nsp_graph_destroy(nsp_graph *g) {
+    if (!g) return NSP_OK;
+    (void)hipDeviceSynchronize();  // no replay may still use what is freed
+    free_graph(g);
+    return NSP_OK;
 }
 
 nsp_status nsp_coarse_step(nsp_handle *h, nsp_state y, int batch, double t0, double t1, double DT,

@@ -150,6 +150,23 @@ hipError_t max_coresident_workgroups(int device, int *out);
 hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream);
 // zero nwords 32-bit words at p on the stream (a kernel, not a memset)
 hipError_t launch_zero_words(void *p, long long nwords, hipStream_t stream);
+// What a replayed graph keeps across its replays (cleared by the host):
+// per slice the worst status, the most CG iterations of one step, and the
+// sums of CG iterations and sweeps; whether a barrier wait was abandoned.
+struct GraphFold {
+    int status[kMaxSlices];
+    int max_it[kMaxSlices];
+    long long it[kMaxSlices];
+    long long outer[kMaxSlices];
+    int abort;
+    int pad;
+};
+// Adds to `graph` the kernel nodes of one persistent launch: zero the
+// control blocks, reset the barrier words, the persistent kernel (a
+// cooperative node) and a fold of the slices' results and the abort flag
+// into *fold, which the graph never clears.
+hipError_t add_persistent_graph_nodes(hipGraph_t graph, const KParams *P_dev, int workgroups, bool rr,
+                                      SliceCtl *ctl, int nslices, SyncWords *sync, GraphFold *fold);
 
 struct UpdateSeg {
     double *y;          // slice-end state to overwrite (y^{k+1}_{n+1})

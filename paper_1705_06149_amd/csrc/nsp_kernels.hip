@@ -2702,6 +2702,19 @@ k_persistent(const KParams *__restrict__ Pp) {
 
 // zero n 32-bit words (a kernel rather than a memset node, so that the
 // launch sequence stays valid under stream capture)
+// one replay's slice results folded into what the graph keeps across replays
+__global__ void k_fold_status(const SliceCtl *ctl, const SyncWords *sync, int nslices, GraphFold *f) {
+    const int s = threadIdx.x;
+    if (s < nslices) {
+        const SliceCtl &c = ctl[s];
+        if (c.status > f->status[s]) f->status[s] = c.status;
+        if (c.max_it > f->max_it[s]) f->max_it[s] = c.max_it;
+        f->it[s] += c.tot_it;
+        f->outer[s] += c.tot_outer;
+    }
+    if (s == 0 && sync->abort) f->abort = 1;
+}
+
 __global__ void k_zero_words(unsigned *w, long long n) {
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x)
         w[x] = 0u;
@@ -2863,6 +2876,53 @@ hipError_t launch_zero_words(void *p, long long nwords, hipStream_t stream) {
 
 hipError_t launch_reset_sync(SyncWords *s, hipStream_t stream) {
     return launch_zero_words(s, (long long)(sizeof(SyncWords) / sizeof(unsigned)), stream);
+}
+
+hipError_t add_persistent_graph_nodes(hipGraph_t graph, const KParams *P_dev, int workgroups, bool rr,
+                                      SliceCtl *ctl, int nslices, SyncWords *sync, GraphFold *fold) {
+    if (nslices <= 0 || nslices > kMaxSlices) return hipErrorInvalidValue;
+    // node 1: zero the control blocks; node 2: reset the barrier words
+    unsigned *cw = reinterpret_cast<unsigned *>(ctl);
+    long long cn = (long long)nslices * (long long)(sizeof(SliceCtl) / sizeof(unsigned));
+    unsigned *sw = reinterpret_cast<unsigned *>(sync);
+    long long sn = (long long)(sizeof(SyncWords) / sizeof(unsigned));
+    void *a1[] = {&cw, &cn};
+    void *a2[] = {&sw, &sn};
+    hipKernelNodeParams k1{}, k2{}, k3{}, k4{};
+    k1.func = reinterpret_cast<void *>(&k_zero_words);
+    k1.gridDim = dim3((unsigned)((cn + 255) / 256));
+    k1.blockDim = dim3(256);
+    k1.kernelParams = a1;
+    k2.func = reinterpret_cast<void *>(&k_zero_words);
+    k2.gridDim = dim3((unsigned)((sn + 255) / 256 > 1024 ? 1024 : (sn + 255) / 256));
+    k2.blockDim = dim3(256);
+    k2.kernelParams = a2;
+    // node 3: the persistent kernel, a cooperative launch
+    const KParams *arg = P_dev;
+    void *a3[] = {&arg};
+    k3.func = rr ? reinterpret_cast<void *>(&k_persistent<true>) : reinterpret_cast<void *>(&k_persistent<false>);
+    k3.gridDim = dim3((unsigned)workgroups);
+    k3.blockDim = dim3(kBlock);
+    k3.kernelParams = a3;
+    // node 4: fold this replay's slice results and the abort flag into what
+    // the graph keeps across replays
+    const SliceCtl *cc = ctl;
+    const SyncWords *sc = sync;
+    int ns = nslices;
+    void *a4[] = {&cc, &sc, &ns, &fold};
+    k4.func = reinterpret_cast<void *>(&k_fold_status);
+    k4.gridDim = dim3(1);
+    k4.blockDim = dim3(64);
+    k4.kernelParams = a4;
+    hipGraphNode_t n1, n2, n3, n4;
+    hipError_t e = hipGraphAddKernelNode(&n1, graph, nullptr, 0, &k1);
+    if (e != hipSuccess) return e;
+    if ((e = hipGraphAddKernelNode(&n2, graph, &n1, 1, &k2)) != hipSuccess) return e;
+    if ((e = hipGraphAddKernelNode(&n3, graph, &n2, 1, &k3)) != hipSuccess) return e;
+    hipKernelNodeAttrValue coop{};
+    coop.cooperative = 1;
+    if ((e = hipGraphKernelNodeSetAttribute(n3, hipKernelNodeAttributeCooperative, &coop)) != hipSuccess) return e;
+    return hipGraphAddKernelNode(&n4, graph, &n3, 1, &k4);
 }
 
 hipError_t launch_parareal_update(const UpdateParams &U, hipStream_t stream) {

@@ -115,6 +115,11 @@ def lib():
         L.nsp_fine_solve_reverse.argtypes = [P, ctypes.c_ulonglong, _State, P, P]
         L.nsp_fine_solve_tape_valid.argtypes = [P, ctypes.c_ulonglong]
         L.nsp_momentum_adjoint.argtypes = [P, _State, _State, _State, P, D, P]
+        L.nsp_fine_step_graph_create.argtypes = [P, _State, I, D, D, D, ctypes.POINTER(_Opts),
+                                                 ctypes.POINTER(ctypes.c_void_p)]
+        L.nsp_graph_launch.argtypes = [P, P]
+        L.nsp_graph_finish.argtypes = [P, P, P]
+        L.nsp_graph_destroy.argtypes = [P]
         L.nsp_fine_solve_tape_valid.restype = I
         L.nsp_lid_from_modes.argtypes = [P, P, I, P, P]
         L.nsp_lid_modes_grad.argtypes = [P, P, I, P, P]
@@ -125,7 +130,8 @@ def lib():
                      "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
                      "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
                      "nsp_launch_stats_get", "nsp_set_coarse_convection", "nsp_fine_solve_record",
-                     "nsp_fine_solve_reverse", "nsp_momentum_adjoint"):
+                     "nsp_fine_solve_reverse", "nsp_momentum_adjoint", "nsp_fine_step_graph_create",
+                     "nsp_graph_launch", "nsp_graph_finish", "nsp_graph_destroy"):
             getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -307,6 +313,20 @@ class Handle:
     def fine_step(self, y, t0, t1, dt, opts=None, check=True):
         """F(y, t1, t0): (t1-t0)/dt projection steps in place on the batch y."""
         return self._prop(lib().nsp_fine_step, y, t0, t1, dt, opts, check)
+
+    def fine_step_graph(self, y, t0, t1, dt, opts=None):
+        """Record F(y, t1, t0) on the batch y as a replayable HIP graph
+        (nsp_fine_step_graph_create); returns a FineStepGraph.  The graph keeps
+        references to the tensors of y, whose storage it writes."""
+        opts = opts or PoissonOpts()
+        B = self._batch_of(y)
+        s = self._state(y, B)
+        o = opts.c()
+        out = ctypes.c_void_p()
+        st = lib().nsp_fine_step_graph_create(self._h, s, B, float(t0), float(t1), float(dt), ctypes.byref(o),
+                                              ctypes.byref(out))
+        self._err(st, "nsp_fine_step_graph_create")
+        return FineStepGraph(self, out, tuple(y), B)
 
     def coarse_step(self, y, t0, t1, DT, opts=None, check=True):
         """G(y, t1, t0): (t1-t0)/DT projection steps in place on the batch y."""
@@ -548,6 +568,51 @@ def group_parareal_iterate(handles, Ys, Fks, Gks, nslices, k, t0, T, dt, DT, fin
     return [(float(jump[2 * g]), float(jump[2 * g + 1])) for g in range(n)]
 
 
+class FineStepGraph:
+    """A recorded fine step (nsp_fine_step_graph_create).  launch() enqueues
+    one replay on the current stream without synchronising; finish()
+    synchronises and returns per-slice info summed over the replays since the
+    previous finish (raising NSPError on a failed solve when check)."""
+
+    def __init__(self, handle, ptr, y, batch):
+        self._handle = handle
+        self._g = ptr
+        self._y = y  # the graph writes these tensors' storage
+        self.batch = batch
+
+    def launch(self):
+        self._handle._err(lib().nsp_graph_launch(self._g, _stream_ptr()), "nsp_graph_launch")
+
+    def finish(self, check=True):
+        info = (_Info * self.batch)()
+        st = lib().nsp_graph_finish(self._g, _stream_ptr(), info)
+        res = [_info_dict(x) for x in info]
+        self.last_status = st
+        if check:
+            self._handle._err(st, "nsp_graph_finish", res)
+        return res
+
+    def close(self):
+        if self._g:
+            lib().nsp_graph_destroy(self._g)
+            self._g = None
+            self._y = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_poisson_solve",
             "nsp_poisson_solve_noalloc", "nsp_fine_step",
             "nsp_coarse_step", "nsp_group_fine_step", "nsp_parareal_start", "nsp_parareal_iterate",
@@ -555,4 +620,5 @@ EXPORTED = ("nsp_create", "nsp_destroy", "nsp_last_error", "nsp_set_lid", "nsp_p
             "nsp_last_launch_ms", "nsp_fine_solve_adjoint", "nsp_lid_from_modes", "nsp_lid_modes_grad",
             "nsp_restrict", "nsp_prolong", "nsp_parareal_start_cgrid", "nsp_parareal_iterate_cgrid",
             "nsp_launch_stats_get", "nsp_set_coarse_convection", "nsp_fine_solve_record",
-            "nsp_fine_solve_reverse", "nsp_fine_solve_tape_valid", "nsp_momentum_adjoint")
+            "nsp_fine_solve_reverse", "nsp_fine_solve_tape_valid", "nsp_momentum_adjoint",
+            "nsp_fine_step_graph_create", "nsp_graph_launch", "nsp_graph_finish", "nsp_graph_destroy")

@@ -1,0 +1,105 @@
+"""The fine propagator as a replayable HIP graph (the batched fine sweep of
+Sec. 2.1.2 as one persistent, graph-captured launch): every replay gives
+bitwise the state and iteration counts of the eager nsp_fine_step from the
+same state, with eager calls on the same handle and synchronisations between
+the replays; replays enqueued back to back add up; a solve that hits its
+limit is reported by the replays' fold; bad arguments are refused."""
+import numpy as np
+import pytest
+
+from paper_1705_06149_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def T(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = [
+    # n, batch, obstacles seed, precision: flat tiles with obstacles; the
+    # register-resident loop (one 64^3 slice); a mixed batch on column tiles
+    (48, 2, 7, 0),
+    (64, 1, None, 0),
+    (64, 2, None, 2),
+]
+
+
+@pytest.mark.parametrize("n,batch,seed,prec", CASES)
+def test_replays_equal_eager_steps(gpu, n, batch, seed, prec):
+    import torch
+    _say("graph replays", n, batch, seed, prec)
+    solid = inputs.obstacle_mask(n, seed) if seed else None
+    h = gpu.Handle(n, n, n, re=1000.0, solid=solid, max_batch=batch)
+    opts = gpu.PoissonOpts(rtol=1e-10, prec=prec, inner_rtol=0.01 if prec == 2 else 1e-5,
+                           max_outer=64 if prec == 2 else 8)
+    st = [inputs.random_state(n, n, n, seed=10 + b, scale=0.2, pscale=0.0) for b in range(batch)]
+    y0 = tuple(np.stack([s[c] for s in st]) for c in range(4))
+    yg = tuple(T(a) for a in y0)
+    ye = tuple(T(a) for a in y0)
+    other = tuple(T(a[:1]) for a in y0)
+    g = h.fine_step_graph(yg, 0.0, 0.004, 1e-3, opts)
+    for rep in range(3):
+        g.launch()
+        ig = g.finish()
+        # eager work on the same handle between replays
+        h.fine_step(other, 0.0, 0.002, 1e-3, opts)
+        torch.cuda.synchronize()
+        ie = h.fine_step(ye, 0.0, 0.004, 1e-3, opts)
+        for c in range(4):
+            assert np.array_equal(N(yg[c]), N(ye[c])), (rep, c)
+        assert [x["iters"] for x in ig] == [x["iters"] for x in ie]
+        assert [x["max_iters"] for x in ig] == [x["max_iters"] for x in ie]
+    # three replays back to back, one finish: three eager calls
+    for _ in range(3):
+        g.launch()
+    ig = g.finish()
+    its = [0] * batch
+    for _ in range(3):
+        ie = h.fine_step(ye, 0.0, 0.004, 1e-3, opts)
+        its = [a + x["iters"] for a, x in zip(its, ie)]
+    for c in range(4):
+        assert np.array_equal(N(yg[c]), N(ye[c])), c
+    assert [x["iters"] for x in ig] == its
+    g.close()
+    h.close()
+
+
+def test_graph_reports_a_solve_at_its_limit(gpu):
+    n = 32
+    _say("graph not converged", n)
+    h = gpu.Handle(n, n, n, re=100.0, max_batch=1)
+    st = inputs.random_state(n, n, n, seed=3, scale=0.3, pscale=0.0)
+    y = tuple(T(a[None]) for a in st)
+    ye = tuple(T(a[None]) for a in st)
+    opts = gpu.PoissonOpts(rtol=1e-12, maxit=1)
+    g = h.fine_step_graph(y, 0.0, 0.002, 1e-3, opts)
+    g.launch()
+    g.launch()
+    info = g.finish(check=False)
+    assert g.last_status == gpu.NSP_ERR_NOT_CONVERGED
+    assert info[0]["status"] == gpu.NSP_ERR_NOT_CONVERGED
+    ie = [h.fine_step(ye, 0.0, 0.002, 1e-3, opts, check=False)[0] for _ in range(2)]
+    assert info[0]["iters"] == ie[0]["iters"] + ie[1]["iters"]
+    for c in range(4):
+        assert np.array_equal(N(y[c]), N(ye[c])), c
+    with pytest.raises(gpu.NSPError):
+        g.launch()
+        g.finish()
+    g.close()
+    with pytest.raises(gpu.NSPError) as e:
+        h.fine_step_graph(y, 0.0, 0.0025, 1e-3)
+    assert e.value.status == gpu.NSP_ERR_ARG
+    with pytest.raises(gpu.NSPError) as e:
+        h.fine_step_graph(y, 0.0, 0.0, 1e-3)
+    assert e.value.status == gpu.NSP_ERR_ARG
+    h.close()
