@@ -54,6 +54,8 @@ def test_noalloc_poisson_matches_the_allocating_solve(gpu):
     assert h.launch_stats()["poisson"]["rr_launches"] == 2
     _say("noalloc 64^3 batch 1 mixed")
     _case(gpu, h, 1, gpu.PoissonOpts(rtol=1e-10, prec=gpu.MIXED), 2)
+    _say("noalloc 64^3 batch 2 mixed with reliable updates")
+    _case(gpu, h, 2, gpu.PoissonOpts(rtol=1e-10, prec=gpu.MIXED_RU, inner_rtol=1e-3, max_outer=64), 5)
     h.close()
     h2 = gpu.Handle(24, 20, 16, lx=1.2, periodic_z=True, max_batch=1)
     _say("noalloc 24x20x16 periodic batch 1 bicgstab")
