@@ -212,27 +212,44 @@ static double stencil_val(const og_grid *g, int c, const double *phi, const int 
  * upwind, central and downwind values U, C, D give phi_hat = (C-U)/(D-U);
  * the face value is 3 phi_hat on (0,1/6), 3/4 phi_hat + 3/8 on [1/6,5/6),
  * 1 on [5/6,1) and phi_hat (first-order upwind) elsewhere. */
-double og_smart(double U, double C, double D) {
+/* seg (if not NULL) receives the segment taken: 0 upwind (D = U, or phi_hat
+ * outside [0,1)), 1 slope 3, 2 QUICK, 3 the cap at 1. */
+static double smart_seg(double U, double C, double D, int *seg) {
     double delta = D - U;
-    if (delta == 0.0) return C;
+    if (delta == 0.0) {
+        if (seg) *seg = 0;
+        return C;
+    }
     double ph = (C - U) / delta;
     double pf;
-    if (ph > 0.0 && ph < 1.0 / 6.0)
+    int k;
+    if (ph > 0.0 && ph < 1.0 / 6.0) {
         pf = 3.0 * ph;
-    else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0)
+        k = 1;
+    } else if (ph >= 1.0 / 6.0 && ph < 5.0 / 6.0) {
         pf = 0.75 * ph + 0.375;
-    else if (ph >= 5.0 / 6.0 && ph < 1.0)
+        k = 2;
+    } else if (ph >= 5.0 / 6.0 && ph < 1.0) {
         pf = 1.0;
-    else
+        k = 3;
+    } else {
         pf = ph;
+        k = 0;
+    }
+    if (seg) *seg = k;
     return U + pf * delta;
 }
+
+double og_smart(double U, double C, double D) { return smart_seg(U, C, D, NULL); }
 
 /* --------------------------------------------------------- momentum (a1) */
 
 /* Convective flux of component c through the control-volume face at
- * f + s/2 e_d: transport velocity times the SMART upwind face value. */
-static double conv_flux(const og_grid *g, int c, const double *vel[3], const int f[3], int d, int s) {
+ * f + s/2 e_d: transport velocity times the SMART upwind face value.  code
+ * (if not NULL) receives the branch taken: 0 for a zero transport velocity,
+ * else 1 + (transport velocity < 0) + 2 * (SMART segment). */
+static double conv_flux(const og_grid *g, int c, const double *vel[3], const int f[3], int d, int s,
+                        signed char *code) {
     const double *phi = vel[c];
     double abar;
     if (d == c) {
@@ -246,6 +263,7 @@ static double conv_flux(const og_grid *g, int c, const double *vel[3], const int
         q1[c] -= 1;
         abar = 0.5 * (real_val(g, d, vel[d], q1) + real_val(g, d, vel[d], q2));
     }
+    if (code) *code = 0;
     if (abar == 0.0) return 0.0;
     double phi0 = phi[fidx(g, c, f)];
     double U, C, D;
@@ -258,8 +276,14 @@ static double conv_flux(const og_grid *g, int c, const double *vel[3], const int
         if (abar > 0.0) { U = stencil_val(g, c, phi, f, d, -2); C = stencil_val(g, c, phi, f, d, -1); D = phi0; }
         else { U = stencil_val(g, c, phi, f, d, 1); C = phi0; D = stencil_val(g, c, phi, f, d, -1); }
     }
-    if (g->upwind) return abar * C;
-    return abar * og_smart(U, C, D);
+    if (g->upwind) {
+        if (code) *code = (signed char)(1 + (abar < 0.0));
+        return abar * C;
+    }
+    int seg = 0;
+    const double v = smart_seg(U, C, D, &seg);
+    if (code) *code = (signed char)(1 + (abar < 0.0) + 2 * seg);
+    return abar * v;
 }
 
 /* Predictor F = phi + dt (Lap(phi)/Re - Conv(phi)) for every open face of
@@ -281,14 +305,44 @@ void og_momentum(const og_grid *g, const double *u, const double *v, const doubl
                     double conv = 0.0, lap = 0.0;
                     for (int d = 0; d < 3; ++d) {
                         double h = hdir(g, d);
-                        double fp = conv_flux(g, c, vel, f, d, 1);
-                        double fm = conv_flux(g, c, vel, f, d, -1);
+                        double fp = conv_flux(g, c, vel, f, d, 1, NULL);
+                        double fm = conv_flux(g, c, vel, f, d, -1, NULL);
                         conv += (fp - fm) / h;
                         double vp = stencil_val(g, c, vel[c], f, d, 1);
                         double vm = stencil_val(g, c, vel[c], f, d, -1);
                         lap += (vp - 2.0 * phi0 + vm) / (h * h);
                     }
                     out[c][od] = phi0 + dt * (lap / g->re - conv);
+                }
+    }
+}
+
+/* The branch each convective flux of the predictor takes (conv_flux's
+ * code) at the state (u, v, w): codes[c] has 6 entries per face of
+ * component c (direction d, side s = -1, +1 at 2 d + (s > 0)); closed faces
+ * get -1.  Test infrastructure for finite-difference checks: the flux is
+ * piecewise smooth, and two nearby states whose codes agree lie on the same
+ * smooth piece. */
+void og_momentum_branches(const og_grid *g, const double *u, const double *v, const double *w, signed char *cu,
+                          signed char *cv, signed char *cw) {
+    const double *vel[3] = {u, v, w};
+    signed char *out[3] = {cu, cv, cw};
+    for (int c = 0; c < 3; ++c) {
+        int ex = fext(g, c, 0), ey = fext(g, c, 1), ez = fext(g, c, 2);
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < ez; ++k)
+            for (int j = 0; j < ey; ++j)
+                for (int i = 0; i < ex; ++i) {
+                    int f[3] = {i, j, k};
+                    signed char *o = out[c] + 6 * fidx_raw(g, c, f);
+                    if (!face_open(g, c, f)) {
+                        for (int q = 0; q < 6; ++q) o[q] = -1;
+                        continue;
+                    }
+                    for (int d = 0; d < 3; ++d) {
+                        (void)conv_flux(g, c, vel, f, d, -1, &o[2 * d]);
+                        (void)conv_flux(g, c, vel, f, d, 1, &o[2 * d + 1]);
+                    }
                 }
     }
 }

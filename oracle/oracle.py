@@ -62,6 +62,7 @@ def lib():
         _lib.og_smart.argtypes = [D, D, D]
         _lib.og_smart.restype = D
         _lib.og_momentum.argtypes = [G, P, P, P, D, P, P, P]
+        _lib.og_momentum_branches.argtypes = [G, P, P, P, P, P, P]
         _lib.og_divergence.argtypes = [G, P, P, P, P]
         _lib.og_gradient.argtypes = [G, P, P, P, P]
         _lib.og_apply_A.argtypes = [G, P, P]
@@ -172,6 +173,20 @@ def momentum(g: Grid, u, v, w, dt):
     gc = g.c()
     lib().og_momentum(ctypes.byref(gc), _p(u), _p(v), _p(w), float(dt), _p(Fu), _p(Fv), _p(Fw))
     return Fu, Fv, Fw
+
+
+def momentum_branches(g: Grid, u, v, w):
+    """The branch every convective flux of the predictor takes at (u, v, w):
+    per component an int8 array of the face array's shape plus a last axis
+    of 6 (direction d, side -1/+1 at 2 d, 2 d + 1); 0 for a zero transport
+    velocity, else 1 + (velocity < 0) + 2 * SMART segment; -1 on closed
+    faces."""
+    su, sv, sw, _ = g.shapes()
+    u, v, w = _chk(u, su), _chk(v, sv), _chk(w, sw)
+    out = [np.empty(s + (6,), dtype=np.int8) for s in (su, sv, sw)]
+    gc = g.c()
+    lib().og_momentum_branches(ctypes.byref(gc), _p(u), _p(v), _p(w), _p(out[0]), _p(out[1]), _p(out[2]))
+    return out
 
 
 def divergence(g: Grid, u, v, w):
