@@ -1207,6 +1207,11 @@ AdjParams adj_params(const nsp_handle *h, double dt) {
     return A;
 }
 
+// the momentum adjoint kernel indexes faces in 32 bits
+bool adj_size_ok(const nsp_handle *h) {
+    return (long long)(h->nx + 1) * (h->ny + 1) * (h->nz + 1) < (1LL << 31);
+}
+
 nsp_status ensure_adj(nsp_handle *h, int nck, int seg) {
     const long long L = state_len(h);
     if (!h->adj_y) {
@@ -1242,6 +1247,7 @@ nsp_status nsp_fine_solve_record(nsp_handle *h, nsp_state y0, int nsteps, double
     if (!h) return NSP_ERR_ARG;
     if (h->pz) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for walls in z only");
     if (h->slip) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for no-slip obstacles only");
+    if (!adj_size_ok(h)) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint takes grids of fewer than 2^31 faces");
     if (!state_ok(y0) || nsteps < 0 || !(dt > 0) || !J) return fail(h, NSP_ERR_ARG, "bad adjoint arguments");
     if (!valid_opts(o)) return fail(h, NSP_ERR_ARG, "invalid Poisson options");
     const bool keep = tape != nullptr;
@@ -1356,6 +1362,7 @@ nsp_status nsp_fine_solve_reverse(nsp_handle *h, unsigned long long tape, nsp_st
 nsp_status nsp_momentum_adjoint(nsp_handle *h, nsp_state vel, nsp_state mu, nsp_state lam, double *g_lid, double dt,
                                 void *stream) {
     if (!h) return NSP_ERR_ARG;
+    if (!adj_size_ok(h)) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint takes grids of fewer than 2^31 faces");
     if (h->pz) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for walls in z only");
     if (h->slip) return fail(h, NSP_ERR_UNSUPPORTED, "the adjoint is implemented for no-slip obstacles only");
     if (!(vel.u && vel.v && vel.w && mu.u && mu.v && mu.w && lam.u && lam.v && lam.w) || !(dt > 0))

@@ -222,6 +222,8 @@ class Handle:
         _live_handles.add(self)
 
     def close(self):
+        for g in list(getattr(self, "_graphs", ())):
+            g.close()  # a graph uses the handle's workspace
         if getattr(self, "_h", None):
             lib().nsp_destroy(self._h)
             self._h = None
@@ -326,7 +328,11 @@ class Handle:
         st = lib().nsp_fine_step_graph_create(self._h, s, B, float(t0), float(t1), float(dt), ctypes.byref(o),
                                               ctypes.byref(out))
         self._err(st, "nsp_fine_step_graph_create")
-        return FineStepGraph(self, out, tuple(y), B)
+        g = FineStepGraph(self, out, tuple(y), B)
+        if not hasattr(self, "_graphs"):
+            self._graphs = weakref.WeakSet()
+        self._graphs.add(g)
+        return g
 
     def coarse_step(self, y, t0, t1, DT, opts=None, check=True):
         """G(y, t1, t0): (t1-t0)/DT projection steps in place on the batch y."""
@@ -580,10 +586,16 @@ class FineStepGraph:
         self._y = y  # the graph writes these tensors' storage
         self.batch = batch
 
+    def _live(self):
+        if not self._g:
+            raise RuntimeError("the graph is closed (or its handle was)")
+
     def launch(self):
+        self._live()
         self._handle._err(lib().nsp_graph_launch(self._g, _stream_ptr()), "nsp_graph_launch")
 
     def finish(self, check=True):
+        self._live()
         info = (_Info * self.batch)()
         st = lib().nsp_graph_finish(self._g, _stream_ptr(), info)
         res = [_info_dict(x) for x in info]

@@ -102,4 +102,8 @@ def test_graph_reports_a_solve_at_its_limit(gpu):
     with pytest.raises(gpu.NSPError) as e:
         h.fine_step_graph(y, 0.0, 0.0, 1e-3)
     assert e.value.status == gpu.NSP_ERR_ARG
+    # closing the handle closes its graphs, which then refuse to run
+    g2 = h.fine_step_graph(y, 0.0, 0.001, 1e-3)
     h.close()
+    with pytest.raises(RuntimeError):
+        g2.launch()
