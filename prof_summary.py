@@ -7,8 +7,9 @@ kept under profiles/.
            DIR holds `rocprofv3 --kernel-trace --stats --output-format csv
            -o run` output; the summary lists the per-kernel statistics and the
            mean duration of the last K dispatches of the kernel (bench.py's
-           timed launches) beside bench.py's own HIP-event figure
-           (--bench-field, default roofline.avg_launch_ms).
+           timed launches; --skip-last N leaves out N dispatches after them)
+           beside bench.py's own HIP-event figure (--bench-field, default
+           roofline.avg_launch_ms).
 
   traffic: python prof_summary.py traffic --fetch DIR --write DIR
                --copy-fetch DIR --copy-write DIR --kernel k_persistent --last K
@@ -76,6 +77,8 @@ def cmd_trace(a):
     bench = _bench_line(a.bench_json)
     mine = sorted((r for r in trace if _short(r["Kernel_Name"]) == a.kernel), key=lambda r: int(r["Dispatch_Id"]))
     dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in mine]
+    if a.skip_last:
+        dur = dur[:-a.skip_last]
     last = dur[-a.last:]
     out = ["# rocprofv3 kernel trace of: %s" % a.cmd,
            "# workload: %s" % json.dumps(bench.get("config", {})),
@@ -88,8 +91,9 @@ def cmd_trace(a):
             float(r["AverageNs"]) * 1e-6, float(r["MinNs"]) * 1e-6, float(r["MaxNs"]) * 1e-6))
     out += ["#",
             "kernel=%s" % a.kernel,
-            "dispatches=%d" % len(dur),
+            "dispatches=%d" % (len(dur) + a.skip_last),
             "timed_dispatches=%d" % len(last),
+            "dispatches_after_the_timed_ones=%d" % a.skip_last,
             "trace_avg_ms_timed=%.4f" % (sum(last) / max(len(last), 1)),
             "bench_avg_launch_ms=%s" % _field(bench, a.bench_field),
             "bench_value=%s %s" % (bench["value"], bench["unit"])]
@@ -153,6 +157,8 @@ def main():
     t.add_argument("--bench-json", required=True)
     t.add_argument("--cmd", required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--skip-last", type=int, default=0,
+                   help="dispatches of the kernel after the timed ones (left out)")
     t.add_argument("--bench-field", default="roofline.avg_launch_ms",
                    help="the bench.py JSON field with the kernel's own HIP-event launch time")
     p = sub.add_parser("traffic")

@@ -1,0 +1,61 @@
+"""The adjoint workload at full size against the oracle's gradient: 96^3
+cavity, Re 400, 100 steps of 1e-3, J = kinetic energy at T, the seeded
+divergence-free start (sigma 1e-2, seed 5) and the 16 x 16 sine-mode lid
+with c ~ N(0, 1e-3^2) (seed 6).  The reference (tests/golden/
+c5_adjoint96_re400_100steps.npz, written by make_adjoint_reference.py with
+the oracle alone) holds J, dJ/d(u0, v0, w0) at 16384 seeded samples per
+component, dJ/dlid at every top u-face and dJ/dc.  The GPU gradient, run as
+the benchmark runs it (checkpoints every 10 steps, Poisson to 1e-12),
+matches it to 1e-9 of each quantity's max norm; J to 1e-12."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1705_06149_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+REF = os.path.join(HERE, "golden", "c5_adjoint96_re400_100steps.npz")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def T(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def N(t):
+    return t.detach().cpu().numpy()
+
+
+def test_adjoint_gradient_matches_oracle_full_size(gpu):
+    import torch
+    if not os.path.exists(REF):
+        pytest.skip("the oracle reference %s has not been generated" % os.path.basename(REF))
+    z = np.load(REF)
+    n, steps, dt, M = int(z["n"]), int(z["nsteps"]), float(z["dt"]), int(z["nmodes"])
+    assert (n, steps, dt, M, float(z["re"])) == (96, 100, 1e-3, 16, 400.0)
+    _say("c5 adjoint vs oracle", n, steps)
+    h = gpu.Handle(n, n, n, re=400.0, max_batch=1)
+    coef = T(np.random.default_rng(6).normal(0.0, 1e-3, (M, M)))
+    h.set_lid(h.lid_from_modes(coef))
+    u0 = inputs.div_free_perturbation(n, n, n, seed=5, sigma=1e-2)
+    y0 = tuple(T(a[None]) for a in u0) + (torch.zeros((1, n, n, n), dtype=torch.float64, device="cuda"),)
+    J, g, gl = h.fine_solve_adjoint(y0, steps, dt, ckpt_every=10, opts=gpu.PoissonOpts(rtol=1e-12))
+    gc = h.lid_modes_grad(gl, M)
+    errs = {"J": abs(J - float(z["J"])) / abs(float(z["J"]))}
+    for name, a in zip("uvw", g):
+        v = N(a).ravel()[z["idx_" + name]]
+        errs[name] = float(np.max(np.abs(v - z["val_" + name]))) / float(z["max_" + name])
+    errs["lid"] = float(np.max(np.abs(N(gl) - z["glid"]))) / float(np.max(np.abs(z["glid"])))
+    errs["coef"] = float(np.max(np.abs(N(gc) - z["gcoef"]))) / float(np.max(np.abs(z["gcoef"])))
+    _say("  errors", errs)
+    assert errs["J"] <= 1e-12
+    for k in ("u", "v", "w", "lid", "coef"):
+        assert errs[k] <= 1e-9, k
+    h.close()
