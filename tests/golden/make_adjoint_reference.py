@@ -14,7 +14,7 @@ dJ/dc (16 x 16, the lid gradient projected on the sine basis).  Usage:
 
     python tests/golden/make_adjoint_reference.py
 
-It takes about half an hour on a few CPU cores and 3 GB of memory.
+It takes about an hour on 8 CPU cores (measured: 57 min) and 3 GB of memory.
 """
 from __future__ import annotations
 
