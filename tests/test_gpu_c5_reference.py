@@ -6,7 +6,10 @@ c5_adjoint96_re400_100steps.npz, written by make_adjoint_reference.py with
 the oracle alone) holds J, dJ/d(u0, v0, w0) at 16384 seeded samples per
 component, dJ/dlid at every top u-face and dJ/dc.  The GPU gradient, run as
 the benchmark runs it (checkpoints every 10 steps, Poisson to 1e-12),
-matches it to 1e-9 of each quantity's max norm; J to 1e-12."""
+matches it to 1e-11 of each quantity's max norm; J to 1e-12.  Both sides
+solve every Poisson system, forward and transposed, to a relative residual
+of 1e-12, and the gradient's error is of that order times the few-step
+growth of the adjoint; measured: 4.7e-14 (w) and below."""
 import os
 
 import numpy as np
@@ -57,5 +60,5 @@ def test_adjoint_gradient_matches_oracle_full_size(gpu):
     _say("  errors", errs)
     assert errs["J"] <= 1e-12
     for k in ("u", "v", "w", "lid", "coef"):
-        assert errs[k] <= 1e-9, k
+        assert errs[k] <= 1e-11, k
     h.close()
