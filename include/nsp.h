@@ -206,7 +206,8 @@ nsp_status nsp_fine_step(nsp_handle *h, nsp_state y, int batch, double t0, doubl
  * nsp_graph_launch enqueues one replay on `stream` (asynchronous: y advances
  * by (t1 - t0)/dt steps when it runs; nothing is read back).
  * nsp_graph_finish synchronises `stream` and reports every replay since the
- * previous finish: info (HOST, `batch` entries, or NULL) gets per slice the
+ * previous finish (with none it returns NSP_OK and leaves info as it is):
+ * info (HOST, `batch` entries, or NULL) gets per slice the
  * summed CG iterations and sweeps, the most iterations of one step, the
  * worst status and the last replay's true residual; the return value is the
  * worst status (NSP_ERR_NOT_CONVERGED, NSP_ERR_NONFINITE, or NSP_ERR_HIP if

@@ -97,15 +97,19 @@ __device__ __forceinline__ double smart_lin(double U, double C, double D, double
 }
 
 // A block gathers lam for a tile of TX x TY x TZ faces of component T.
-// Phase 1 evaluates, once each, the interfaces the tile's faces read into
+// The block evaluates, once each, the interfaces the tile's faces read into
 // LDS: those of component T along x, y and z whose lines hold a face of the
 // tile (lower faces from 2 before the tile to 1 past it), and those of the
 // two other components along T whose transport velocity averages a face of
-// the tile.  Phase 2 sums each face's records in a fixed order.
-constexpr int TX = 8, TY = 8, TZ = 4, kTile = TX * TY * TZ;
+// the tile.  Each face sums its records in a fixed order, family by family.
+// 16 x 8 x 4 faces: x rows of 16 doubles fill whole 128-byte lines
+constexpr int TX = 16, TY = 8, TZ = 4, kTile = TX * TY * TZ;
 constexpr int kAdjThreads = kTile;
 constexpr int NFX = (TX + 3) * TY * TZ, NFY = TX * (TY + 3) * TZ, NFZ = TX * TY * (TZ + 3);
-constexpr int NKMAX = (TX + 1) * TY * TZ > TX * TY * (TZ + 1) ? (TX + 1) * TY * TZ : TX * TY * (TZ + 1);
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// the largest family of carried interfaces: the tile extended by one face
+// along the carried component's axis
+constexpr int NKMAX = cmax(cmax((TX + 1) * TY * TZ, TX * (TY + 1) * TZ), TX * TY * (TZ + 1));
 
 // The cell flags of a tile and 3 cells around it, staged in LDS (cells
 // outside the domain: 0, so their faces read as closed); every face an
@@ -261,11 +265,17 @@ __device__ __forceinline__ void iface(const AdjGrid &G, const FlagBox &FB, const
     }
 }
 
+// Records of one interface family at a time: r[pos][record], row 4 the lid
+// part of the y interfaces of u.  The families are evaluated and gathered
+// one after another (own interfaces along x, y, z, then the carried ones),
+// so the block needs LDS for the largest family only (38.9 KB instead of
+// the 89.6 KB all families would take) and several blocks share a compute
+// unit.
+constexpr int NREC = cmax(cmax(NFX, NFY), NFZ);
+static_assert(NKMAX <= NREC, "each family of carried records fits one record row");
 struct AdjLds {
-    double fx[4][NFX], fy[4][NFY], fz[4][NFZ];  // r[pos][record]
-    double fl[NFY];                             // lid part of the y interfaces (u only)
-    double k1[NKMAX], k2[NKMAX];                // transport weights of the carried interfaces
-    uint8_t flg[FBX * FBY * FBZ];               // cell flags of the tile and 3 cells around it
+    double rec[5][NREC];
+    uint8_t flg[FBX * FBY * FBZ];  // cell flags of the tile and 3 cells around it
 };
 
 // local box of a record family: base offset from the tile origin, extents
@@ -285,90 +295,106 @@ __device__ __forceinline__ Box carried_box() {
     return Box{-(T == 0), -(T == 1), -(T == 2), TX + (C == 0), TY + (C == 1), TZ + (C == 2)};
 }
 
+// own interfaces of component T along D whose lines hold a face of the
+// tile: lower faces from 2 before the tile to 1 past it
+template <int D>
+__device__ __forceinline__ Box own_box() {
+    return Box{-2 * (D == 0), -2 * (D == 1), -2 * (D == 2), TX + 3 * (D == 0), TY + 3 * (D == 1), TZ + 3 * (D == 2)};
+}
+
+template <int T, int D>
+__device__ __forceinline__ void own_records(const AdjGrid &G, const FlagBox &FB, const double *const *vel,
+                                            const double *const *mu, int x0, int y0, int z0, AdjLds &S) {
+    const Box B = own_box<D>();
+    for (int q = threadIdx.x; q < B.size(); q += kAdjThreads) {
+        double r[4], rl, tw;
+        int a, b, c;
+        B.at(q, a, b, c);
+        iface<T, D>(G, FB, vel, mu, x0 + B.bx + a, y0 + B.by + b, z0 + B.bz + c, r, rl, tw);
+        for (int m = 0; m < 4; ++m) S.rec[m][q] = r[m];
+        if (T == 0 && D == 1) S.rec[4][q] = rl;
+    }
+}
+
+// the four records of face t along D: lower faces t - 2e .. t + e hold t at
+// positions 3 .. 0 of their lines
+template <int D>
+__device__ __forceinline__ double own_sum(const AdjLds &S, int tx, int ty, int tz) {
+    const Box B = own_box<D>();
+    const int q = (tz * B.ey + ty) * B.ex + tx;
+    constexpr int st = D == 0 ? 1 : (D == 1 ? TX : TX * TY);
+    return (S.rec[3][q] + S.rec[2][q + st]) + (S.rec[1][q + 2 * st] + S.rec[0][q + 3 * st]);
+}
+
 template <int T>
 __device__ void adj_tile(const AdjGrid &G, const double *const *vel, const double *const *mu, double *__restrict__ lam,
                          double *__restrict__ glid, int x0, int y0, int z0, AdjLds &S) {
     constexpr int C1 = T == 0 ? 1 : 0, C2 = T == 2 ? 1 : 2;  // the other two components
-    const Box BX{-2, 0, 0, TX + 3, TY, TZ}, BY{0, -2, 0, TX, TY + 3, TZ}, BZ{0, 0, -2, TX, TY, TZ + 3};
     const Box K1 = carried_box<T, C1>(), K2 = carried_box<T, C2>();
-    const int n1 = NFX, n2 = n1 + NFY, n3 = n2 + NFZ, n4 = n3 + K1.size(), n5 = n4 + K2.size();
     const FlagBox FB{S.flg, x0 - 3, y0 - 3, z0 - 3};
     for (int q = threadIdx.x; q < FBX * FBY * FBZ; q += kAdjThreads) {
         const int i = FB.ox + q % FBX, j = FB.oy + (q / FBX) % FBY, k = FB.oz + q / (FBX * FBY);
         const bool in = (unsigned)i < (unsigned)G.nx && (unsigned)j < (unsigned)G.ny && (unsigned)k < (unsigned)G.nz;
         S.flg[q] = in ? G.flags[((long)k * G.ny + j) * G.nx + i] : (uint8_t)0;
     }
+    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+    const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
+    // every thread takes part in every phase's records and barriers; only
+    // faces inside the array gather and store
+    const bool in = i < ext(G, T, 0) && j < ext(G, T, 1) && k < ext(G, T, 2);
+    const long x = in ? fid<T>(G, i, j, k) : 0;
     __syncthreads();
-    for (int q = threadIdx.x; q < n5; q += kAdjThreads) {
+    const bool open = in && FB.open(T, i, j, k);
+    double acc = open ? mu[T][x] : 0.0;
+    own_records<T, 0>(G, FB, vel, mu, x0, y0, z0, S);
+    __syncthreads();
+    if (open) acc += own_sum<0>(S, tx, ty, tz);
+    __syncthreads();
+    own_records<T, 1>(G, FB, vel, mu, x0, y0, z0, S);
+    __syncthreads();
+    if (open) acc += own_sum<1>(S, tx, ty, tz);
+    if (T == 0 && in && j == G.ny - 1) {
+        // lid beside the top row of u: the y interfaces below and above it
+        const int q0 = (tz * (TY + 3) + ty + 1) * TX + tx;
+        glid[(long)k * (G.nx + 1) + i] += S.rec[4][q0] + S.rec[4][q0 + TX];
+    }
+    __syncthreads();
+    own_records<T, 2>(G, FB, vel, mu, x0, y0, z0, S);
+    __syncthreads();
+    if (open) acc += own_sum<2>(S, tx, ty, tz);
+    __syncthreads();
+    // carried interfaces (the other components along T, whose transport
+    // velocity averages a face of the tile): K1 in row 0, K2 in row 1
+    const int n1 = K1.size(), n2 = n1 + K2.size();
+    for (int q = threadIdx.x; q < n2; q += kAdjThreads) {
         double r[4], rl, tw;
         int a, b, c;
         if (q < n1) {
-            BX.at(q, a, b, c);
-            iface<T, 0>(G, FB, vel, mu, x0 + BX.bx + a, y0 + BX.by + b, z0 + BX.bz + c, r, rl, tw);
-            for (int m = 0; m < 4; ++m) S.fx[m][q] = r[m];
-        } else if (q < n2) {
-            const int qq = q - n1;
-            BY.at(qq, a, b, c);
-            iface<T, 1>(G, FB, vel, mu, x0 + BY.bx + a, y0 + BY.by + b, z0 + BY.bz + c, r, rl, tw);
-            for (int m = 0; m < 4; ++m) S.fy[m][qq] = r[m];
-            S.fl[qq] = rl;
-        } else if (q < n3) {
-            const int qq = q - n2;
-            BZ.at(qq, a, b, c);
-            iface<T, 2>(G, FB, vel, mu, x0 + BZ.bx + a, y0 + BZ.by + b, z0 + BZ.bz + c, r, rl, tw);
-            for (int m = 0; m < 4; ++m) S.fz[m][qq] = r[m];
-        } else if (q < n4) {
-            const int qq = q - n3;
-            K1.at(qq, a, b, c);
+            K1.at(q, a, b, c);
             iface<C1, T>(G, FB, vel, mu, x0 + K1.bx + a, y0 + K1.by + b, z0 + K1.bz + c, r, rl, tw);
-            S.k1[qq] = tw;
+            S.rec[0][q] = tw;
         } else {
-            const int qq = q - n4;
-            K2.at(qq, a, b, c);
+            K2.at(q - n1, a, b, c);
             iface<C2, T>(G, FB, vel, mu, x0 + K2.bx + a, y0 + K2.by + b, z0 + K2.bz + c, r, rl, tw);
-            S.k2[qq] = tw;
+            S.rec[1][q - n1] = tw;
         }
     }
     __syncthreads();
-    const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
-    const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
-    if (i >= ext(G, T, 0) || j >= ext(G, T, 1) || k >= ext(G, T, 2)) return;
-    const long x = fid<T>(G, i, j, k);
-    if (T == 0 && j == G.ny - 1) {
-        // lid beside the top row of u: the y interfaces below and above it
-        const int q0 = ((tz * (TY + 3) + ty + 1) * TX + tx);
-        glid[(long)k * (G.nx + 1) + i] += S.fl[q0] + S.fl[q0 + TX];
-    }
-    if (!FB.open(T, i, j, k)) {
+    if (!in) return;
+    if (!open) {
         lam[x] = 0.0;
         return;
-    }
-    double acc = mu[T][x];
-    // own interfaces along x, y, z: lower faces t - 2e .. t + e hold t at
-    // positions 3 .. 0 of their lines
-    {
-        const int q = (tz * TY + ty) * (TX + 3) + tx;
-        acc += ((S.fx[3][q] + S.fx[2][q + 1]) + (S.fx[1][q + 2] + S.fx[0][q + 3]));
-    }
-    {
-        const int q = (tz * (TY + 3) + ty) * TX + tx;
-        acc += ((S.fy[3][q] + S.fy[2][q + TX]) + (S.fy[1][q + 2 * TX] + S.fy[0][q + 3 * TX]));
-    }
-    {
-        const int q = (tz * TY + ty) * TX + tx;
-        constexpr int P = TX * TY;
-        acc += ((S.fz[3][q] + S.fz[2][q + P]) + (S.fz[1][q + 2 * P] + S.fz[0][q + 3 * P]));
     }
     // carried interfaces: L = t - e_T and t - e_T + e_C
     {
         const int q = (tz * K1.ey + ty) * K1.ex + tx;
         const int st = C1 == 0 ? 1 : (C1 == 1 ? K1.ex : K1.ex * K1.ey);
-        acc += S.k1[q] + S.k1[q + st];
+        acc += S.rec[0][q] + S.rec[0][q + st];
     }
     {
         const int q = (tz * K2.ey + ty) * K2.ex + tx;
         const int st = C2 == 0 ? 1 : (C2 == 1 ? K2.ex : K2.ex * K2.ey);
-        acc += S.k2[q] + S.k2[q + st];
+        acc += S.rec[1][q] + S.rec[1][q + st];
     }
     lam[x] = acc;
 }

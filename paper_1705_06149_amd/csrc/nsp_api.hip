@@ -1212,27 +1212,31 @@ bool adj_size_ok(const nsp_handle *h) {
     return (long long)(h->nx + 1) * (h->ny + 1) * (h->nz + 1) < (1LL << 31);
 }
 
+// Each buffer is allocated on its own test, so a call after a failed
+// allocation retries what is missing instead of running with a null buffer;
+// a checkpoint store is counted only once it exists.
 nsp_status ensure_adj(nsp_handle *h, int nck, int seg) {
     const long long L = state_len(h);
-    if (!h->adj_y) {
-        HIPCHK(h, dalloc(&h->adj_y, L));
-        HIPCHK(h, dalloc(&h->adj_lam, h->nu + h->nv + h->nw));
-        HIPCHK(h, dalloc(&h->adj_mu, h->nu + h->nv + h->nw));
-        HIPCHK(h, dalloc(&h->adj_p, h->ncells));
-        HIPCHK(h, dalloc(&h->adj_glid, (size_t)h->nz * (h->nx + 1)));
-        HIPCHK(h, dalloc(&h->adj_part, 3 * kSumBlocks + 1));
-        HIPCHK(h, dalloc(&h->adj_fin, h->nu + h->nv + h->nw));
-    }
+    const long long F3 = h->nu + h->nv + h->nw;
+    if (!h->adj_y) HIPCHK(h, dalloc(&h->adj_y, L));
+    if (!h->adj_lam) HIPCHK(h, dalloc(&h->adj_lam, F3));
+    if (!h->adj_mu) HIPCHK(h, dalloc(&h->adj_mu, F3));
+    if (!h->adj_p) HIPCHK(h, dalloc(&h->adj_p, h->ncells));
+    if (!h->adj_glid) HIPCHK(h, dalloc(&h->adj_glid, (size_t)h->nz * (h->nx + 1)));
+    if (!h->adj_part) HIPCHK(h, dalloc(&h->adj_part, 3 * kSumBlocks + 1));
+    if (!h->adj_fin) HIPCHK(h, dalloc(&h->adj_fin, F3));
     if (nck > h->adj_nck) {
         if (h->adj_ck) (void)hipFree(h->adj_ck);
         h->adj_ck = nullptr;
+        h->adj_nck = 0;
         HIPCHK(h, dalloc(&h->adj_ck, (size_t)nck * L));
         h->adj_nck = nck;
     }
     if (seg > h->adj_seg) {
         if (h->adj_segu) (void)hipFree(h->adj_segu);
         h->adj_segu = nullptr;
-        HIPCHK(h, dalloc(&h->adj_segu, (size_t)seg * (h->nu + h->nv + h->nw)));
+        h->adj_seg = 0;
+        HIPCHK(h, dalloc(&h->adj_segu, (size_t)seg * F3));
         h->adj_seg = seg;
     }
     return NSP_OK;

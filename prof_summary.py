@@ -20,6 +20,15 @@ kept under profiles/.
            bytes), and the summary records HBM bytes per launch of the last K
            dispatches together with the kernel source hash, which bench.py
            checks before it reports the figure as `traffic`.
+
+  sq:      python prof_summary.py sq DIR --kernel k_mom_adjoint --last K
+               --workload "..." --cmd "..." --out profiles/NAME.txt
+           DIR holds `rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY
+           SQ_ACTIVE_INST_VALU ...` output; the summary gives each counter's
+           mean per dispatch over the last K dispatches of the kernel, its
+           value per wave, and the fractions of the wave lifetime spent
+           waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) and issuing VALU work
+           (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES).
 """
 from __future__ import annotations
 
@@ -147,6 +156,36 @@ def _write(path, lines):
     print("\n".join(lines))
 
 
+def cmd_sq(a):
+    rows = _csv(a.dir, "counter_collection.csv")
+    names = sorted({r["Counter_Name"] for r in rows})
+    mean = {}
+    for n in names:
+        v = _counter(a.dir, n, a.kernel)[-a.last:]
+        if not v:
+            raise SystemExit("no %s dispatches of %s under %s" % (n, a.kernel, a.dir))
+        mean[n] = sum(v) / len(v)
+    waves = mean.get("SQ_WAVES", 0.0)
+    out = ["# rocprofv3 SQ counters of: %s" % a.cmd,
+           "# workload: %s" % a.workload,
+           "# SQ_WAVE_CYCLES, SQ_WAIT_ANY and SQ_ACTIVE_* are summed over waves in one unit, so their ratios are "
+           "fractions of the wave lifetime; per_wave = value / SQ_WAVES",
+           "kernel=%s" % a.kernel,
+           "dispatches_used=%d" % a.last]
+    for n in names:
+        pw = " per_wave=%.1f" % (mean[n] / waves) if waves else ""
+        out.append("%s=%.1f%s" % (n, mean[n], pw))
+    cyc = mean.get("SQ_WAVE_CYCLES")
+    if cyc:
+        if "SQ_WAIT_ANY" in mean:
+            out.append("wait_fraction_of_wave_lifetime=%.3f" % (mean["SQ_WAIT_ANY"] / cyc))
+        if "SQ_ACTIVE_INST_VALU" in mean:
+            out.append("valu_active_fraction_of_wave_lifetime=%.3f" % (mean["SQ_ACTIVE_INST_VALU"] / cyc))
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -167,9 +206,18 @@ def main():
         p.add_argument(k, required=True)
     p.add_argument("--kernel", default="k_persistent")
     p.add_argument("--last", type=int, required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("dir")
+    q.add_argument("--kernel", default="k_persistent")
+    q.add_argument("--last", type=int, required=True)
+    q.add_argument("--workload", required=True)
+    q.add_argument("--cmd", required=True)
+    q.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd_name == "trace":
         cmd_trace(a)
+    elif a.cmd_name == "sq":
+        cmd_sq(a)
     else:
         cmd_traffic(a)
 
