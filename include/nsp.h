@@ -144,6 +144,11 @@ typedef struct {
  * max_batch outside 1..64 or fluid cells that are not face-connected
  * (across the z seam too when periodic). */
 nsp_status nsp_create(const nsp_grid *grid, nsp_handle **out);
+/* nsp_destroy waits for the device and frees the handle and all its
+ * workspace (records of nsp_fine_solve_record included); destroy the
+ * handle's graphs first.  NSP_ERR_ARG for a NULL handle.
+ * nsp_last_error: the message of the handle's last failed call ("null
+ * handle" for NULL), owned by the handle and valid until its next call. */
 nsp_status nsp_destroy(nsp_handle *h);
 const char *nsp_last_error(const nsp_handle *h);
 
