@@ -28,7 +28,12 @@ kept under profiles/.
            mean per dispatch over the last K dispatches of the kernel, its
            value per wave, and the fractions of the wave lifetime spent
            waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) and issuing VALU work
-           (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES).
+           (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES).  With GRBM_GUI_ACTIVE (the
+           GPU's busy cycles of the dispatch, summed over the --xcds
+           dies) it adds the share of the dispatch each SIMD spent issuing
+           VALU work: SQ_ACTIVE_INST_VALU x 4 (the counter ticks once per 4
+           cycles) / (SIMDs x GRBM_GUI_ACTIVE / xcds), with 4 SIMDs on each
+           of --cus compute units.
 """
 from __future__ import annotations
 
@@ -181,6 +186,12 @@ def cmd_sq(a):
             out.append("wait_fraction_of_wave_lifetime=%.3f" % (mean["SQ_WAIT_ANY"] / cyc))
         if "SQ_ACTIVE_INST_VALU" in mean:
             out.append("valu_active_fraction_of_wave_lifetime=%.3f" % (mean["SQ_ACTIVE_INST_VALU"] / cyc))
+    gui = mean.get("GRBM_GUI_ACTIVE")
+    if gui and "SQ_ACTIVE_INST_VALU" in mean:
+        cycles = gui / a.xcds
+        out.append("gpu_busy_cycles_per_xcd=%.0f" % cycles)
+        out.append("valu_busy_per_simd=%.3f  (SQ_ACTIVE_INST_VALU x 4 / (4 x %d SIMDs x GRBM_GUI_ACTIVE / %d))"
+                   % (mean["SQ_ACTIVE_INST_VALU"] * 4.0 / (4 * a.cus * cycles), a.cus, a.xcds))
     with open(a.out, "w") as fh:
         fh.write("\n".join(out) + "\n")
     print("\n".join(out))
@@ -213,6 +224,8 @@ def main():
     q.add_argument("--workload", required=True)
     q.add_argument("--cmd", required=True)
     q.add_argument("--out", required=True)
+    q.add_argument("--cus", type=int, default=256, help="compute units of the GPU")
+    q.add_argument("--xcds", type=int, default=8, help="dies GRBM_GUI_ACTIVE is summed over")
     a = ap.parse_args()
     if a.cmd_name == "trace":
         cmd_trace(a)
