@@ -192,9 +192,7 @@ def cmd_sq(a):
         out.append("gpu_busy_cycles_per_xcd=%.0f" % cycles)
         out.append("valu_busy_per_simd=%.3f  (SQ_ACTIVE_INST_VALU x 4 / (4 x %d SIMDs x GRBM_GUI_ACTIVE / %d))"
                    % (mean["SQ_ACTIVE_INST_VALU"] * 4.0 / (4 * a.cus * cycles), a.cus, a.xcds))
-    with open(a.out, "w") as fh:
-        fh.write("\n".join(out) + "\n")
-    print("\n".join(out))
+    _write(a.out, out)
 
 
 def main():

@@ -1,7 +1,9 @@
 """prof_summary.py (the script that turns rocprofv3 CSV output into the
 summaries under profiles/) on synthetic CSV files: kernel names reduced to
-their bare name, the mean of the last K dispatches, and HBM bytes per launch
-scaled by the copy calibration."""
+their bare name, the mean of the last K dispatches (also with trailing
+dispatches left out), HBM bytes per launch scaled by the copy calibration,
+and the SQ counter ratios (per wave, VALU busy per SIMD from the busy cycles
+summed over the dies)."""
 import csv
 import json
 import os
@@ -79,3 +81,41 @@ def test_traffic_summary(tmp_path):
     assert float(rec["hbm_bytes_per_launch"]) == (4000.0 + 1000.0) * 1024
     assert abs(float(rec["traffic_over_algorithmic"]) - 5000.0 / 4096.0) < 1e-4
     assert rec["kernel_source_sha256_16"] == "abc123"
+
+
+def test_trace_summary_leaves_out_trailing_dispatches(tmp_path):
+    d = tmp_path / "tr"
+    d.mkdir()
+    _write_csv(d / "run_kernel_stats.csv", [
+        {"Name": KNAME, "Calls": 5, "TotalDurationNs": 25e6, "AverageNs": 5e6, "MinNs": 1e6, "MaxNs": 9e6}])
+    _write_csv(d / "run_kernel_trace.csv", [
+        {"Kernel_Name": KNAME, "Dispatch_Id": i, "Start_Timestamp": 0, "End_Timestamp": int(ns)}
+        for i, ns in enumerate([1e6, 2e6, 4e6, 9e6, 9e6])])
+    _bench_log(tmp_path / "b.log", 1e9)
+    out = tmp_path / "t.txt"
+    _run("trace", str(d), "--last", "2", "--skip-last", "2", "--bench-json", str(tmp_path / "b.log"), "--cmd",
+         "CMD", "--out", str(out))
+    text = out.read_text()
+    assert "dispatches=5" in text and "dispatches_after_the_timed_ones=2" in text
+    assert "trace_avg_ms_timed=3.0000" in text   # 2 ms and 4 ms; the two 9 ms dispatches after them left out
+
+
+def test_sq_summary(tmp_path):
+    d = tmp_path / "sq"
+    d.mkdir()
+    per = {"SQ_WAVES": 100.0, "SQ_WAVE_CYCLES": 1000.0, "SQ_WAIT_ANY": 600.0, "SQ_ACTIVE_INST_VALU": 32.0,
+           "GRBM_GUI_ACTIVE": 80.0}
+    # dispatch i holds (i + 1) times the values above
+    _write_csv(d / "run_counter_collection.csv", [
+        {"Kernel_Name": KNAME, "Dispatch_Id": i, "Counter_Name": k, "Counter_Value": v * (i + 1)}
+        for i in range(3) for k, v in per.items()])
+    out = tmp_path / "q.txt"
+    _run("sq", str(d), "--kernel", "k_persistent", "--last", "2", "--workload", "W", "--cmd", "CMD", "--out",
+         str(out), "--cus", "2", "--xcds", "2")
+    rec = {k: v.split()[0] for k, v in (line.split("=", 1) for line in out.read_text().splitlines()
+                                          if "=" in line and not line.startswith("#"))}
+    assert float(rec["SQ_WAVES"]) == 250.0   # mean of the last two dispatches, 200 and 300
+    assert float(rec["wait_fraction_of_wave_lifetime"]) == 0.6
+    # 4 x ACTIVE_INST_VALU / (4 SIMDs x 2 CUs x GRBM_GUI_ACTIVE / 2 dies) = 4 x 80 / (8 x 100)
+    assert float(rec["gpu_busy_cycles_per_xcd"]) == 100.0
+    assert float(rec["valu_busy_per_simd"]) == 0.4
