@@ -13,6 +13,7 @@ kept under profiles/.
 
   traffic: python prof_summary.py traffic --fetch DIR --write DIR
                --copy-fetch DIR --copy-write DIR --kernel k_persistent --last K
+               [--skip-last N]
                --bench-json FILE --hash FILE --cmd "..." --out profiles/NAME.txt
            The four DIRs hold `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
            output of the benchmark and of bench.py's 1 GiB copy.  Each counter
@@ -127,8 +128,11 @@ def cmd_traffic(a):
     cf, cw = cf[-1], cw[-1]
     sf = nread / (cf * 1024.0)
     sw = nwrite / (cw * 1024.0)
-    f = _counter(a.fetch, "FETCH_SIZE", a.kernel)[-a.last:]
-    w = _counter(a.write, "WRITE_SIZE", a.kernel)[-a.last:]
+    f = _counter(a.fetch, "FETCH_SIZE", a.kernel)
+    w = _counter(a.write, "WRITE_SIZE", a.kernel)
+    if a.skip_last:
+        f, w = f[:-a.skip_last], w[:-a.skip_last]
+    f, w = f[-a.last:], w[-a.last:]
     rd = sf * 1024.0 * sum(f) / len(f)
     wr = sw * 1024.0 * sum(w) / len(w)
     with open(a.hash) as fh:
@@ -143,6 +147,7 @@ def cmd_traffic(a):
            "write_scale=%.4f" % sw,
            "kernel=%s" % a.kernel,
            "dispatches_used=%d" % len(f),
+           "dispatches_after_the_used_ones=%d" % a.skip_last,
            "fetch_kib_per_dispatch=%.1f" % (sum(f) / len(f)),
            "write_kib_per_dispatch=%.1f" % (sum(w) / len(w)),
            "hbm_read_bytes_per_launch=%.6e" % rd,
@@ -215,6 +220,8 @@ def main():
         p.add_argument(k, required=True)
     p.add_argument("--kernel", default="k_persistent")
     p.add_argument("--last", type=int, required=True)
+    p.add_argument("--skip-last", type=int, default=0,
+                   help="dispatches of the kernel after the ones to average (left out)")
     q = sub.add_parser("sq")
     q.add_argument("dir")
     q.add_argument("--kernel", default="k_persistent")

@@ -81,6 +81,12 @@ def test_traffic_summary(tmp_path):
     assert float(rec["hbm_bytes_per_launch"]) == (4000.0 + 1000.0) * 1024
     assert abs(float(rec["traffic_over_algorithmic"]) - 5000.0 / 4096.0) < 1e-4
     assert rec["kernel_source_sha256_16"] == "abc123"
+    # the same with the last dispatch left out: dispatches 0 and 1
+    _run("traffic", "--fetch", kf, "--write", kw, "--copy-fetch", cf, "--copy-write", cw, "--bench-json",
+         str(tmp_path / "b.log"), "--copy-json", str(tmp_path / "copy.log"), "--hash", str(tmp_path / "hash.txt"),
+         "--last", "2", "--skip-last", "1", "--cmd", "CMD", "--out", str(out))
+    rec = dict(line.split("=", 1) for line in out.read_text().splitlines() if "=" in line and not line.startswith("#"))
+    assert float(rec["hbm_bytes_per_launch"]) == (999.0 + 1000.0 + (7.0 + 500.0) / 2) * 1024
 
 
 def test_trace_summary_leaves_out_trailing_dispatches(tmp_path):
