@@ -22,7 +22,7 @@ kept under profiles/.
            dispatches together with the kernel source hash, which bench.py
            checks before it reports the figure as `traffic`.
 
-  sq:      python prof_summary.py sq DIR --kernel k_mom_adjoint --last K
+  sq:      python prof_summary.py sq DIR --kernel k_mom_adjoint --last K [--skip-last N]
                --workload "..." --cmd "..." --out profiles/NAME.txt
            DIR holds `rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY
            SQ_ACTIVE_INST_VALU ...` output; the summary gives each counter's
@@ -171,7 +171,10 @@ def cmd_sq(a):
     names = sorted({r["Counter_Name"] for r in rows})
     mean = {}
     for n in names:
-        v = _counter(a.dir, n, a.kernel)[-a.last:]
+        v = _counter(a.dir, n, a.kernel)
+        if a.skip_last:
+            v = v[:-a.skip_last]
+        v = v[-a.last:]
         if not v:
             raise SystemExit("no %s dispatches of %s under %s" % (n, a.kernel, a.dir))
         mean[n] = sum(v) / len(v)
@@ -181,7 +184,8 @@ def cmd_sq(a):
            "# SQ_WAVE_CYCLES, SQ_WAIT_ANY and SQ_ACTIVE_* are summed over waves in one unit, so their ratios are "
            "fractions of the wave lifetime; per_wave = value / SQ_WAVES",
            "kernel=%s" % a.kernel,
-           "dispatches_used=%d" % a.last]
+           "dispatches_used=%d" % a.last,
+           "dispatches_after_the_used_ones=%d" % a.skip_last]
     for n in names:
         pw = " per_wave=%.1f" % (mean[n] / waves) if waves else ""
         out.append("%s=%.1f%s" % (n, mean[n], pw))
@@ -231,6 +235,8 @@ def main():
     q.add_argument("--out", required=True)
     q.add_argument("--cus", type=int, default=256, help="compute units of the GPU")
     q.add_argument("--xcds", type=int, default=8, help="dies GRBM_GUI_ACTIVE is summed over")
+    q.add_argument("--skip-last", type=int, default=0,
+                   help="dispatches of the kernel after the ones to average (left out)")
     a = ap.parse_args()
     if a.cmd_name == "trace":
         cmd_trace(a)

@@ -125,3 +125,7 @@ def test_sq_summary(tmp_path):
     # 4 x ACTIVE_INST_VALU / (4 SIMDs x 2 CUs x GRBM_GUI_ACTIVE / 2 dies) = 4 x 80 / (8 x 100)
     assert float(rec["gpu_busy_cycles_per_xcd"]) == 100.0
     assert float(rec["valu_busy_per_simd"]) == 0.4
+    # the last dispatch left out: dispatches 0 and 1 (100 and 200 waves)
+    _run("sq", str(d), "--kernel", "k_persistent", "--last", "2", "--skip-last", "1", "--workload", "W", "--cmd",
+         "CMD", "--out", str(out), "--cus", "2", "--xcds", "2")
+    assert "SQ_WAVES=150.0" in out.read_text()
