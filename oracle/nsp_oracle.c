@@ -944,19 +944,44 @@ int og_fine_steps(const og_grid *g, double *u, double *v, double *w, double *p, 
     return og_fine_steps_solver(g, u, v, w, p, nsteps, dt, prec, 0, rtol, maxit, eta, max_outer, iters, rel_true);
 }
 
+int og_fine_steps_ex(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
+                     int prec, int solver, double rtol, int maxit, double eta, int max_outer, int extrap,
+                     int *iters, double *rel_true);
+
 /* as og_fine_steps; solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed), 1: FP64
  * Jacobi-BiCGStab (prec ignored), 2: single-reduction Jacobi-PCG (FP64) */
 int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
                          int prec, int solver, double rtol, int maxit, double eta, int max_outer, int *iters,
                          double *rel_true) {
+    return og_fine_steps_ex(g, u, v, w, p, nsteps, dt, prec, solver, rtol, maxit, eta, max_outer, 0, iters,
+                            rel_true);
+}
+
+/* as og_fine_steps_solver.  extrap = 1: the Poisson solve of step s >= 1
+ * starts from the linear extrapolation 2 p^s - p^(s-1) of the last two
+ * pressures of this call instead of p^s (step 0 starts from the caller's
+ * p, as always).  The equation solved and its stopping test are the same,
+ * so a step's result is unchanged up to the solver tolerance; only the
+ * initial guess, and so the iteration count, differs. */
+int og_fine_steps_ex(const og_grid *g, double *u, double *v, double *w, double *p, int nsteps, double dt,
+                     int prec, int solver, double rtol, int maxit, double eta, int max_outer, int extrap,
+                     int *iters, double *rel_true) {
     size_t nu = og_face_count(g, 0), nv = og_face_count(g, 1), nw = og_face_count(g, 2);
     size_t n = ncells(g);
     double *Fu = malloc(nu * sizeof(double)), *Fv = malloc(nv * sizeof(double));
     double *Fw = malloc(nw * sizeof(double)), *b = malloc(n * sizeof(double));
+    double *pprev = extrap ? malloc(n * sizeof(double)) : NULL;
     int worst = 0;
     for (int s = 0; s < nsteps; ++s) {
         og_momentum(g, u, v, w, dt, Fu, Fv, Fw);
         og_rhs(g, Fu, Fv, Fw, dt, b);
+        if (extrap) {
+            for (size_t c = 0; c < n; ++c) {
+                const double ps = p[c];
+                if (s > 0) p[c] = 2.0 * ps - pprev[c];
+                pprev[c] = ps;
+            }
+        }
         og_info info;
         int st = solver == 1               ? og_bicgstab(g, b, p, rtol, maxit, &info)
                  : solver == 2 && prec == 0 ? og_pcg_sr(g, b, p, rtol, maxit, &info)
@@ -968,7 +993,7 @@ int og_fine_steps_solver(const og_grid *g, double *u, double *v, double *w, doub
         if (rel_true) rel_true[s] = info.rel_res_true;
         og_correct(g, Fu, Fv, Fw, p, dt, u, v, w);
     }
-    free(Fu); free(Fv); free(Fw); free(b);
+    free(Fu); free(Fv); free(Fw); free(b); free(pprev);
     return worst;
 }
 

@@ -76,6 +76,8 @@ def lib():
         _lib.og_fine_steps.restype = I
         _lib.og_fine_steps_solver.argtypes = [G, P, P, P, P, I, D, I, I, D, I, D, I, P, P]
         _lib.og_fine_steps_solver.restype = I
+        _lib.og_fine_steps_ex.argtypes = [G, P, P, P, P, I, D, I, I, D, I, D, I, I, P, P]
+        _lib.og_fine_steps_ex.restype = I
         _lib.og_bicgstab.argtypes = [G, P, P, D, I, ctypes.POINTER(_Info)]
         _lib.og_bicgstab.restype = I
         _lib.og_pcg_sr.argtypes = [G, P, P, D, I, ctypes.POINTER(_Info)]
@@ -292,11 +294,14 @@ def correct(g: Grid, Fu, Fv, Fw, p, dt):
     return u, v, w
 
 
-def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta=1e-5, max_outer=8, solver=0):
+def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta=1e-5, max_outer=8, solver=0,
+               extrapolate=False):
     """nsteps projection steps of size dt; returns (new state, iters, rel_true, status).
     solver 0: Jacobi-PCG (prec 0 FP64, 1 mixed restarts, 2 mixed reliable
     updates with eta = delta and max_outer = update limit); 1: FP64
-    Jacobi-BiCGStab; 2: single-reduction Jacobi-PCG (FP64).
+    Jacobi-BiCGStab; 2: single-reduction Jacobi-PCG (FP64).  extrapolate:
+    from the second step of the call on, each Poisson solve starts from
+    2 p^s - p^(s-1) instead of p^s (same equation and stopping test).
 
     The input state tuple (u, v, w, p) is not modified."""
     su, sv, sw, sp = g.shapes()
@@ -304,9 +309,9 @@ def fine_steps(g: Grid, state, nsteps, dt, prec=0, rtol=1e-10, maxit=100000, eta
     iters = np.zeros(max(nsteps, 1), dtype=np.int32)
     rel = np.zeros(max(nsteps, 1))
     gc = g.c()
-    st = lib().og_fine_steps_solver(ctypes.byref(gc), _p(u), _p(v), _p(w), _p(p), int(nsteps), float(dt),
-                                    int(prec), int(solver), float(rtol), int(maxit), float(eta), int(max_outer),
-                                    _p(iters), _p(rel))
+    st = lib().og_fine_steps_ex(ctypes.byref(gc), _p(u), _p(v), _p(w), _p(p), int(nsteps), float(dt),
+                                int(prec), int(solver), float(rtol), int(maxit), float(eta), int(max_outer),
+                                int(bool(extrapolate)), _p(iters), _p(rel))
     return (u, v, w, p), iters[:nsteps], rel[:nsteps], st
 
 
