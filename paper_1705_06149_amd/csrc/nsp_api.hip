@@ -60,6 +60,7 @@ struct nsp_handle {
     double *r = nullptr, *d0 = nullptr, *d1 = nullptr, *q = nullptr;
     float *e = nullptr;
     double *bv0 = nullptr, *bv1 = nullptr, *brh = nullptr;  // BiCGStab (allocated on first use)
+    double *pprev = nullptr;  // extrapolated warm start: previous pressure per slice (allocated on first use)
     nsp_state gs{nullptr, nullptr, nullptr, nullptr};  // scratch state for the coarse sweep
     LaunchRes L;
     // adjoint workspace (allocated on first use)
@@ -236,7 +237,8 @@ bool valid_opts(const nsp_poisson_opts *o) {
     return o && o->rtol >= 0 && o->maxit >= 0 &&
            (o->prec == NSP_FP64 || o->prec == NSP_MIXED || o->prec == NSP_MIXED_RU) &&
            (o->prec == NSP_FP64 || (o->inner_rtol > 0 && o->inner_rtol < 1 && o->max_outer >= 0)) &&
-           (o->solver == NSP_PCG || o->solver == NSP_BICGSTAB || o->solver == NSP_PCG_SR);
+           (o->solver == NSP_PCG || o->solver == NSP_BICGSTAB || o->solver == NSP_PCG_SR) &&
+           (o->extrapolate == 0 || o->extrapolate == 1);
 }
 
 // number of steps (t1 - t0)/dt, which must be a non-negative integer
@@ -294,6 +296,7 @@ void fill_group(GroupDesc &G, nsp_handle *h, nsp_state y, int slice_off, int nsl
     G.v = y.v ? y.v + (long long)slice_off * h->nv : nullptr;
     G.w = y.w ? y.w + (long long)slice_off * h->nw : nullptr;
     G.p = y.p ? y.p + (long long)slice_off * h->ncells : nullptr;
+    G.pprev = nullptr;  // set by plan_launch when the launch extrapolates the warm start
     G.Fu = h->Fu;
     G.Fv = h->Fv;
     G.Fw = h->Fw;
@@ -438,6 +441,17 @@ nsp_status plan_launch(nsp_handle *const *hs, int ngroups, const GroupDesc *grou
             lg[g].bv1 = hg->bv1;
             lg[g].brh = hg->brh;
         }
+    // extrapolated warm start: every grid of the launch needs its previous-
+    // pressure array (one cell array per slice of max_batch)
+    const bool extrap = o->extrapolate != 0 && mode == MODE_FINE && nsteps > 1;
+    if (extrap) {
+        if (caller_ws) return fail(h, NSP_ERR_UNSUPPORTED, "the extrapolated warm start needs the handle's workspace");
+        for (int g = 0; g < ngroups; ++g) {
+            nsp_handle *hg = hs[g];
+            if (!hg->pprev) HIPCHK(h, dalloc(&hg->pprev, (size_t)hg->max_batch * hg->ncells));
+            lg[g].pprev = hg->pprev;
+        }
+    }
     int depth = h->force_depth, items = h->force_items;
     if (depth <= 0 && items <= 0)
         for (const TuneEntry &t : h->tuned)
@@ -465,6 +479,7 @@ nsp_status plan_launch(nsp_handle *const *hs, int ngroups, const GroupDesc *grou
     P.max_outer = o->max_outer;
     P.xcd_remap = 1;
     P.solver = o->solver;
+    P.extrap = extrap ? 1 : 0;
     {
         // write-through CG stores while the launch is cache-resident (<= 8 M cells)
         long long cells = 0;
@@ -946,7 +961,7 @@ nsp_status nsp_destroy(nsp_handle *h) {
         if (p) (void)hipFree(p);
     void *aptrs[] = {h->adj_ck, h->adj_segu, h->adj_y, h->adj_lam, h->adj_mu, h->adj_p, h->adj_glid, h->adj_part,
                      h->adj_fin,
-                     h->bv0, h->bv1, h->brh};
+                     h->bv0, h->bv1, h->brh, h->pprev};
     for (void *p : aptrs)
         if (p) (void)hipFree(p);
     if (h->L.ctl_host) (void)hipHostFree(h->L.ctl_host);
@@ -1257,6 +1272,11 @@ nsp_status nsp_fine_solve_record(nsp_handle *h, nsp_state y0, int nsteps, double
     const bool keep = tape != nullptr;
     if (keep) *tape = 0;
     h->tape = 0;  // the workspace is about to be overwritten
+    // the reverse sweep recomputes steps one call at a time, where no
+    // extrapolation happens: the record must take the same plain warm start
+    nsp_poisson_opts of = *o;
+    of.extrapolate = 0;
+    o = &of;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int ck = ckpt_every > 0 ? std::min(ckpt_every, std::max(nsteps, 1)) : std::max(nsteps, 1);
     const int nseg = nsteps > 0 ? (nsteps + ck - 1) / ck : 0;

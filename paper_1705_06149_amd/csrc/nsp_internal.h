@@ -70,6 +70,7 @@ struct GroupDesc {
                                    // CG: w (two buffers) and the second residual buffer
     float *e;                      // FP32 defect correction
     const double *bin;             // Poisson mode: caller's right-hand side
+    double *pprev;                 // KParams::extrap: the previous step's pressure per slice (slice stride ncells)
 };
 
 // Per-slice solver state, written by the reducing workgroup at barriers and
@@ -135,6 +136,7 @@ struct KParams {
     int rr;                // CG vectors held in registers: every group has column tiles of 4 or 8
                            // planes (one partial block deep, nz a multiple), one item per thread, and
                            // the launch has no more CG tiles than workgroups
+    int extrap;            // MODE_FINE: warm start 2 p^s - p^(s-1) from the second step on (GroupDesc::pprev)
     double dt;
     double rtol, eta;
     SliceCtl *ctl;         // [nslices]

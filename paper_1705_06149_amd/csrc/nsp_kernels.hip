@@ -884,7 +884,15 @@ struct Runner {
                      // the w plane at z = Lz: a closed wall, or (periodic) the face at z = 0
                      if (!G.pz && x.k == G.nz - 1) Fw[fidx<2>(G, x.i, x.j, G.nz)] = 0.0;
                      if (G.pz && x.k == 0) Fw[fidx<2>(G, x.i, x.j, G.nz)] = fw;
-                     if (gauge) {
+                     if (P.extrap) {
+                         // warm start of this step's solve: p^s after the gauge
+                         // fix, then 2 p^s - p^(s-1) from the second step on
+                         double GAS *p = gp(G.p) + (long)sl * G.ncells;
+                         double GAS *pp = gp(G.pprev) + (long)sl * G.ncells;
+                         const double ps = gauge ? p_eff(ctl(gs), p[c], fl & FL_FLUID) : p[c];
+                         if (gauge) p[c] = 2.0 * ps - pp[c];
+                         pp[c] = ps;
+                     } else if (gauge) {
                          double GAS *p = gp(G.p) + (long)sl * G.ncells;
                          p[c] = p_eff(ctl(gs), p[c], fl & FL_FLUID);
                      }

@@ -47,7 +47,8 @@ class _Grid(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("prec", ctypes.c_int),
-                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("solver", ctypes.c_int)]
+                ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int), ("solver", ctypes.c_int),
+                ("extrapolate", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -146,10 +147,11 @@ class PoissonOpts:
     inner_rtol: float = 1e-5
     max_outer: int = 8
     solver: int = 0  # PCG, BICGSTAB or PCG_SR
+    extrapolate: bool = False  # warm start 2 p^s - p^(s-1) from the second step of a call on
 
     def c(self):
         return _Opts(float(self.rtol), int(self.maxit), int(self.prec), float(self.inner_rtol), int(self.max_outer),
-                     int(self.solver))
+                     int(self.solver), int(bool(self.extrapolate)))
 
 
 def _torch():
