@@ -33,6 +33,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -178,7 +179,10 @@ def bench_fine(args):
     n, re_, dt = 128, 1000.0, 5e-4
     prec = _prec(args)
     opts = nsp.PoissonOpts(rtol=1e-10, maxit=100000, prec=prec, inner_rtol=_eta(args),
-                           max_outer=_max_outer(args), solver=_solver(args))
+                           max_outer=_max_outer(args), solver=_solver(args), extrapolate=args.extrapolate)
+    # equal launches of S steps: the largest divisor of the timed steps up to
+    # --steps-per-launch (a graph replays one step)
+    S = 1 if args.graph else math.gcd(args.steps, max(args.steps_per_launch, 1))
     h = nsp.Handle(n, n, n, re=re_, max_batch=1, solid=_fine_solid(args), slip_obstacles=args.slip)
     y = h.zeros_state(1)
     t = 0.0
@@ -208,10 +212,11 @@ def bench_fine(args):
         outer_per_launch = info[0]["outer"] / K
         g.close()
     else:
+        # K steps as K / S calls of S steps each (S = --steps-per-launch)
         t0 = time.perf_counter()
-        for _ in range(K):
-            info = h.fine_step(y, t, t + dt, dt, opts)
-            t += dt
+        for _ in range(K // S):
+            info = h.fine_step(y, t, t + S * dt, dt, opts)
+            t += S * dt
             iters += info[0]["iters"]
             launch_ms.append(h.last_launch_ms())
         _sync()
@@ -231,7 +236,7 @@ def bench_fine(args):
     # bytes by the kernels' own phase layout
     per_iter = _bytes_per_iter(args)
     fixed = BYTES_STEP_FIXED[args.precision] + (BYTES_SR_START if args.solver == "pcg_sr" else 0.0)
-    layout_bytes = cells * (fixed + per_iter * iters / K)
+    layout_bytes = S * cells * (fixed + per_iter * iters / K)
     if args.precision != "fp64":
         layout_bytes += cells * BYTES_MIXED_SWEEP * outer_per_launch
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
@@ -239,7 +244,7 @@ def bench_fine(args):
     # step, 112 B plus 80 B per FP64 CG iteration (mixed: 40 B per FP32
     # iteration and 40 B per FP64 correction sweep), independent of how the
     # kernels lay the phases out or keep vectors on chip
-    model_bytes = _model_bytes(args, cells, iters / K, outer_per_launch)
+    model_bytes = S * _model_bytes(args, cells, iters / K, outer_per_launch / S)
     achieved = model_bytes / avg_launch_s / 1e9
     sfx = "" if args.solver == "pcg" else "_" + args.solver
     traffic = (_traffic_from_profile("k_persistent_cavity128_%s%s_pmc.txt" % (args.precision, sfx))
@@ -259,15 +264,17 @@ def bench_fine(args):
         "data": "synthetic",
         "config": {"workload": _fine_workload(args), "grid": [n, n, n], "re": re_, "dt": dt,
                    "start": "rest, after %d warm-up steps" % args.warmup,
-                   "poisson": _solver_name(args) + " rtol 1e-10",
+                   "poisson": _solver_name(args) + " rtol 1e-10" +
+                   (", warm start 2 p^s - p^(s-1)" if args.extrapolate else ", warm start p^s"),
                    "precision": args.precision},
-        "launch": "one HIP graph replayed per step, read back once" if args.graph else "one call per step",
+        "launch": ("one HIP graph replayed per step, read back once" if args.graph else
+                   "one call per step" if S == 1 else "one call per %d steps" % S),
         "cg_iters_per_step": iters / K,
         "inner_rtol": _eta(args) if args.precision != "fp64" else None,
         "velocity_rel_l2_vs_fp64": err_vs_fp64,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_persistent (one fused fine step per launch)",
+                     "kernel": "k_persistent (%d fused fine step%s per launch)" % (S, "" if S == 1 else "s"),
                      "avg_launch_ms": 1e3 * avg_launch_s,
                      "algorithmic_bytes_per_launch": model_bytes,
                      "byte_model": "112 + 80 I B per cell and step (mixed: 112 + 40 I32 + 40 per sweep)",
@@ -294,7 +301,7 @@ def cpu_baseline_fine(args, host_state, t):
         O.set_num_threads(nthr)
         t0 = time.perf_counter()
         _, iters, _, st = O.fine_steps(g, host_state, nsteps, 5e-4, prec=prec, rtol=1e-10, eta=_eta(args),
-                                       max_outer=_max_outer(args))
+                                       max_outer=_max_outer(args), extrapolate=args.extrapolate)
         runs[label] = (nsteps, time.perf_counter() - t0, int(iters.sum()))
     O.set_num_threads(threads)
     (ns, wall, it), (n1, wall1, it1) = runs["all"], runs["one"]
@@ -899,6 +906,12 @@ def main():
     # the obstacle batch, whose 128^3 grid needs dt < ~4.4e-3.
     ap.add_argument("--graph", action="store_true",
                     help="fine mode: record the step as a HIP graph and replay it (nsp_fine_step_graph_create)")
+    ap.add_argument("--steps-per-launch", type=int, default=15,
+                    help="fine mode: the timed steps run as calls of this many steps each (default 15: the "
+                         "30 timed steps in two launches)")
+    ap.add_argument("--extrapolate", action=argparse.BooleanOptionalAction, default=True,
+                    help="fine mode: Poisson warm start 2 p^s - p^(s-1) from the second step of a call on "
+                         "(--no-extrapolate: p^s)")
     ap.add_argument("--coarse-dt", type=float, default=None)
     ap.add_argument("--coarse-rtol", type=float, default=1e-6,
                     help="parareal and obstacles modes: relative residual of the coarse propagator's Poisson "
