@@ -89,7 +89,7 @@ def _parareal_fine_opts(args, nsp):
     prec = {"fp64": nsp.FP64, "mixed": nsp.MIXED, "mixed_ru": nsp.MIXED_RU}[args.parareal_fine]
     eta = args.eta if args.eta is not None else (RU_DELTA if args.parareal_fine == "mixed_ru" else 1e-5)
     return nsp.PoissonOpts(rtol=1e-10, prec=prec, inner_rtol=eta, max_outer=64 if args.parareal_fine == "mixed_ru"
-                           else 8)
+                           else 8, extrapolate=args.parareal_extrapolate)
 
 
 def _model_bytes(args, cells, iters_per_step, sweeps_per_launch):
@@ -389,7 +389,7 @@ def bench_parareal(args):
     # (Courant number 0.48, diffusion term 0.14)
     DT = args.coarse_dt if args.coarse_dt is not None else (1e-2 if cgrid else 5e-3)
     tol = 1e-6
-    fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
+    fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64, extrapolate=args.parareal_extrapolate)
     mixed = _parareal_fine_opts(args, nsp)
     # the serial coarse sweep is a batch of one, latency-bound: FP32 saves no
     # time there and each defect-correction restart adds iterations, so G
@@ -480,7 +480,8 @@ def bench_parareal(args):
         "config": {"workload": "parareal96_re1000", "grid": [n, n, n], "slices": N, "T": T, "dt": dt, "DT": DT,
                    "jump_tol": tol, "coarse_grid": [n // 2] * 3 if cgrid else [n, n, n],
                    "coarse_convection": "upwind" if args.coarse_upwind else "smart",
-                   "fine_poisson": "%s, inner %g" % (args.parareal_fine, mixed.inner_rtol), "coarse_poisson": "fp64, rtol %g" % args.coarse_rtol},
+                   "fine_poisson": "%s, inner %g%s" % (args.parareal_fine, mixed.inner_rtol,
+                                                       ", extrapolated start" if args.parareal_extrapolate else ""), "coarse_poisson": "fp64, rtol %g" % args.coarse_rtol},
         "parareal_iterations": k, "jumps": jumps, "iteration_s": iter_s, "serial_fp64_s": serial, "parareal_s": par,
         "batched_fine_sweep": sweep,
         "serial_equiv_cell_updates_per_s": cells * nf / par,
@@ -506,7 +507,7 @@ def bench_obstacles(args):
     re_, dt, N, T = 1000.0, 5e-4, 16, 0.32
     DT = args.coarse_dt if args.coarse_dt is not None else 2.5e-3
     tol = 1e-6
-    fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64)
+    fine64 = nsp.PoissonOpts(rtol=1e-10, prec=nsp.FP64, extrapolate=args.parareal_extrapolate)
     mixed = _parareal_fine_opts(args, nsp)
     # the serial coarse sweep is a batch of one, latency-bound: FP32 saves no
     # time there and each defect-correction restart adds iterations, so G
@@ -913,6 +914,9 @@ def main():
                     help="fine mode: Poisson warm start 2 p^s - p^(s-1) from the second step of a call on "
                          "(--no-extrapolate: p^s)")
     ap.add_argument("--coarse-dt", type=float, default=None)
+    ap.add_argument("--parareal-extrapolate", action="store_true",
+                    help="parareal and obstacles modes: the extrapolated warm start in the fine sweeps and in "
+                         "the serial FP64 reference alike")
     ap.add_argument("--coarse-rtol", type=float, default=1e-6,
                     help="parareal and obstacles modes: relative residual of the coarse propagator's Poisson "
                          "solves (G only predicts; 1e-6 keeps the iterations of 1e-10, 1e-4 does not)")
